@@ -1,0 +1,198 @@
+/*
+ * tsfde.h -- C ABI of the MI355X (gfx950) solver for the quasi-boundary-value
+ * inverse source problem of a time-space fractional diffusion equation
+ * (Majumdar, Serra-Capizzano, Sormani, arXiv 2507.02809).
+ *
+ * The library solves the all-at-once system  A y = z  of §5 (eq. lin-syst)
+ * with flexible GMRES, right-preconditioned by the block lower-triangular
+ * matrix P of §5.1, and returns the regularised source f~ (the last block of y).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - Grid (§4): Omega = (0, length)^d, n = N interior points per direction,
+ *    h = length/(N+1), x_j = j h; t_s = s T/M, s = 1..M (M is the paper's S).
+ *  - Vector layout (§5, eq. lin-syst; multi-index rule of §2): a solution or
+ *    right-hand side has (M+1) * N^d entries: M slices v^(1..M) followed by
+ *    f~, slice-major; inside a slice the multi-index (j_1, .., j_d) runs with
+ *    the LAST index fastest.
+ *  - Ownership: create functions COPY their host arrays into device memory
+ *    owned by the problem; the caller may free its arrays on return.  Every
+ *    other pointer argument is a caller-owned DEVICE pointer unless stated
+ *    otherwise; the library never retains it after the call returns.
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *    enqueued on it; entry points that report statistics synchronise it.
+ *  - Errors: every function returns a tsfde_status; nothing is thrown across
+ *    the ABI.  tsfde_last_error() returns a thread-local message describing
+ *    the last failure.  On error, output buffers hold unspecified values.
+ *  - Calls that share one problem object must not overlap (the problem owns
+ *    its work buffers); different problem objects are independent.
+ */
+#ifndef TSFDE_H
+#define TSFDE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tsfde_problem tsfde_problem; /* opaque, library-owned */
+
+typedef enum {
+    TSFDE_OK = 0,
+    TSFDE_EINVAL = 1,     /* invalid argument (parameter range, NULL, aliasing)   */
+    TSFDE_ENOMEM = 2,     /* device allocation failed or exceeded max_device_bytes */
+    TSFDE_EDEVICE = 3,    /* a HIP runtime call failed                             */
+    TSFDE_ENOCONV = 4,    /* solver hit maxit; x holds the last iterate            */
+    TSFDE_ENONFINITE = 5, /* NaN or Inf in an input array                          */
+    TSFDE_ENOTIMPL = 6    /* combination not supported by this build               */
+} tsfde_status;
+
+typedef enum { TSFDE_FP64 = 0, TSFDE_MIXED = 1 } tsfde_precision;
+
+/* Solver options.  tsfde_default_opts() fills the defaults listed here. */
+typedef struct tsfde_opts {
+    int restart;         /* FGMRES restart length m                       (50)   */
+    int maxit;           /* max outer iterations (all restarts, all refinement
+                            sweeps together); <= 0 means min(n_tot, 1000)  (0)   */
+    double tol;          /* stop when ||b - A x||_2 <= tol ||b||_2        (1e-10) */
+    int precision;       /* TSFDE_FP64: every operator application in FP64;
+                            TSFDE_MIXED: A and P^{-1} inside FGMRES in FP32, the
+                            residual b - A x, Arnoldi, Givens and the update in
+                            FP64, closed by iterative refinement        (FP64)  */
+    int use_precond;     /* 1: right preconditioning by P of §5.1; 0: none (1)   */
+    double inner_tol;    /* relative residual of each diagonal-block solve inside
+                            P^{-1} (preconditioned CG)                  (1e-12) */
+    int inner_maxit;     /* cap on CG iterations per block solve        (200)   */
+    double refine_tol;   /* MIXED: relative tolerance of each inner FGMRES
+                            sweep on A d = r                            (1e-5)  */
+    int max_refine;      /* MIXED: max refinement sweeps                (30)    */
+} tsfde_opts;
+
+/* Statistics of a solve.  Times are wall-clock seconds on the host, measured
+   around stream-synchronised phases. */
+typedef struct tsfde_stats {
+    int iters;                 /* outer (Arnoldi) iterations, all sweeps        */
+    int restarts;              /* FGMRES restarts                               */
+    int refinements;           /* MIXED: refinement sweeps (FP64: 1)            */
+    int converged;             /* 1 if ||b - A x|| <= tol ||b|| was reached     */
+    long long inner_iters;     /* CG iterations inside all P^{-1} applications  */
+    double rel_res;            /* final ||b - A x||_2 / ||b||_2, FP64 A         */
+    double t_total;            /* seconds in the solve                          */
+    double t_precond;          /* seconds applying P^{-1}                       */
+    double t_matvec;           /* seconds applying A                            */
+    double t_ortho;            /* seconds in Gram-Schmidt and the x update      */
+} tsfde_stats;
+
+void tsfde_default_opts(tsfde_opts* opts);
+
+/*
+ * Create a problem on the current HIP device (§4 eq. numer-scheme, §5 eq. lin-syst).
+ *   d         spatial dimension, 1 or 2
+ *   N         interior grid points per direction (N >= 1)
+ *   M         time steps (the paper's S, M >= 1);  T > 0 final time
+ *   beta      Caputo order, 0 < beta < 1 (§1)
+ *   omega     fractional-Laplacian order, 1 < omega < 2 (§1)
+ *   alpha     quasi-boundary regularisation parameter (the paper's lambda), > 0 (§3)
+ *   gamma1    host [M][N^d], gamma_1(x_j, t_s), s = 1..M, must be >= 0
+ *   gamma2    host [M][N^d], gamma_2(x_j, t_s), must be > 0
+ *   q         host [M], q(t_s) > 0
+ *   rho       host [N^d] initial state, or NULL for zero
+ *   mu        host [N^d] noisy final-time data mu_eps, or NULL for zero
+ *   out       receives the problem handle
+ * Omega = (0,1)^d.  Returns EINVAL for out-of-range parameters, ENONFINITE for
+ * NaN/Inf inputs, ENOMEM / EDEVICE on device failures.
+ */
+tsfde_status tsfde_create_problem(int d, int N, int M, double T, double beta, double omega,
+                                  double alpha, const double* gamma1, const double* gamma2,
+                                  const double* q, const double* rho, const double* mu,
+                                  tsfde_problem** out);
+
+/*
+ * As tsfde_create_problem with Omega = (0, length)^d (the paper's experiments use
+ * length = pi, §6) and an optional stencil override: `stencil` (host, N^d values,
+ * a_l for 0 <= l_i <= N-1, last index fastest) replaces the library's own
+ * Fourier coefficients of eq. fourier-coeff; NULL computes them (d = 1: eq.
+ * fourier-coeff-1d through Lemma 1; d = 2: FFT of the sampled generating
+ * function with Richardson extrapolation, the FFT route named in §4).
+ */
+tsfde_status tsfde_create_problem_ex(int d, int N, int M, double T, double beta, double omega,
+                                     double alpha, const double* gamma1, const double* gamma2,
+                                     const double* q, const double* rho, const double* mu,
+                                     double length, const double* stencil, tsfde_problem** out);
+
+/* Replace mu_eps (host [N^d]) without rebuilding the problem. */
+tsfde_status tsfde_set_mu(tsfde_problem* prob, const double* mu);
+
+void tsfde_destroy_problem(tsfde_problem* prob);
+
+/* (M+1) * N^d, the length of y and z. */
+size_t tsfde_vector_length(const tsfde_problem* prob);
+
+/* Scalars of the discretisation: out[0] = h, out[1] = dt, out[2] = eta = dt^beta Gamma(2-beta),
+   out[3] = eta/h^omega, out[4] = alpha/h^omega, out[5] = circulant embedding size L. */
+tsfde_status tsfde_problem_scalars(const tsfde_problem* prob, double out[6]);
+
+/* Copy the stencil table a_l, 0 <= l_i <= N-1 (N^d values) used by the problem into
+   host memory `out` (§4 eq. fourier-coeff). */
+tsfde_status tsfde_get_stencil(const tsfde_problem* prob, double* out);
+
+/* Compute the stencil table a_l, 0 <= l_i <= N-1 (host, N^d doubles) for dimension d and
+   order omega without creating a problem (host computation only). */
+tsfde_status tsfde_compute_stencil(int d, int N, double omega, double* out);
+
+/*
+ * z = A y  (§5 'Implementation': time-history sum with the e_m weights scaled by D_1^(s),
+ * Toeplitz product (eta/h^omega) D_2^(s) B y^(s) through a zero-padded circulant
+ * embedding and FFTs, minus eta q^(s) y^(M+1); last block (alpha/h^omega) D_2^(M) B y^(M+1)
+ * + y^(M)).  y, z: device, (M+1) N^d entries, must not overlap.
+ */
+tsfde_status tsfde_apply_A(tsfde_problem* prob, const double* y, double* z, void* stream);
+tsfde_status tsfde_apply_A_f32(tsfde_problem* prob, const float* y, float* z, void* stream);
+
+/*
+ * y ~= P^{-1} z by the forward substitution of §5.1: for s = 1..M solve
+ * (e_0 D_1^(s) + (eta/h^omega) D_2^(s) B) y^(s) = z^(s) - D_1^(s) sum_{m<s} e_{s-m} y^(m),
+ * then (alpha/h^omega) D_2^(M) B y^(M+1) = z^(M+1) - y^(M).  Each block is solved by
+ * preconditioned CG on its symmetrised form to opts->inner_tol (the paper uses a direct
+ * solve; see the design notes).  opts may be NULL (defaults).  z, y: device, no overlap.
+ */
+tsfde_status tsfde_apply_P_inv(tsfde_problem* prob, const double* z, double* y,
+                               const tsfde_opts* opts, void* stream);
+tsfde_status tsfde_apply_P_inv_f32(tsfde_problem* prob, const float* z, float* y,
+                                   const tsfde_opts* opts, void* stream);
+
+/*
+ * Solve A x = b by right-preconditioned flexible GMRES(m) (§5: GMRES with P of §5.1).
+ *   b      device, (M+1) N^d; NULL uses the system's own right-hand side z of eq. lin-syst
+ *   x      device, (M+1) N^d; in: initial guess, out: solution (last iterate on ENOCONV)
+ *   opts   NULL for defaults;  stats  may be NULL.
+ * Returns TSFDE_ENOCONV if tol was not reached within maxit.
+ */
+tsfde_status tsfde_gmres_solve(tsfde_problem* prob, const double* b, double* x,
+                               const tsfde_opts* opts, tsfde_stats* stats, void* stream);
+
+/*
+ * Recover the regularised source: build z (eq. lin-syst), solve from x0 = 0 (§6) and write
+ * f~ = y^(M+1) into f_out (device, N^d).  `work` is a device buffer of (M+1) N^d doubles
+ * that receives the full solution y, or NULL to use an internal buffer.
+ */
+tsfde_status tsfde_recover_f(tsfde_problem* prob, double* f_out, double* work,
+                             const tsfde_opts* opts, tsfde_stats* stats, void* stream);
+
+/*
+ * Direct problem of §6.1: v = A-hat^{-1} z-hat with z-hat^(s) = b_{s-1} D_1^(s) rho + eta q^(s) f,
+ * i.e. the first M steps of the forward substitution (used to synthesise mu).
+ *   f    device, N^d        v  device, M N^d (slices v^(1..M)); mu = v^(M)
+ */
+tsfde_status tsfde_forward_solve(tsfde_problem* prob, const double* f, double* v,
+                                 const tsfde_opts* opts, void* stream);
+
+/* Last error message of the calling thread ("" if none). */
+const char* tsfde_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSFDE_H */

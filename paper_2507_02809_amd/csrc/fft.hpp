@@ -1,0 +1,125 @@
+// LDS-resident Stockham FFT for power-of-two lengths (radix 8, with one radix-4 or
+// radix-2 pass when log2(L) is not a multiple of 3).
+//
+// A group of `nthr` threads transforms one sequence of L = VPT * nthr complex values
+// held in LDS; several groups of a workgroup may run side by side on their own
+// sequences (every group executes the same passes, so the passes synchronise with
+// __syncthreads()).  Each pass reads all its butterfly inputs into registers, waits,
+// and writes the outputs in Stockham (self-sorting) order in place.
+//
+// Twiddles come from a table tw[m] = exp(-2 pi i m / L), m = 0..L-1, computed on
+// the host in double precision (rounded once for FP32).  Forward transforms use
+// exp(-2 pi i jk/L); the inverse uses the conjugate and is not scaled.
+#pragma once
+
+#include "common.hpp"
+
+namespace tsfde {
+
+template <typename T, bool INV>
+__device__ __forceinline__ cplx<T> mul_mi(cplx<T> a) {  // * (-i) forward, * (+i) inverse
+    return INV ? cplx<T>{-a.y, a.x} : cplx<T>{a.y, -a.x};
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cplx<T>* v) {
+    cplx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cplx<T>& x0, cplx<T>& x1, cplx<T>& x2, cplx<T>& x3) {
+    cplx<T> a = cadd(x0, x2), b = csub(x0, x2);
+    cplx<T> c = cadd(x1, x3), d = mul_mi<T, INV>(csub(x1, x3));
+    x0 = cadd(a, c);
+    x2 = csub(a, c);
+    x1 = cadd(b, d);
+    x3 = csub(b, d);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(cplx<T>* v) {
+    // even / odd halves, then combine with W8^k
+    cplx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cplx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<T, INV>(e0, e1, e2, e3);
+    dft4<T, INV>(o0, o1, o2, o3);
+    const T r = T(0.70710678118654752440084436210484903928);
+    // W8^1 = (1 - i)/sqrt2 forward, (1 + i)/sqrt2 inverse
+    cplx<T> t1 = INV ? cplx<T>{r * (o1.x - o1.y), r * (o1.x + o1.y)}
+                     : cplx<T>{r * (o1.x + o1.y), r * (o1.y - o1.x)};
+    cplx<T> t2 = mul_mi<T, INV>(o2);
+    // W8^3 = (-1 - i)/sqrt2 forward, (-1 + i)/sqrt2 inverse
+    cplx<T> t3 = INV ? cplx<T>{-r * (o3.x + o3.y), r * (o3.x - o3.y)}
+                     : cplx<T>{r * (o3.y - o3.x), -r * (o3.x + o3.y)};
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, t1);
+    v[5] = csub(e1, t1);
+    v[2] = cadd(e2, t2);
+    v[6] = csub(e2, t2);
+    v[3] = cadd(e3, t3);
+    v[7] = csub(e3, t3);
+}
+
+template <typename T, int R, int VPT, bool INV>
+__device__ __forceinline__ void stockham_pass(cplx<T>* a, int L, int Ns, const cplx<T>* __restrict__ tw,
+                                              int tid, int nthr) {
+    constexpr int NB = VPT / R;  // butterflies per thread
+    const int nbut = L / R;
+    cplx<T> v[NB][R];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        const int b = tid + c * nthr;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[c][r] = a[b + r * nbut];
+    }
+    __syncthreads();
+    const int tstride = L / (Ns * R);
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        const int b = tid + c * nthr;
+        const int k = b & (Ns - 1);
+        if (Ns > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cplx<T> w = tw[r * k * tstride];
+                v[c][r] = INV ? cmulc(v[c][r], w) : cmul(v[c][r], w);
+            }
+        }
+        if constexpr (R == 8) {
+            dft8<T, INV>(v[c]);
+        } else if constexpr (R == 4) {
+            dft4<T, INV>(v[c][0], v[c][1], v[c][2], v[c][3]);
+        } else {
+            dft2<T, INV>(v[c]);
+        }
+        const int base = (b - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[base + r * Ns] = v[c][r];
+    }
+    __syncthreads();
+}
+
+// In-place FFT of a[0..L) with L = VPT * nthr.  Must be called by all threads of the
+// workgroup (it contains __syncthreads()); `tid` is the thread's index within its group.
+template <typename T, int VPT, bool INV>
+__device__ void fft_lds(cplx<T>* a, int L, const cplx<T>* __restrict__ tw, int tid, int nthr) {
+    int Ns = 1;
+    while (Ns < L) {
+        const int rem = L / Ns;
+        if (rem >= 8) {
+            stockham_pass<T, 8, VPT, INV>(a, L, Ns, tw, tid, nthr);
+            Ns *= 8;
+        } else if (rem == 4) {
+            stockham_pass<T, 4, VPT, INV>(a, L, Ns, tw, tid, nthr);
+            Ns *= 4;
+        } else {
+            stockham_pass<T, 2, VPT, INV>(a, L, Ns, tw, tid, nthr);
+            Ns *= 2;
+        }
+    }
+}
+
+}  // namespace tsfde

@@ -1,0 +1,141 @@
+// Internal declarations of the tsfde library: the problem object, device buffers
+// and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tsfde.h"
+#include "common.hpp"
+
+namespace tsfde {
+
+void set_error(const char* fmt, ...);
+
+struct HipError {
+    hipError_t code;
+    std::string where;
+};
+
+#define TSFDE_HIP(call)                                                  \
+    do {                                                                 \
+        hipError_t e_ = (call);                                          \
+        if (e_ != hipSuccess) throw ::tsfde::HipError{e_, #call};        \
+    } while (0)
+
+// Device arrays of one precision.
+template <typename T>
+struct Dev {
+    T* gamma1 = nullptr;   // [M][Nd]
+    T* gamma2 = nullptr;   // [M][Nd]
+    T* dg = nullptr;       // [M][Nd]  e_0 gamma1 / gamma2 (symmetrised diagonal of block s)
+    T* epad = nullptr;     // [kEpad + M] zeros then e_0..e_{M-1}
+    T* q = nullptr;        // [M]
+    T* sym = nullptr;      // Toeplitz circulant symbol / L^d; d=1: [L]; d=2: [H][L]
+    cplx<T>* tw = nullptr;   // [L]  twiddles exp(-2 pi i m / L)
+    cplx<T>* twd = nullptr;  // [Ld] twiddles for the sine transform (tau preconditioner)
+    T* tau = nullptr;        // [Nd] tau eigenvalues of B (natural tau matrix), k-major like x
+    // work
+    cplx<T>* spec = nullptr;  // [nspec_slices][H][N] (d=2) half spectra of row transforms
+    T* pcg = nullptr;         // 8 vectors of Nd: x r z p q t1 t2 rhs
+    T* partial = nullptr;     // block partial sums
+    T* vecA = nullptr;        // scratch vectors of n_tot (mixed-mode staging)
+    T* vecB = nullptr;
+};
+
+constexpr int kEpad = 256;   // leading zeros in epad (covers the history tile overhang)
+constexpr int kMaxPartials = 4096;
+
+struct Problem {
+    int d = 1, N = 1, M = 1;
+    double T = 1, beta = 0.5, omega = 1.5, alpha = 1e-3, length = 1;
+    long long Nd = 1, ntot = 1;
+    double h = 0, dt = 0, eta = 0, ct = 0, cf = 0;
+    int L = 8, H = 5;     // circulant embedding length per direction (pow2 >= 2N-1), L/2+1
+    int Ld = 0;           // sine-transform extension 2(N+1) when it is a power of two, else 0
+    int nspec = 0;        // slices the spectrum buffer holds
+    std::vector<double> stencil;  // a_l, 0 <= l_i < N, last index fastest
+    std::vector<double> e, b, sigma;  // e_m, b_m, mean of dg per step
+    std::vector<double> gamma1_h, gamma2_h, q_h, rho_h, mu_h;
+    Dev<double> f64;
+    Dev<float> f32;
+    bool have_f32 = false;
+    double* d_bw = nullptr;    // [M] b_0..b_{M-1}
+    double* d_rho = nullptr;   // [Nd]
+    double* d_mu = nullptr;    // [Nd]
+    bool tau_ok = false;       // sine-transform preconditioner available (2(N+1) a power of two)
+    double a0 = 0;             // stencil centre a_0 (Jacobi fallback)
+    double* z_rhs = nullptr;   // built right-hand side z (FP64, n_tot)
+    double* xbuf = nullptr;    // solution buffer for recover_f (n_tot)
+    // FGMRES basis storage (allocated on demand)
+    double* V = nullptr;
+    double* Z = nullptr;
+    int basis_m = 0;
+    double* dev_scalars = nullptr;  // small device scratch (dots, flags)
+    double* host_scalars = nullptr; // pinned mirror
+    size_t bytes = 0;
+};
+
+// ---- launchers (kernels.hip / spectral.hip) ----
+template <typename T>
+void launch_history_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s);
+
+template <typename T>
+void launch_toeplitz_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s);
+
+// q = dg .* p + c * B p  (single slice, dg may be null), with per-block partials of (p, q)
+template <typename T>
+void launch_spd_apply(const Problem& P, const Dev<T>& D, const T* p, T* q, const T* dg, T c,
+                      T* partials, int* nparts, hipStream_t s);
+
+// z = (2/(N+1))^d S diag(1/(sigma + c*tau)) S r with S the sine transform (tau preconditioner),
+// per-block partials of (r, z)
+template <typename T>
+void launch_tau_prec(const Problem& P, const Dev<T>& D, const T* r, T* z, T sigma, T c,
+                     T* partials, int* nparts, hipStream_t s);
+
+// r = (z_s - gamma1_s .* sum_{m<s} e_{s-m} y_m) ./ gamma2_s  for block step s (0-based)
+template <typename T>
+void launch_step_rhs(const Problem& P, const Dev<T>& D, const T* z, const T* y, int s, T* rhs,
+                     T scale_last, hipStream_t st);
+
+// BLAS-1 helpers
+template <typename T>
+void launch_dot_partials(const T* a, const T* b, long long n, T* partials, int* nparts, hipStream_t s);
+template <typename T>
+void launch_copy(const T* a, T* b, long long n, hipStream_t s);
+void launch_d2f(const double* a, float* b, long long n, hipStream_t s);
+void launch_f2d(const float* a, double* b, long long n, hipStream_t s);
+void launch_sum_partials(const double* partials, int n, double* out, hipStream_t s);
+void launch_sum_partials(const float* partials, int n, double* out, hipStream_t s);
+
+// CG vector updates with device scalars: see kernels.hip
+template <typename T>
+void launch_cg_update_xr(T* x, T* r, const T* p, const T* q, const double* scal, long long n,
+                         T* partials, int* nparts, hipStream_t s);
+template <typename T>
+void launch_cg_update_p(T* p, const T* z, const double* scal, long long n, hipStream_t s);
+void launch_cg_scalars(double* scal, int mode, hipStream_t s);
+
+// Arnoldi helpers (FP64)
+void launch_multidot(const double* V, long long n, int k, const double* w, double* partials,
+                     int nblk, hipStream_t s);
+void launch_multidot_finish(const double* partials, int nblk, int k, double* h, hipStream_t s);
+void launch_gemv_sub(const double* V, long long n, int k, const double* h, double* w, hipStream_t s);
+void launch_gemv_add(const double* Z, long long n, int k, const double* y, double* x, hipStream_t s);
+void launch_scale(double* v, long long n, const double* num, const double* den, hipStream_t s);
+void launch_axpby(double a, const double* x, double b, const double* y, double* out, long long n,
+                  hipStream_t s);
+void launch_build_z(const Problem& P, double* z, hipStream_t s);
+void launch_build_zhat(const Problem& P, const double* f, double* zhat, hipStream_t s);
+void launch_fill(double* p, long long n, double v, hipStream_t s);
+void launch_fill(float* p, long long n, float v, hipStream_t s);
+template <typename T>
+void launch_sub_partials(const T* a, const T* b, T* out, long long n, T* partials, int* nparts, hipStream_t s);
+template <typename T>
+void launch_jacobi_prec(const T* r, T* z, const T* dg, T c, T a0, long long n, T* partials, int* nparts,
+                        hipStream_t s);
+
+}  // namespace tsfde

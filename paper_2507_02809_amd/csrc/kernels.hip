@@ -1,0 +1,438 @@
+// Streaming kernels: the time-history part of A y (§5 matvec step 1(a)), the history
+// right-hand side of each forward-substitution step for P (§5.1), CG vector updates,
+// Arnoldi (classical Gram-Schmidt) reductions and small vector helpers.
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace tsfde {
+
+// ---------------------------------------------------------------------------
+// z^(s) = gamma1^(s) .* sum_{m=1}^{s} e_{s-m} y^(m) - eta q^(s) y^(M+1),  s = 1..M
+// (0-based here: s = 0..M-1, y[M] is f~).
+//
+// One workgroup = 64 spatial points (one per lane) x 64 output steps (16 per wave).
+// The input steps are staged through LDS 16 at a time; e_{s-m} is wave-uniform, so
+// the weights come from the scalar cache.  epad holds kEpad zeros before e_0 so that
+// e_{s-m} with m > s reads a zero.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void history_matvec(const T* __restrict__ y, T* __restrict__ z,
+                                                      const T* __restrict__ g1, const T* __restrict__ epad,
+                                                      const T* __restrict__ q, T eta, long long Nd, int M) {
+    __shared__ T tile[16][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long j = (long long)blockIdx.x * 64 + lane;
+    const int s0 = blockIdx.y * 64;
+    const int sw = s0 + wave * 16;
+    const int s_end = min(s0 + 64, M);
+    T acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = T(0);
+    for (int m0 = 0; m0 < s_end; m0 += 16) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < 16 * 64; t += 256) {
+            const int mm = t >> 6, jj = t & 63;
+            const long long jg = (long long)blockIdx.x * 64 + jj;
+            const int m = m0 + mm;
+            tile[mm][jj] = (m < s_end && jg < Nd) ? y[(long long)m * Nd + jg] : T(0);
+        }
+        __syncthreads();
+        if (m0 <= sw + 15) {
+            const T* ew = epad + kEpad + sw - m0;
+#pragma unroll
+            for (int mm = 0; mm < 16; ++mm) {
+                const T yv = tile[mm][lane];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[i] += ew[i - mm] * yv;
+            }
+        }
+    }
+    if (j < Nd) {
+        const T f = y[(long long)M * Nd + j];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int s = sw + i;
+            if (s < M) z[(long long)s * Nd + j] = g1[(long long)s * Nd + j] * acc[i] - eta * q[s] * f;
+        }
+    }
+}
+
+template <typename T>
+void launch_history_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s) {
+    dim3 grid((unsigned)((P.Nd + 63) / 64), (unsigned)((P.M + 63) / 64));
+    hipLaunchKernelGGL(history_matvec<T>, grid, dim3(256), 0, s, y, z, D.gamma1, D.epad, D.q, T(P.eta), P.Nd, P.M);
+    TSFDE_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// right-hand side of forward-substitution step s (0-based):
+//   s < M : rhs = (z^(s) - gamma1^(s) .* sum_{m<s} e_{s-m} y^(m)) ./ gamma2^(s)
+//   s = M : rhs = (z^(M) - y^(M-1)) ./ (cf gamma2^(M-1))          (last block row)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void step_rhs(const T* __restrict__ z, const T* __restrict__ y, const T* __restrict__ g1,
+                         const T* __restrict__ g2, const T* __restrict__ epad, int s, int M, long long Nd,
+                         T cf, T* __restrict__ rhs) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= Nd) return;
+    if (s == M) {
+        rhs[j] = (z[(long long)M * Nd + j] - y[(long long)(M - 1) * Nd + j]) / (cf * g2[(long long)(M - 1) * Nd + j]);
+        return;
+    }
+    T h = T(0);
+    const T* e = epad + kEpad;
+    for (int m = 0; m < s; ++m) h += e[s - m] * y[(long long)m * Nd + j];
+    const long long o = (long long)s * Nd + j;
+    rhs[j] = (z[o] - g1[o] * h) / g2[o];
+}
+
+template <typename T>
+void launch_step_rhs(const Problem& P, const Dev<T>& D, const T* z, const T* y, int s, T* rhs, T cf,
+                     hipStream_t st) {
+    const int bs = 256;
+    hipLaunchKernelGGL(step_rhs<T>, dim3((unsigned)((P.Nd + bs - 1) / bs)), dim3(bs), 0, st, z, y, D.gamma1,
+                       D.gamma2, D.epad, s, P.M, P.Nd, cf, rhs);
+    TSFDE_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void dot_partials(const T* __restrict__ a, const T* __restrict__ b, long long n, T* __restrict__ partials) {
+    __shared__ T red[4];
+    T acc = T(0);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        acc += a[i] * b[i];
+    T s = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+static int blocks_for(long long n, int bs, int cap) {
+    long long b = (n + bs - 1) / bs;
+    return (int)std::max(1LL, std::min<long long>(b, cap));
+}
+
+template <typename T>
+void launch_dot_partials(const T* a, const T* b, long long n, T* partials, int* nparts, hipStream_t s) {
+    const int nb = blocks_for(n, 256, 1024);
+    hipLaunchKernelGGL(dot_partials<T>, dim3(nb), dim3(256), 0, s, a, b, n, partials);
+    TSFDE_HIP(hipGetLastError());
+    *nparts = nb;
+}
+
+template <typename T>
+__global__ void sum_partials_k(const T* __restrict__ partials, int n, double* __restrict__ out) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += (double)partials[i];
+    double s = block_sum(acc, red);
+    if (threadIdx.x == 0) *out = s;
+}
+
+void launch_sum_partials(const double* partials, int n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_partials_k<double>, dim3(1), dim3(256), 0, s, partials, n, out);
+    TSFDE_HIP(hipGetLastError());
+}
+void launch_sum_partials(const float* partials, int n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_partials_k<float>, dim3(1), dim3(256), 0, s, partials, n, out);
+    TSFDE_HIP(hipGetLastError());
+}
+
+// CG scalars, one thread.  scal: [0] rz  [1] pq  [2] alpha  [3] rr  [4] beta  [5] rz_new
+__global__ void cg_scalars_k(double* scal, int mode) {
+    if (threadIdx.x != 0) return;
+    if (mode == 0) {  // alpha = rz / pq
+        scal[2] = scal[1] != 0.0 ? scal[0] / scal[1] : 0.0;
+    } else {          // beta = rz_new / rz ; rz = rz_new
+        scal[4] = scal[0] != 0.0 ? scal[5] / scal[0] : 0.0;
+        scal[0] = scal[5];
+    }
+}
+void launch_cg_scalars(double* scal, int mode, hipStream_t s) {
+    hipLaunchKernelGGL(cg_scalars_k, dim3(1), dim3(64), 0, s, scal, mode);
+    TSFDE_HIP(hipGetLastError());
+}
+
+// x += alpha p ; r -= alpha q ; partials of (r, r)
+template <typename T>
+__global__ void cg_update_xr(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
+                             const double* __restrict__ scal, long long n, T* __restrict__ partials) {
+    __shared__ T red[4];
+    const T al = T(scal[2]);
+    T acc = T(0);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        x[i] += al * p[i];
+        const T rv = r[i] - al * q[i];
+        r[i] = rv;
+        acc += rv * rv;
+    }
+    T s = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+template <typename T>
+void launch_cg_update_xr(T* x, T* r, const T* p, const T* q, const double* scal, long long n, T* partials, int* nparts,
+                         hipStream_t s) {
+    const int nb = blocks_for(n, 256, 512);
+    hipLaunchKernelGGL(cg_update_xr<T>, dim3(nb), dim3(256), 0, s, x, r, p, q, scal, n, partials);
+    TSFDE_HIP(hipGetLastError());
+    *nparts = nb;
+}
+
+// p = z + beta p
+template <typename T>
+__global__ void cg_update_p(T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ scal, long long n) {
+    const T be = T(scal[4]);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = z[i] + be * p[i];
+}
+template <typename T>
+void launch_cg_update_p(T* p, const T* z, const double* scal, long long n, hipStream_t s) {
+    const int nb = blocks_for(n, 256, 1024);
+    hipLaunchKernelGGL(cg_update_p<T>, dim3(nb), dim3(256), 0, s, p, z, scal, n);
+    TSFDE_HIP(hipGetLastError());
+}
+
+template <typename T>
+__global__ void copy_k(const T* __restrict__ a, T* __restrict__ b, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+template <typename T>
+void launch_copy(const T* a, T* b, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(copy_k<T>, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, a, b, n);
+    TSFDE_HIP(hipGetLastError());
+}
+
+template <typename A, typename B>
+__global__ void convert_k(const A* __restrict__ a, B* __restrict__ b, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        b[i] = (B)a[i];
+}
+void launch_d2f(const double* a, float* b, long long n, hipStream_t s) {
+    hipLaunchKernelGGL((convert_k<double, float>), dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, a, b, n);
+    TSFDE_HIP(hipGetLastError());
+}
+void launch_f2d(const float* a, double* b, long long n, hipStream_t s) {
+    hipLaunchKernelGGL((convert_k<float, double>), dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, a, b, n);
+    TSFDE_HIP(hipGetLastError());
+}
+
+template <typename T>
+__global__ void fill_k(T* p, long long n, T v) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+void launch_fill(double* p, long long n, double v, hipStream_t s) {
+    hipLaunchKernelGGL(fill_k<double>, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, p, n, v);
+    TSFDE_HIP(hipGetLastError());
+}
+void launch_fill(float* p, long long n, float v, hipStream_t s) {
+    hipLaunchKernelGGL(fill_k<float>, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, p, n, v);
+    TSFDE_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Arnoldi helpers (FP64).  multidot: partials[blk][k] = sum over the block's chunk of V[k] . w
+// ---------------------------------------------------------------------------
+constexpr int kMD = 8;  // basis vectors per pass over w
+
+__global__ void multidot_k(const double* __restrict__ V, long long n, int k, const double* __restrict__ w,
+                           double* __restrict__ partials) {
+    __shared__ double red[4];
+    const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+    const long long lo = (long long)blockIdx.x * chunk;
+    const long long hi = min(n, lo + chunk);
+    for (int k0 = 0; k0 < k; k0 += kMD) {
+        double acc[kMD];
+#pragma unroll
+        for (int t = 0; t < kMD; ++t) acc[t] = 0.0;
+        const int kk = min(kMD, k - k0);
+        for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            const double wv = w[i];
+#pragma unroll
+            for (int t = 0; t < kMD; ++t)
+                if (t < kk) acc[t] += V[(long long)(k0 + t) * n + i] * wv;
+        }
+        for (int t = 0; t < kk; ++t) {
+            double s = block_sum(acc[t], red);
+            if (threadIdx.x == 0) partials[(long long)blockIdx.x * k + k0 + t] = s;
+        }
+    }
+}
+void launch_multidot(const double* V, long long n, int k, const double* w, double* partials, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL(multidot_k, dim3(nblk), dim3(256), 0, s, V, n, k, w, partials);
+    TSFDE_HIP(hipGetLastError());
+}
+
+__global__ void multidot_finish_k(const double* __restrict__ partials, int nblk, int k, double* __restrict__ h) {
+    __shared__ double red[4];
+    for (int t = 0; t < k; ++t) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += partials[(long long)b * k + t];
+        double s = block_sum(acc, red);
+        if (threadIdx.x == 0) h[t] = s;
+    }
+}
+void launch_multidot_finish(const double* partials, int nblk, int k, double* h, hipStream_t s) {
+    hipLaunchKernelGGL(multidot_finish_k, dim3(1), dim3(256), 0, s, partials, nblk, k, h);
+    TSFDE_HIP(hipGetLastError());
+}
+
+// w -= V[0..k) h
+__global__ void gemv_sub_k(const double* __restrict__ V, long long n, int k, const double* __restrict__ h,
+                           double* __restrict__ w) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        double acc = w[i];
+        for (int t = 0; t < k; ++t) acc -= V[(long long)t * n + i] * h[t];
+        w[i] = acc;
+    }
+}
+void launch_gemv_sub(const double* V, long long n, int k, const double* h, double* w, hipStream_t s) {
+    hipLaunchKernelGGL(gemv_sub_k, dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, V, n, k, h, w);
+    TSFDE_HIP(hipGetLastError());
+}
+
+// x += Z[0..k) y
+__global__ void gemv_add_k(const double* __restrict__ Z, long long n, int k, const double* __restrict__ y,
+                           double* __restrict__ x) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        double acc = x[i];
+        for (int t = 0; t < k; ++t) acc += Z[(long long)t * n + i] * y[t];
+        x[i] = acc;
+    }
+}
+void launch_gemv_add(const double* Z, long long n, int k, const double* y, double* x, hipStream_t s) {
+    hipLaunchKernelGGL(gemv_add_k, dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, Z, n, k, y, x);
+    TSFDE_HIP(hipGetLastError());
+}
+
+// v *= 1/den  (den a device scalar holding a norm)
+__global__ void scale_k(double* __restrict__ v, long long n, const double* __restrict__ den) {
+    const double inv = 1.0 / (*den);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        v[i] *= inv;
+}
+void launch_scale(double* v, long long n, const double* num, const double* den, hipStream_t s) {
+    (void)num;
+    hipLaunchKernelGGL(scale_k, dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, v, n, den);
+    TSFDE_HIP(hipGetLastError());
+}
+
+__global__ void axpby_k(double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                        double* __restrict__ out, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = a * x[i] + b * y[i];
+}
+void launch_axpby(double a, const double* x, double b, const double* y, double* out, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(axpby_k, dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, a, x, b, y, out, n);
+    TSFDE_HIP(hipGetLastError());
+}
+
+// z = [b_{s-1} gamma1^(s) rho ; mu]   (eq. lin-syst right-hand side)
+__global__ void build_z_k(const double* __restrict__ g1, const double* __restrict__ bw, const double* __restrict__ rho,
+                          const double* __restrict__ mu, long long Nd, int M, double* __restrict__ z) {
+    const long long n = (long long)(M + 1) * Nd;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const long long s = i / Nd, j = i - s * Nd;
+        z[i] = (s < M) ? bw[s] * g1[i] * rho[j] : mu[j];
+    }
+}
+// z-hat = b_{s-1} gamma1^(s) rho + eta q^(s) f, s = 1..M, plus a zero last block
+__global__ void build_zhat_k(const double* __restrict__ g1, const double* __restrict__ bw,
+                             const double* __restrict__ rho, const double* __restrict__ q, const double* __restrict__ f,
+                             double eta, long long Nd, int M, double* __restrict__ z) {
+    const long long n = (long long)(M + 1) * Nd;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const long long s = i / Nd, j = i - s * Nd;
+        z[i] = (s < M) ? bw[s] * g1[i] * rho[j] + eta * q[s] * f[j] : 0.0;
+    }
+}
+
+void launch_build_z(const Problem& P, double* z, hipStream_t s) {
+    const long long n = P.ntot;
+    hipLaunchKernelGGL(build_z_k, dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, P.f64.gamma1, P.d_bw, P.d_rho,
+                       P.d_mu, P.Nd, P.M, z);
+    TSFDE_HIP(hipGetLastError());
+}
+void launch_build_zhat(const Problem& P, const double* f, double* zhat, hipStream_t s) {
+    const long long n = P.ntot;
+    hipLaunchKernelGGL(build_zhat_k, dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, P.f64.gamma1, P.d_bw, P.d_rho,
+                       P.f64.q, f, P.eta, P.Nd, P.M, zhat);
+    TSFDE_HIP(hipGetLastError());
+}
+
+// out = a - b, partials of (out, out)
+template <typename T>
+__global__ void sub_partials_k(const T* __restrict__ a, const T* __restrict__ b, T* __restrict__ out, long long n,
+                               T* __restrict__ partials) {
+    __shared__ T red[4];
+    T acc = T(0);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const T v = a[i] - b[i];
+        out[i] = v;
+        acc += v * v;
+    }
+    T s = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+template <typename T>
+void launch_sub_partials(const T* a, const T* b, T* out, long long n, T* partials, int* nparts, hipStream_t s) {
+    const int nb = blocks_for(n, 256, 512);
+    hipLaunchKernelGGL(sub_partials_k<T>, dim3(nb), dim3(256), 0, s, a, b, out, n, partials);
+    TSFDE_HIP(hipGetLastError());
+    *nparts = nb;
+}
+
+// z = r / (dg + c a0), partials of (r, z)   (diagonal preconditioner when the sine transform is unavailable)
+template <typename T>
+__global__ void jacobi_prec_k(const T* __restrict__ r, T* __restrict__ z, const T* __restrict__ dg, T c, T a0,
+                              long long n, T* __restrict__ partials) {
+    __shared__ T red[4];
+    T acc = T(0);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const T v = r[i] / ((dg ? dg[i] : T(0)) + c * a0);
+        z[i] = v;
+        acc += r[i] * v;
+    }
+    T s = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+template <typename T>
+void launch_jacobi_prec(const T* r, T* z, const T* dg, T c, T a0, long long n, T* partials, int* nparts,
+                        hipStream_t s) {
+    const int nb = blocks_for(n, 256, 512);
+    hipLaunchKernelGGL(jacobi_prec_k<T>, dim3(nb), dim3(256), 0, s, r, z, dg, c, a0, n, partials);
+    TSFDE_HIP(hipGetLastError());
+    *nparts = nb;
+}
+
+}  // namespace tsfde
+
+// explicit instantiations
+namespace tsfde {
+template void launch_history_matvec<double>(const Problem&, const Dev<double>&, const double*, double*, hipStream_t);
+template void launch_history_matvec<float>(const Problem&, const Dev<float>&, const float*, float*, hipStream_t);
+template void launch_step_rhs<double>(const Problem&, const Dev<double>&, const double*, const double*, int, double*,
+                                      double, hipStream_t);
+template void launch_step_rhs<float>(const Problem&, const Dev<float>&, const float*, const float*, int, float*, float,
+                                     hipStream_t);
+template void launch_dot_partials<double>(const double*, const double*, long long, double*, int*, hipStream_t);
+template void launch_dot_partials<float>(const float*, const float*, long long, float*, int*, hipStream_t);
+template void launch_cg_update_xr<double>(double*, double*, const double*, const double*, const double*, long long,
+                                          double*, int*, hipStream_t);
+template void launch_cg_update_xr<float>(float*, float*, const float*, const float*, const double*, long long, float*,
+                                         int*, hipStream_t);
+template void launch_cg_update_p<double>(double*, const double*, const double*, long long, hipStream_t);
+template void launch_cg_update_p<float>(float*, const float*, const double*, long long, hipStream_t);
+template void launch_copy<double>(const double*, double*, long long, hipStream_t);
+template void launch_copy<float>(const float*, float*, long long, hipStream_t);
+template void launch_sub_partials<double>(const double*, const double*, double*, long long, double*, int*, hipStream_t);
+template void launch_sub_partials<float>(const float*, const float*, float*, long long, float*, int*, hipStream_t);
+template void launch_jacobi_prec<double>(const double*, double*, const double*, double, double, long long, double*,
+                                         int*, hipStream_t);
+template void launch_jacobi_prec<float>(const float*, float*, const float*, float, float, long long, float*, int*,
+                                        hipStream_t);
+}  // namespace tsfde

@@ -1,0 +1,584 @@
+// Operator applications and the Krylov solver behind the C ABI:
+//   apply_A      z = A y (§5 'Implementation' of the matvec)
+//   apply_P_inv  y = P^{-1} z by forward substitution over time (§5.1 'Implementation'),
+//                diagonal blocks solved by preconditioned CG on their symmetrised form
+//   gmres_solve  right-preconditioned flexible GMRES(m) with classical Gram-Schmidt done
+//                twice, Givens rotations on the host in FP64; MIXED precision wraps it in
+//                iterative refinement with an FP64 residual
+//   recover_f    z of eq. lin-syst, solve from x0 = 0, f~ = last block (§5, §6)
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <functional>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace tsfde {
+
+tsfde_status create(int d, int N, int M, double T, double beta, double omega, double alpha, const double* gamma1,
+                    const double* gamma2, const double* q, const double* rho, const double* mu, double length,
+                    const double* stencil, Problem** out);
+tsfde_status set_mu(Problem* P, const double* mu);
+tsfde_status compute_stencil(int d, int N, double omega, double* out);
+void free_problem(Problem* P);
+const char* last_error();
+
+static double now() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Opts {
+    int restart = 50, maxit = 0, precision = TSFDE_FP64, use_precond = 1, inner_maxit = 200, max_refine = 30;
+    double tol = 1e-10, inner_tol = 1e-12, refine_tol = 1e-5;
+};
+
+static Opts get_opts(const tsfde_opts* o) {
+    Opts r;
+    if (!o) return r;
+    r.restart = o->restart;
+    r.maxit = o->maxit;
+    r.tol = o->tol;
+    r.precision = o->precision;
+    r.use_precond = o->use_precond;
+    r.inner_tol = o->inner_tol;
+    r.inner_maxit = o->inner_maxit;
+    r.refine_tol = o->refine_tol;
+    r.max_refine = o->max_refine;
+    return r;
+}
+
+static bool check_opts(const Opts& o) {
+    if (o.restart < 1 || o.restart > 1000) { set_error("opts.restart must be in [1, 1000]"); return false; }
+    if (!(o.tol > 0.0) || !(o.inner_tol > 0.0) || !(o.refine_tol > 0.0)) {
+        set_error("opts tolerances must be > 0");
+        return false;
+    }
+    if (o.inner_maxit < 1 || o.max_refine < 1) { set_error("opts.inner_maxit and max_refine must be >= 1"); return false; }
+    if (o.precision != TSFDE_FP64 && o.precision != TSFDE_MIXED) { set_error("opts.precision invalid"); return false; }
+    return true;
+}
+
+template <typename T>
+static Dev<T>& dev(Problem& P);
+template <>
+Dev<double>& dev<double>(Problem& P) { return P.f64; }
+template <>
+Dev<float>& dev<float>(Problem& P) { return P.f32; }
+
+// ---------------------------------------------------------------------------
+// A y
+// ---------------------------------------------------------------------------
+template <typename T>
+static void apply_A_impl(Problem& P, const T* y, T* z, hipStream_t st) {
+    Dev<T>& D = dev<T>(P);
+    launch_history_matvec<T>(P, D, y, z, st);
+    launch_toeplitz_matvec<T>(P, D, y, z, st);
+}
+
+// ---------------------------------------------------------------------------
+// P^{-1} z by forward substitution; returns CG iterations
+// ---------------------------------------------------------------------------
+template <typename T>
+static long long pinv_impl(Problem& P, const T* z, T* y, const Opts& o, hipStream_t st, bool last_block) {
+    Dev<T>& D = dev<T>(P);
+    const long long Nd = P.Nd;
+    T* x = D.pcg;
+    T* r = x + Nd;
+    T* zz = x + 2 * Nd;
+    T* p = x + 3 * Nd;
+    T* q = x + 4 * Nd;
+    T* rhs = x + 7 * Nd;
+    double* scal = P.dev_scalars;
+    double* hs = P.host_scalars;
+    long long total = 0;
+    const double tol2 = o.inner_tol * o.inner_tol;
+    int np = 0;
+    auto prec = [&](const T* rin, T* zout, const T* dg, T c, T sigma) {
+        if (P.tau_ok) launch_tau_prec<T>(P, D, rin, zout, sigma, c, D.partial, &np, st);
+        else launch_jacobi_prec<T>(rin, zout, dg, c, T(P.a0), Nd, D.partial, &np, st);
+    };
+    const int last = last_block ? P.M : P.M - 1;
+    for (int s = 0; s <= last; ++s) {
+        launch_step_rhs<T>(P, D, z, y, s, rhs, T(P.cf), st);
+        const T* dg = (s < P.M) ? D.dg + (long long)s * Nd : nullptr;
+        const T c = (s < P.M) ? T(P.ct) : T(1);
+        const T sigma = (s < P.M) ? T(P.sigma[s]) : T(0);
+        if (s > 0 && s < P.M) launch_copy<T>(y + (long long)(s - 1) * Nd, x, Nd, st);
+        else launch_fill(x, Nd, T(0), st);
+        // r = rhs - A_s x ; ||r||^2 ; ||rhs||^2
+        launch_spd_apply<T>(P, D, x, q, dg, c, D.partial, &np, st);
+        launch_sub_partials<T>(rhs, q, r, Nd, D.partial, &np, st);
+        launch_sum_partials(D.partial, np, scal + 3, st);
+        launch_dot_partials<T>(rhs, rhs, Nd, D.partial, &np, st);
+        launch_sum_partials(D.partial, np, scal + 8, st);
+        TSFDE_HIP(hipMemcpyAsync(hs, scal, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+        TSFDE_HIP(hipStreamSynchronize(st));
+        const double bb = hs[8];
+        double rr = hs[3];
+        if (!(bb > 0.0)) {
+            launch_fill(x, Nd, T(0), st);
+        } else if (rr > tol2 * bb) {
+            prec(r, zz, dg, c, sigma);
+            launch_sum_partials(D.partial, np, scal + 0, st);
+            launch_copy<T>(zz, p, Nd, st);
+            for (int it = 1; it <= o.inner_maxit; ++it) {
+                launch_spd_apply<T>(P, D, p, q, dg, c, D.partial, &np, st);
+                launch_sum_partials(D.partial, np, scal + 1, st);
+                launch_cg_scalars(scal, 0, st);
+                launch_cg_update_xr<T>(x, r, p, q, scal, Nd, D.partial, &np, st);
+                launch_sum_partials(D.partial, np, scal + 3, st);
+                TSFDE_HIP(hipMemcpyAsync(hs + 3, scal + 3, sizeof(double), hipMemcpyDeviceToHost, st));
+                TSFDE_HIP(hipStreamSynchronize(st));
+                ++total;
+                rr = hs[3];
+                if (rr <= tol2 * bb || !std::isfinite(rr)) break;
+                prec(r, zz, dg, c, sigma);
+                launch_sum_partials(D.partial, np, scal + 5, st);
+                launch_cg_scalars(scal, 1, st);
+                launch_cg_update_p<T>(p, zz, scal, Nd, st);
+            }
+        }
+        launch_copy<T>(x, y + (long long)s * Nd, Nd, st);
+    }
+    return total;
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES (FP64 Arnoldi), operators given as callbacks on FP64 vectors
+// ---------------------------------------------------------------------------
+struct SolveOps {
+    std::function<void(const double*, double*)> A;     // out = A v
+    std::function<long long(const double*, double*)> M; // out = M v (returns inner iterations)
+};
+
+struct Basis {
+    double* V;
+    double* Z;
+    double* partials;
+    int nblk;
+};
+
+static void ensure_basis(Problem& P, int m) {
+    if (P.basis_m >= m) return;
+    if (P.V) (void)hipFree(P.V);
+    if (P.Z) (void)hipFree(P.Z);
+    P.V = P.Z = nullptr;
+    P.basis_m = 0;
+    TSFDE_HIP(hipMalloc(&P.V, sizeof(double) * (size_t)(m + 1) * P.ntot));
+    TSFDE_HIP(hipMalloc(&P.Z, sizeof(double) * (size_t)m * P.ntot));
+    P.basis_m = m;
+}
+
+static double dev_dot(Problem& P, const double* a, const double* b, long long n, hipStream_t st) {
+    int np = 0;
+    launch_dot_partials<double>(a, b, n, P.f64.partial, &np, st);
+    launch_sum_partials(P.f64.partial, np, P.dev_scalars + 16, st);
+    TSFDE_HIP(hipMemcpyAsync(P.host_scalars + 16, P.dev_scalars + 16, sizeof(double), hipMemcpyDeviceToHost, st));
+    TSFDE_HIP(hipStreamSynchronize(st));
+    return P.host_scalars[16];
+}
+
+// Solves A x = b to ||b - A x|| <= rtol * ||b|| (estimated from the Arnoldi least-squares residual,
+// checked exactly at each restart).  x holds the initial guess.  r_work: n_tot scratch.
+// Returns the number of Arnoldi steps; *conv set when the tolerance was met.
+static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, double* r_work, double rtol,
+                  int restart, int maxit, hipStream_t st, tsfde_stats& S, bool& conv, double& relres,
+                  bool exact_final) {
+    const long long n = P.ntot;
+    ensure_basis(P, restart);
+    const int nblk = 2048;
+    double* partials = nullptr;
+    TSFDE_HIP(hipMalloc(&partials, sizeof(double) * nblk * (restart + 1)));
+    double* hdev = P.dev_scalars + 24;  // up to 32 values... use a dedicated buffer for long restarts
+    double* hbuf = nullptr;
+    TSFDE_HIP(hipMalloc(&hbuf, sizeof(double) * (restart + 2)));
+    (void)hdev;
+    std::vector<double> Hc((size_t)(restart + 1) * restart, 0.0), cs(restart), sn(restart), g(restart + 1), yk(restart);
+    std::vector<double> hcol(restart + 2), hcol2(restart + 2);
+    const double bnorm = std::sqrt(dev_dot(P, b, b, n, st));
+    int its = 0;
+    conv = false;
+    relres = 1.0;
+    if (!(bnorm > 0.0)) {
+        launch_fill(x, n, 0.0, st);
+        conv = true;
+        relres = 0.0;
+        (void)hipFree(partials);
+        (void)hipFree(hbuf);
+        return 0;
+    }
+    while (true) {
+        double t0 = now();
+        ops.A(x, r_work);
+        TSFDE_HIP(hipStreamSynchronize(st));
+        S.t_matvec += now() - t0;
+        launch_axpby(1.0, b, -1.0, r_work, r_work, n, st);
+        const double beta = std::sqrt(dev_dot(P, r_work, r_work, n, st));
+        relres = beta / bnorm;
+        if (relres <= rtol) { conv = true; break; }
+        if (its >= maxit) break;
+        const int m = std::min(restart, maxit - its);
+        launch_axpby(1.0 / beta, r_work, 0.0, r_work, P.V, n, st);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        bool lucky = false;
+        for (int j = 0; j < m; ++j) {
+            double* vj = P.V + (size_t)j * n;
+            double* zj = P.Z + (size_t)j * n;
+            double* w = P.V + (size_t)(j + 1) * n;
+            t0 = now();
+            S.inner_iters += ops.M(vj, zj);
+            TSFDE_HIP(hipStreamSynchronize(st));
+            S.t_precond += now() - t0;
+            t0 = now();
+            ops.A(zj, w);
+            TSFDE_HIP(hipStreamSynchronize(st));
+            S.t_matvec += now() - t0;
+            t0 = now();
+            // classical Gram-Schmidt, twice
+            launch_multidot(P.V, n, j + 1, w, partials, nblk, st);
+            launch_multidot_finish(partials, nblk, j + 1, hbuf, st);
+            launch_gemv_sub(P.V, n, j + 1, hbuf, w, st);
+            TSFDE_HIP(hipMemcpyAsync(hcol.data(), hbuf, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
+            launch_multidot(P.V, n, j + 1, w, partials, nblk, st);
+            launch_multidot_finish(partials, nblk, j + 1, hbuf, st);
+            launch_gemv_sub(P.V, n, j + 1, hbuf, w, st);
+            TSFDE_HIP(hipMemcpyAsync(hcol2.data(), hbuf, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
+            const double hn = std::sqrt(dev_dot(P, w, w, n, st));  // synchronises
+            for (int i = 0; i <= j; ++i) Hc[(size_t)i * restart + j] = hcol[i] + hcol2[i];
+            Hc[(size_t)(j + 1) * restart + j] = hn;
+            if (hn > 0.0) launch_axpby(1.0 / hn, w, 0.0, w, w, n, st);
+            S.t_ortho += now() - t0;
+            // Givens on column j
+            for (int i = 0; i < j; ++i) {
+                const double a = Hc[(size_t)i * restart + j], bq = Hc[(size_t)(i + 1) * restart + j];
+                Hc[(size_t)i * restart + j] = cs[i] * a + sn[i] * bq;
+                Hc[(size_t)(i + 1) * restart + j] = -sn[i] * a + cs[i] * bq;
+            }
+            const double a = Hc[(size_t)j * restart + j], bq = Hc[(size_t)(j + 1) * restart + j];
+            const double rr = std::hypot(a, bq);
+            cs[j] = rr > 0.0 ? a / rr : 1.0;
+            sn[j] = rr > 0.0 ? bq / rr : 0.0;
+            Hc[(size_t)j * restart + j] = rr;
+            Hc[(size_t)(j + 1) * restart + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            ++its;
+            ++S.iters;
+            if (std::fabs(g[j + 1]) <= rtol * bnorm) break;
+            if (hn == 0.0) { lucky = true; break; }
+        }
+        (void)lucky;
+        // y = R^{-1} g, x += Z y
+        for (int i = k - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int l = i + 1; l < k; ++l) acc -= Hc[(size_t)i * restart + l] * yk[l];
+            yk[i] = acc / Hc[(size_t)i * restart + i];
+        }
+        TSFDE_HIP(hipMemcpyAsync(hbuf, yk.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+        double t0u = now();
+        launch_gemv_add(P.Z, n, k, hbuf, x, st);
+        TSFDE_HIP(hipStreamSynchronize(st));
+        S.t_ortho += now() - t0u;
+        const double est = std::fabs(g[k]) / bnorm;
+        if (est <= rtol && !exact_final) {
+            relres = est;
+            conv = true;
+            break;
+        }
+        ++S.restarts;
+    }
+    (void)hipFree(partials);
+    (void)hipFree(hbuf);
+    return its;
+}
+
+static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o, tsfde_stats& S, hipStream_t st) {
+    const long long n = P.ntot;
+    const int maxit = o.maxit > 0 ? o.maxit : (int)std::min<long long>(n, 1000);
+    const double t_start = now();
+    if (o.precision == TSFDE_FP64) {
+        SolveOps ops;
+        ops.A = [&](const double* v, double* out) { apply_A_impl<double>(P, v, out, st); };
+        ops.M = [&](const double* v, double* out) -> long long {
+            if (!o.use_precond) { launch_copy<double>(v, out, n, st); return 0; }
+            return pinv_impl<double>(P, v, out, o, st, true);
+        };
+        double* r = nullptr;
+        TSFDE_HIP(hipMalloc(&r, sizeof(double) * n));
+        bool conv = false;
+        double rel = 1.0;
+        fgmres(P, ops, b, x, r, o.tol, o.restart, maxit, st, S, conv, rel, true);
+        (void)hipFree(r);
+        S.refinements = 1;
+        S.converged = conv ? 1 : 0;
+        S.rel_res = rel;
+    } else {
+        // iterative refinement: r = b - A x in FP64; inner FGMRES with FP32 operators on A d = r
+        Dev<float>& F = P.f32;
+        if (!F.vecA) {
+            TSFDE_HIP(hipMalloc(&F.vecA, sizeof(float) * n));
+            TSFDE_HIP(hipMalloc(&F.vecB, sizeof(float) * n));
+        }
+        SolveOps ops;
+        ops.A = [&](const double* v, double* out) {
+            launch_d2f(v, F.vecA, n, st);
+            apply_A_impl<float>(P, F.vecA, F.vecB, st);
+            launch_f2d(F.vecB, out, n, st);
+        };
+        ops.M = [&](const double* v, double* out) -> long long {
+            if (!o.use_precond) { launch_copy<double>(v, out, n, st); return 0; }
+            launch_d2f(v, F.vecA, n, st);
+            long long it = pinv_impl<float>(P, F.vecA, F.vecB, o, st, true);
+            launch_f2d(F.vecB, out, n, st);
+            return it;
+        };
+        double *r = nullptr, *d = nullptr, *rw = nullptr;
+        TSFDE_HIP(hipMalloc(&r, sizeof(double) * n));
+        TSFDE_HIP(hipMalloc(&d, sizeof(double) * n));
+        TSFDE_HIP(hipMalloc(&rw, sizeof(double) * n));
+        const double bnorm = std::sqrt(dev_dot(P, b, b, n, st));
+        double rel = 1.0;
+        S.converged = 0;
+        int used = 0;
+        for (int ref = 0; ref < o.max_refine; ++ref) {
+            double t0 = now();
+            apply_A_impl<double>(P, x, r, st);
+            TSFDE_HIP(hipStreamSynchronize(st));
+            S.t_matvec += now() - t0;
+            launch_axpby(1.0, b, -1.0, r, r, n, st);
+            const double rn = std::sqrt(dev_dot(P, r, r, n, st));
+            rel = bnorm > 0.0 ? rn / bnorm : 0.0;
+            if (rel <= o.tol) { S.converged = 1; break; }
+            if (used >= maxit) break;
+            launch_fill(d, n, 0.0, st);
+            bool conv = false;
+            double rr = 1.0;
+            used += fgmres(P, ops, r, d, rw, std::max(o.refine_tol, 0.5 * o.tol / std::max(rel, 1e-300)), o.restart,
+                           maxit - used, st, S, conv, rr, false);
+            launch_axpby(1.0, x, 1.0, d, x, n, st);
+            ++S.refinements;
+        }
+        (void)hipFree(r);
+        (void)hipFree(d);
+        (void)hipFree(rw);
+        S.rel_res = rel;
+    }
+    TSFDE_HIP(hipStreamSynchronize(st));
+    S.t_total = now() - t_start;
+    return S.converged ? TSFDE_OK : TSFDE_ENOCONV;
+}
+
+}  // namespace tsfde
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace tsfde;
+
+struct tsfde_problem {
+    Problem* p;
+};
+
+#define TSFDE_GUARD(name, body)                                                           \
+    try {                                                                                 \
+        body                                                                              \
+    } catch (const HipError& e) {                                                         \
+        set_error("%s: %s failed: %s", name, e.where.c_str(), hipGetErrorString(e.code)); \
+        return e.code == hipErrorOutOfMemory ? TSFDE_ENOMEM : TSFDE_EDEVICE;              \
+    } catch (const std::bad_alloc&) {                                                     \
+        set_error("%s: host allocation failed", name);                                    \
+        return TSFDE_ENOMEM;                                                              \
+    }
+
+static bool overlap(const void* a, const void* b, size_t bytes) {
+    const char* x = static_cast<const char*>(a);
+    const char* y = static_cast<const char*>(b);
+    return x < y + bytes && y < x + bytes;
+}
+
+extern "C" {
+
+void tsfde_default_opts(tsfde_opts* o) {
+    if (!o) return;
+    o->restart = 50;
+    o->maxit = 0;
+    o->tol = 1e-10;
+    o->precision = TSFDE_FP64;
+    o->use_precond = 1;
+    o->inner_tol = 1e-12;
+    o->inner_maxit = 200;
+    o->refine_tol = 1e-5;
+    o->max_refine = 30;
+}
+
+tsfde_status tsfde_create_problem_ex(int d, int N, int M, double T, double beta, double omega, double alpha,
+                                     const double* gamma1, const double* gamma2, const double* q, const double* rho,
+                                     const double* mu, double length, const double* stencil, tsfde_problem** out) {
+    if (!out) {
+        set_error("create_problem: out is NULL");
+        return TSFDE_EINVAL;
+    }
+    *out = nullptr;
+    Problem* P = nullptr;
+    tsfde_status st = create(d, N, M, T, beta, omega, alpha, gamma1, gamma2, q, rho, mu, length, stencil, &P);
+    if (st != TSFDE_OK) return st;
+    *out = new tsfde_problem{P};
+    return TSFDE_OK;
+}
+
+tsfde_status tsfde_create_problem(int d, int N, int M, double T, double beta, double omega, double alpha,
+                                  const double* gamma1, const double* gamma2, const double* q, const double* rho,
+                                  const double* mu, tsfde_problem** out) {
+    return tsfde_create_problem_ex(d, N, M, T, beta, omega, alpha, gamma1, gamma2, q, rho, mu, 1.0, nullptr, out);
+}
+
+tsfde_status tsfde_set_mu(tsfde_problem* prob, const double* mu) {
+    if (!prob) { set_error("set_mu: NULL problem"); return TSFDE_EINVAL; }
+    return set_mu(prob->p, mu);
+}
+
+void tsfde_destroy_problem(tsfde_problem* prob) {
+    if (!prob) return;
+    free_problem(prob->p);
+    delete prob;
+}
+
+size_t tsfde_vector_length(const tsfde_problem* prob) { return prob ? (size_t)prob->p->ntot : 0; }
+
+tsfde_status tsfde_problem_scalars(const tsfde_problem* prob, double out[6]) {
+    if (!prob || !out) { set_error("problem_scalars: NULL argument"); return TSFDE_EINVAL; }
+    const Problem& P = *prob->p;
+    out[0] = P.h;
+    out[1] = P.dt;
+    out[2] = P.eta;
+    out[3] = P.ct;
+    out[4] = P.cf;
+    out[5] = P.L;
+    return TSFDE_OK;
+}
+
+tsfde_status tsfde_get_stencil(const tsfde_problem* prob, double* out) {
+    if (!prob || !out) { set_error("get_stencil: NULL argument"); return TSFDE_EINVAL; }
+    std::copy(prob->p->stencil.begin(), prob->p->stencil.end(), out);
+    return TSFDE_OK;
+}
+
+tsfde_status tsfde_compute_stencil(int d, int N, double omega, double* out) {
+    return compute_stencil(d, N, omega, out);
+}
+
+tsfde_status tsfde_apply_A(tsfde_problem* prob, const double* y, double* z, void* stream) {
+    if (!prob || !y || !z) { set_error("apply_A: NULL argument"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    if (overlap(y, z, sizeof(double) * P.ntot)) { set_error("apply_A: y and z overlap"); return TSFDE_EINVAL; }
+    TSFDE_GUARD("apply_A", apply_A_impl<double>(P, y, z, (hipStream_t)stream);)
+    return TSFDE_OK;
+}
+
+tsfde_status tsfde_apply_A_f32(tsfde_problem* prob, const float* y, float* z, void* stream) {
+    if (!prob || !y || !z) { set_error("apply_A_f32: NULL argument"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    if (overlap(y, z, sizeof(float) * P.ntot)) { set_error("apply_A_f32: y and z overlap"); return TSFDE_EINVAL; }
+    TSFDE_GUARD("apply_A_f32", apply_A_impl<float>(P, y, z, (hipStream_t)stream);)
+    return TSFDE_OK;
+}
+
+tsfde_status tsfde_apply_P_inv(tsfde_problem* prob, const double* z, double* y, const tsfde_opts* opts, void* stream) {
+    if (!prob || !y || !z) { set_error("apply_P_inv: NULL argument"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    if (overlap(y, z, sizeof(double) * P.ntot)) { set_error("apply_P_inv: y and z overlap"); return TSFDE_EINVAL; }
+    const Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    TSFDE_GUARD("apply_P_inv", pinv_impl<double>(P, z, y, o, (hipStream_t)stream, true);)
+    return TSFDE_OK;
+}
+
+tsfde_status tsfde_apply_P_inv_f32(tsfde_problem* prob, const float* z, float* y, const tsfde_opts* opts,
+                                   void* stream) {
+    if (!prob || !y || !z) { set_error("apply_P_inv_f32: NULL argument"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    if (overlap(y, z, sizeof(float) * P.ntot)) { set_error("apply_P_inv_f32: y and z overlap"); return TSFDE_EINVAL; }
+    Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    if (!opts) o.inner_tol = 1e-6;
+    TSFDE_GUARD("apply_P_inv_f32", pinv_impl<float>(P, z, y, o, (hipStream_t)stream, true);)
+    return TSFDE_OK;
+}
+
+tsfde_status tsfde_gmres_solve(tsfde_problem* prob, const double* b, double* x, const tsfde_opts* opts,
+                               tsfde_stats* stats, void* stream) {
+    if (!prob || !x) { set_error("gmres_solve: NULL argument"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    const Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    if (b && overlap(b, x, sizeof(double) * P.ntot)) { set_error("gmres_solve: b and x overlap"); return TSFDE_EINVAL; }
+    tsfde_stats S{};
+    tsfde_status rc = TSFDE_OK;
+    hipStream_t st = (hipStream_t)stream;
+    TSFDE_GUARD("gmres_solve", {
+        if (!b) {
+            launch_build_z(P, P.z_rhs, st);
+            b = P.z_rhs;
+        }
+        rc = solve(P, b, x, o, S, st);
+    })
+    if (stats) *stats = S;
+    if (rc == TSFDE_ENOCONV) set_error("gmres_solve: tolerance not reached (rel. residual %.3e)", S.rel_res);
+    return rc;
+}
+
+tsfde_status tsfde_recover_f(tsfde_problem* prob, double* f_out, double* work, const tsfde_opts* opts,
+                             tsfde_stats* stats, void* stream) {
+    if (!prob || !f_out) { set_error("recover_f: NULL argument"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    const Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    tsfde_stats S{};
+    tsfde_status rc = TSFDE_OK;
+    hipStream_t st = (hipStream_t)stream;
+    TSFDE_GUARD("recover_f", {
+        double* x = work;
+        if (!x) {
+            if (!P.xbuf) TSFDE_HIP(hipMalloc(&P.xbuf, sizeof(double) * P.ntot));
+            x = P.xbuf;
+        }
+        launch_fill(x, P.ntot, 0.0, st);
+        launch_build_z(P, P.z_rhs, st);
+        rc = solve(P, P.z_rhs, x, o, S, st);
+        launch_copy<double>(x + (size_t)P.M * P.Nd, f_out, P.Nd, st);
+        TSFDE_HIP(hipStreamSynchronize(st));
+    })
+    if (stats) *stats = S;
+    if (rc == TSFDE_ENOCONV) set_error("recover_f: tolerance not reached (rel. residual %.3e)", S.rel_res);
+    return rc;
+}
+
+tsfde_status tsfde_forward_solve(tsfde_problem* prob, const double* f, double* v, const tsfde_opts* opts,
+                                 void* stream) {
+    if (!prob || !f || !v) { set_error("forward_solve: NULL argument"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    const Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    TSFDE_GUARD("forward_solve", {
+        double* zh = nullptr;
+        double* y = nullptr;
+        TSFDE_HIP(hipMalloc(&zh, sizeof(double) * P.ntot));
+        TSFDE_HIP(hipMalloc(&y, sizeof(double) * P.ntot));
+        launch_build_zhat(P, f, zh, st);
+        pinv_impl<double>(P, zh, y, o, st, false);
+        launch_copy<double>(y, v, (long long)P.M * P.Nd, st);
+        TSFDE_HIP(hipStreamSynchronize(st));
+        (void)hipFree(zh);
+        (void)hipFree(y);
+    })
+    return TSFDE_OK;
+}
+
+const char* tsfde_last_error(void) { return last_error(); }
+
+}  // extern "C"

@@ -1,0 +1,244 @@
+"""ctypes binding of libtsfde.so (include/tsfde.h).  Argument marshalling only: every step
+of the solver runs in the library's HIP kernels.  Device arrays are torch tensors on a ROCm
+device; host arrays are numpy arrays.  Raises RuntimeError when the library is missing."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_LIBPATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtsfde.so")
+_lib = None
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ENONFINITE, ENOTIMPL = range(7)
+FP64, MIXED = 0, 1
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOCONV", 5: "ENONFINITE", 6: "ENOTIMPL"}
+
+EXPORTED = [
+    "tsfde_default_opts", "tsfde_create_problem", "tsfde_create_problem_ex", "tsfde_set_mu",
+    "tsfde_destroy_problem", "tsfde_vector_length", "tsfde_problem_scalars", "tsfde_get_stencil",
+    "tsfde_compute_stencil", "tsfde_apply_A", "tsfde_apply_A_f32", "tsfde_apply_P_inv",
+    "tsfde_apply_P_inv_f32", "tsfde_gmres_solve", "tsfde_recover_f", "tsfde_forward_solve",
+    "tsfde_last_error",
+]
+
+
+class Opts(C.Structure):
+    _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("tol", C.c_double), ("precision", C.c_int),
+                ("use_precond", C.c_int), ("inner_tol", C.c_double), ("inner_maxit", C.c_int),
+                ("refine_tol", C.c_double), ("max_refine", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("refinements", C.c_int), ("converged", C.c_int),
+                ("inner_iters", C.c_longlong), ("rel_res", C.c_double), ("t_total", C.c_double),
+                ("t_precond", C.c_double), ("t_matvec", C.c_double), ("t_ortho", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TsfdeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libtsfde.so (built in-tree by paper_2507_02809_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        raise RuntimeError(f"{_LIBPATH} is missing: build it with python -m paper_2507_02809_amd.build")
+    L = C.CDLL(_LIBPATH)
+    dp, fp, vp = C.POINTER(C.c_double), C.POINTER(C.c_float), C.c_void_p
+    i, d = C.c_int, C.c_double
+    pp = C.POINTER(C.c_void_p)
+    L.tsfde_default_opts.argtypes = [C.POINTER(Opts)]
+    L.tsfde_default_opts.restype = None
+    L.tsfde_create_problem.argtypes = [i, i, i, d, d, d, d, dp, dp, dp, dp, dp, pp]
+    L.tsfde_create_problem_ex.argtypes = [i, i, i, d, d, d, d, dp, dp, dp, dp, dp, d, dp, pp]
+    L.tsfde_set_mu.argtypes = [vp, dp]
+    L.tsfde_destroy_problem.argtypes = [vp]
+    L.tsfde_destroy_problem.restype = None
+    L.tsfde_vector_length.argtypes = [vp]
+    L.tsfde_vector_length.restype = C.c_size_t
+    L.tsfde_problem_scalars.argtypes = [vp, dp]
+    L.tsfde_get_stencil.argtypes = [vp, dp]
+    L.tsfde_compute_stencil.argtypes = [i, i, d, dp]
+    L.tsfde_apply_A.argtypes = [vp, vp, vp, vp]
+    L.tsfde_apply_A_f32.argtypes = [vp, vp, vp, vp]
+    L.tsfde_apply_P_inv.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
+    L.tsfde_apply_P_inv_f32.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
+    L.tsfde_gmres_solve.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
+    L.tsfde_recover_f.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
+    L.tsfde_forward_solve.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
+    L.tsfde_last_error.argtypes = []
+    L.tsfde_last_error.restype = C.c_char_p
+    for name in EXPORTED:
+        if name not in ("tsfde_default_opts", "tsfde_destroy_problem", "tsfde_vector_length", "tsfde_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().tsfde_last_error().decode()
+
+
+def _check(status: int, allow=()):
+    if status != OK and status not in allow:
+        raise TsfdeError(status, last_error())
+    return status
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().tsfde_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _host(a, n: int, name: str):
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1))
+    if arr.size != n:
+        raise ValueError(f"{name}: expected {n} values, got {arr.size}")
+    return arr, arr.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, dtype, n: int, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name}: expected a device tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: expected a contiguous {dtype} tensor of {n} elements")
+    return C.c_void_p(t.data_ptr())
+
+
+def compute_stencil(d: int, N: int, omega: float) -> np.ndarray:
+    """The library's stencil a_l, 0 <= l_i < N (host computation, no device needed)."""
+    out = np.empty(N ** d)
+    _check(lib().tsfde_compute_stencil(d, N, omega, out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out.reshape((N,) * d)
+
+
+class Problem:
+    """A problem on the current ROCm device (tsfde_create_problem_ex)."""
+
+    def __init__(self, d, N, M, T, beta, omega, alpha, gamma1, gamma2, q, rho=None, mu=None,
+                 length: float = 1.0, stencil=None):
+        L = lib()
+        Nd = N ** d
+        self.d, self.N, self.M = d, N, M
+        self.Nd = Nd
+        keep = []
+        args = []
+        for a, n, name in ((gamma1, M * Nd, "gamma1"), (gamma2, M * Nd, "gamma2"), (q, M, "q"),
+                           (rho, Nd, "rho"), (mu, Nd, "mu")):
+            arr, ptr = _host(a, n, name)
+            keep.append(arr)
+            args.append(ptr)
+        st_arr, st_ptr = _host(stencil, Nd, "stencil")
+        h = C.c_void_p()
+        _check(L.tsfde_create_problem_ex(d, N, M, T, beta, omega, alpha, *args, length, st_ptr, C.byref(h)))
+        self._h = h
+        self.n_tot = int(L.tsfde_vector_length(h))
+
+    @classmethod
+    def from_inputs(cls, inp, mu=None, stencil=None):
+        return cls(inp.d, inp.N, inp.M, inp.T, inp.beta, inp.omega, inp.alpha, inp.gamma1, inp.gamma2,
+                   inp.q, inp.rho, mu, inp.length, stencil)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tsfde_destroy_problem(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_mu(self, mu):
+        arr, ptr = _host(mu, self.Nd, "mu")
+        _check(lib().tsfde_set_mu(self._h, ptr))
+
+    def scalars(self) -> dict:
+        out = (C.c_double * 6)()
+        _check(lib().tsfde_problem_scalars(self._h, out))
+        return dict(zip(["h", "dt", "eta", "c_t", "c_f", "L"], list(out)))
+
+    def stencil(self) -> np.ndarray:
+        out = np.empty(self.Nd)
+        _check(lib().tsfde_get_stencil(self._h, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out.reshape((self.N,) * self.d)
+
+    def apply_A(self, y, z=None, stream=None):
+        import torch
+        f32 = y.dtype == torch.float32
+        if z is None:
+            z = torch.empty_like(y)
+        fn = lib().tsfde_apply_A_f32 if f32 else lib().tsfde_apply_A
+        _check(fn(self._h, _dptr(y, y.dtype, self.n_tot, "y"), _dptr(z, y.dtype, self.n_tot, "z"), _stream(stream)))
+        return z
+
+    def apply_P_inv(self, z, y=None, opts: Optional[Opts] = None, stream=None):
+        import torch
+        f32 = z.dtype == torch.float32
+        if y is None:
+            y = torch.empty_like(z)
+        fn = lib().tsfde_apply_P_inv_f32 if f32 else lib().tsfde_apply_P_inv
+        _check(fn(self._h, _dptr(z, z.dtype, self.n_tot, "z"), _dptr(y, z.dtype, self.n_tot, "y"),
+                  C.byref(opts) if opts is not None else None, _stream(stream)))
+        return y
+
+    def gmres_solve(self, b=None, x=None, opts: Optional[Opts] = None, stream=None, raise_noconv=False):
+        import torch
+        if x is None:
+            x = torch.zeros(self.n_tot, dtype=torch.float64, device="cuda")
+        bp = _dptr(b, torch.float64, self.n_tot, "b") if b is not None else None
+        st = Stats()
+        rc = lib().tsfde_gmres_solve(self._h, bp, _dptr(x, torch.float64, self.n_tot, "x"),
+                                     C.byref(opts) if opts is not None else None, C.byref(st), _stream(stream))
+        _check(rc, allow=() if raise_noconv else (ENOCONV,))
+        return x, st
+
+    def recover_f(self, opts: Optional[Opts] = None, work=None, stream=None, raise_noconv=False):
+        import torch
+        f = torch.empty(self.Nd, dtype=torch.float64, device="cuda")
+        wp = _dptr(work, torch.float64, self.n_tot, "work") if work is not None else None
+        st = Stats()
+        rc = lib().tsfde_recover_f(self._h, _dptr(f, torch.float64, self.Nd, "f"), wp,
+                                   C.byref(opts) if opts is not None else None, C.byref(st), _stream(stream))
+        _check(rc, allow=() if raise_noconv else (ENOCONV,))
+        return f, st
+
+    def forward_solve(self, f, opts: Optional[Opts] = None, stream=None):
+        import torch
+        v = torch.empty(self.M * self.Nd, dtype=torch.float64, device="cuda")
+        _check(lib().tsfde_forward_solve(self._h, _dptr(f, torch.float64, self.Nd, "f"),
+                                         _dptr(v, torch.float64, self.M * self.Nd, "v"),
+                                         C.byref(opts) if opts is not None else None, _stream(stream)))
+        return v

@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every function
+that include/tsfde.h declares, and its host logic (argument validation, the stencil set-up)
+behaves as documented."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2507_02809_amd import tsfde
+from oracle import coeffs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "tsfde.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tsfde_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = tsfde.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(tsfde.EXPORTED)
+
+
+def test_default_opts():
+    o = tsfde.default_opts()
+    assert (o.restart, o.maxit, o.tol, o.precision, o.use_precond) == (50, 0, 1e-10, 0, 1)
+    assert o.inner_tol == 1e-12 and o.inner_maxit == 200
+
+
+@pytest.mark.parametrize("omega", [1.2, 1.5, 1.8])
+def test_library_stencil_1d_matches_closed_form(omega):
+    np.testing.assert_allclose(tsfde.compute_stencil(1, 500, omega), coeffs.stencil_1d_closed(omega, 500),
+                               rtol=1e-13, atol=1e-17)
+
+
+@pytest.mark.parametrize("N,omega", [(7, 1.5), (31, 1.1), (31, 1.6), (63, 1.9)])
+def test_library_stencil_2d_matches_subordination(N, omega):
+    """The library's FFT-of-samples route (with Richardson extrapolation) against the oracle's
+    independent subordination integral."""
+    a = tsfde.compute_stencil(2, N, omega)
+    ref = coeffs.stencil_subordination(omega, 2, N)
+    assert np.abs(a - ref).max() <= 5e-15 * ref[0, 0]
+
+
+def _create(**over):
+    kw = dict(d=1, N=8, M=4, T=1.0, beta=0.5, omega=1.5, alpha=1e-3, length=1.0)
+    kw.update(over)
+    Nd = kw["N"] ** kw["d"]
+    M = kw["M"]
+    g1 = over.get("g1", np.ones(M * Nd))
+    g2 = over.get("g2", np.ones(M * Nd))
+    q = over.get("q", np.ones(M))
+    mu = over.get("mu", np.zeros(Nd))
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    h = C.c_void_p()
+    rc = tsfde.lib().tsfde_create_problem_ex(kw["d"], kw["N"], kw["M"], kw["T"], kw["beta"], kw["omega"],
+                                             kw["alpha"], dp(g1), dp(g2), dp(q), None, dp(mu), kw["length"],
+                                             None, C.byref(h))
+    assert not h.value  # every case below fails before any device allocation
+    return rc
+
+
+@pytest.mark.parametrize("over", [dict(beta=0.0), dict(beta=1.0), dict(omega=1.0), dict(omega=2.0),
+                                  dict(alpha=0.0), dict(alpha=-1.0), dict(T=0.0), dict(N=0), dict(M=0),
+                                  dict(d=3), dict(length=-1.0), dict(N=5000),
+                                  dict(q=-np.ones(4)), dict(g2=np.zeros(32)), dict(g1=-np.ones(32))])
+def test_invalid_parameters_rejected(over):
+    assert _create(**over) == tsfde.EINVAL
+    assert tsfde.last_error() != ""
+
+
+def test_nonfinite_inputs_rejected():
+    mu = np.zeros(8)
+    mu[3] = np.nan
+    assert _create(mu=mu) == tsfde.ENONFINITE
+    g1 = np.ones(32)
+    g1[0] = np.inf
+    assert _create(g1=g1) == tsfde.ENONFINITE
+
+
+def test_null_arguments_rejected():
+    lib = tsfde.lib()
+    assert lib.tsfde_create_problem_ex(1, 8, 4, 1.0, 0.5, 1.5, 1e-3, None, None, None, None, None, 1.0, None,
+                                       None) == tsfde.EINVAL
+    assert lib.tsfde_apply_A(None, None, None, None) == tsfde.EINVAL
+    assert lib.tsfde_gmres_solve(None, None, None, None, None, None) == tsfde.EINVAL
+    assert lib.tsfde_compute_stencil(2, 8, 2.5, None) == tsfde.EINVAL

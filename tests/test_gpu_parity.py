@@ -1,0 +1,150 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on the same seeded
+inputs.  Solver parity is isolated from coefficient parity by handing the oracle's stencil to
+the library (create_problem_ex override); the library's own stencil is compared with the
+oracle's separately (tests/test_abi.py and test_library_stencil_used_by_problem below)."""
+import numpy as np
+import pytest
+import scipy.linalg as sl
+
+from oracle import matfree, system, workloads
+from paper_2507_02809_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no ROCm device", allow_module_level=True)
+
+from paper_2507_02809_amd import tsfde  # noqa: E402
+
+DEV = "cuda"
+
+
+def gpu_problem(inp, p):
+    """Library problem with the oracle problem's data (mu) and stencil."""
+    return tsfde.Problem.from_inputs(inp, mu=p.mu, stencil=p.a())
+
+
+def rel_err(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+SMALL_DENSE = [
+    ("1d_12x7", lambda: inputs.small(1, 12, 7)),
+    ("1d_c1", lambda: inputs.c1()),
+    ("2d_6x5_jacobi", lambda: inputs.small(2, 6, 5, beta=0.6, omega=1.6)),
+    ("2d_7x9", lambda: inputs.small(2, 7, 9, beta=0.3, omega=1.2)),
+]
+
+
+@pytest.fixture(scope="module", params=SMALL_DENSE, ids=[n for n, _ in SMALL_DENSE])
+def dense_case(request):
+    inp = request.param[1]()
+    p = workloads.with_data(inp)
+    return inp, p, system.dense_A(p), system.dense_P(p)
+
+
+def test_apply_A_fp64_matches_dense(dense_case):
+    inp, p, A, _ = dense_case
+    rng = np.random.default_rng(11)
+    y = rng.standard_normal(p.n_tot)
+    with gpu_problem(inp, p) as g:
+        z = g.apply_A(torch.tensor(y, device=DEV)).cpu().numpy()
+    assert rel_err(z, A @ y) <= 1e-13
+
+
+def test_apply_A_fp32_matches_dense(dense_case):
+    inp, p, A, _ = dense_case
+    rng = np.random.default_rng(12)
+    y = rng.standard_normal(p.n_tot)
+    with gpu_problem(inp, p) as g:
+        z = g.apply_A(torch.tensor(y, device=DEV, dtype=torch.float32)).cpu().double().numpy()
+    assert rel_err(z, A @ y.astype(np.float32).astype(np.float64)) <= 2e-5
+
+
+def test_apply_P_inv_matches_dense(dense_case):
+    inp, p, _, P = dense_case
+    rng = np.random.default_rng(13)
+    zz = rng.standard_normal(p.n_tot)
+    ref = np.linalg.solve(P, zz)
+    with gpu_problem(inp, p) as g:
+        o = tsfde.default_opts(inner_tol=1e-14, inner_maxit=500)
+        y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=o).cpu().numpy()
+        y32 = g.apply_P_inv(torch.tensor(zz, device=DEV, dtype=torch.float32)).cpu().double().numpy()
+    assert rel_err(y, ref) <= 1e-10
+    assert rel_err(y32, ref) <= 5e-4
+
+
+def test_gmres_fp64_and_mixed_match_dense_lu(dense_case):
+    inp, p, A, _ = dense_case
+    b = system.rhs_z(p)
+    x_lu = np.linalg.solve(A, b)
+    f_lu = x_lu[p.S * p.Nd:]
+    with gpu_problem(inp, p) as g:
+        f, st = g.recover_f(tsfde.default_opts(tol=1e-13, inner_tol=1e-14, inner_maxit=500), raise_noconv=True)
+        assert st.converged == 1 and st.rel_res <= 1e-13
+        assert rel_err(f.cpu().numpy(), f_lu) <= 1e-10
+        fm, sm = g.recover_f(tsfde.default_opts(tol=1e-12, precision=tsfde.MIXED), raise_noconv=True)
+        assert sm.converged == 1 and sm.refinements >= 1
+        assert rel_err(fm.cpu().numpy(), f_lu) <= 1e-8
+        # explicit right-hand side and initial guess through gmres_solve
+        x, st2 = g.gmres_solve(torch.tensor(b, device=DEV), opts=tsfde.default_opts(tol=1e-13, inner_tol=1e-14))
+        assert np.linalg.norm(x.cpu().numpy() - x_lu) <= 1e-10 * np.linalg.norm(x_lu)
+
+
+def test_forward_solve_matches_oracle():
+    inp = inputs.c1()
+    p = workloads.problem(inp)
+    zh = system.rhs_zhat(p, inp.f_true)
+    ref = matfree.forward_solve(p, zh)
+    with tsfde.Problem.from_inputs(inp, stencil=p.a()) as g:
+        v = g.forward_solve(torch.tensor(inp.f_true, device=DEV), opts=tsfde.default_opts(inner_tol=1e-14))
+    assert rel_err(v.cpu().numpy(), ref) <= 1e-11
+
+
+@pytest.mark.parametrize("shape", [(1, 100, 70), (1, 255, 130), (2, 13, 70), (2, 31, 20)])
+def test_apply_A_ragged_tiles_match_oracle_matvec(shape):
+    """Sizes that span several history tiles (64 points x 64 steps) with ragged tails and several
+    FFT row pairs, against the oracle's FFT matvec."""
+    d, N, M = shape
+    inp = inputs.small(d, N, M, beta=0.7, omega=1.8)
+    p = workloads.problem(inp, mu=np.zeros(inp.Nd))
+    rng = np.random.default_rng(14)
+    y = rng.standard_normal(p.n_tot)
+    ref = matfree.matvec(p, y)
+    with gpu_problem(inp, p) as g:
+        z = g.apply_A(torch.tensor(y, device=DEV)).cpu().numpy()
+    assert rel_err(z, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("which", ["c2a", "c3"])
+def test_apply_A_full_size_sampled(which):
+    """apply_A at the full workload sizes in the launch configuration the benchmark uses, checked
+    on sampled entries that the oracle computes one by one from the scheme's definition."""
+    inp = inputs.c2(0) if which == "c2a" else inputs.c3()
+    p = workloads.problem(inp, mu=np.zeros(inp.Nd))
+    rng = np.random.default_rng(15)
+    y = rng.standard_normal(p.n_tot)
+    with gpu_problem(inp, p) as g:
+        z = g.apply_A(torch.tensor(y, device=DEV)).cpu().numpy()
+    samples = [(0, 0), (p.S - 1, p.Nd - 1), (p.S, 0), (p.S, p.Nd - 1), (p.S // 2, p.Nd // 2)]
+    samples += [(int(rng.integers(0, p.S + 1)), int(rng.integers(0, p.Nd))) for _ in range(40)]
+    scale = np.abs(z).max()
+    for s, j in samples:
+        ref = matfree.matvec_entry(p, y, s, j)
+        assert abs(z[s * p.Nd + j] - ref) <= 1e-13 * scale, (s, j)
+
+
+def test_library_stencil_used_by_problem():
+    inp = inputs.small(2, 15, 4, beta=0.5, omega=1.5)
+    p = workloads.problem(inp)
+    with tsfde.Problem.from_inputs(inp) as g:
+        a = g.stencil()
+        sc = g.scalars()
+    assert np.abs(a - p.a()).max() <= 5e-15 * p.a()[0, 0]
+    assert sc["h"] == pytest.approx(p.h, rel=1e-15)
+    assert sc["eta"] == pytest.approx(p.eta, rel=1e-14)
+    assert sc["c_t"] == pytest.approx(p.c_t, rel=1e-14)
+    assert sc["c_f"] == pytest.approx(p.c_f, rel=1e-14)
