@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark: GMRES solves/s to 1e-8 relative f error on the d=2, N=255^2, M=256 workload,
+plus the structured matvec's HBM throughput.
+
+One step = one complete recover_f call: build z (eq. lin-syst), right-preconditioned FGMRES
+with P^{-1} applied by forward substitution over the 256 time steps, and the recovered source
+f~ = y^(M+1).  Inputs are seeded and synthetic (paper_2507_02809_amd.inputs.c3); the final-time
+data mu comes from the library's own forward solve of the direct problem plus 1e-3 relative
+noise.  The relative f error of every timed solve is measured against a tight FP64 solve
+(relative residual 1e-11) of the same problem.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline]
+
+Prints one JSON line.  Single GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GMRES solves/sec to 1e-8 rel. f error (d=2,N=255²,M=256); matvec HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-8, help="FGMRES relative residual of the timed solves")
+    ap.add_argument("--inner-tol", type=float, default=1e-6, help="CG tolerance of the diagonal-block solves")
+    ap.add_argument("--matvec-reps", type=int, default=50)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(inp, outer_iters: int, restarts: int) -> dict:
+    """The oracle (oracle/, FP64 NumPy) timed on the host on a bounded sample of the same workload:
+    two forward-substitution steps of P^{-1} (CG inner solves, inner tolerance 1e-6) and one A y,
+    extrapolated to a full solve with the GPU run's outer-iteration count."""
+    import dataclasses
+    from oracle import matfree, workloads
+    p = workloads.problem(inp)
+    p.a()
+    k = 2
+    pk = dataclasses.replace(p, S=k, gamma1=p.gamma1[:k], gamma2=p.gamma2[:k], q=p.q[:k], stencil=p.a())
+    rng = np.random.default_rng(0)
+    z = rng.standard_normal((k + 1) * p.Nd)
+    t0 = time.perf_counter()
+    matfree.P_solve(pk, z, inner="cg", inner_tol=1e-6, last_block=False)
+    t_step = (time.perf_counter() - t0) / k
+    y = rng.standard_normal(p.n_tot)
+    sym = matfree.circulant_symbol(p)
+    t0 = time.perf_counter()
+    matfree.matvec(p, y, sym)
+    t_mv = time.perf_counter() - t0
+    t_solve = outer_iters * ((p.S + 1) * t_step + t_mv) + (restarts + 1) * t_mv
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"2 forward-substitution steps of P^-1 ({t_step:.2f} s/step, CG inner tol 1e-6) and one "
+                       f"A y ({t_mv:.2f} s) of the same workload, extrapolated to {outer_iters} outer iterations "
+                       f"x ({p.S + 1} steps + 1 matvec); NumPy FFT single-threaded"),
+            "est_seconds_per_solve": t_solve}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2507_02809_amd import inputs, tsfde
+
+    dev = "cuda"
+    inp = inputs.c3()
+    t_setup = time.perf_counter()
+    prob = tsfde.Problem.from_inputs(inp)
+    t_setup = time.perf_counter() - t_setup
+    log(f"problem created in {t_setup:.2f} s (n_tot = {prob.n_tot})")
+    # final-time data from the library's forward solve of the direct problem, plus noise
+    v = prob.forward_solve(torch.tensor(inp.f_true, device=dev), opts=tsfde.default_opts(inner_tol=1e-12))
+    mu = v[(inp.M - 1) * inp.Nd:].cpu().numpy()
+    prob.set_mu(inp.noisy(mu))
+    # reference f: tight FP64 solve
+    f_ref, st_ref = prob.recover_f(tsfde.default_opts(tol=1e-11, inner_tol=1e-12, maxit=300))
+    f_ref = f_ref.cpu().numpy()
+    log(f"reference solve: {st_ref.iters} outer iterations, rel. residual {st_ref.rel_res:.2e}")
+    nref = np.linalg.norm(f_ref)
+
+    def run(opts, n):
+        errs, stats = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            f, st = prob.recover_f(opts)
+            stats.append(st.as_dict())
+            errs.append(f)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        e = [float(np.linalg.norm(x.cpu().numpy() - f_ref) / nref) for x in errs]
+        return dt, e, stats
+
+    o64 = tsfde.default_opts(tol=a.tol, inner_tol=a.inner_tol, maxit=300)
+    if a.warmup:
+        run(o64, a.warmup)
+    dt, errs, stats = run(o64, a.steps)
+    log(f"fp64: {a.steps} solves in {dt:.2f} s, max f error {max(errs):.2e}")
+    ms_per = 1e3 * dt / a.steps
+
+    # mixed precision form (FP32 A and P^{-1} inside FGMRES, FP64 residual + refinement)
+    mixed = None
+    if not a.no_mixed:
+        om = tsfde.default_opts(tol=a.tol * 0.1, precision=tsfde.MIXED, inner_tol=1e-6, maxit=300)
+        run(om, 1)
+        dtm, errm, stm = run(om, a.steps)
+        log(f"mixed: {a.steps} solves in {dtm:.2f} s, max f error {max(errm):.2e}")
+        mixed = {"solves_per_s": a.steps / dtm, "ms_per_solve": 1e3 * dtm / a.steps, "f_rel_err": max(errm),
+                 "tol": a.tol * 0.1, "outer_iters": stm[-1]["iters"], "refinements": stm[-1]["refinements"],
+                 "inner_cg_iters": stm[-1]["inner_iters"]}
+
+    # structured matvec (FP64 and FP32), HIP events on the stream the library launches on
+    n = prob.n_tot
+    y = torch.randn(n, dtype=torch.float64, device=dev)
+    z = torch.empty_like(y)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def time_mv(yy, zz):
+        for _ in range(5):
+            prob.apply_A(yy, zz, stream=stream)
+        ev0.record(stream)
+        for _ in range(a.matvec_reps):
+            prob.apply_A(yy, zz, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / a.matvec_reps  # ms
+
+    mv64 = time_mv(y, z)
+    y32 = y.float()
+    mv32 = time_mv(y32, torch.empty_like(y32))
+    Nd, M = inp.Nd, inp.M
+    bytes64 = 8 * (2 * n + 2 * M * Nd)  # y in, z out, gamma1, gamma2 (compulsory)
+    gbs64 = bytes64 / (mv64 * 1e-3) / 1e9
+    gbs32 = (bytes64 / 2) / (mv32 * 1e-3) / 1e9
+
+    log(f"apply_A: fp64 {mv64:.3f} ms ({gbs64:.0f} GB/s), fp32 {mv32:.3f} ms ({gbs32:.0f} GB/s)")
+    last = stats[-1]
+    out = {
+        "metric": METRIC,
+        "value": a.steps / dt,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "d=2, N=255 per direction, M=256, beta=0.6, omega=1.6, alpha=1e-4 (seeded inputs c3)",
+                   "mode": "fp64", "tol": a.tol, "inner_tol": a.inner_tol, "restart": 50},
+        "f_rel_err": max(errs),
+        "outer_iters": last["iters"],
+        "inner_cg_iters": last["inner_iters"],
+        "time_split_s": {"precond": last["t_precond"], "matvec": last["t_matvec"], "ortho": last["t_ortho"]},
+        "reference": {"tol": 1e-11, "outer_iters": st_ref.iters, "rel_res": st_ref.rel_res},
+        "setup_s": t_setup,
+        "mixed": mixed,
+        "matvec": {"fp64_ms": mv64, "fp64_GB_s": gbs64, "fp32_ms": mv32, "fp32_GB_s": gbs32,
+                   "algorithmic_bytes_fp64": bytes64},
+        "roofline": {"kernel": "apply_A (history_matvec + toep2d_rows_fwd + toep2d_cols + toep2d_rows_inv), FP64",
+                     "bound": "hbm", "achieved": gbs64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs64 / HBM_PEAK_GBS, "traffic": None},
+    }
+    if not a.no_cpu_baseline:
+        log("timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(inp, last["iters"], last["restarts"])
+    prob.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <functional>
 #include <vector>
 
@@ -24,9 +26,20 @@ tsfde_status compute_stencil(int d, int N, double omega, double* out);
 void free_problem(Problem* P);
 const char* last_error();
 
+static bool verbose() {
+    static const int v = [] {
+        const char* e = std::getenv("TSFDE_VERBOSE");
+        return (e && *e && *e != '0') ? 1 : 0;
+    }();
+    return v != 0;
+}
+
 static double now() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+
+// FP32 diagonal-block solves cannot reach residuals much below the FP32 rounding level
+constexpr double kInnerTolF32 = 1e-6;
 
 struct Opts {
     int restart = 50, maxit = 0, precision = TSFDE_FP64, use_precond = 1, inner_maxit = 200, max_refine = 30;
@@ -216,6 +229,9 @@ static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, d
         launch_axpby(1.0, b, -1.0, r_work, r_work, n, st);
         const double beta = std::sqrt(dev_dot(P, r_work, r_work, n, st));
         relres = beta / bnorm;
+        if (verbose())
+            std::fprintf(stderr, "[tsfde] fgmres its=%d restarts=%d true relres=%.3e (target %.1e)\n", its, S.restarts,
+                         relres, rtol);
         if (relres <= rtol) { conv = true; break; }
         if (its >= maxit) break;
         const int m = std::min(restart, maxit - its);
@@ -268,6 +284,9 @@ static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, d
             k = j + 1;
             ++its;
             ++S.iters;
+            if (verbose())
+                std::fprintf(stderr, "[tsfde]   it=%d est relres=%.3e inner=%lld\n", its, std::fabs(g[j + 1]) / bnorm,
+                             (long long)S.inner_iters);
             if (std::fabs(g[j + 1]) <= rtol * bnorm) break;
             if (hn == 0.0) { lucky = true; break; }
         }
@@ -329,10 +348,12 @@ static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o,
             apply_A_impl<float>(P, F.vecA, F.vecB, st);
             launch_f2d(F.vecB, out, n, st);
         };
+        Opts o32 = o;
+        o32.inner_tol = std::max(o.inner_tol, kInnerTolF32);
         ops.M = [&](const double* v, double* out) -> long long {
             if (!o.use_precond) { launch_copy<double>(v, out, n, st); return 0; }
             launch_d2f(v, F.vecA, n, st);
-            long long it = pinv_impl<float>(P, F.vecA, F.vecB, o, st, true);
+            long long it = pinv_impl<float>(P, F.vecA, F.vecB, o32, st, true);
             launch_f2d(F.vecB, out, n, st);
             return it;
         };
@@ -504,7 +525,7 @@ tsfde_status tsfde_apply_P_inv_f32(tsfde_problem* prob, const float* z, float* y
     if (overlap(y, z, sizeof(float) * P.ntot)) { set_error("apply_P_inv_f32: y and z overlap"); return TSFDE_EINVAL; }
     Opts o = get_opts(opts);
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
-    if (!opts) o.inner_tol = 1e-6;
+    o.inner_tol = std::max(o.inner_tol, kInnerTolF32);
     TSFDE_GUARD("apply_P_inv_f32", pinv_impl<float>(P, z, y, o, (hipStream_t)stream, true);)
     return TSFDE_OK;
 }
