@@ -16,6 +16,12 @@
 
 namespace tsfde {
 
+// LDS sequences are stored with one pad slot after every 8 complex values: the Stockham write
+// a[(b - k) R + k + r Ns] otherwise sends all 64 lanes of a wave to the same LDS banks (a stride of
+// 8 complex values is 128 bytes); with the pad each 128-bit access is spread over all banks.
+__host__ __device__ __forceinline__ constexpr int lx(int i) { return i + (i >> 3); }
+__host__ __device__ __forceinline__ constexpr int lds_len(int L) { return L + (L >> 3); }
+
 template <typename T, bool INV>
 __device__ __forceinline__ cplx<T> mul_mi(cplx<T> a) {  // * (-i) forward, * (+i) inverse
     return INV ? cplx<T>{-a.y, a.x} : cplx<T>{a.y, -a.x};
@@ -73,7 +79,7 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* a, int L, int Ns, const c
     for (int c = 0; c < NB; ++c) {
         const int b = tid + c * nthr;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[c][r] = a[b + r * nbut];
+        for (int r = 0; r < R; ++r) v[c][r] = a[lx(b + r * nbut)];
     }
     __syncthreads();
     const int tstride = L / (Ns * R);
@@ -97,12 +103,12 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* a, int L, int Ns, const c
         }
         const int base = (b - k) * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) a[base + r * Ns] = v[c][r];
+        for (int r = 0; r < R; ++r) a[lx(base + r * Ns)] = v[c][r];
     }
     __syncthreads();
 }
 
-// In-place FFT of a[0..L) with L = VPT * nthr.  Must be called by all threads of the
+// In-place FFT of a[0..L) (stored with the lx() padding) with L = VPT * nthr.  Must be called by all threads of the
 // workgroup (it contains __syncthreads()); `tid` is the thread's index within its group.
 template <typename T, int VPT, bool INV>
 __device__ void fft_lds(cplx<T>* a, int L, const cplx<T>* __restrict__ tw, int tid, int nthr) {

@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/tsfde.h"
+#include "tsfde.h"
 #include "common.hpp"
 
 namespace tsfde {
@@ -73,6 +73,8 @@ struct Problem {
     double* V = nullptr;
     double* Z = nullptr;
     int basis_m = 0;
+    void* pw64 = nullptr;           // persistent P^{-1} work buffers (FP64 / FP32)
+    void* pw32 = nullptr;
     double* dev_scalars = nullptr;  // small device scratch (dots, flags)
     double* host_scalars = nullptr; // pinned mirror
     size_t bytes = 0;
@@ -137,5 +139,15 @@ void launch_sub_partials(const T* a, const T* b, T* out, long long n, T* partial
 template <typename T>
 void launch_jacobi_prec(const T* r, T* z, const T* dg, T c, T a0, long long n, T* partials, int* nparts,
                         hipStream_t s);
+
+// persistent P^{-1} (pinv_persistent.hip)
+bool persistent_supported(const Problem& P);
+template <typename T>
+long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T* z, T* y, double inner_tol,
+                              int inner_maxit, bool last_block, int extrap, hipStream_t st);
+template <typename T>
+void pinv_persistent_free(void* wptr);
+void set_persistent_blocks(int g);
+void set_persistent_block_size(int bs);
 
 }  // namespace tsfde

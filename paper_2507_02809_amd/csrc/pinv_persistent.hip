@@ -1,0 +1,914 @@
+// P^{-1} z with persistent cooperative kernels (§5.1 'Implementation': forward substitution over
+// the time steps; each diagonal block solved by preconditioned CG on its symmetrised form).
+//
+// The forward substitution is a chain of M+1 dependent solves on one spatial slice each, and every
+// CG iteration is a handful of small transforms and two reductions.  Launching those as separate
+// kernels costs microseconds per launch plus a host round trip per convergence test, so here a
+// cooperative grid of G workgroups runs a segment of up to kHB consecutive steps, separating
+// phases with a device-wide barrier and taking every convergence decision on the device: all
+// workgroups reduce the same partial sums in the same order and take the same branch.
+//
+// Between segments an ordinary full-GPU kernel sums the "far" part of the time history,
+//   hacc[i] = sum_{m < sa} e_{sa+i-m} y_m,   i < kHB,
+// a bandwidth-bound block Toeplitz product over all earlier slices; inside a segment each step
+// adds only the near terms m in [sa, s).
+//
+// Per step s (0-based; s = M is the last block row), inside a segment:
+//   E   (pointwise) finish step s-1 (y_{s-1} = x, B x_{s-1} recovered from its CG residual),
+//       history, rhs = (z_s - gamma1 hist)/gamma2, warm start x0 = 2 y_{s-1} - y_{s-2} with
+//       B x0 from the stored B y's, r0 = rhs - A_s x0, (r0, r0), (rhs, rhs)
+//   CG: [z = M^{-1} r: pass A | pass B | pass D, (r, z)]
+//       loop { [rows_fwd of p = z + beta p] [columns] [rows_inv: q = A_s p, (p, q)]
+//              [x += a p, r -= a q, (r, r), pass A] check [pass B] [pass D, (r, z)] }
+// (2D, tau preconditioner: 6 device-wide barriers per CG iteration.)  d = 1 runs the same chain
+// with one workgroup (each transform is a single FFT, barriers are workgroup barriers).
+// Every phase issues all of its global loads before its stores, so that a thread's independent
+// memory accesses overlap instead of waiting one cache miss at a time.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "fft.hpp"
+#include "internal.hpp"
+
+namespace tsfde {
+
+constexpr int kHB = 16;    // steps per segment (history block)
+constexpr int kNPart = 4;  // reduction slots per workgroup
+enum : int { SL_RR = 0, SL_BB = 1, SL_RZ = 2, SL_PQ = 3 };
+
+template <typename T>
+struct PinvArgs {
+    int d, N, M, L, H;
+    long long Nd;
+    int use_tau;  // 1: tau (sine transform) preconditioner, 0: diagonal
+    int extrap;   // 1: linear extrapolation of the warm start in time
+    int tw_lds;   // 1: twiddles copied to LDS (when they fit beside the sequences)
+    const T* z;
+    T* y;
+    const T* g1;
+    const T* g2;
+    const T* dg;
+    const T* epad;
+    const T* sym;
+    const T* tau;
+    const cplx<T>* tw;
+    const double* sigma;  // [M]
+    T ct, cf, a0;
+    double tol2;
+    int maxit;
+    // work (Nd each unless noted)
+    T *x, *r, *zz, *p, *q, *t1, *t2, *rhs, *bxb;
+    T* hacc;           // [kHB][Nd]
+    cplx<T>* spec;     // [H][N]
+    double* part;      // [G][kNPart]
+    unsigned* bar;     // barrier counter, zero at launch
+    long long* iters;  // accumulated CG iterations
+};
+
+// Device-wide barrier: arrive on a counter, wait until all blocks of this epoch arrived.  The
+// release/acquire pair at agent scope makes every block's earlier writes visible to every block.
+__device__ __forceinline__ void grid_barrier(unsigned* ctr, unsigned& epoch) {
+    __syncthreads();
+    if (gridDim.x > 1) {
+        epoch += gridDim.x;
+        if (threadIdx.x == 0) {
+            __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch)
+                __builtin_amdgcn_s_sleep(1);
+        }
+        __syncthreads();
+    }
+}
+
+// block-reduce v into this block's slot
+template <typename T>
+__device__ __forceinline__ void put_partial(double* part, int slot, T v, double* red) {
+    const double s = block_sum((double)v, red);
+    if (threadIdx.x == 0) part[blockIdx.x * kNPart + slot] = s;
+}
+
+// After a barrier: wave 0 loads every block's slots (lane b reads block b), reduces them with the
+// same shuffle tree in every block and leaves the totals in tot[kNPart] (LDS) for all threads.
+__device__ __forceinline__ void gather_totals(const double* part, double* tot) {
+    if (threadIdx.x < kWave) {
+        const int lane = threadIdx.x;
+        const int G = gridDim.x;
+        double v[kNPart];
+#pragma unroll
+        for (int k = 0; k < kNPart; ++k) v[k] = 0.0;
+        for (int b = lane; b < G; b += kWave) {
+#pragma unroll
+            for (int k = 0; k < kNPart; ++k) v[k] += part[b * kNPart + k];
+        }
+#pragma unroll
+        for (int k = 0; k < kNPart; ++k) {
+            for (int off = kWave / 2; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, kWave);
+            if (lane == 0) tot[k] = v[k];
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// far history: hacc[i][j] = sum_{m < sa} e_{sa+i-m} y_m[j], i < cnt (<= kHB).
+// One workgroup = 64 points x 4 waves; wave w sums the steps m = w, w+4, ...
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void far_history(const T* __restrict__ y, T* __restrict__ hacc,
+                                                   const T* __restrict__ epad, int sa, int cnt, long long Nd) {
+    __shared__ T part[4][kHB][64];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const long long j = (long long)blockIdx.x * 64 + lane;
+    const T* e = epad + kEpad;
+    T acc[kHB];
+#pragma unroll
+    for (int i = 0; i < kHB; ++i) acc[i] = T(0);
+    if (j < Nd) {
+#pragma unroll 4
+        for (int m = w; m < sa; m += 4) {
+            const T ym = y[(long long)m * Nd + j];
+#pragma unroll
+            for (int i = 0; i < kHB; ++i) acc[i] += e[sa + i - m] * ym;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kHB; ++i) part[w][i][lane] = acc[i];
+    __syncthreads();
+    if (w == 0 && j < Nd) {
+        for (int i = 0; i < cnt; ++i)
+            hacc[(long long)i * Nd + j] = (part[0][i][lane] + part[1][i][lane]) + (part[2][i][lane] + part[3][i][lane]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// group-level transforms (a group = nthr threads sharing one LDS sequence of length L)
+// ---------------------------------------------------------------------------
+
+// 2D: rows (i0, i1) of p -> half spectra spec[k][i] (k < L/2+1), after p = zz + beta p
+template <typename T, int VPT>
+__device__ void g_rows_fwd(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, int pair, bool valid, T beta, int tid,
+                           int nthr) {
+    const int N = a.N, L = a.L;
+    const int i0 = 2 * pair, i1 = i0 + 1;
+    const bool two = i1 < N;
+    T z0[VPT], z1[VPT], p0[VPT], p1[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int j = tid + u * nthr;
+        z0[u] = z1[u] = p0[u] = p1[u] = T(0);
+        if (valid && j < N) {
+            const long long o0 = (long long)i0 * N + j;
+            z0[u] = a.zz[o0];
+            if (beta != T(0)) p0[u] = a.p[o0];
+            if (two) {
+                z1[u] = a.zz[o0 + N];
+                if (beta != T(0)) p1[u] = a.p[o0 + N];
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int j = tid + u * nthr;
+        const T v0 = z0[u] + beta * p0[u], v1 = z1[u] + beta * p1[u];
+        if (valid && j < N) {
+            const long long o0 = (long long)i0 * N + j;
+            a.p[o0] = v0;
+            if (two) a.p[o0 + N] = v1;
+        }
+        c[lx(j)] = {v0, v1};
+    }
+    __syncthreads();
+    fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
+    if (valid) {
+        const int H = a.H;
+        for (int k = tid; k < H; k += nthr) {
+            const cplx<T> C = c[lx(k)];
+            const cplx<T> Cm = c[lx((L - k) & (L - 1))];
+            a.spec[(long long)k * N + i0] = {T(0.5) * (C.x + Cm.x), T(0.5) * (C.y - Cm.y)};
+            if (two) a.spec[(long long)k * N + i1] = {T(0.5) * (C.y + Cm.y), T(0.5) * (Cm.x - C.x)};
+        }
+    }
+    __syncthreads();
+}
+
+// 2D: spectral row k2: FFT over i, times the circulant symbol, inverse FFT over k1
+template <typename T, int VPT>
+__device__ void g_cols(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, int k2, bool valid, int tid, int nthr) {
+    const int N = a.N, L = a.L;
+    cplx<T>* row = a.spec + (long long)k2 * N;
+    const T* sy = a.sym + (long long)k2 * L;
+    T sv[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int i = tid + u * nthr;
+        c[lx(i)] = (valid && i < N) ? row[i] : cplx<T>{T(0), T(0)};
+        sv[u] = valid ? sy[i] : T(0);
+    }
+    __syncthreads();
+    fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int k1 = tid + u * nthr;
+        c[lx(k1)] = {c[lx(k1)].x * sv[u], c[lx(k1)].y * sv[u]};
+    }
+    __syncthreads();
+    fft_lds<T, VPT, true>(c, L, tw, tid, nthr);
+    if (valid) {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int i = tid + u * nthr;
+            if (i < N) row[i] = c[lx(i)];
+        }
+    }
+    __syncthreads();
+}
+
+// 2D: rows (i0, i1): inverse transform of the half spectra, q = dg p + c u, accumulate (p, q)
+template <typename T, int VPT>
+__device__ void g_rows_inv(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, int pair, bool valid, const T* dg,
+                           T cc, int tid, int nthr, T& pq) {
+    const int N = a.N, L = a.L, H = a.H;
+    const int i0 = 2 * pair, i1 = i0 + 1;
+    const bool two = i1 < N;
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int k = tid + u * nthr;
+        cplx<T> v = {T(0), T(0)};
+        if (valid) {
+            const int kk = (k < H) ? k : L - k;
+            const cplx<T> Y0 = a.spec[(long long)kk * N + i0];
+            const cplx<T> Y1 = two ? a.spec[(long long)kk * N + i1] : cplx<T>{T(0), T(0)};
+            v = (k < H) ? cplx<T>{Y0.x - Y1.y, Y0.y + Y1.x} : cplx<T>{Y0.x + Y1.y, Y1.x - Y0.y};
+        }
+        c[lx(k)] = v;
+    }
+    // loads of p and dg for the epilogue, in flight while the transform runs
+    T p0[VPT], p1[VPT], d0[VPT], d1[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int j = tid + u * nthr;
+        p0[u] = p1[u] = d0[u] = d1[u] = T(0);
+        if (valid && j < N) {
+            const long long o0 = (long long)i0 * N + j;
+            p0[u] = a.p[o0];
+            if (dg) d0[u] = dg[o0];
+            if (two) {
+                p1[u] = a.p[o0 + N];
+                if (dg) d1[u] = dg[o0 + N];
+            }
+        }
+    }
+    __syncthreads();
+    fft_lds<T, VPT, true>(c, L, tw, tid, nthr);
+    if (valid) {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int j = tid + u * nthr;
+            if (j < N) {
+                const cplx<T> uu = c[lx(j)];
+                const long long o0 = (long long)i0 * N + j;
+                const T q0 = d0[u] * p0[u] + cc * uu.x;
+                a.q[o0] = q0;
+                pq += p0[u] * q0;
+                if (two) {
+                    const T q1 = d1[u] * p1[u] + cc * uu.y;
+                    a.q[o0 + N] = q1;
+                    pq += p1[u] * q1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Sine transform (DST-I via the odd extension of length L = 2(N+1)) of rows (i0, i1) of `in`, with
+// the two rows packed as real + i*imag; afterwards c[lx(k+1)] = -2i DST(row i0)_k + 2 DST(row i1)_k.
+// With upd, first x += alpha p and in -= alpha q on those rows (accumulating (in, in)).
+// d = 1: a single row.
+template <typename T, int VPT>
+__device__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, T* in, int i0, bool valid, int tid,
+                           int nthr, bool upd, T alpha, T& rr) {
+    const int N = a.N, L = a.L;
+    const bool two = (a.d == 2) && (i0 + 1 < N);
+    T v0[VPT], v1[VPT];
+    if (upd) {
+        T q0[VPT], q1[VPT], x0[VPT], x1[VPT], pp0[VPT], pp1[VPT];
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int m = tid + u * nthr;
+            v0[u] = v1[u] = q0[u] = q1[u] = x0[u] = x1[u] = pp0[u] = pp1[u] = T(0);
+            if (valid && m < N) {
+                const long long o0 = (long long)i0 * N + m;
+                v0[u] = in[o0];
+                q0[u] = a.q[o0];
+                x0[u] = a.x[o0];
+                pp0[u] = a.p[o0];
+                if (two) {
+                    v1[u] = in[o0 + N];
+                    q1[u] = a.q[o0 + N];
+                    x1[u] = a.x[o0 + N];
+                    pp1[u] = a.p[o0 + N];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int m = tid + u * nthr;
+            v0[u] -= alpha * q0[u];
+            v1[u] -= alpha * q1[u];
+            rr += v0[u] * v0[u] + v1[u] * v1[u];
+            if (valid && m < N) {
+                const long long o0 = (long long)i0 * N + m;
+                in[o0] = v0[u];
+                a.x[o0] = x0[u] + alpha * pp0[u];
+                if (two) {
+                    in[o0 + N] = v1[u];
+                    a.x[o0 + N] = x1[u] + alpha * pp1[u];
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int m = tid + u * nthr;
+            v0[u] = v1[u] = T(0);
+            if (valid && m < N) {
+                const long long o0 = (long long)i0 * N + m;
+                v0[u] = in[o0];
+                if (two) v1[u] = in[o0 + N];
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int m = tid + u * nthr;
+        if (m < N) {
+            c[lx(m + 1)] = {v0[u], v1[u]};
+            c[lx(L - m - 1)] = {-v0[u], -v1[u]};
+        }
+    }
+    if (tid == 0) {
+        c[lx(0)] = {T(0), T(0)};
+        c[lx(N + 1)] = {T(0), T(0)};
+    }
+    __syncthreads();
+    fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
+}
+
+// ---------------------------------------------------------------------------
+// segment kernel: steps [sa, sb)
+// ---------------------------------------------------------------------------
+template <typename T, int VPT, int BS>
+__global__ __launch_bounds__(BS) void pinv_segment(PinvArgs<T> a, int sa, int sb) {
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ double red[BS / 64];
+    __shared__ double tot[kNPart];
+    const int nthr = a.L / VPT;             // threads per transform group
+    const int gpb = blockDim.x / nthr;      // groups per workgroup (1 for d = 1)
+    const int grp = threadIdx.x / nthr;
+    const int tid = threadIdx.x - grp * nthr;
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int twn = a.tw_lds ? a.L : 0;  // twiddles first (when in LDS), then the sequences
+    cplx<T>* c = lds + twn + (size_t)grp * lds_len(a.L);
+    for (int k = threadIdx.x; k < twn; k += blockDim.x) lds[k] = a.tw[k];
+    const cplx<T>* twl = a.tw_lds ? lds : a.tw;
+    __syncthreads();
+    const int NG = gridDim.x * gpb;         // groups in the grid
+    const int gg = blockIdx.x * gpb + grp;  // this group's index
+    const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long gthreads = (long long)gridDim.x * blockDim.x;
+    const int N = a.N;
+    const long long Nd = a.Nd;
+    const int M = a.M;
+    const bool two_d = (a.d == 2);
+    const bool tau2 = a.use_tau && two_d;
+    const int NP = two_d ? (N + 1) / 2 : 1;  // row pairs (2D)
+    const int NR = (NP + NG - 1) / NG;       // rounds over row pairs
+    const int NC = (a.H + NG - 1) / NG;      // rounds over spectral rows
+    const T* e = a.epad + kEpad;
+    const T scale = two_d ? T(4.0 / ((double)(N + 1) * (N + 1))) : T(2.0 / (N + 1));
+    unsigned epoch = 0;
+    long long total_it = 0;
+
+    for (int s = sa; s < sb; ++s) {
+        const bool lastrow = (s == M);
+        const T* dg = lastrow ? nullptr : a.dg + (long long)s * Nd;
+        const T cc = lastrow ? T(1) : a.ct;
+        const T sig = lastrow ? T(0) : T(a.sigma[s]);
+
+        // pass A of z = M^{-1} r (2D tau: sine transform of r rows into t1[k2][i]; 1D tau and the
+        // diagonal preconditioner: the whole z and (r, z)), optionally after the CG update
+        auto prec_A = [&](bool upd, T alpha) {
+            T rr = T(0), rzl = T(0);
+            if (tau2) {
+                for (int rd = 0; rd < NR; ++rd) {
+                    const int pr = rd * NG + gg;
+                    const bool valid = pr < NP;
+                    const int i0 = 2 * pr;
+                    g_dst_load<T, VPT>(a, c, twl, a.r, i0, valid, tid, nthr, upd, alpha, rr);
+                    if (valid) {
+#pragma unroll
+                        for (int u = 0; u < VPT; ++u) {
+                            const int k = tid + u * nthr;
+                            if (k < N) {
+                                const cplx<T> C = c[lx(k + 1)];
+                                a.t1[(long long)k * N + i0] = T(-0.5) * C.y;
+                                if (i0 + 1 < N) a.t1[(long long)k * N + i0 + 1] = T(0.5) * C.x;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            } else if (a.use_tau) {
+                const bool act = gg == 0;
+                g_dst_load<T, VPT>(a, c, twl, a.r, 0, act, tid, nthr, upd, alpha, rr);
+                T hv[VPT], tv[VPT], rv[VPT];
+#pragma unroll
+                for (int u = 0; u < VPT; ++u) {
+                    const int k = tid + u * nthr;
+                    tv[u] = (k < N) ? a.tau[k] : T(1);
+                    rv[u] = (act && k < N) ? a.r[k] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < VPT; ++u) {
+                    const int k = tid + u * nthr;
+                    hv[u] = (k < N) ? T(-0.5) * c[lx(k + 1)].y * scale / (sig + cc * tv[u]) : T(0);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < VPT; ++u) {
+                    const int k = tid + u * nthr;
+                    if (k < N) {
+                        c[lx(k + 1)] = {hv[u], T(0)};
+                        c[lx(a.L - k - 1)] = {-hv[u], T(0)};
+                    }
+                }
+                if (tid == 0) {
+                    c[lx(0)] = {T(0), T(0)};
+                    c[lx(N + 1)] = {T(0), T(0)};
+                }
+                __syncthreads();
+                fft_lds<T, VPT, false>(c, a.L, twl, tid, nthr);
+                if (act) {
+#pragma unroll
+                    for (int u = 0; u < VPT; ++u) {
+                        const int k = tid + u * nthr;
+                        if (k < N) {
+                            const T zv = T(-0.5) * c[lx(k + 1)].y;
+                            a.zz[k] = zv;
+                            rzl += rv[u] * zv;
+                        }
+                    }
+                }
+                __syncthreads();
+            } else {
+                for (long long j = gtid; j < Nd; j += gthreads) {
+                    T rv = a.r[j];
+                    const T qv = upd ? a.q[j] : T(0);
+                    const T xv = upd ? a.x[j] : T(0);
+                    const T pv = upd ? a.p[j] : T(0);
+                    const T dv = dg ? dg[j] : T(0);
+                    if (upd) {
+                        rv -= alpha * qv;
+                        a.x[j] = xv + alpha * pv;
+                        a.r[j] = rv;
+                        rr += rv * rv;
+                    }
+                    const T zv = rv / (dv + cc * a.a0);
+                    a.zz[j] = zv;
+                    rzl += rv * zv;
+                }
+            }
+            if (upd) put_partial(a.part, SL_RR, rr, red);
+            if (!tau2) put_partial(a.part, SL_RZ, rzl, red);
+            grid_barrier(a.bar, epoch);
+            gather_totals(a.part, tot);
+        };
+
+        // passes B and D of z = M^{-1} r for 2D tau, and (r, z)
+        auto prec_BD = [&]() {
+            for (int rd = 0; rd < NR; ++rd) {
+                const int pr = rd * NG + gg;
+                const bool valid = pr < NP;
+                const int k0 = 2 * pr;
+                const bool two = k0 + 1 < N;
+                T dummy = T(0);
+                T tv0[VPT], tv1[VPT];
+#pragma unroll
+                for (int u = 0; u < VPT; ++u) {
+                    const int k1 = tid + u * nthr;
+                    tv0[u] = tv1[u] = T(1);
+                    if (valid && k1 < N) {
+                        tv0[u] = a.tau[(long long)k1 * N + k0];
+                        if (two) tv1[u] = a.tau[(long long)k1 * N + k0 + 1];
+                    }
+                }
+                g_dst_load<T, VPT>(a, c, twl, a.t1, k0, valid, tid, nthr, false, T(0), dummy);
+                T hv0[VPT], hv1[VPT];
+#pragma unroll
+                for (int u = 0; u < VPT; ++u) {
+                    const int k1 = tid + u * nthr;
+                    hv0[u] = hv1[u] = T(0);
+                    if (valid && k1 < N) {
+                        const cplx<T> C = c[lx(k1 + 1)];
+                        hv0[u] = T(-0.5) * C.y * scale / (sig + cc * tv0[u]);
+                        if (two) hv1[u] = T(0.5) * C.x * scale / (sig + cc * tv1[u]);
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < VPT; ++u) {
+                    const int k1 = tid + u * nthr;
+                    if (k1 < N) {
+                        c[lx(k1 + 1)] = {hv0[u], hv1[u]};
+                        c[lx(a.L - k1 - 1)] = {-hv0[u], -hv1[u]};
+                    }
+                }
+                if (tid == 0) {
+                    c[lx(0)] = {T(0), T(0)};
+                    c[lx(N + 1)] = {T(0), T(0)};
+                }
+                __syncthreads();
+                fft_lds<T, VPT, false>(c, a.L, twl, tid, nthr);
+                if (valid) {
+#pragma unroll
+                    for (int u = 0; u < VPT; ++u) {
+                        const int i = tid + u * nthr;
+                        if (i < N) {
+                            const cplx<T> C = c[lx(i + 1)];
+                            a.t2[(long long)i * N + k0] = T(-0.5) * C.y;
+                            if (two) a.t2[(long long)i * N + k0 + 1] = T(0.5) * C.x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            grid_barrier(a.bar, epoch);
+            T rzl = T(0);
+            for (int rd = 0; rd < NR; ++rd) {
+                const int pr = rd * NG + gg;
+                const bool valid = pr < NP;
+                const int i0 = 2 * pr;
+                const bool two = i0 + 1 < N;
+                T dummy = T(0);
+                T r0[VPT], r1[VPT];
+#pragma unroll
+                for (int u = 0; u < VPT; ++u) {
+                    const int k = tid + u * nthr;
+                    r0[u] = r1[u] = T(0);
+                    if (valid && k < N) {
+                        r0[u] = a.r[(long long)i0 * N + k];
+                        if (two) r1[u] = a.r[(long long)i0 * N + k + N];
+                    }
+                }
+                g_dst_load<T, VPT>(a, c, twl, a.t2, i0, valid, tid, nthr, false, T(0), dummy);
+                if (valid) {
+#pragma unroll
+                    for (int u = 0; u < VPT; ++u) {
+                        const int k = tid + u * nthr;
+                        if (k < N) {
+                            const cplx<T> C = c[lx(k + 1)];
+                            const long long o0 = (long long)i0 * N + k;
+                            const T z0 = T(-0.5) * C.y;
+                            a.zz[o0] = z0;
+                            rzl += r0[u] * z0;
+                            if (two) {
+                                const T z1 = T(0.5) * C.x;
+                                a.zz[o0 + N] = z1;
+                                rzl += r1[u] * z1;
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            put_partial(a.part, SL_RZ, rzl, red);
+            grid_barrier(a.bar, epoch);
+            gather_totals(a.part, tot);
+        };
+
+        // ---------------- E: finish step s-1, history, rhs, warm start, r0 ----------------
+        {
+            T rr = T(0), bb = T(0);
+            const int nnear = s - sa;  // near-history terms m in [sa, s)
+            for (long long j = gtid; j < Nd; j += gthreads) {
+                // all loads first
+                const long long o = (long long)s * Nd + j;
+                const T xv = (s > 0) ? a.x[j] : T(0);
+                const T rhs_o = (s > 0) ? a.rhs[j] : T(0);
+                const T r_o = (s > 0) ? a.r[j] : T(0);
+                const T dgp = (s > 0) ? a.dg[(long long)(s - 1) * Nd + j] : T(0);
+                const bool ext = (s >= 2 && !lastrow && a.extrap);
+                const T bxb = (s >= 2 && !lastrow) ? a.bxb[j] : T(0);
+                const T ym2 = ext ? a.y[(long long)(s - 2) * Nd + j] : T(0);
+                const T zo = lastrow ? a.z[(long long)M * Nd + j] : a.z[o];
+                const T g2o = lastrow ? a.g2[(long long)(M - 1) * Nd + j] : a.g2[o];
+                const T g1o = lastrow ? T(0) : a.g1[o];
+                const T dgo = dg ? dg[j] : T(0);
+                const T ha = lastrow ? T(0) : a.hacc[(long long)(s - sa) * Nd + j];
+                T yv[kHB];
+#pragma unroll
+                for (int i = 0; i < kHB; ++i) {
+                    // y_m for m = sa + i < s - 1 (y_{s-1} is xv)
+                    yv[i] = (!lastrow && i + 1 < nnear) ? a.y[(long long)(sa + i) * Nd + j] : T(0);
+                }
+                // compute
+                const T yprev = xv;
+                const T bxprev = (s > 0) ? (rhs_o - r_o - dgp * xv) / a.ct : T(0);  // B y_{s-1}
+                T rhs, x0 = T(0), bx0 = T(0);
+                if (lastrow) {
+                    rhs = (zo - yprev) / (a.cf * g2o);
+                } else {
+                    T h = ha;
+#pragma unroll
+                    for (int i = 0; i < kHB; ++i)
+                        if (i + 1 < nnear) h += e[s - sa - i] * yv[i];
+                    if (nnear >= 1) h += e[1] * yprev;
+                    rhs = (zo - g1o * h) / g2o;
+                    if (s >= 1) {
+                        x0 = ext ? T(2) * yprev - ym2 : yprev;
+                        bx0 = ext ? T(2) * bxprev - bxb : bxprev;
+                    }
+                }
+                const T rv = rhs - (dgo * x0 + cc * bx0);
+                // stores
+                if (s > 0) a.y[(long long)(s - 1) * Nd + j] = xv;
+                if (s >= 1 && !lastrow) a.bxb[j] = bxprev;  // B y_{s-1} is "B y_{s-2}" next step
+                a.rhs[j] = rhs;
+                a.x[j] = x0;
+                a.r[j] = rv;
+                rr += rv * rv;
+                bb += rhs * rhs;
+            }
+            put_partial(a.part, SL_RR, rr, red);
+            put_partial(a.part, SL_BB, bb, red);
+            grid_barrier(a.bar, epoch);
+            gather_totals(a.part, tot);
+        }
+        const double bbt = tot[SL_BB];
+        double rrt = tot[SL_RR];
+        if (!(bbt > 0.0)) {
+            // zero right-hand side: the solution is zero
+            for (long long j = gtid; j < Nd; j += gthreads) {
+                a.x[j] = T(0);
+                a.r[j] = T(0);
+            }
+            grid_barrier(a.bar, epoch);
+            continue;
+        }
+        if (rrt <= a.tol2 * bbt) continue;  // the warm start already meets the tolerance
+
+        // ---------------- preconditioned CG ----------------
+        prec_A(false, T(0));
+        if (tau2) prec_BD();
+        double rz = tot[SL_RZ];
+        T beta = T(0);
+        int it = 0;
+        while (true) {
+            // q = A_s p with p = z + beta p ; (p, q)
+            T pq = T(0);
+            if (two_d) {
+                for (int rd = 0; rd < NR; ++rd) {
+                    const int pr = rd * NG + gg;
+                    g_rows_fwd<T, VPT>(a, c, twl, pr, pr < NP, beta, tid, nthr);
+                }
+                grid_barrier(a.bar, epoch);
+                for (int rd = 0; rd < NC; ++rd) {
+                    const int k2 = rd * NG + gg;
+                    g_cols<T, VPT>(a, c, twl, k2, k2 < a.H, tid, nthr);
+                }
+                grid_barrier(a.bar, epoch);
+                for (int rd = 0; rd < NR; ++rd) {
+                    const int pr = rd * NG + gg;
+                    g_rows_inv<T, VPT>(a, c, twl, pr, pr < NP, dg, cc, tid, nthr, pq);
+                }
+            } else {
+                // d = 1: one group does the p update, FFT, symbol, inverse FFT, q
+                const bool act = gg == 0;
+                T pv[VPT], zv[VPT], pold[VPT], sy[VPT], dv[VPT];
+#pragma unroll
+                for (int u = 0; u < VPT; ++u) {
+                    const int j = tid + u * nthr;
+                    zv[u] = pold[u] = dv[u] = T(0);
+                    sy[u] = a.sym[j];
+                    if (act && j < N) {
+                        zv[u] = a.zz[j];
+                        if (beta != T(0)) pold[u] = a.p[j];
+                        if (dg) dv[u] = dg[j];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < VPT; ++u) {
+                    const int j = tid + u * nthr;
+                    pv[u] = zv[u] + beta * pold[u];
+                    if (act && j < N) a.p[j] = pv[u];
+                    c[lx(j)] = {pv[u], T(0)};
+                }
+                __syncthreads();
+                fft_lds<T, VPT, false>(c, a.L, twl, tid, nthr);
+#pragma unroll
+                for (int u = 0; u < VPT; ++u) {
+                    const int k = tid + u * nthr;
+                    c[lx(k)] = {c[lx(k)].x * sy[u], c[lx(k)].y * sy[u]};
+                }
+                __syncthreads();
+                fft_lds<T, VPT, true>(c, a.L, twl, tid, nthr);
+                if (act) {
+#pragma unroll
+                    for (int u = 0; u < VPT; ++u) {
+                        const int j = tid + u * nthr;
+                        if (j < N) {
+                            const T qv = dv[u] * pv[u] + cc * c[lx(j)].x;
+                            a.q[j] = qv;
+                            pq += pv[u] * qv;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            put_partial(a.part, SL_PQ, pq, red);
+            grid_barrier(a.bar, epoch);
+            gather_totals(a.part, tot);
+            const double pqt = tot[SL_PQ];
+            const T alpha = T(pqt != 0.0 ? rz / pqt : 0.0);
+            // x += alpha p, r -= alpha q, (r, r), and pass A of z = M^{-1} r
+            prec_A(true, alpha);
+            ++it;
+            rrt = tot[SL_RR];
+            if (rrt <= a.tol2 * bbt || it >= a.maxit || !(rrt == rrt)) break;
+            if (tau2) prec_BD();
+            const double rz_new = tot[SL_RZ];
+            beta = T(rz != 0.0 ? rz_new / rz : 0.0);
+            rz = rz_new;
+        }
+        total_it += it;
+    }
+    // the segment's last step: y_{sb-1} = x (same pointwise ownership as phase E)
+    for (long long j = gtid; j < Nd; j += gthreads) a.y[(long long)(sb - 1) * Nd + j] = a.x[j];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.iters += total_it;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PersistentWork {
+    T* buf = nullptr;  // 9 Nd + kHB Nd
+    cplx<T>* spec = nullptr;
+    double* part = nullptr;
+    unsigned* bar = nullptr;
+    long long* iters = nullptr;
+    double* sigma = nullptr;
+};
+
+static int g_blocks_override = -1;
+static int g_bs_override = -1;
+
+template <typename T>
+static void ensure_work(Problem& P, PersistentWork<T>& W) {
+    if (W.buf) return;
+    TSFDE_HIP(hipMalloc(&W.buf, sizeof(T) * (size_t)(9 + kHB) * P.Nd));
+    TSFDE_HIP(hipMalloc(&W.spec, sizeof(cplx<T>) * (size_t)P.H * P.N));
+    TSFDE_HIP(hipMalloc(&W.part, sizeof(double) * 1024 * kNPart));
+    TSFDE_HIP(hipMalloc(&W.bar, 64));
+    TSFDE_HIP(hipMalloc(&W.iters, sizeof(long long)));
+    TSFDE_HIP(hipMalloc(&W.sigma, sizeof(double) * P.M));
+    TSFDE_HIP(hipMemcpy(W.sigma, P.sigma.data(), sizeof(double) * P.M, hipMemcpyHostToDevice));
+    TSFDE_HIP(hipMemset(W.buf, 0, sizeof(T) * (size_t)(9 + kHB) * P.Nd));
+}
+
+template <typename T, int VPT, int BS>
+static void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T* z, T* y, double inner_tol,
+                            int inner_maxit, bool last_block, int extrap, hipStream_t st) {
+    PinvArgs<T> a{};
+    a.d = P.d;
+    a.N = P.N;
+    a.M = P.M;
+    a.L = P.L;
+    a.H = P.H;
+    a.Nd = P.Nd;
+    a.use_tau = P.tau_ok ? 1 : 0;
+    a.extrap = extrap;
+    a.z = z;
+    a.y = y;
+    a.g1 = D.gamma1;
+    a.g2 = D.gamma2;
+    a.dg = D.dg;
+    a.epad = D.epad;
+    a.sym = D.sym;
+    a.tau = D.tau;
+    a.tw = D.tw;
+    a.sigma = W.sigma;
+    a.ct = T(P.ct);
+    a.cf = T(P.cf);
+    a.a0 = T(P.a0);
+    a.tol2 = inner_tol * inner_tol;
+    a.maxit = inner_maxit;
+    T* b = W.buf;
+    const long long Nd = P.Nd;
+    a.x = b;
+    a.r = b + Nd;
+    a.zz = b + 2 * Nd;
+    a.p = b + 3 * Nd;
+    a.q = b + 4 * Nd;
+    a.t1 = b + 5 * Nd;
+    a.t2 = b + 6 * Nd;
+    a.rhs = b + 7 * Nd;
+    a.bxb = b + 8 * Nd;
+    a.hacc = b + 9 * Nd;
+    a.spec = W.spec;
+    a.part = W.part;
+    a.bar = W.bar;
+    a.iters = W.iters;
+    const int nthr = P.L / VPT;
+    const int block = (P.d == 2) ? BS : nthr;
+    const int gpb = block / nthr;
+    size_t lds = sizeof(cplx<T>) * (P.L + (size_t)gpb * lds_len(P.L));
+    a.tw_lds = 1;
+    if (lds > 160 * 1024) {
+        a.tw_lds = 0;
+        lds = sizeof(cplx<T>) * (size_t)gpb * lds_len(P.L);
+    }
+    // 2D: enough groups that the L/2+1 spectral rows take two rounds
+    int grid = 1;
+    if (P.d == 2) {
+        grid = (P.H + 2 * gpb - 1) / (2 * gpb);
+        if (g_blocks_override > 0) grid = g_blocks_override;
+    }
+    int per_cu = 0;
+    TSFDE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pinv_segment<T, VPT, BS>, block, lds));
+    int dev = 0, ncu = 0;
+    TSFDE_HIP(hipGetDevice(&dev));
+    TSFDE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    grid = std::max(1, std::min(grid, per_cu * ncu));
+    launch_fill(reinterpret_cast<float*>(W.iters), 2, 0.0f, st);  // zero the iteration counter
+    const int s_last = last_block ? P.M : P.M - 1;
+    for (int sa = 0; sa <= s_last; sa += kHB) {
+        int sa_ = sa;
+        int sb_ = std::min(sa + kHB, s_last + 1);
+        const int cnt = std::min(kHB, P.M - sa);
+        if (cnt > 0) {
+            hipLaunchKernelGGL(far_history<T>, dim3((unsigned)((Nd + 63) / 64)), dim3(256), 0, st, y, a.hacc, D.epad,
+                               sa, cnt, Nd);
+            TSFDE_HIP(hipGetLastError());
+        }
+        launch_fill(reinterpret_cast<float*>(W.bar), 1, 0.0f, st);  // zero the barrier counter
+        void* args[] = {&a, &sa_, &sb_};
+        TSFDE_HIP(hipLaunchCooperativeKernel((void*)pinv_segment<T, VPT, BS>, dim3(grid), dim3(block), args, lds, st));
+    }
+}
+
+bool persistent_supported(const Problem& P) {
+    // the sine transform shares the FFT length with the Toeplitz embedding when 2(N+1) = L
+    return (!P.tau_ok || P.Ld == P.L) && P.L <= 8192;
+}
+
+template <typename T>
+long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T* z, T* y, double inner_tol,
+                              int inner_maxit, bool last_block, int extrap, hipStream_t st) {
+    if (!wptr) wptr = new PersistentWork<T>();
+    PersistentWork<T>& W = *static_cast<PersistentWork<T>*>(wptr);
+    ensure_work(P, W);
+    const int L = P.L;
+    const int vpt = (L <= 2048) ? 8 : (L == 4096 ? 16 : 32);
+    const int bs = (g_bs_override == 512 || g_bs_override == 1024) ? g_bs_override : 256;
+#define TSFDE_SEG(V, B) launch_segments<T, V, B>(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, st)
+    if (vpt == 8) {
+        if (bs == 1024) TSFDE_SEG(8, 1024);
+        else if (bs == 512) TSFDE_SEG(8, 512);
+        else TSFDE_SEG(8, 256);
+    } else if (vpt == 16) {
+        TSFDE_SEG(16, 256);
+    } else {
+        TSFDE_SEG(32, 256);
+    }
+#undef TSFDE_SEG
+    long long it = 0;
+    TSFDE_HIP(hipMemcpyAsync(&it, W.iters, sizeof(long long), hipMemcpyDeviceToHost, st));
+    TSFDE_HIP(hipStreamSynchronize(st));
+    return it;
+}
+
+template <typename T>
+void pinv_persistent_free(void* wptr) {
+    if (!wptr) return;
+    PersistentWork<T>* W = static_cast<PersistentWork<T>*>(wptr);
+    void* ptrs[] = {W->buf, W->spec, W->part, W->bar, W->iters, W->sigma};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    delete W;
+}
+
+void set_persistent_blocks(int g) { g_blocks_override = g; }
+void set_persistent_block_size(int bs) { g_bs_override = bs; }
+
+template long long pinv_persistent_run<double>(Problem&, const Dev<double>&, void*&, const double*, double*, double,
+                                               int, bool, int, hipStream_t);
+template long long pinv_persistent_run<float>(Problem&, const Dev<float>&, void*&, const float*, float*, double, int,
+                                              bool, int, hipStream_t);
+template void pinv_persistent_free<double>(void*);
+template void pinv_persistent_free<float>(void*);
+
+}  // namespace tsfde

