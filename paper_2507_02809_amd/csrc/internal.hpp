@@ -36,7 +36,8 @@ struct Dev {
     T* sym = nullptr;      // Toeplitz circulant symbol / L^d; d=1: [L]; d=2: [H][L]
     cplx<T>* tw = nullptr;   // [L]  twiddles exp(-2 pi i m / L)
     cplx<T>* twd = nullptr;  // [Ld] twiddles for the sine transform (tau preconditioner)
-    T* tau = nullptr;        // [Nd] tau eigenvalues of B (natural tau matrix), k-major like x
+    T* tau = nullptr;        // [Nd] tau eigenvalues of B (natural tau matrix); 2D: tau[k2 N + k1], k2 the
+                             // frequency along the fast (last) index, so a row holds all k1 for one k2
     // work
     cplx<T>* spec = nullptr;  // [nspec_slices][H][N] (d=2) half spectra of row transforms
     T* pcg = nullptr;         // 8 vectors of Nd: x r z p q t1 t2 rhs

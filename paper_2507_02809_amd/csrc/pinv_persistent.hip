@@ -34,12 +34,14 @@
 namespace tsfde {
 
 constexpr int kHB = 16;    // steps per segment (history block)
-constexpr int kNPart = 4;  // reduction slots per workgroup
-enum : int { SL_RR = 0, SL_BB = 1, SL_RZ = 2, SL_PQ = 3 };
+constexpr int kNPart = 6;  // reduction slots per workgroup
+// (r,r) (rhs,rhs) (r,z) (p,q) (p,dg p) (p,B p)
+enum : int { SL_RR = 0, SL_BB = 1, SL_RZ = 2, SL_PQ = 3, SL_PD = 4, SL_PB = 5 };
 
 template <typename T>
 struct PinvArgs {
     int d, N, M, L, H;
+    int ns;  // row stride of the transposed 2D intermediates spec, t1, t2 (N rounded up to 16)
     long long Nd;
     int use_tau;  // 1: tau (sine transform) preconditioner, 0: diagonal
     int extrap;   // 1: linear extrapolation of the warm start in time
@@ -60,7 +62,7 @@ struct PinvArgs {
     // work (Nd each unless noted)
     T *x, *r, *zz, *p, *q, *t1, *t2, *rhs, *bxb;
     T* hacc;           // [kHB][Nd]
-    cplx<T>* spec;     // [H][N]
+    cplx<T>* spec;     // [H][ns]
     double* part;      // [G][kNPart]
     unsigned* bar;     // barrier counter, zero at launch
     long long* iters;  // accumulated CG iterations
@@ -186,8 +188,8 @@ __device__ void g_rows_fwd(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, 
         for (int k = tid; k < H; k += nthr) {
             const cplx<T> C = c[lx(k)];
             const cplx<T> Cm = c[lx((L - k) & (L - 1))];
-            a.spec[(long long)k * N + i0] = {T(0.5) * (C.x + Cm.x), T(0.5) * (C.y - Cm.y)};
-            if (two) a.spec[(long long)k * N + i1] = {T(0.5) * (C.y + Cm.y), T(0.5) * (Cm.x - C.x)};
+            a.spec[(long long)k * a.ns + i0] = {T(0.5) * (C.x + Cm.x), T(0.5) * (C.y - Cm.y)};
+            if (two) a.spec[(long long)k * a.ns + i1] = {T(0.5) * (C.y + Cm.y), T(0.5) * (Cm.x - C.x)};
         }
     }
     __syncthreads();
@@ -197,7 +199,7 @@ __device__ void g_rows_fwd(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, 
 template <typename T, int VPT>
 __device__ void g_cols(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, int k2, bool valid, int tid, int nthr) {
     const int N = a.N, L = a.L;
-    cplx<T>* row = a.spec + (long long)k2 * N;
+    cplx<T>* row = a.spec + (long long)k2 * a.ns;
     const T* sy = a.sym + (long long)k2 * L;
     T sv[VPT];
 #pragma unroll
@@ -238,8 +240,8 @@ __device__ void g_rows_inv(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, 
         cplx<T> v = {T(0), T(0)};
         if (valid) {
             const int kk = (k < H) ? k : L - k;
-            const cplx<T> Y0 = a.spec[(long long)kk * N + i0];
-            const cplx<T> Y1 = two ? a.spec[(long long)kk * N + i1] : cplx<T>{T(0), T(0)};
+            const cplx<T> Y0 = a.spec[(long long)kk * a.ns + i0];
+            const cplx<T> Y1 = two ? a.spec[(long long)kk * a.ns + i1] : cplx<T>{T(0), T(0)};
             v = (k < H) ? cplx<T>{Y0.x - Y1.y, Y0.y + Y1.x} : cplx<T>{Y0.x + Y1.y, Y1.x - Y0.y};
         }
         c[lx(k)] = v;
@@ -288,8 +290,8 @@ __device__ void g_rows_inv(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, 
 // With upd, first x += alpha p and in -= alpha q on those rows (accumulating (in, in)).
 // d = 1: a single row.
 template <typename T, int VPT>
-__device__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, T* in, int i0, bool valid, int tid,
-                           int nthr, bool upd, T alpha, T& rr) {
+__device__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, T* in, int ld, int i0, bool valid,
+                           int tid, int nthr, bool upd, T alpha, T& rr) {
     const int N = a.N, L = a.L;
     const bool two = (a.d == 2) && (i0 + 1 < N);
     T v0[VPT], v1[VPT];
@@ -300,16 +302,16 @@ __device__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, 
             const int m = tid + u * nthr;
             v0[u] = v1[u] = q0[u] = q1[u] = x0[u] = x1[u] = pp0[u] = pp1[u] = T(0);
             if (valid && m < N) {
-                const long long o0 = (long long)i0 * N + m;
+                const long long o0 = (long long)i0 * ld + m;
                 v0[u] = in[o0];
                 q0[u] = a.q[o0];
                 x0[u] = a.x[o0];
                 pp0[u] = a.p[o0];
                 if (two) {
-                    v1[u] = in[o0 + N];
-                    q1[u] = a.q[o0 + N];
-                    x1[u] = a.x[o0 + N];
-                    pp1[u] = a.p[o0 + N];
+                    v1[u] = in[o0 + ld];
+                    q1[u] = a.q[o0 + ld];
+                    x1[u] = a.x[o0 + ld];
+                    pp1[u] = a.p[o0 + ld];
                 }
             }
         }
@@ -320,12 +322,12 @@ __device__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, 
             v1[u] -= alpha * q1[u];
             rr += v0[u] * v0[u] + v1[u] * v1[u];
             if (valid && m < N) {
-                const long long o0 = (long long)i0 * N + m;
+                const long long o0 = (long long)i0 * ld + m;
                 in[o0] = v0[u];
                 a.x[o0] = x0[u] + alpha * pp0[u];
                 if (two) {
-                    in[o0 + N] = v1[u];
-                    a.x[o0 + N] = x1[u] + alpha * pp1[u];
+                    in[o0 + ld] = v1[u];
+                    a.x[o0 + ld] = x1[u] + alpha * pp1[u];
                 }
             }
         }
@@ -335,9 +337,9 @@ __device__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, 
             const int m = tid + u * nthr;
             v0[u] = v1[u] = T(0);
             if (valid && m < N) {
-                const long long o0 = (long long)i0 * N + m;
+                const long long o0 = (long long)i0 * ld + m;
                 v0[u] = in[o0];
-                if (two) v1[u] = in[o0 + N];
+                if (two) v1[u] = in[o0 + ld];
             }
         }
     }
@@ -358,6 +360,306 @@ __device__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, 
 }
 
 // ---------------------------------------------------------------------------
+// fused phases of the 2D tau-preconditioned CG (4 device-wide barriers per iteration)
+//
+// Row phases are organised per workgroup: its gpb groups transform 2 gpb adjacent rows (group g:
+// rows ibase + 2g and ibase + 2g + 1, packed as one complex sequence).  Transposed intermediates
+// (half spectra spec[k][i], sine-transform buffers t1/t2 [k][i], row stride ns) are written and
+// read by the whole workgroup, thread (k, g) moving the two adjacent values of pair g, so that
+// one wave covers 16 rows k with 2 gpb consecutive i each instead of one value per row.
+// ---------------------------------------------------------------------------
+
+// after each group's forward row FFT: spec[k][ibase + 2g (+1)] = half spectra of the pair's rows
+template <typename T>
+__device__ void wg_write_spec(const PinvArgs<T>& a, const cplx<T>* cbase, int ibase, int gpb) {
+    const int N = a.N, L = a.L, H = a.H, LP = lds_len(L);
+    for (int idx = threadIdx.x; idx < H * gpb; idx += blockDim.x) {
+        const int k = idx / gpb, g = idx - k * gpb;
+        const int i = ibase + 2 * g;
+        if (i >= N) continue;
+        const cplx<T>* cg = cbase + (size_t)g * LP;
+        const cplx<T> C = cg[lx(k)];
+        const cplx<T> Cm = cg[lx((L - k) & (L - 1))];
+        cplx<T>* dst = a.spec + (long long)k * a.ns + i;
+        dst[0] = {T(0.5) * (C.x + Cm.x), T(0.5) * (C.y - Cm.y)};
+        if (i + 1 < N) dst[1] = {T(0.5) * (C.y + Cm.y), T(0.5) * (Cm.x - C.x)};
+    }
+}
+
+// after each group's sine-transform FFT (c[k+1] = -2i DST(row 2g) + 2 DST(row 2g+1)):
+// out[k][ibase + 2g (+1)] = DST of the pair's rows at k
+template <typename T>
+__device__ void wg_write_T(const PinvArgs<T>& a, const cplx<T>* cbase, T* out, int ibase, int gpb) {
+    const int N = a.N, LP = lds_len(a.L);
+    for (int idx = threadIdx.x; idx < N * gpb; idx += blockDim.x) {
+        const int k = idx / gpb, g = idx - k * gpb;
+        const int i = ibase + 2 * g;
+        if (i >= N) continue;
+        const cplx<T> C = cbase[(size_t)g * LP + lx(k + 1)];
+        T* dst = out + (long long)k * a.ns + i;
+        dst[0] = T(-0.5) * C.y;
+        if (i + 1 < N) dst[1] = T(0.5) * C.x;
+    }
+}
+
+// before the inverse row FFT: group g's sequence = Y0 + i Y1 over the full length, from the half
+// spectra Y0, Y1 of its rows (Hermitian completion for k > L/2)
+template <typename T>
+__device__ void wg_load_spec(const PinvArgs<T>& a, cplx<T>* cbase, int ibase, int gpb) {
+    const int N = a.N, L = a.L, H = a.H, LP = lds_len(L);
+    for (int idx = threadIdx.x; idx < H * gpb; idx += blockDim.x) {
+        const int k = idx / gpb, g = idx - k * gpb;
+        const int i = ibase + 2 * g;
+        cplx<T> Y0 = {T(0), T(0)}, Y1 = {T(0), T(0)};
+        if (i < N) {
+            const cplx<T>* src = a.spec + (long long)k * a.ns + i;
+            Y0 = src[0];
+            if (i + 1 < N) Y1 = src[1];
+        }
+        cplx<T>* cg = cbase + (size_t)g * LP;
+        cg[lx(k)] = {Y0.x - Y1.y, Y0.y + Y1.x};
+        if (k > 0 && k < H - 1) cg[lx(L - k)] = {Y0.x + Y1.y, Y1.x - Y0.y};
+    }
+}
+
+// pass A of z = M^{-1} r without update: DST of rows of r -> t1 (transposed)
+template <typename T, int VPT>
+__device__ void wg_pass_A(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, const cplx<T>* tw, int ibase, int grp,
+                          int gpb, int tid, int nthr) {
+    const int i0 = ibase + 2 * grp;
+    T dummy = T(0);
+    g_dst_load<T, VPT>(a, c, tw, a.r, a.N, i0, i0 < a.N, tid, nthr, false, T(0), dummy);
+    wg_write_T(a, cbase, a.t1, ibase, gpb);
+    __syncthreads();
+}
+
+// pass B: rows k0 = kbase + 2g (+1) of t1 hold (S r)^T rows; a DST over i gives Y = S r S (up to
+// scale), Y is scaled by scale/(sigma + c tau) and transformed again into t2 = S Yhat (transposed).
+// (r, z) = (r, M^{-1} r) = scale * sum Y^2/(sigma + c tau) is accumulated in rz.  tau is stored
+// [k2][k1], so the eigenvalues for rows k0, k0 + 1 are two contiguous rows.
+template <typename T, int VPT>
+__device__ void wg_pass_B(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, const cplx<T>* tw, int kbase, int grp,
+                          int gpb, T sig, T cc, T scale, int tid, int nthr, T& rz) {
+    const int N = a.N;
+    const int k0 = kbase + 2 * grp;
+    const bool valid = k0 < N;
+    const bool two = k0 + 1 < N;
+    T tv0[VPT], tv1[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int k1 = tid + u * nthr;
+        tv0[u] = tv1[u] = T(1);
+        if (valid && k1 < N) {
+            tv0[u] = a.tau[(long long)k0 * N + k1];
+            if (two) tv1[u] = a.tau[(long long)(k0 + 1) * N + k1];
+        }
+    }
+    T dummy = T(0);
+    g_dst_load<T, VPT>(a, c, tw, a.t1, a.ns, k0, valid, tid, nthr, false, T(0), dummy);
+    T hv0[VPT], hv1[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int k1 = tid + u * nthr;
+        hv0[u] = hv1[u] = T(0);
+        if (valid && k1 < N) {
+            const cplx<T> C = c[lx(k1 + 1)];
+            const T y0 = T(-0.5) * C.y, y1 = T(0.5) * C.x;
+            hv0[u] = y0 * scale / (sig + cc * tv0[u]);
+            rz += y0 * hv0[u];
+            if (two) {
+                hv1[u] = y1 * scale / (sig + cc * tv1[u]);
+                rz += y1 * hv1[u];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int k1 = tid + u * nthr;
+        if (k1 < N) {
+            c[lx(k1 + 1)] = {hv0[u], hv1[u]};
+            c[lx(a.L - k1 - 1)] = {-hv0[u], -hv1[u]};
+        }
+    }
+    if (tid == 0) {
+        c[lx(0)] = {T(0), T(0)};
+        c[lx(N + 1)] = {T(0), T(0)};
+    }
+    __syncthreads();
+    fft_lds<T, VPT, false>(c, a.L, tw, tid, nthr);
+    wg_write_T(a, cbase, a.t2, kbase, gpb);
+    __syncthreads();
+}
+
+// pass D of z = M^{-1} r on rows (i0, i1) of t2 (z rows), then p = z + beta p, (p, dg p), and the
+// forward row transform of the new p rows into the half spectra.
+template <typename T, int VPT>
+__device__ void wg_pass_DF(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, const cplx<T>* tw, int ibase, int grp,
+                           int gpb, T beta, const T* dg, int tid, int nthr, T& pdp) {
+    const int N = a.N, L = a.L;
+    const int i0 = ibase + 2 * grp;
+    const bool valid = i0 < N;
+    const bool two = i0 + 1 < N;
+    T pold0[VPT], pold1[VPT], d0[VPT], d1[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int m = tid + u * nthr;
+        pold0[u] = pold1[u] = d0[u] = d1[u] = T(0);
+        if (valid && m < N) {
+            const long long o0 = (long long)i0 * N + m;
+            if (beta != T(0)) {
+                pold0[u] = a.p[o0];
+                if (two) pold1[u] = a.p[o0 + N];
+            }
+            if (dg) {
+                d0[u] = dg[o0];
+                if (two) d1[u] = dg[o0 + N];
+            }
+        }
+    }
+    T dummy = T(0);
+    g_dst_load<T, VPT>(a, c, tw, a.t2, a.ns, i0, valid, tid, nthr, false, T(0), dummy);
+    T pn0[VPT], pn1[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int m = tid + u * nthr;
+        pn0[u] = pn1[u] = T(0);
+        if (valid && m < N) {
+            const cplx<T> C = c[lx(m + 1)];
+            pn0[u] = T(-0.5) * C.y + beta * pold0[u];
+            if (two) pn1[u] = T(0.5) * C.x + beta * pold1[u];
+            pdp += d0[u] * pn0[u] * pn0[u] + d1[u] * pn1[u] * pn1[u];
+            const long long o0 = (long long)i0 * N + m;
+            a.p[o0] = pn0[u];
+            if (two) a.p[o0 + N] = pn1[u];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) c[lx(tid + u * nthr)] = {pn0[u], pn1[u]};
+    __syncthreads();
+    fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
+    wg_write_spec(a, cbase, ibase, gpb);
+    __syncthreads();
+}
+
+// column pass of B p with (p, B p) = sum |V|^2 lambda/L^2 over the full spectrum (the half spectrum
+// counted twice except k2 = 0 and L/2)
+template <typename T, int VPT>
+__device__ void g_cols_pbp(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, int k2, bool valid, int tid, int nthr,
+                           T& pbp) {
+    const int N = a.N, L = a.L;
+    cplx<T>* row = a.spec + (long long)k2 * a.ns;
+    const T* sy = a.sym + (long long)k2 * L;
+    T sv[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int i = tid + u * nthr;
+        c[lx(i)] = (valid && i < N) ? row[i] : cplx<T>{T(0), T(0)};
+        sv[u] = valid ? sy[i] : T(0);
+    }
+    __syncthreads();
+    fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
+    const T wk = (k2 == 0 || 2 * k2 == L) ? T(1) : T(2);
+    T acc = T(0);
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int k1 = tid + u * nthr;
+        const cplx<T> v = c[lx(k1)];
+        acc += (v.x * v.x + v.y * v.y) * sv[u];
+        c[lx(k1)] = {v.x * sv[u], v.y * sv[u]};
+    }
+    pbp += wk * acc;
+    __syncthreads();
+    fft_lds<T, VPT, true>(c, L, tw, tid, nthr);
+    if (valid) {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int i = tid + u * nthr;
+            if (i < N) row[i] = c[lx(i)];
+        }
+    }
+    __syncthreads();
+}
+
+// inverse row transform -> u = B p rows; q = dg p + c u; r -= alpha q; x += alpha p; (r, r);
+// then pass A (DST of the new r rows into t1)
+template <typename T, int VPT>
+__device__ void wg_pass_IUA(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, const cplx<T>* tw, int ibase, int grp,
+                            int gpb, const T* dg, T cc, T alpha, int tid, int nthr, T& rr) {
+    const int N = a.N, L = a.L;
+    const int i0 = ibase + 2 * grp;
+    const bool valid = i0 < N;
+    const bool two = i0 + 1 < N;
+    T p0[VPT], p1[VPT], d0[VPT], d1[VPT], r0[VPT], r1[VPT], x0[VPT], x1[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int m = tid + u * nthr;
+        p0[u] = p1[u] = d0[u] = d1[u] = r0[u] = r1[u] = x0[u] = x1[u] = T(0);
+        if (valid && m < N) {
+            const long long o0 = (long long)i0 * N + m;
+            p0[u] = a.p[o0];
+            r0[u] = a.r[o0];
+            x0[u] = a.x[o0];
+            if (dg) d0[u] = dg[o0];
+            if (two) {
+                p1[u] = a.p[o0 + N];
+                r1[u] = a.r[o0 + N];
+                x1[u] = a.x[o0 + N];
+                if (dg) d1[u] = dg[o0 + N];
+            }
+        }
+    }
+    wg_load_spec(a, cbase, ibase, gpb);
+    __syncthreads();
+    fft_lds<T, VPT, true>(c, L, tw, tid, nthr);
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int m = tid + u * nthr;
+        const cplx<T> uu = c[lx(m)];
+        if (valid && m < N) {
+            const T q0 = d0[u] * p0[u] + cc * uu.x;
+            r0[u] -= alpha * q0;
+            x0[u] += alpha * p0[u];
+            const long long o0 = (long long)i0 * N + m;
+            a.r[o0] = r0[u];
+            a.x[o0] = x0[u];
+            rr += r0[u] * r0[u];
+            if (two) {
+                const T q1 = d1[u] * p1[u] + cc * uu.y;
+                r1[u] -= alpha * q1;
+                x1[u] += alpha * p1[u];
+                a.r[o0 + N] = r1[u];
+                a.x[o0 + N] = x1[u];
+                rr += r1[u] * r1[u];
+            } else {
+                r1[u] = T(0);
+            }
+        } else {
+            r0[u] = r1[u] = T(0);
+        }
+    }
+    __syncthreads();
+    // pass A on the updated rows: odd extension, FFT, DST rows -> t1 (transposed)
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int m = tid + u * nthr;
+        if (m < N) {
+            c[lx(m + 1)] = {r0[u], r1[u]};
+            c[lx(L - m - 1)] = {-r0[u], -r1[u]};
+        }
+    }
+    if (tid == 0) {
+        c[lx(0)] = {T(0), T(0)};
+        c[lx(N + 1)] = {T(0), T(0)};
+    }
+    __syncthreads();
+    fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
+    wg_write_T(a, cbase, a.t1, ibase, gpb);
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // segment kernel: steps [sa, sb)
 // ---------------------------------------------------------------------------
 template <typename T, int VPT, int BS>
@@ -371,7 +673,8 @@ __global__ __launch_bounds__(BS) void pinv_segment(PinvArgs<T> a, int sa, int sb
     const int tid = threadIdx.x - grp * nthr;
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
     const int twn = a.tw_lds ? a.L : 0;  // twiddles first (when in LDS), then the sequences
-    cplx<T>* c = lds + twn + (size_t)grp * lds_len(a.L);
+    cplx<T>* cbase = lds + twn;                              // the groups' sequences
+    cplx<T>* c = cbase + (size_t)grp * lds_len(a.L);
     for (int k = threadIdx.x; k < twn; k += blockDim.x) lds[k] = a.tw[k];
     const cplx<T>* twl = a.tw_lds ? lds : a.tw;
     __syncthreads();
@@ -398,32 +701,13 @@ __global__ __launch_bounds__(BS) void pinv_segment(PinvArgs<T> a, int sa, int sb
         const T cc = lastrow ? T(1) : a.ct;
         const T sig = lastrow ? T(0) : T(a.sigma[s]);
 
-        // pass A of z = M^{-1} r (2D tau: sine transform of r rows into t1[k2][i]; 1D tau and the
-        // diagonal preconditioner: the whole z and (r, z)), optionally after the CG update
+        // z = M^{-1} r and (r, z) for the 1D tau and the diagonal preconditioners (the 2D tau
+        // preconditioner has its own fused loop below), optionally after the CG update
         auto prec_A = [&](bool upd, T alpha) {
             T rr = T(0), rzl = T(0);
-            if (tau2) {
-                for (int rd = 0; rd < NR; ++rd) {
-                    const int pr = rd * NG + gg;
-                    const bool valid = pr < NP;
-                    const int i0 = 2 * pr;
-                    g_dst_load<T, VPT>(a, c, twl, a.r, i0, valid, tid, nthr, upd, alpha, rr);
-                    if (valid) {
-#pragma unroll
-                        for (int u = 0; u < VPT; ++u) {
-                            const int k = tid + u * nthr;
-                            if (k < N) {
-                                const cplx<T> C = c[lx(k + 1)];
-                                a.t1[(long long)k * N + i0] = T(-0.5) * C.y;
-                                if (i0 + 1 < N) a.t1[(long long)k * N + i0 + 1] = T(0.5) * C.x;
-                            }
-                        }
-                    }
-                    __syncthreads();
-                }
-            } else if (a.use_tau) {
+            if (a.use_tau) {
                 const bool act = gg == 0;
-                g_dst_load<T, VPT>(a, c, twl, a.r, 0, act, tid, nthr, upd, alpha, rr);
+                g_dst_load<T, VPT>(a, c, twl, a.r, N, 0, act, tid, nthr, upd, alpha, rr);
                 T hv[VPT], tv[VPT], rv[VPT];
 #pragma unroll
                 for (int u = 0; u < VPT; ++u) {
@@ -482,108 +766,6 @@ __global__ __launch_bounds__(BS) void pinv_segment(PinvArgs<T> a, int sa, int sb
                 }
             }
             if (upd) put_partial(a.part, SL_RR, rr, red);
-            if (!tau2) put_partial(a.part, SL_RZ, rzl, red);
-            grid_barrier(a.bar, epoch);
-            gather_totals(a.part, tot);
-        };
-
-        // passes B and D of z = M^{-1} r for 2D tau, and (r, z)
-        auto prec_BD = [&]() {
-            for (int rd = 0; rd < NR; ++rd) {
-                const int pr = rd * NG + gg;
-                const bool valid = pr < NP;
-                const int k0 = 2 * pr;
-                const bool two = k0 + 1 < N;
-                T dummy = T(0);
-                T tv0[VPT], tv1[VPT];
-#pragma unroll
-                for (int u = 0; u < VPT; ++u) {
-                    const int k1 = tid + u * nthr;
-                    tv0[u] = tv1[u] = T(1);
-                    if (valid && k1 < N) {
-                        tv0[u] = a.tau[(long long)k1 * N + k0];
-                        if (two) tv1[u] = a.tau[(long long)k1 * N + k0 + 1];
-                    }
-                }
-                g_dst_load<T, VPT>(a, c, twl, a.t1, k0, valid, tid, nthr, false, T(0), dummy);
-                T hv0[VPT], hv1[VPT];
-#pragma unroll
-                for (int u = 0; u < VPT; ++u) {
-                    const int k1 = tid + u * nthr;
-                    hv0[u] = hv1[u] = T(0);
-                    if (valid && k1 < N) {
-                        const cplx<T> C = c[lx(k1 + 1)];
-                        hv0[u] = T(-0.5) * C.y * scale / (sig + cc * tv0[u]);
-                        if (two) hv1[u] = T(0.5) * C.x * scale / (sig + cc * tv1[u]);
-                    }
-                }
-                __syncthreads();
-#pragma unroll
-                for (int u = 0; u < VPT; ++u) {
-                    const int k1 = tid + u * nthr;
-                    if (k1 < N) {
-                        c[lx(k1 + 1)] = {hv0[u], hv1[u]};
-                        c[lx(a.L - k1 - 1)] = {-hv0[u], -hv1[u]};
-                    }
-                }
-                if (tid == 0) {
-                    c[lx(0)] = {T(0), T(0)};
-                    c[lx(N + 1)] = {T(0), T(0)};
-                }
-                __syncthreads();
-                fft_lds<T, VPT, false>(c, a.L, twl, tid, nthr);
-                if (valid) {
-#pragma unroll
-                    for (int u = 0; u < VPT; ++u) {
-                        const int i = tid + u * nthr;
-                        if (i < N) {
-                            const cplx<T> C = c[lx(i + 1)];
-                            a.t2[(long long)i * N + k0] = T(-0.5) * C.y;
-                            if (two) a.t2[(long long)i * N + k0 + 1] = T(0.5) * C.x;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-            grid_barrier(a.bar, epoch);
-            T rzl = T(0);
-            for (int rd = 0; rd < NR; ++rd) {
-                const int pr = rd * NG + gg;
-                const bool valid = pr < NP;
-                const int i0 = 2 * pr;
-                const bool two = i0 + 1 < N;
-                T dummy = T(0);
-                T r0[VPT], r1[VPT];
-#pragma unroll
-                for (int u = 0; u < VPT; ++u) {
-                    const int k = tid + u * nthr;
-                    r0[u] = r1[u] = T(0);
-                    if (valid && k < N) {
-                        r0[u] = a.r[(long long)i0 * N + k];
-                        if (two) r1[u] = a.r[(long long)i0 * N + k + N];
-                    }
-                }
-                g_dst_load<T, VPT>(a, c, twl, a.t2, i0, valid, tid, nthr, false, T(0), dummy);
-                if (valid) {
-#pragma unroll
-                    for (int u = 0; u < VPT; ++u) {
-                        const int k = tid + u * nthr;
-                        if (k < N) {
-                            const cplx<T> C = c[lx(k + 1)];
-                            const long long o0 = (long long)i0 * N + k;
-                            const T z0 = T(-0.5) * C.y;
-                            a.zz[o0] = z0;
-                            rzl += r0[u] * z0;
-                            if (two) {
-                                const T z1 = T(0.5) * C.x;
-                                a.zz[o0 + N] = z1;
-                                rzl += r1[u] * z1;
-                            }
-                        }
-                    }
-                }
-                __syncthreads();
-            }
             put_partial(a.part, SL_RZ, rzl, red);
             grid_barrier(a.bar, epoch);
             gather_totals(a.part, tot);
@@ -661,8 +843,69 @@ __global__ __launch_bounds__(BS) void pinv_segment(PinvArgs<T> a, int sa, int sb
         if (rrt <= a.tol2 * bbt) continue;  // the warm start already meets the tolerance
 
         // ---------------- preconditioned CG ----------------
+        if (tau2) {
+            // z0 = M^{-1} r0: pass A, pass B (with (r, z))
+            for (int rd = 0; rd < NR; ++rd) {
+                const int ibase = 2 * (rd * NG + blockIdx.x * gpb);
+                wg_pass_A<T, VPT>(a, cbase, c, twl, ibase, grp, gpb, tid, nthr);
+            }
+            grid_barrier(a.bar, epoch);
+            {
+                T rzl = T(0);
+                for (int rd = 0; rd < NR; ++rd) {
+                    const int kbase = 2 * (rd * NG + blockIdx.x * gpb);
+                    wg_pass_B<T, VPT>(a, cbase, c, twl, kbase, grp, gpb, sig, cc, scale, tid, nthr, rzl);
+                }
+                put_partial(a.part, SL_RZ, rzl, red);
+                grid_barrier(a.bar, epoch);
+                gather_totals(a.part, tot);
+            }
+            double rz = tot[SL_RZ];
+            T beta = T(0);
+            int it = 0;
+            while (true) {
+                T pdp = T(0), pbp = T(0), rr = T(0);
+                for (int rd = 0; rd < NR; ++rd) {
+                    const int ibase = 2 * (rd * NG + blockIdx.x * gpb);
+                    wg_pass_DF<T, VPT>(a, cbase, c, twl, ibase, grp, gpb, beta, dg, tid, nthr, pdp);
+                }
+                put_partial(a.part, SL_PD, pdp, red);
+                grid_barrier(a.bar, epoch);
+                for (int rd = 0; rd < NC; ++rd) {
+                    const int k2 = rd * NG + gg;
+                    g_cols_pbp<T, VPT>(a, c, twl, k2, k2 < a.H, tid, nthr, pbp);
+                }
+                put_partial(a.part, SL_PB, pbp, red);
+                grid_barrier(a.bar, epoch);
+                gather_totals(a.part, tot);
+                const double pqt = tot[SL_PD] + (double)cc * tot[SL_PB];
+                const T alpha = T(pqt != 0.0 ? rz / pqt : 0.0);
+                for (int rd = 0; rd < NR; ++rd) {
+                    const int ibase = 2 * (rd * NG + blockIdx.x * gpb);
+                    wg_pass_IUA<T, VPT>(a, cbase, c, twl, ibase, grp, gpb, dg, cc, alpha, tid, nthr, rr);
+                }
+                put_partial(a.part, SL_RR, rr, red);
+                grid_barrier(a.bar, epoch);
+                gather_totals(a.part, tot);
+                ++it;
+                rrt = tot[SL_RR];
+                if (rrt <= a.tol2 * bbt || it >= a.maxit || !(rrt == rrt)) break;
+                T rzl = T(0);
+                for (int rd = 0; rd < NR; ++rd) {
+                    const int kbase = 2 * (rd * NG + blockIdx.x * gpb);
+                    wg_pass_B<T, VPT>(a, cbase, c, twl, kbase, grp, gpb, sig, cc, scale, tid, nthr, rzl);
+                }
+                put_partial(a.part, SL_RZ, rzl, red);
+                grid_barrier(a.bar, epoch);
+                gather_totals(a.part, tot);
+                const double rz_new = tot[SL_RZ];
+                beta = T(rz != 0.0 ? rz_new / rz : 0.0);
+                rz = rz_new;
+            }
+            total_it += it;
+            continue;
+        }
         prec_A(false, T(0));
-        if (tau2) prec_BD();
         double rz = tot[SL_RZ];
         T beta = T(0);
         int it = 0;
@@ -738,7 +981,6 @@ __global__ __launch_bounds__(BS) void pinv_segment(PinvArgs<T> a, int sa, int sb
             ++it;
             rrt = tot[SL_RR];
             if (rrt <= a.tol2 * bbt || it >= a.maxit || !(rrt == rrt)) break;
-            if (tau2) prec_BD();
             const double rz_new = tot[SL_RZ];
             beta = T(rz != 0.0 ? rz_new / rz : 0.0);
             rz = rz_new;
@@ -755,13 +997,18 @@ __global__ __launch_bounds__(BS) void pinv_segment(PinvArgs<T> a, int sa, int sb
 // ---------------------------------------------------------------------------
 template <typename T>
 struct PersistentWork {
-    T* buf = nullptr;  // 9 Nd + kHB Nd
-    cplx<T>* spec = nullptr;
+    T* buf = nullptr;       // x r zz p q rhs bxb: 7 Nd, then hacc: kHB Nd
+    T* tt = nullptr;        // t1, t2: N ns each (2D)
+    cplx<T>* spec = nullptr;  // [H][ns] (2D)
     double* part = nullptr;
     unsigned* bar = nullptr;
     long long* iters = nullptr;
     double* sigma = nullptr;
 };
+
+// row stride of the transposed 2D intermediates: N rounded up to 16 values, so that the rows of
+// spec (16-byte complex FP64) start on 256-byte boundaries
+static int spec_stride(int N) { return (N + 15) & ~15; }
 
 static int g_blocks_override = -1;
 static int g_bs_override = -1;
@@ -769,14 +1016,18 @@ static int g_bs_override = -1;
 template <typename T>
 static void ensure_work(Problem& P, PersistentWork<T>& W) {
     if (W.buf) return;
-    TSFDE_HIP(hipMalloc(&W.buf, sizeof(T) * (size_t)(9 + kHB) * P.Nd));
-    TSFDE_HIP(hipMalloc(&W.spec, sizeof(cplx<T>) * (size_t)P.H * P.N));
+    const size_t ns = (size_t)spec_stride(P.N);
+    TSFDE_HIP(hipMalloc(&W.buf, sizeof(T) * (size_t)(7 + kHB) * P.Nd));
+    if (P.d == 2) {
+        TSFDE_HIP(hipMalloc(&W.tt, sizeof(T) * 2 * (size_t)P.N * ns));
+        TSFDE_HIP(hipMalloc(&W.spec, sizeof(cplx<T>) * (size_t)P.H * ns));
+    }
     TSFDE_HIP(hipMalloc(&W.part, sizeof(double) * 1024 * kNPart));
     TSFDE_HIP(hipMalloc(&W.bar, 64));
     TSFDE_HIP(hipMalloc(&W.iters, sizeof(long long)));
     TSFDE_HIP(hipMalloc(&W.sigma, sizeof(double) * P.M));
     TSFDE_HIP(hipMemcpy(W.sigma, P.sigma.data(), sizeof(double) * P.M, hipMemcpyHostToDevice));
-    TSFDE_HIP(hipMemset(W.buf, 0, sizeof(T) * (size_t)(9 + kHB) * P.Nd));
+    TSFDE_HIP(hipMemset(W.buf, 0, sizeof(T) * (size_t)(7 + kHB) * P.Nd));
 }
 
 template <typename T, int VPT, int BS>
@@ -813,11 +1064,12 @@ static void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, c
     a.zz = b + 2 * Nd;
     a.p = b + 3 * Nd;
     a.q = b + 4 * Nd;
-    a.t1 = b + 5 * Nd;
-    a.t2 = b + 6 * Nd;
-    a.rhs = b + 7 * Nd;
-    a.bxb = b + 8 * Nd;
-    a.hacc = b + 9 * Nd;
+    a.rhs = b + 5 * Nd;
+    a.bxb = b + 6 * Nd;
+    a.hacc = b + 7 * Nd;
+    a.ns = spec_stride(P.N);
+    a.t1 = W.tt;
+    a.t2 = W.tt ? W.tt + (long long)P.N * a.ns : nullptr;
     a.spec = W.spec;
     a.part = W.part;
     a.bar = W.bar;
@@ -895,7 +1147,7 @@ template <typename T>
 void pinv_persistent_free(void* wptr) {
     if (!wptr) return;
     PersistentWork<T>* W = static_cast<PersistentWork<T>*>(wptr);
-    void* ptrs[] = {W->buf, W->spec, W->part, W->bar, W->iters, W->sigma};
+    void* ptrs[] = {W->buf, W->tt, W->spec, W->part, W->bar, W->iters, W->sigma};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete W;

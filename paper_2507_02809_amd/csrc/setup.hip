@@ -222,7 +222,7 @@ static std::vector<double> tau_eigs(int d, int N, const std::vector<double>& a) 
         for (int k2 = 0; k2 < N; ++k2) {
             double acc = 0.0;
             for (int l1 = 0; l1 < N; ++l1) acc += (l1 == 0 ? 1.0 : 2.0) * cosk(l1, k1 + 1) * G[(size_t)l1 * N + k2];
-            t[k1 * N + k2] = acc;
+            t[(size_t)k2 * N + k1] = acc;  // stored [k2][k1]: row k2 holds the k1 values
         }
     });
     return t;

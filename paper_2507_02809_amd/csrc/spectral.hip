@@ -226,8 +226,8 @@ __global__ void dst2d_rows(const T* __restrict__ x, T* __restrict__ out, int N, 
         T d0 = T(-0.5) * C.y, d1 = T(0.5) * C.x;
         const long long o0 = (long long)k * N + i0, o1 = (long long)k * N + i1;
         if (mode == DST_SCALE) {
-            d0 *= scale / (sigma + cfac * tau[o0]);
-            if (i1 < N) d1 *= scale / (sigma + cfac * tau[o1]);
+            d0 *= scale / (sigma + cfac * tau[(long long)i0 * N + k]);
+            if (i1 < N) d1 *= scale / (sigma + cfac * tau[(long long)i1 * N + k]);
         }
         out[o0] = d0;
         if (i1 < N) out[o1] = d1;
