@@ -149,6 +149,5 @@ long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T*
 template <typename T>
 void pinv_persistent_free(void* wptr);
 void set_persistent_blocks(int g);
-void set_persistent_block_size(int bs);
 
 }  // namespace tsfde

@@ -45,7 +45,6 @@ struct PinvArgs {
     long long Nd;
     int use_tau;  // 1: tau (sine transform) preconditioner, 0: diagonal
     int extrap;   // 1: linear extrapolation of the warm start in time
-    int tw_lds;   // 1: twiddles copied to LDS (when they fit beside the sequences)
     const T* z;
     T* y;
     const T* g1;
@@ -150,7 +149,7 @@ __global__ __launch_bounds__(256) void far_history(const T* __restrict__ y, T* _
 
 // 2D: rows (i0, i1) of p -> half spectra spec[k][i] (k < L/2+1), after p = zz + beta p
 template <typename T, int VPT>
-__device__ void g_rows_fwd(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, int pair, bool valid, T beta, int tid,
+__device__ __forceinline__ void g_rows_fwd(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, int pair, bool valid, T beta, int tid,
                            int nthr) {
     const int N = a.N, L = a.L;
     const int i0 = 2 * pair, i1 = i0 + 1;
@@ -197,7 +196,7 @@ __device__ void g_rows_fwd(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, 
 
 // 2D: spectral row k2: FFT over i, times the circulant symbol, inverse FFT over k1
 template <typename T, int VPT>
-__device__ void g_cols(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, int k2, bool valid, int tid, int nthr) {
+__device__ __forceinline__ void g_cols(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, int k2, bool valid, int tid, int nthr) {
     const int N = a.N, L = a.L;
     cplx<T>* row = a.spec + (long long)k2 * a.ns;
     const T* sy = a.sym + (long long)k2 * L;
@@ -229,7 +228,7 @@ __device__ void g_cols(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, int 
 
 // 2D: rows (i0, i1): inverse transform of the half spectra, q = dg p + c u, accumulate (p, q)
 template <typename T, int VPT>
-__device__ void g_rows_inv(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, int pair, bool valid, const T* dg,
+__device__ __forceinline__ void g_rows_inv(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, int pair, bool valid, const T* dg,
                            T cc, int tid, int nthr, T& pq) {
     const int N = a.N, L = a.L, H = a.H;
     const int i0 = 2 * pair, i1 = i0 + 1;
@@ -290,7 +289,7 @@ __device__ void g_rows_inv(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, 
 // With upd, first x += alpha p and in -= alpha q on those rows (accumulating (in, in)).
 // d = 1: a single row.
 template <typename T, int VPT>
-__device__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, T* in, int ld, int i0, bool valid,
+__device__ __forceinline__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, T* in, int ld, int i0, bool valid,
                            int tid, int nthr, bool upd, T alpha, T& rr) {
     const int N = a.N, L = a.L;
     const bool two = (a.d == 2) && (i0 + 1 < N);
@@ -371,7 +370,7 @@ __device__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, 
 
 // after each group's forward row FFT: spec[k][ibase + 2g (+1)] = half spectra of the pair's rows
 template <typename T>
-__device__ void wg_write_spec(const PinvArgs<T>& a, const cplx<T>* cbase, int ibase, int gpb) {
+__device__ __forceinline__ void wg_write_spec(const PinvArgs<T>& a, const cplx<T>* cbase, int ibase, int gpb) {
     const int N = a.N, L = a.L, H = a.H, LP = lds_len(L);
     for (int idx = threadIdx.x; idx < H * gpb; idx += blockDim.x) {
         const int k = idx / gpb, g = idx - k * gpb;
@@ -389,7 +388,7 @@ __device__ void wg_write_spec(const PinvArgs<T>& a, const cplx<T>* cbase, int ib
 // after each group's sine-transform FFT (c[k+1] = -2i DST(row 2g) + 2 DST(row 2g+1)):
 // out[k][ibase + 2g (+1)] = DST of the pair's rows at k
 template <typename T>
-__device__ void wg_write_T(const PinvArgs<T>& a, const cplx<T>* cbase, T* out, int ibase, int gpb) {
+__device__ __forceinline__ void wg_write_T(const PinvArgs<T>& a, const cplx<T>* cbase, T* out, int ibase, int gpb) {
     const int N = a.N, LP = lds_len(a.L);
     for (int idx = threadIdx.x; idx < N * gpb; idx += blockDim.x) {
         const int k = idx / gpb, g = idx - k * gpb;
@@ -405,7 +404,7 @@ __device__ void wg_write_T(const PinvArgs<T>& a, const cplx<T>* cbase, T* out, i
 // before the inverse row FFT: group g's sequence = Y0 + i Y1 over the full length, from the half
 // spectra Y0, Y1 of its rows (Hermitian completion for k > L/2)
 template <typename T>
-__device__ void wg_load_spec(const PinvArgs<T>& a, cplx<T>* cbase, int ibase, int gpb) {
+__device__ __forceinline__ void wg_load_spec(const PinvArgs<T>& a, cplx<T>* cbase, int ibase, int gpb) {
     const int N = a.N, L = a.L, H = a.H, LP = lds_len(L);
     for (int idx = threadIdx.x; idx < H * gpb; idx += blockDim.x) {
         const int k = idx / gpb, g = idx - k * gpb;
@@ -424,7 +423,7 @@ __device__ void wg_load_spec(const PinvArgs<T>& a, cplx<T>* cbase, int ibase, in
 
 // pass A of z = M^{-1} r without update: DST of rows of r -> t1 (transposed)
 template <typename T, int VPT>
-__device__ void wg_pass_A(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, const cplx<T>* tw, int ibase, int grp,
+__device__ __forceinline__ void wg_pass_A(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, const cplx<T>* tw, int ibase, int grp,
                           int gpb, int tid, int nthr) {
     const int i0 = ibase + 2 * grp;
     T dummy = T(0);
@@ -438,21 +437,25 @@ __device__ void wg_pass_A(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, cons
 // (r, z) = (r, M^{-1} r) = scale * sum Y^2/(sigma + c tau) is accumulated in rz.  tau is stored
 // [k2][k1], so the eigenvalues for rows k0, k0 + 1 are two contiguous rows.
 template <typename T, int VPT>
-__device__ void wg_pass_B(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, const cplx<T>* tw, int kbase, int grp,
+__device__ __forceinline__ void wg_pass_B(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, const cplx<T>* tw, int kbase, int grp,
                           int gpb, T sig, T cc, T scale, int tid, int nthr, T& rz) {
     const int N = a.N;
     const int k0 = kbase + 2 * grp;
     const bool valid = k0 < N;
     const bool two = k0 + 1 < N;
+    constexpr bool PREF = VPT <= 8;  // prefetch the epilogue operands before the transform
     T tv0[VPT], tv1[VPT];
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) {
+    auto load_tau = [&](int u) {
         const int k1 = tid + u * nthr;
         tv0[u] = tv1[u] = T(1);
         if (valid && k1 < N) {
             tv0[u] = a.tau[(long long)k0 * N + k1];
             if (two) tv1[u] = a.tau[(long long)(k0 + 1) * N + k1];
         }
+    };
+    if constexpr (PREF) {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) load_tau(u);
     }
     T dummy = T(0);
     g_dst_load<T, VPT>(a, c, tw, a.t1, a.ns, k0, valid, tid, nthr, false, T(0), dummy);
@@ -461,6 +464,7 @@ __device__ void wg_pass_B(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, cons
     for (int u = 0; u < VPT; ++u) {
         const int k1 = tid + u * nthr;
         hv0[u] = hv1[u] = T(0);
+        if constexpr (!PREF) load_tau(u);
         if (valid && k1 < N) {
             const cplx<T> C = c[lx(k1 + 1)];
             const T y0 = T(-0.5) * C.y, y1 = T(0.5) * C.x;
@@ -494,15 +498,15 @@ __device__ void wg_pass_B(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, cons
 // pass D of z = M^{-1} r on rows (i0, i1) of t2 (z rows), then p = z + beta p, (p, dg p), and the
 // forward row transform of the new p rows into the half spectra.
 template <typename T, int VPT>
-__device__ void wg_pass_DF(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, const cplx<T>* tw, int ibase, int grp,
+__device__ __forceinline__ void wg_pass_DF(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, const cplx<T>* tw, int ibase, int grp,
                            int gpb, T beta, const T* dg, int tid, int nthr, T& pdp) {
     const int N = a.N, L = a.L;
     const int i0 = ibase + 2 * grp;
     const bool valid = i0 < N;
     const bool two = i0 + 1 < N;
+    constexpr bool PREF = VPT <= 8;  // prefetch the epilogue operands before the transform
     T pold0[VPT], pold1[VPT], d0[VPT], d1[VPT];
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) {
+    auto load_pd = [&](int u) {
         const int m = tid + u * nthr;
         pold0[u] = pold1[u] = d0[u] = d1[u] = T(0);
         if (valid && m < N) {
@@ -516,6 +520,10 @@ __device__ void wg_pass_DF(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, con
                 if (two) d1[u] = dg[o0 + N];
             }
         }
+    };
+    if constexpr (PREF) {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) load_pd(u);
     }
     T dummy = T(0);
     g_dst_load<T, VPT>(a, c, tw, a.t2, a.ns, i0, valid, tid, nthr, false, T(0), dummy);
@@ -524,6 +532,7 @@ __device__ void wg_pass_DF(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, con
     for (int u = 0; u < VPT; ++u) {
         const int m = tid + u * nthr;
         pn0[u] = pn1[u] = T(0);
+        if constexpr (!PREF) load_pd(u);
         if (valid && m < N) {
             const cplx<T> C = c[lx(m + 1)];
             pn0[u] = T(-0.5) * C.y + beta * pold0[u];
@@ -546,7 +555,7 @@ __device__ void wg_pass_DF(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, con
 // column pass of B p with (p, B p) = sum |V|^2 lambda/L^2 over the full spectrum (the half spectrum
 // counted twice except k2 = 0 and L/2)
 template <typename T, int VPT>
-__device__ void g_cols_pbp(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, int k2, bool valid, int tid, int nthr,
+__device__ __forceinline__ void g_cols_pbp(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, int k2, bool valid, int tid, int nthr,
                            T& pbp) {
     const int N = a.N, L = a.L;
     cplx<T>* row = a.spec + (long long)k2 * a.ns;
@@ -585,15 +594,15 @@ __device__ void g_cols_pbp(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, 
 // inverse row transform -> u = B p rows; q = dg p + c u; r -= alpha q; x += alpha p; (r, r);
 // then pass A (DST of the new r rows into t1)
 template <typename T, int VPT>
-__device__ void wg_pass_IUA(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, const cplx<T>* tw, int ibase, int grp,
+__device__ __forceinline__ void wg_pass_IUA(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, const cplx<T>* tw, int ibase, int grp,
                             int gpb, const T* dg, T cc, T alpha, int tid, int nthr, T& rr) {
     const int N = a.N, L = a.L;
     const int i0 = ibase + 2 * grp;
     const bool valid = i0 < N;
     const bool two = i0 + 1 < N;
+    constexpr bool PREF = VPT <= 8;  // prefetch the epilogue operands before the transform
     T p0[VPT], p1[VPT], d0[VPT], d1[VPT], r0[VPT], r1[VPT], x0[VPT], x1[VPT];
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) {
+    auto load_prx = [&](int u) {
         const int m = tid + u * nthr;
         p0[u] = p1[u] = d0[u] = d1[u] = r0[u] = r1[u] = x0[u] = x1[u] = T(0);
         if (valid && m < N) {
@@ -609,6 +618,10 @@ __device__ void wg_pass_IUA(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, co
                 if (dg) d1[u] = dg[o0 + N];
             }
         }
+    };
+    if constexpr (PREF) {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) load_prx(u);
     }
     wg_load_spec(a, cbase, ibase, gpb);
     __syncthreads();
@@ -616,6 +629,7 @@ __device__ void wg_pass_IUA(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, co
 #pragma unroll
     for (int u = 0; u < VPT; ++u) {
         const int m = tid + u * nthr;
+        if constexpr (!PREF) load_prx(u);
         const cplx<T> uu = c[lx(m)];
         if (valid && m < N) {
             const T q0 = d0[u] * p0[u] + cc * uu.x;
@@ -662,21 +676,28 @@ __device__ void wg_pass_IUA(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, co
 // ---------------------------------------------------------------------------
 // segment kernel: steps [sa, sb)
 // ---------------------------------------------------------------------------
-template <typename T, int VPT, int BS>
-__global__ __launch_bounds__(BS) void pinv_segment(PinvArgs<T> a, int sa, int sb) {
+// twiddles live in LDS beside the sequences unless that exceeds the 160 KB of a CU (FP64, L = 8192)
+template <typename T>
+__host__ __device__ constexpr bool tw_in_lds(int vpt) { return !(vpt == 32 && sizeof(T) == 8); }
+
+constexpr int kSegBlock = 256;  // workgroup size of the 2D segment kernel (1D: one transform group)
+
+template <typename T, int VPT, bool TAU2>
+__global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> a, int sa, int sb) {
     extern __shared__ unsigned char smem_raw[];
-    __shared__ double red[BS / 64];
+    __shared__ double red[kSegBlock / 64];
     __shared__ double tot[kNPart];
+    constexpr bool TWL = tw_in_lds<T>(VPT);
     const int nthr = a.L / VPT;             // threads per transform group
     const int gpb = blockDim.x / nthr;      // groups per workgroup (1 for d = 1)
     const int grp = threadIdx.x / nthr;
     const int tid = threadIdx.x - grp * nthr;
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-    const int twn = a.tw_lds ? a.L : 0;  // twiddles first (when in LDS), then the sequences
-    cplx<T>* cbase = lds + twn;                              // the groups' sequences
+    const int twn = TWL ? a.L : 0;  // twiddles first (when in LDS), then the sequences
+    cplx<T>* cbase = lds + twn;     // the groups' sequences
     cplx<T>* c = cbase + (size_t)grp * lds_len(a.L);
     for (int k = threadIdx.x; k < twn; k += blockDim.x) lds[k] = a.tw[k];
-    const cplx<T>* twl = a.tw_lds ? lds : a.tw;
+    const cplx<T>* twl = TWL ? lds : a.tw;
     __syncthreads();
     const int NG = gridDim.x * gpb;         // groups in the grid
     const int gg = blockIdx.x * gpb + grp;  // this group's index
@@ -686,7 +707,6 @@ __global__ __launch_bounds__(BS) void pinv_segment(PinvArgs<T> a, int sa, int sb
     const long long Nd = a.Nd;
     const int M = a.M;
     const bool two_d = (a.d == 2);
-    const bool tau2 = a.use_tau && two_d;
     const int NP = two_d ? (N + 1) / 2 : 1;  // row pairs (2D)
     const int NR = (NP + NG - 1) / NG;       // rounds over row pairs
     const int NC = (a.H + NG - 1) / NG;      // rounds over spectral rows
@@ -843,7 +863,7 @@ __global__ __launch_bounds__(BS) void pinv_segment(PinvArgs<T> a, int sa, int sb
         if (rrt <= a.tol2 * bbt) continue;  // the warm start already meets the tolerance
 
         // ---------------- preconditioned CG ----------------
-        if (tau2) {
+        if constexpr (TAU2) {
             // z0 = M^{-1} r0: pass A, pass B (with (r, z))
             for (int rd = 0; rd < NR; ++rd) {
                 const int ibase = 2 * (rd * NG + blockIdx.x * gpb);
@@ -904,7 +924,7 @@ __global__ __launch_bounds__(BS) void pinv_segment(PinvArgs<T> a, int sa, int sb
             }
             total_it += it;
             continue;
-        }
+        } else {
         prec_A(false, T(0));
         double rz = tot[SL_RZ];
         T beta = T(0);
@@ -986,6 +1006,7 @@ __global__ __launch_bounds__(BS) void pinv_segment(PinvArgs<T> a, int sa, int sb
             rz = rz_new;
         }
         total_it += it;
+        }
     }
     // the segment's last step: y_{sb-1} = x (same pointwise ownership as phase E)
     for (long long j = gtid; j < Nd; j += gthreads) a.y[(long long)(sb - 1) * Nd + j] = a.x[j];
@@ -1011,7 +1032,6 @@ struct PersistentWork {
 static int spec_stride(int N) { return (N + 15) & ~15; }
 
 static int g_blocks_override = -1;
-static int g_bs_override = -1;
 
 template <typename T>
 static void ensure_work(Problem& P, PersistentWork<T>& W) {
@@ -1030,7 +1050,7 @@ static void ensure_work(Problem& P, PersistentWork<T>& W) {
     TSFDE_HIP(hipMemset(W.buf, 0, sizeof(T) * (size_t)(7 + kHB) * P.Nd));
 }
 
-template <typename T, int VPT, int BS>
+template <typename T, int VPT, bool TAU2>
 static void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T* z, T* y, double inner_tol,
                             int inner_maxit, bool last_block, int extrap, hipStream_t st) {
     PinvArgs<T> a{};
@@ -1075,14 +1095,10 @@ static void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, c
     a.bar = W.bar;
     a.iters = W.iters;
     const int nthr = P.L / VPT;
-    const int block = (P.d == 2) ? BS : nthr;
+    const int block = (P.d == 2) ? kSegBlock : nthr;
     const int gpb = block / nthr;
-    size_t lds = sizeof(cplx<T>) * (P.L + (size_t)gpb * lds_len(P.L));
-    a.tw_lds = 1;
-    if (lds > 160 * 1024) {
-        a.tw_lds = 0;
-        lds = sizeof(cplx<T>) * (size_t)gpb * lds_len(P.L);
-    }
+    const size_t lds = sizeof(cplx<T>) * ((tw_in_lds<T>(VPT) ? P.L : 0) + (size_t)gpb * lds_len(P.L));
+    if (lds > 160 * 1024) throw HipError{hipErrorInvalidConfiguration, "persistent P^-1 LDS size"};
     // 2D: enough groups that the L/2+1 spectral rows take two rounds
     int grid = 1;
     if (P.d == 2) {
@@ -1090,7 +1106,7 @@ static void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, c
         if (g_blocks_override > 0) grid = g_blocks_override;
     }
     int per_cu = 0;
-    TSFDE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pinv_segment<T, VPT, BS>, block, lds));
+    TSFDE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pinv_segment<T, VPT, TAU2>, block, lds));
     int dev = 0, ncu = 0;
     TSFDE_HIP(hipGetDevice(&dev));
     TSFDE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1108,7 +1124,7 @@ static void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, c
         }
         launch_fill(reinterpret_cast<float*>(W.bar), 1, 0.0f, st);  // zero the barrier counter
         void* args[] = {&a, &sa_, &sb_};
-        TSFDE_HIP(hipLaunchCooperativeKernel((void*)pinv_segment<T, VPT, BS>, dim3(grid), dim3(block), args, lds, st));
+        TSFDE_HIP(hipLaunchCooperativeKernel((void*)pinv_segment<T, VPT, TAU2>, dim3(grid), dim3(block), args, lds, st));
     }
 }
 
@@ -1125,16 +1141,17 @@ long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T*
     ensure_work(P, W);
     const int L = P.L;
     const int vpt = (L <= 2048) ? 8 : (L == 4096 ? 16 : 32);
-    const int bs = (g_bs_override == 512 || g_bs_override == 1024) ? g_bs_override : 256;
 #define TSFDE_SEG(V, B) launch_segments<T, V, B>(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, st)
+    const bool tau2 = (P.d == 2) && P.tau_ok;
     if (vpt == 8) {
-        if (bs == 1024) TSFDE_SEG(8, 1024);
-        else if (bs == 512) TSFDE_SEG(8, 512);
-        else TSFDE_SEG(8, 256);
+        if (tau2) TSFDE_SEG(8, true);
+        else TSFDE_SEG(8, false);
     } else if (vpt == 16) {
-        TSFDE_SEG(16, 256);
+        if (tau2) TSFDE_SEG(16, true);
+        else TSFDE_SEG(16, false);
     } else {
-        TSFDE_SEG(32, 256);
+        if (tau2) TSFDE_SEG(32, true);
+        else TSFDE_SEG(32, false);
     }
 #undef TSFDE_SEG
     long long it = 0;
@@ -1154,7 +1171,6 @@ void pinv_persistent_free(void* wptr) {
 }
 
 void set_persistent_blocks(int g) { g_blocks_override = g; }
-void set_persistent_block_size(int bs) { g_bs_override = bs; }
 
 template long long pinv_persistent_run<double>(Problem&, const Dev<double>&, void*&, const double*, double*, double,
                                                int, bool, int, hipStream_t);

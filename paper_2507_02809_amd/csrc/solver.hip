@@ -115,7 +115,6 @@ static long long pinv_impl(Problem& P, const T* z, T* y, const Opts& o, hipStrea
     // TSFDE_EXTRAP=0 disables the linear-in-time warm start
     if (env_int("TSFDE_PINV", 1) != 0 && persistent_supported(P)) {
         set_persistent_blocks(env_int("TSFDE_PINV_BLOCKS", -1));
-        set_persistent_block_size(env_int("TSFDE_PINV_BS", 256));
         return pinv_persistent_run<T>(P, dev<T>(P), pwork<T>(P), z, y, o.inner_tol, o.inner_maxit, last_block,
                                       env_int("TSFDE_EXTRAP", 1), st);
     }
