@@ -293,11 +293,12 @@ __device__ __forceinline__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, con
                            int tid, int nthr, bool upd, T alpha, T& rr) {
     const int N = a.N, L = a.L;
     const bool two = (a.d == 2) && (i0 + 1 < N);
-    T v0[VPT], v1[VPT];
+    constexpr int VH = VPT / 2;  // the sine transform has L = 2(N + 1), so m < N < L/2 = VH * nthr
+    T v0[VH], v1[VH];
     if (upd) {
-        T q0[VPT], q1[VPT], x0[VPT], x1[VPT], pp0[VPT], pp1[VPT];
+        T q0[VH], q1[VH], x0[VH], x1[VH], pp0[VH], pp1[VH];
 #pragma unroll
-        for (int u = 0; u < VPT; ++u) {
+        for (int u = 0; u < VH; ++u) {
             const int m = tid + u * nthr;
             v0[u] = v1[u] = q0[u] = q1[u] = x0[u] = x1[u] = pp0[u] = pp1[u] = T(0);
             if (valid && m < N) {
@@ -315,7 +316,7 @@ __device__ __forceinline__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, con
             }
         }
 #pragma unroll
-        for (int u = 0; u < VPT; ++u) {
+        for (int u = 0; u < VH; ++u) {
             const int m = tid + u * nthr;
             v0[u] -= alpha * q0[u];
             v1[u] -= alpha * q1[u];
@@ -332,7 +333,7 @@ __device__ __forceinline__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, con
         }
     } else {
 #pragma unroll
-        for (int u = 0; u < VPT; ++u) {
+        for (int u = 0; u < VH; ++u) {
             const int m = tid + u * nthr;
             v0[u] = v1[u] = T(0);
             if (valid && m < N) {
@@ -343,7 +344,7 @@ __device__ __forceinline__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, con
         }
     }
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) {
+    for (int u = 0; u < VH; ++u) {
         const int m = tid + u * nthr;
         if (m < N) {
             c[lx(m + 1)] = {v0[u], v1[u]};
@@ -421,17 +422,6 @@ __device__ __forceinline__ void wg_load_spec(const PinvArgs<T>& a, cplx<T>* cbas
     }
 }
 
-// pass A of z = M^{-1} r without update: DST of rows of r -> t1 (transposed)
-template <typename T, int VPT>
-__device__ __forceinline__ void wg_pass_A(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, const cplx<T>* tw, int ibase, int grp,
-                          int gpb, int tid, int nthr) {
-    const int i0 = ibase + 2 * grp;
-    T dummy = T(0);
-    g_dst_load<T, VPT>(a, c, tw, a.r, a.N, i0, i0 < a.N, tid, nthr, false, T(0), dummy);
-    wg_write_T(a, cbase, a.t1, ibase, gpb);
-    __syncthreads();
-}
-
 // pass B: rows k0 = kbase + 2g (+1) of t1 hold (S r)^T rows; a DST over i gives Y = S r S (up to
 // scale), Y is scaled by scale/(sigma + c tau) and transformed again into t2 = S Yhat (transposed).
 // (r, z) = (r, M^{-1} r) = scale * sum Y^2/(sigma + c tau) is accumulated in rz.  tau is stored
@@ -444,7 +434,8 @@ __device__ __forceinline__ void wg_pass_B(const PinvArgs<T>& a, cplx<T>* cbase, 
     const bool valid = k0 < N;
     const bool two = k0 + 1 < N;
     constexpr bool PREF = VPT <= 8;  // prefetch the epilogue operands before the transform
-    T tv0[VPT], tv1[VPT];
+    constexpr int VH = VPT / 2;      // k1 < N < L/2 = VH * nthr
+    T tv0[VH], tv1[VH];
     auto load_tau = [&](int u) {
         const int k1 = tid + u * nthr;
         tv0[u] = tv1[u] = T(1);
@@ -455,13 +446,13 @@ __device__ __forceinline__ void wg_pass_B(const PinvArgs<T>& a, cplx<T>* cbase, 
     };
     if constexpr (PREF) {
 #pragma unroll
-        for (int u = 0; u < VPT; ++u) load_tau(u);
+        for (int u = 0; u < VH; ++u) load_tau(u);
     }
     T dummy = T(0);
     g_dst_load<T, VPT>(a, c, tw, a.t1, a.ns, k0, valid, tid, nthr, false, T(0), dummy);
-    T hv0[VPT], hv1[VPT];
+    T hv0[VH], hv1[VH];
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) {
+    for (int u = 0; u < VH; ++u) {
         const int k1 = tid + u * nthr;
         hv0[u] = hv1[u] = T(0);
         if constexpr (!PREF) load_tau(u);
@@ -478,7 +469,7 @@ __device__ __forceinline__ void wg_pass_B(const PinvArgs<T>& a, cplx<T>* cbase, 
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) {
+    for (int u = 0; u < VH; ++u) {
         const int k1 = tid + u * nthr;
         if (k1 < N) {
             c[lx(k1 + 1)] = {hv0[u], hv1[u]};
@@ -505,7 +496,8 @@ __device__ __forceinline__ void wg_pass_DF(const PinvArgs<T>& a, cplx<T>* cbase,
     const bool valid = i0 < N;
     const bool two = i0 + 1 < N;
     constexpr bool PREF = VPT <= 8;  // prefetch the epilogue operands before the transform
-    T pold0[VPT], pold1[VPT], d0[VPT], d1[VPT];
+    constexpr int VH = VPT / 2;      // m < N < L/2 = VH * nthr
+    T pold0[VH], pold1[VH], d0[VH], d1[VH];
     auto load_pd = [&](int u) {
         const int m = tid + u * nthr;
         pold0[u] = pold1[u] = d0[u] = d1[u] = T(0);
@@ -523,13 +515,13 @@ __device__ __forceinline__ void wg_pass_DF(const PinvArgs<T>& a, cplx<T>* cbase,
     };
     if constexpr (PREF) {
 #pragma unroll
-        for (int u = 0; u < VPT; ++u) load_pd(u);
+        for (int u = 0; u < VH; ++u) load_pd(u);
     }
     T dummy = T(0);
     g_dst_load<T, VPT>(a, c, tw, a.t2, a.ns, i0, valid, tid, nthr, false, T(0), dummy);
-    T pn0[VPT], pn1[VPT];
+    T pn0[VH], pn1[VH];
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) {
+    for (int u = 0; u < VH; ++u) {
         const int m = tid + u * nthr;
         pn0[u] = pn1[u] = T(0);
         if constexpr (!PREF) load_pd(u);
@@ -545,7 +537,9 @@ __device__ __forceinline__ void wg_pass_DF(const PinvArgs<T>& a, cplx<T>* cbase,
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) c[lx(tid + u * nthr)] = {pn0[u], pn1[u]};
+    for (int u = 0; u < VH; ++u) c[lx(tid + u * nthr)] = {pn0[u], pn1[u]};
+#pragma unroll
+    for (int u = VH; u < VPT; ++u) c[lx(tid + u * nthr)] = {T(0), T(0)};
     __syncthreads();
     fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
     wg_write_spec(a, cbase, ibase, gpb);
@@ -560,11 +554,13 @@ __device__ __forceinline__ void g_cols_pbp(const PinvArgs<T>& a, cplx<T>* c, con
     const int N = a.N, L = a.L;
     cplx<T>* row = a.spec + (long long)k2 * a.ns;
     const T* sy = a.sym + (long long)k2 * L;
+    constexpr int VH = VPT / 2;  // i < N < L/2 = VH * nthr
     T sv[VPT];
 #pragma unroll
     for (int u = 0; u < VPT; ++u) {
         const int i = tid + u * nthr;
-        c[lx(i)] = (valid && i < N) ? row[i] : cplx<T>{T(0), T(0)};
+        if (u < VH) c[lx(i)] = (valid && i < N) ? row[i] : cplx<T>{T(0), T(0)};
+        else c[lx(i)] = {T(0), T(0)};
         sv[u] = valid ? sy[i] : T(0);
     }
     __syncthreads();
@@ -583,7 +579,7 @@ __device__ __forceinline__ void g_cols_pbp(const PinvArgs<T>& a, cplx<T>* c, con
     fft_lds<T, VPT, true>(c, L, tw, tid, nthr);
     if (valid) {
 #pragma unroll
-        for (int u = 0; u < VPT; ++u) {
+        for (int u = 0; u < VH; ++u) {
             const int i = tid + u * nthr;
             if (i < N) row[i] = c[lx(i)];
         }
@@ -601,7 +597,8 @@ __device__ __forceinline__ void wg_pass_IUA(const PinvArgs<T>& a, cplx<T>* cbase
     const bool valid = i0 < N;
     const bool two = i0 + 1 < N;
     constexpr bool PREF = VPT <= 8;  // prefetch the epilogue operands before the transform
-    T p0[VPT], p1[VPT], d0[VPT], d1[VPT], r0[VPT], r1[VPT], x0[VPT], x1[VPT];
+    constexpr int VH = VPT / 2;      // m < N < L/2 = VH * nthr
+    T p0[VH], p1[VH], d0[VH], d1[VH], r0[VH], r1[VH], x0[VH], x1[VH];
     auto load_prx = [&](int u) {
         const int m = tid + u * nthr;
         p0[u] = p1[u] = d0[u] = d1[u] = r0[u] = r1[u] = x0[u] = x1[u] = T(0);
@@ -621,13 +618,13 @@ __device__ __forceinline__ void wg_pass_IUA(const PinvArgs<T>& a, cplx<T>* cbase
     };
     if constexpr (PREF) {
 #pragma unroll
-        for (int u = 0; u < VPT; ++u) load_prx(u);
+        for (int u = 0; u < VH; ++u) load_prx(u);
     }
     wg_load_spec(a, cbase, ibase, gpb);
     __syncthreads();
     fft_lds<T, VPT, true>(c, L, tw, tid, nthr);
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) {
+    for (int u = 0; u < VH; ++u) {
         const int m = tid + u * nthr;
         if constexpr (!PREF) load_prx(u);
         const cplx<T> uu = c[lx(m)];
@@ -656,7 +653,7 @@ __device__ __forceinline__ void wg_pass_IUA(const PinvArgs<T>& a, cplx<T>* cbase
     __syncthreads();
     // pass A on the updated rows: odd extension, FFT, DST rows -> t1 (transposed)
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) {
+    for (int u = 0; u < VH; ++u) {
         const int m = tid + u * nthr;
         if (m < N) {
             c[lx(m + 1)] = {r0[u], r1[u]};
@@ -682,12 +679,18 @@ __host__ __device__ constexpr bool tw_in_lds(int vpt) { return !(vpt == 32 && si
 
 constexpr int kSegBlock = 256;  // workgroup size of the 2D segment kernel (1D: one transform group)
 
-template <typename T, int VPT, bool TAU2>
+// kernel variants: the 1D problem, the 2D problem with the diagonal preconditioner, and the 2D
+// problem with the sine-transform (tau) preconditioner and its fused CG phases
+enum SegMode : int { SEG_1D = 0, SEG_2D_DIAG = 1, SEG_2D_TAU = 2 };
+
+template <typename T, int VPT, int MODE>
 __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> a, int sa, int sb) {
     extern __shared__ unsigned char smem_raw[];
     __shared__ double red[kSegBlock / 64];
     __shared__ double tot[kNPart];
     constexpr bool TWL = tw_in_lds<T>(VPT);
+    constexpr bool TAU2 = (MODE == SEG_2D_TAU);
+    constexpr bool two_d = (MODE != SEG_1D);
     const int nthr = a.L / VPT;             // threads per transform group
     const int gpb = blockDim.x / nthr;      // groups per workgroup (1 for d = 1)
     const int grp = threadIdx.x / nthr;
@@ -706,7 +709,6 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> a, int sa,
     const int N = a.N;
     const long long Nd = a.Nd;
     const int M = a.M;
-    const bool two_d = (a.d == 2);
     const int NP = two_d ? (N + 1) / 2 : 1;  // row pairs (2D)
     const int NR = (NP + NG - 1) / NG;       // rounds over row pairs
     const int NC = (a.H + NG - 1) / NG;      // rounds over spectral rows
@@ -792,57 +794,95 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> a, int sa,
         };
 
         // ---------------- E: finish step s-1, history, rhs, warm start, r0 ----------------
+        // For point j: y_{s-1} = x is stored, B y_{s-1} is recovered from the residual identity, the
+        // history term and the right-hand side of block row s are formed, the warm start x0 (linear
+        // extrapolation in time) and r0 = rhs - A_s x0 are stored; returns r0 and adds to (r, r), (b, b).
+        const int nnear = s - sa;  // near-history terms m in [sa, s)
+        auto e_point = [&](long long j, T& rr, T& bb) -> T {
+            // all loads first
+            const long long o = (long long)s * Nd + j;
+            const T xv = (s > 0) ? a.x[j] : T(0);
+            const T rhs_o = (s > 0) ? a.rhs[j] : T(0);
+            const T r_o = (s > 0) ? a.r[j] : T(0);
+            const T dgp = (s > 0) ? a.dg[(long long)(s - 1) * Nd + j] : T(0);
+            const bool ext = (s >= 2 && !lastrow && a.extrap);
+            const T bxb = (s >= 2 && !lastrow) ? a.bxb[j] : T(0);
+            const T ym2 = ext ? a.y[(long long)(s - 2) * Nd + j] : T(0);
+            const T zo = lastrow ? a.z[(long long)M * Nd + j] : a.z[o];
+            const T g2o = lastrow ? a.g2[(long long)(M - 1) * Nd + j] : a.g2[o];
+            const T g1o = lastrow ? T(0) : a.g1[o];
+            const T dgo = dg ? dg[j] : T(0);
+            const T ha = lastrow ? T(0) : a.hacc[(long long)(s - sa) * Nd + j];
+            T yv[kHB];
+#pragma unroll
+            for (int i = 0; i < kHB; ++i) {
+                // y_m for m = sa + i < s - 1 (y_{s-1} is xv)
+                yv[i] = (!lastrow && i + 1 < nnear) ? a.y[(long long)(sa + i) * Nd + j] : T(0);
+            }
+            // compute
+            const T yprev = xv;
+            const T bxprev = (s > 0) ? (rhs_o - r_o - dgp * xv) / a.ct : T(0);  // B y_{s-1}
+            T rhs, x0 = T(0), bx0 = T(0);
+            if (lastrow) {
+                rhs = (zo - yprev) / (a.cf * g2o);
+            } else {
+                T h = ha;
+#pragma unroll
+                for (int i = 0; i < kHB; ++i)
+                    if (i + 1 < nnear) h += e[s - sa - i] * yv[i];
+                if (nnear >= 1) h += e[1] * yprev;
+                rhs = (zo - g1o * h) / g2o;
+                if (s >= 1) {
+                    x0 = ext ? T(2) * yprev - ym2 : yprev;
+                    bx0 = ext ? T(2) * bxprev - bxb : bxprev;
+                }
+            }
+            const T rv = rhs - (dgo * x0 + cc * bx0);
+            // stores
+            if (s > 0) a.y[(long long)(s - 1) * Nd + j] = xv;
+            if (s >= 1 && !lastrow) a.bxb[j] = bxprev;  // B y_{s-1} is "B y_{s-2}" next step
+            a.rhs[j] = rhs;
+            a.x[j] = x0;
+            a.r[j] = rv;
+            rr += rv * rv;
+            bb += rhs * rhs;
+            return rv;
+        };
         {
             T rr = T(0), bb = T(0);
-            const int nnear = s - sa;  // near-history terms m in [sa, s)
-            for (long long j = gtid; j < Nd; j += gthreads) {
-                // all loads first
-                const long long o = (long long)s * Nd + j;
-                const T xv = (s > 0) ? a.x[j] : T(0);
-                const T rhs_o = (s > 0) ? a.rhs[j] : T(0);
-                const T r_o = (s > 0) ? a.r[j] : T(0);
-                const T dgp = (s > 0) ? a.dg[(long long)(s - 1) * Nd + j] : T(0);
-                const bool ext = (s >= 2 && !lastrow && a.extrap);
-                const T bxb = (s >= 2 && !lastrow) ? a.bxb[j] : T(0);
-                const T ym2 = ext ? a.y[(long long)(s - 2) * Nd + j] : T(0);
-                const T zo = lastrow ? a.z[(long long)M * Nd + j] : a.z[o];
-                const T g2o = lastrow ? a.g2[(long long)(M - 1) * Nd + j] : a.g2[o];
-                const T g1o = lastrow ? T(0) : a.g1[o];
-                const T dgo = dg ? dg[j] : T(0);
-                const T ha = lastrow ? T(0) : a.hacc[(long long)(s - sa) * Nd + j];
-                T yv[kHB];
-#pragma unroll
-                for (int i = 0; i < kHB; ++i) {
-                    // y_m for m = sa + i < s - 1 (y_{s-1} is xv)
-                    yv[i] = (!lastrow && i + 1 < nnear) ? a.y[(long long)(sa + i) * Nd + j] : T(0);
-                }
-                // compute
-                const T yprev = xv;
-                const T bxprev = (s > 0) ? (rhs_o - r_o - dgp * xv) / a.ct : T(0);  // B y_{s-1}
-                T rhs, x0 = T(0), bx0 = T(0);
-                if (lastrow) {
-                    rhs = (zo - yprev) / (a.cf * g2o);
-                } else {
-                    T h = ha;
-#pragma unroll
-                    for (int i = 0; i < kHB; ++i)
-                        if (i + 1 < nnear) h += e[s - sa - i] * yv[i];
-                    if (nnear >= 1) h += e[1] * yprev;
-                    rhs = (zo - g1o * h) / g2o;
-                    if (s >= 1) {
-                        x0 = ext ? T(2) * yprev - ym2 : yprev;
-                        bx0 = ext ? T(2) * bxprev - bxb : bxprev;
+            if constexpr (TAU2) {
+                // row ownership (group: rows i0, i0 + 1), fused with pass A of z0 = M^{-1} r0: the new
+                // residual rows are sine-transformed into t1 right away
+                for (int rd = 0; rd < NR; ++rd) {
+                    const int ibase = 2 * (rd * NG + blockIdx.x * gpb);
+                    const int i0 = ibase + 2 * grp;
+                    const bool valid = i0 < N;
+                    const bool two = i0 + 1 < N;
+#pragma unroll 1
+                    for (int u = 0; u < VPT / 2; ++u) {  // m < N < L/2
+                        const int m = tid + u * nthr;
+                        if (m < N) {
+                            T r0 = T(0), r1 = T(0);
+                            if (valid) {
+                                const long long j0 = (long long)i0 * N + m;
+                                r0 = e_point(j0, rr, bb);
+                                if (two) r1 = e_point(j0 + N, rr, bb);
+                            }
+                            c[lx(m + 1)] = {r0, r1};
+                            c[lx(a.L - m - 1)] = {-r0, -r1};
+                        }
                     }
+                    if (tid == 0) {
+                        c[lx(0)] = {T(0), T(0)};
+                        c[lx(N + 1)] = {T(0), T(0)};
+                    }
+                    __syncthreads();
+                    fft_lds<T, VPT, false>(c, a.L, twl, tid, nthr);
+                    wg_write_T(a, cbase, a.t1, ibase, gpb);
+                    __syncthreads();
                 }
-                const T rv = rhs - (dgo * x0 + cc * bx0);
-                // stores
-                if (s > 0) a.y[(long long)(s - 1) * Nd + j] = xv;
-                if (s >= 1 && !lastrow) a.bxb[j] = bxprev;  // B y_{s-1} is "B y_{s-2}" next step
-                a.rhs[j] = rhs;
-                a.x[j] = x0;
-                a.r[j] = rv;
-                rr += rv * rv;
-                bb += rhs * rhs;
+            } else {
+                for (long long j = gtid; j < Nd; j += gthreads) (void)e_point(j, rr, bb);
             }
             put_partial(a.part, SL_RR, rr, red);
             put_partial(a.part, SL_BB, bb, red);
@@ -864,12 +904,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> a, int sa,
 
         // ---------------- preconditioned CG ----------------
         if constexpr (TAU2) {
-            // z0 = M^{-1} r0: pass A, pass B (with (r, z))
-            for (int rd = 0; rd < NR; ++rd) {
-                const int ibase = 2 * (rd * NG + blockIdx.x * gpb);
-                wg_pass_A<T, VPT>(a, cbase, c, twl, ibase, grp, gpb, tid, nthr);
-            }
-            grid_barrier(a.bar, epoch);
+            // z0 = M^{-1} r0: pass A ran with phase E; pass B (with (r, z))
             {
                 T rzl = T(0);
                 for (int rd = 0; rd < NR; ++rd) {
@@ -932,7 +967,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> a, int sa,
         while (true) {
             // q = A_s p with p = z + beta p ; (p, q)
             T pq = T(0);
-            if (two_d) {
+            if constexpr (two_d) {
                 for (int rd = 0; rd < NR; ++rd) {
                     const int pr = rd * NG + gg;
                     g_rows_fwd<T, VPT>(a, c, twl, pr, pr < NP, beta, tid, nthr);
@@ -1050,7 +1085,7 @@ static void ensure_work(Problem& P, PersistentWork<T>& W) {
     TSFDE_HIP(hipMemset(W.buf, 0, sizeof(T) * (size_t)(7 + kHB) * P.Nd));
 }
 
-template <typename T, int VPT, bool TAU2>
+template <typename T, int VPT, int MODE>
 static void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T* z, T* y, double inner_tol,
                             int inner_maxit, bool last_block, int extrap, hipStream_t st) {
     PinvArgs<T> a{};
@@ -1106,7 +1141,7 @@ static void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, c
         if (g_blocks_override > 0) grid = g_blocks_override;
     }
     int per_cu = 0;
-    TSFDE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pinv_segment<T, VPT, TAU2>, block, lds));
+    TSFDE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pinv_segment<T, VPT, MODE>, block, lds));
     int dev = 0, ncu = 0;
     TSFDE_HIP(hipGetDevice(&dev));
     TSFDE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1124,7 +1159,7 @@ static void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, c
         }
         launch_fill(reinterpret_cast<float*>(W.bar), 1, 0.0f, st);  // zero the barrier counter
         void* args[] = {&a, &sa_, &sb_};
-        TSFDE_HIP(hipLaunchCooperativeKernel((void*)pinv_segment<T, VPT, TAU2>, dim3(grid), dim3(block), args, lds, st));
+        TSFDE_HIP(hipLaunchCooperativeKernel((void*)pinv_segment<T, VPT, MODE>, dim3(grid), dim3(block), args, lds, st));
     }
 }
 
@@ -1142,17 +1177,17 @@ long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T*
     const int L = P.L;
     const int vpt = (L <= 2048) ? 8 : (L == 4096 ? 16 : 32);
 #define TSFDE_SEG(V, B) launch_segments<T, V, B>(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, st)
-    const bool tau2 = (P.d == 2) && P.tau_ok;
-    if (vpt == 8) {
-        if (tau2) TSFDE_SEG(8, true);
-        else TSFDE_SEG(8, false);
-    } else if (vpt == 16) {
-        if (tau2) TSFDE_SEG(16, true);
-        else TSFDE_SEG(16, false);
-    } else {
-        if (tau2) TSFDE_SEG(32, true);
-        else TSFDE_SEG(32, false);
-    }
+    const int mode = (P.d == 1) ? SEG_1D : (P.tau_ok ? SEG_2D_TAU : SEG_2D_DIAG);
+#define TSFDE_SEG_MODES(V)                                  \
+    do {                                                    \
+        if (mode == SEG_1D) TSFDE_SEG(V, SEG_1D);           \
+        else if (mode == SEG_2D_DIAG) TSFDE_SEG(V, SEG_2D_DIAG); \
+        else TSFDE_SEG(V, SEG_2D_TAU);                      \
+    } while (0)
+    if (vpt == 8) TSFDE_SEG_MODES(8);
+    else if (vpt == 16) TSFDE_SEG_MODES(16);
+    else TSFDE_SEG_MODES(32);
+#undef TSFDE_SEG_MODES
 #undef TSFDE_SEG
     long long it = 0;
     TSFDE_HIP(hipMemcpyAsync(&it, W.iters, sizeof(long long), hipMemcpyDeviceToHost, st));
