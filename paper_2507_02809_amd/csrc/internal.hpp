@@ -149,5 +149,6 @@ long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T*
 template <typename T>
 void pinv_persistent_free(void* wptr);
 void set_persistent_blocks(int g);
+void set_persistent_fixed_length(bool on);  // use the fixed-length 2D sine-transform kernels where available
 
 }  // namespace tsfde

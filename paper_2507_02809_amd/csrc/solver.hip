@@ -112,9 +112,11 @@ static long long pinv_launch(Problem& P, const T* z, T* y, const Opts& o, hipStr
 template <typename T>
 static long long pinv_impl(Problem& P, const T* z, T* y, const Opts& o, hipStream_t st, bool last_block) {
     // TSFDE_PINV=0 selects the multi-launch path; TSFDE_PINV_BLOCKS overrides the grid size;
+    // TSFDE_PINV_FIXED=0 keeps the 2D sine-transform path on its run-time-length kernel;
     // TSFDE_EXTRAP=0 disables the linear-in-time warm start
     if (env_int("TSFDE_PINV", 1) != 0 && persistent_supported(P)) {
         set_persistent_blocks(env_int("TSFDE_PINV_BLOCKS", -1));
+        set_persistent_fixed_length(env_int("TSFDE_PINV_FIXED", 1) != 0);
         return pinv_persistent_run<T>(P, dev<T>(P), pwork<T>(P), z, y, o.inner_tol, o.inner_maxit, last_block,
                                       env_int("TSFDE_EXTRAP", 1), st);
     }

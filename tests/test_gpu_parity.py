@@ -2,6 +2,8 @@
 inputs.  Solver parity is isolated from coefficient parity by handing the oracle's stencil to
 the library (create_problem_ex override); the library's own stencil is compared with the
 oracle's separately (tests/test_abi.py and test_library_stencil_used_by_problem below)."""
+import functools
+
 import numpy as np
 import pytest
 import scipy.linalg as sl
@@ -181,6 +183,29 @@ def test_apply_P_inv_zero_rhs_and_warm_start_exact(pinv_path):
     with gpu_problem(inp, p) as g:
         y = g.apply_P_inv(torch.zeros(p.n_tot, dtype=torch.float64, device=DEV))
         assert float(y.abs().max()) == 0.0
+
+
+@functools.lru_cache(maxsize=1)
+def _n127_case():
+    inp = inputs.small(2, 127, 6, beta=0.7, omega=1.3)
+    p = workloads.problem(inp, mu=np.zeros(inp.Nd))
+    zz = np.random.default_rng(19).standard_normal(p.n_tot)
+    return inp, p, zz, matfree.P_solve(p, zz, inner="cg", inner_tol=1e-13)
+
+
+@pytest.mark.parametrize("fixed", [True, False])
+def test_apply_P_inv_fixed_length_kernel_matches_oracle(pinv_path, monkeypatch, fixed):
+    """N = 127 (L = 256), where the 2D sine-transform path has a kernel compiled for that length;
+    it and the run-time-length kernel (TSFDE_PINV_FIXED=0) against the oracle's forward
+    substitution with CG inner solves, both to an inner tolerance far below the bound."""
+    pinv_path(True)
+    monkeypatch.setenv("TSFDE_PINV_FIXED", "1" if fixed else "0")
+    inp, p, zz, ref = _n127_case()
+    with gpu_problem(inp, p) as g:
+        y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=tsfde.default_opts(inner_tol=1e-13, inner_maxit=500))
+        y32 = g.apply_P_inv(torch.tensor(zz, device=DEV, dtype=torch.float32))
+    assert rel_err(y.cpu().numpy(), ref) <= 1e-9
+    assert rel_err(y32.cpu().double().numpy(), ref) <= 5e-4
 
 
 def test_apply_P_inv_full_size_c3_residual():
