@@ -92,30 +92,80 @@ __device__ __forceinline__ void grid_barrier(unsigned* ctr, unsigned& epoch) {
     }
 }
 
-// block-reduce v into this block's slot
-template <typename T>
-__device__ __forceinline__ void put_partial(double* part, int slot, T v, double* red) {
-    const double s = block_sum((double)v, red);
-    if (threadIdx.x == 0) part[blockIdx.x * kNPart + slot] = s;
+// Block-reduce K values at once into this block's slots: the shuffle trees of the K values are
+// interleaved so that their exchanges overlap.  red holds kSegBlock/64 * K doubles.  The order of
+// the additions is fixed (shuffle tree per wave, then the waves in order), so every block reduces
+// its values the same way on every run.
+template <int K, typename T>
+__device__ __forceinline__ void put_partials(double* part, const int (&slot)[K], const T (&val)[K], double* red) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nact = min(kWave, (int)blockDim.x - wid * kWave);  // active lanes of this wave
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = (double)val[k];
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        double o[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) o[k] = __shfl_down(v[k], off, kWave);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (lane + off < nact) v[k] += o[k];
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wid * K + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + kWave - 1) / kWave;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double r = 0.0;
+            for (int w = 0; w < nw; ++w) r += red[w * K + k];
+            part[blockIdx.x * kNPart + slot[k]] = r;
+        }
+    }
+    __syncthreads();
 }
 
-// After a barrier: wave 0 loads every block's slots (lane b reads block b), reduces them with the
-// same shuffle tree in every block and leaves the totals in tot[kNPart] (LDS) for all threads.
+template <typename T>
+__device__ __forceinline__ void put_partial(double* part, int slot, T v, double* red) {
+    const int sl[1] = {slot};
+    const T vv[1] = {v};
+    put_partials<1>(part, sl, vv, red);
+}
+
+// After a barrier: wave 0 loads every block's slots (lane b reads block b), reduces the slots in
+// MASK with the same shuffle tree in every block (the trees of the slots interleaved) and leaves
+// the totals in tot[] (LDS) for all threads.
+template <unsigned MASK = (1u << kNPart) - 1>
 __device__ __forceinline__ void gather_totals(const double* part, double* tot) {
     if (threadIdx.x < kWave) {
         const int lane = threadIdx.x;
         const int G = gridDim.x;
+        const int nact = min(kWave, (int)blockDim.x);
         double v[kNPart];
 #pragma unroll
         for (int k = 0; k < kNPart; ++k) v[k] = 0.0;
         for (int b = lane; b < G; b += kWave) {
 #pragma unroll
-            for (int k = 0; k < kNPart; ++k) v[k] += part[b * kNPart + k];
+            for (int k = 0; k < kNPart; ++k)
+                if (MASK & (1u << k)) v[k] += part[b * kNPart + k];
         }
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            double o[kNPart];
 #pragma unroll
-        for (int k = 0; k < kNPart; ++k) {
-            for (int off = kWave / 2; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, kWave);
-            if (lane == 0) tot[k] = v[k];
+            for (int k = 0; k < kNPart; ++k)
+                if (MASK & (1u << k)) o[k] = __shfl_down(v[k], off, kWave);
+#pragma unroll
+            for (int k = 0; k < kNPart; ++k)
+                if ((MASK & (1u << k)) && lane + off < nact) v[k] += o[k];
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < kNPart; ++k)
+                if (MASK & (1u << k)) tot[k] = v[k];
         }
     }
     __syncthreads();
@@ -718,7 +768,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
         a.ns = spec_stride(LC / 2 - 1);
     }
     extern __shared__ unsigned char smem_raw[];
-    __shared__ double red[kSegBlock / 64];
+    __shared__ double red[kSegBlock / 64 * 2];
     __shared__ double tot[kNPart];
     constexpr bool TWL = tw_in_lds<T>(VPT);
     constexpr bool TAU2 = (MODE == SEG_2D_TAU);
@@ -819,8 +869,13 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                     rzl += rv * zv;
                 }
             }
-            if (upd) put_partial(a.part, SL_RR, rr, red);
-            put_partial(a.part, SL_RZ, rzl, red);
+            if (upd) {
+                const int sl[2] = {SL_RR, SL_RZ};
+                const T vv[2] = {rr, rzl};
+                put_partials<2>(a.part, sl, vv, red);
+            } else {
+                put_partial(a.part, SL_RZ, rzl, red);
+            }
             grid_barrier(a.bar, epoch);
             gather_totals(a.part, tot);
         };
@@ -947,10 +1002,13 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
             } else {
                 for (long long j = gtid; j < Nd; j += gthreads) (void)e_store(j, e_load(j), rr, bb);
             }
-            put_partial(a.part, SL_RR, rr, red);
-            put_partial(a.part, SL_BB, bb, red);
+            {
+                const int sl[2] = {SL_RR, SL_BB};
+                const T vv[2] = {rr, bb};
+                put_partials<2>(a.part, sl, vv, red);
+            }
             grid_barrier(a.bar, epoch);
-            gather_totals(a.part, tot);
+            gather_totals<(1u << SL_RR) | (1u << SL_BB)>(a.part, tot);
         }
         const double bbt = tot[SL_BB];
         double rrt = tot[SL_RR];
@@ -976,7 +1034,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                 }
                 put_partial(a.part, SL_RZ, rzl, red);
                 grid_barrier(a.bar, epoch);
-                gather_totals(a.part, tot);
+                gather_totals<1u << SL_RZ>(a.part, tot);
             }
             double rz = tot[SL_RZ];
             T beta = T(0);
@@ -995,7 +1053,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                 }
                 put_partial(a.part, SL_PB, pbp, red);
                 grid_barrier(a.bar, epoch);
-                gather_totals(a.part, tot);
+                gather_totals<(1u << SL_PD) | (1u << SL_PB)>(a.part, tot);
                 const double pqt = tot[SL_PD] + (double)cc * tot[SL_PB];
                 const T alpha = T(pqt != 0.0 ? rz / pqt : 0.0);
                 for (int rd = 0; rd < NR; ++rd) {
@@ -1004,7 +1062,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                 }
                 put_partial(a.part, SL_RR, rr, red);
                 grid_barrier(a.bar, epoch);
-                gather_totals(a.part, tot);
+                gather_totals<1u << SL_RR>(a.part, tot);
                 ++it;
                 rrt = tot[SL_RR];
                 if (rrt <= a.tol2 * bbt || it >= a.maxit || !(rrt == rrt)) break;
@@ -1015,7 +1073,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                 }
                 put_partial(a.part, SL_RZ, rzl, red);
                 grid_barrier(a.bar, epoch);
-                gather_totals(a.part, tot);
+                gather_totals<1u << SL_RZ>(a.part, tot);
                 const double rz_new = tot[SL_RZ];
                 beta = T(rz != 0.0 ? rz_new / rz : 0.0);
                 rz = rz_new;
