@@ -128,4 +128,98 @@ __device__ void fft_lds(cplx<T>* a, int L, const cplx<T>* __restrict__ tw, int t
     }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident variant.  Thread tid of a group holds v[u] = a_{tid + u nthr}, u < VPT (the
+// "natural" layout).  The first Stockham pass reads exactly those positions and the last pass writes
+// exactly those positions, so with IN_REG the input is taken from v (no LDS write and barrier before
+// the first pass) and with OUT_REG the output is left in v (no LDS read after the last pass); LDS
+// carries only the exchanges between passes.
+//   IN_REG:  on entry the LDS sequence must be free to overwrite (no thread still reading it);
+//   !IN_REG: the input is in LDS and visible to the group;
+//   OUT_REG: on exit the LDS sequence holds scratch data and may be overwritten at once;
+//   !OUT_REG: on exit the output is in LDS and visible to the group.
+// ---------------------------------------------------------------------------
+template <typename T, int R, int VPT, bool INV>
+__device__ __forceinline__ void stockham_pass_x(cplx<T> (&v)[VPT], cplx<T>* a, int L, int Ns,
+                                                const cplx<T>* __restrict__ tw, int tid, int nthr, bool in_reg,
+                                                bool out_reg) {
+    constexpr int NB = VPT / R;  // butterflies per thread
+    const int nbut = L / R;
+    cplx<T> w[NB][R];
+    if (in_reg) {
+        // butterfly (b = tid + c nthr, r) reads position b + r L/R = tid + (c + NB r) nthr
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+#pragma unroll
+            for (int r = 0; r < R; ++r) w[c][r] = v[c + NB * r];
+    } else {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            const int b = tid + c * nthr;
+#pragma unroll
+            for (int r = 0; r < R; ++r) w[c][r] = a[lx(b + r * nbut)];
+        }
+        __syncthreads();
+    }
+    const int tstride = L / (Ns * R);
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        const int b = tid + c * nthr;
+        const int k = b & (Ns - 1);
+        if (Ns > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cplx<T> t = tw[r * k * tstride];
+                w[c][r] = INV ? cmulc(w[c][r], t) : cmul(w[c][r], t);
+            }
+        }
+        if constexpr (R == 8) {
+            dft8<T, INV>(w[c]);
+        } else if constexpr (R == 4) {
+            dft4<T, INV>(w[c][0], w[c][1], w[c][2], w[c][3]);
+        } else {
+            dft2<T, INV>(w[c]);
+        }
+    }
+    if (out_reg) {
+        // last pass (Ns = L/R): butterfly (b, r) writes position b + r Ns = tid + (c + NB r) nthr
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[c + NB * r] = w[c][r];
+    } else {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            const int b = tid + c * nthr;
+            const int k = b & (Ns - 1);
+            const int base = (b - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) a[lx(base + r * Ns)] = w[c][r];
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int VPT, bool INV, bool IN_REG, bool OUT_REG>
+__device__ __forceinline__ void fft_x(cplx<T> (&v)[VPT], cplx<T>* a, int L, const cplx<T>* __restrict__ tw, int tid,
+                                      int nthr) {
+    int Ns = 1;
+    while (Ns < L) {
+        const int rem = L / Ns;
+        const bool first = (Ns == 1);
+        const int R = rem >= 8 ? 8 : rem;
+        const bool last = (Ns * R == L);
+        const bool in_reg = IN_REG && first;
+        const bool out_reg = OUT_REG && last;
+        if (R == 8) {
+            stockham_pass_x<T, 8, VPT, INV>(v, a, L, Ns, tw, tid, nthr, in_reg, out_reg);
+        } else if (R == 4) {
+            stockham_pass_x<T, 4, VPT, INV>(v, a, L, Ns, tw, tid, nthr, in_reg, out_reg);
+        } else {
+            stockham_pass_x<T, 2, VPT, INV>(v, a, L, Ns, tw, tid, nthr, in_reg, out_reg);
+        }
+        Ns *= R;
+    }
+}
+
 }  // namespace tsfde

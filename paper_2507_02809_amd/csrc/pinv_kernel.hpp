@@ -44,6 +44,7 @@
 namespace tsfde {
 
 constexpr int kHB = 16;    // steps per segment (history block)
+static_assert(kHB <= 64, "the weight table e carries 64 trailing zeros for the history tiles");
 constexpr int kNPart = 6;  // reduction slots per workgroup
 // (r,r) (rhs,rhs) (r,z) (p,q) (p,dg p) (p,B p)
 enum : int { SL_RR = 0, SL_BB = 1, SL_RZ = 2, SL_PQ = 3, SL_PD = 4, SL_PB = 5 };
@@ -425,6 +426,40 @@ __device__ __forceinline__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, con
     fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
 }
 
+// Sine transform of rows (i0, i0 + 1) of `in` (row stride ld), packed as real + i*imag: the odd
+// extension of length L = 2(N+1) is loaded from global memory straight into the FFT's register
+// layout (thread tid: positions tid + u nthr), so only the transform's own exchanges use LDS.
+// Afterwards c[lx(k+1)] = -2i DST(row i0)_k + 2 DST(row i0+1)_k.  The LDS sequence must be free.
+template <typename T, int VPT>
+__device__ __forceinline__ void g_dst_rows(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, const T* in, int ld,
+                                           int i0, bool valid, int tid, int nthr) {
+    const int N = a.N, L = a.L;
+    const bool two = i0 + 1 < N;
+    cplx<T> v[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int p = tid + u * nthr;
+        T x0 = T(0), x1 = T(0);
+        if (valid) {
+            // position p holds x_{p-1} (1 <= p <= N), -x_{L-1-p} (N+2 <= p <= L-1), else 0
+            const bool lo = (p >= 1 && p <= N);
+            const bool hi = (p >= N + 2);
+            if (lo || hi) {
+                const int m = lo ? p - 1 : L - 1 - p;
+                const long long o = (long long)i0 * ld + m;
+                x0 = in[o];
+                if (two) x1 = in[o + ld];
+                if (hi) {
+                    x0 = -x0;
+                    x1 = -x1;
+                }
+            }
+        }
+        v[u] = {x0, x1};
+    }
+    fft_x<T, VPT, false, true, false>(v, c, L, tw, tid, nthr);
+}
+
 // ---------------------------------------------------------------------------
 // fused phases of the 2D tau-preconditioned CG (4 device-wide barriers per iteration)
 //
@@ -515,7 +550,7 @@ __device__ __forceinline__ void wg_pass_B(const PinvArgs<T>& a, cplx<T>* cbase, 
         for (int u = 0; u < VH; ++u) load_tau(u);
     }
     T dummy = T(0);
-    g_dst_load<T, VPT>(a, c, tw, a.t1, a.ns, k0, valid, tid, nthr, false, T(0), dummy);
+    g_dst_rows<T, VPT>(a, c, tw, a.t1, a.ns, k0, valid, tid, nthr);
     T hv0[VH], hv1[VH];
 #pragma unroll
     for (int u = 0; u < VH; ++u) {
@@ -584,7 +619,7 @@ __device__ __forceinline__ void wg_pass_DF(const PinvArgs<T>& a, cplx<T>* cbase,
         for (int u = 0; u < VH; ++u) load_pd(u);
     }
     T dummy = T(0);
-    g_dst_load<T, VPT>(a, c, tw, a.t2, a.ns, i0, valid, tid, nthr, false, T(0), dummy);
+    g_dst_rows<T, VPT>(a, c, tw, a.t2, a.ns, i0, valid, tid, nthr);
     T pn0[VH], pn1[VH];
 #pragma unroll
     for (int u = 0; u < VH; ++u) {
@@ -601,13 +636,11 @@ __device__ __forceinline__ void wg_pass_DF(const PinvArgs<T>& a, cplx<T>* cbase,
             if (two) a.p[o0 + N] = pn1[u];
         }
     }
-    __syncthreads();
+    cplx<T> v[VPT];
 #pragma unroll
-    for (int u = 0; u < VH; ++u) c[lx(tid + u * nthr)] = {pn0[u], pn1[u]};
-#pragma unroll
-    for (int u = VH; u < VPT; ++u) c[lx(tid + u * nthr)] = {T(0), T(0)};
-    __syncthreads();
-    fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
+    for (int u = 0; u < VPT; ++u) v[u] = (u < VH) ? cplx<T>{pn0[u], pn1[u]} : cplx<T>{T(0), T(0)};
+    __syncthreads();  // every thread has read its sine-transform values: the sequence is free
+    fft_x<T, VPT, false, true, false>(v, c, L, tw, tid, nthr);
     wg_write_spec(a, cbase, ibase, gpb);
     __syncthreads();
 }
@@ -617,40 +650,36 @@ __device__ __forceinline__ void wg_pass_DF(const PinvArgs<T>& a, cplx<T>* cbase,
 template <typename T, int VPT>
 __device__ __forceinline__ void g_cols_pbp(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, int k2, bool valid, int tid, int nthr,
                            T& pbp) {
+    // both transforms register-resident: thread tid holds positions tid + u nthr throughout
     const int N = a.N, L = a.L;
     cplx<T>* row = a.spec + (long long)k2 * a.ns;
     const T* sy = a.sym + (long long)k2 * L;
     constexpr int VH = VPT / 2;  // i < N < L/2 = VH * nthr
     T sv[VPT];
+    cplx<T> v[VPT];
 #pragma unroll
     for (int u = 0; u < VPT; ++u) {
         const int i = tid + u * nthr;
-        if (u < VH) c[lx(i)] = (valid && i < N) ? row[i] : cplx<T>{T(0), T(0)};
-        else c[lx(i)] = {T(0), T(0)};
+        v[u] = (u < VH && valid && i < N) ? row[i] : cplx<T>{T(0), T(0)};
         sv[u] = valid ? sy[i] : T(0);
     }
-    __syncthreads();
-    fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
+    fft_x<T, VPT, false, true, true>(v, c, L, tw, tid, nthr);
     const T wk = (k2 == 0 || 2 * k2 == L) ? T(1) : T(2);
     T acc = T(0);
 #pragma unroll
     for (int u = 0; u < VPT; ++u) {
-        const int k1 = tid + u * nthr;
-        const cplx<T> v = c[lx(k1)];
-        acc += (v.x * v.x + v.y * v.y) * sv[u];
-        c[lx(k1)] = {v.x * sv[u], v.y * sv[u]};
+        acc += (v[u].x * v[u].x + v[u].y * v[u].y) * sv[u];
+        v[u] = {v[u].x * sv[u], v[u].y * sv[u]};
     }
     pbp += wk * acc;
-    __syncthreads();
-    fft_lds<T, VPT, true>(c, L, tw, tid, nthr);
+    fft_x<T, VPT, true, true, true>(v, c, L, tw, tid, nthr);
     if (valid) {
 #pragma unroll
         for (int u = 0; u < VH; ++u) {
             const int i = tid + u * nthr;
-            if (i < N) row[i] = c[lx(i)];
+            if (i < N) row[i] = v[u];
         }
     }
-    __syncthreads();
 }
 
 // inverse row transform -> u = B p rows; q = dg p + c u; r -= alpha q; x += alpha p; (r, r);
@@ -688,12 +717,13 @@ __device__ __forceinline__ void wg_pass_IUA(const PinvArgs<T>& a, cplx<T>* cbase
     }
     wg_load_spec(a, cbase, ibase, gpb);
     __syncthreads();
-    fft_lds<T, VPT, true>(c, L, tw, tid, nthr);
+    cplx<T> bp[VPT];
+    fft_x<T, VPT, true, false, true>(bp, c, L, tw, tid, nthr);  // B p rows left in registers
 #pragma unroll
     for (int u = 0; u < VH; ++u) {
         const int m = tid + u * nthr;
         if constexpr (!PREF) load_prx(u);
-        const cplx<T> uu = c[lx(m)];
+        const cplx<T> uu = bp[u];
         if (valid && m < N) {
             const T q0 = d0[u] * p0[u] + cc * uu.x;
             r0[u] -= alpha * q0;
@@ -716,8 +746,8 @@ __device__ __forceinline__ void wg_pass_IUA(const PinvArgs<T>& a, cplx<T>* cbase
             r0[u] = r1[u] = T(0);
         }
     }
-    __syncthreads();
-    // pass A on the updated rows: odd extension, FFT, DST rows -> t1 (transposed)
+    // pass A on the updated rows: odd extension, FFT, DST rows -> t1 (transposed); the sequence is
+    // free (the inverse transform left its output in registers)
 #pragma unroll
     for (int u = 0; u < VH; ++u) {
         const int m = tid + u * nthr;
@@ -893,6 +923,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
         T ew[kHB];
 #pragma unroll
         for (int i = 0; i < kHB; ++i) ew[i] = (!lastrow && i + 1 < nnear) ? e[s - sa - i] : T(0);
+        const T e1 = (nnear >= 1) ? e[1] : T(0);  // weight of y_{s-1} when it is a near term
         // loads of point j (no stores, so that the loads of several points can be in flight together);
         // hn = sum over the near-history terms m in [sa, s-1) of e_{s-m} y_m
         auto e_load = [&](long long j) -> EIn {
@@ -932,7 +963,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
             if (lastrow) {
                 rhs = (v.zo - yprev) / (a.cf * v.g2o);
             } else {
-                const T h = (nnear >= 1) ? v.hn + e[1] * yprev : v.hn;
+                const T h = v.hn + e1 * yprev;
                 rhs = v.zo - v.dgo * h;
                 if (s >= 1) {
                     x0 = ext ? T(2) * yprev - v.ym2 : yprev;
