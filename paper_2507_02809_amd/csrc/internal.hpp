@@ -85,6 +85,9 @@ struct Problem {
 template <typename T>
 void launch_history_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s);
 
+// d = 2 matvec Toeplitz part with workgroup-coalesced transposes; false if the shape is not covered
+template <typename T>
+bool launch_toeplitz2d_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s);
 template <typename T>
 void launch_toeplitz_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s);
 

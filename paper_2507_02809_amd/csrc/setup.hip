@@ -274,7 +274,8 @@ static void build_dev(Problem& P, Dev<T>& D, const std::vector<double>& dg, cons
     D.tw = reinterpret_cast<cplx<T>*>(upload<T>(P, tw.data(), tw.size()));
     if (!twd.empty()) D.twd = reinterpret_cast<cplx<T>*>(upload<T>(P, twd.data(), twd.size()));
     if (!tau.empty()) D.tau = upload<T>(P, tau.data(), tau.size());
-    if (P.d == 2) D.spec = reinterpret_cast<cplx<T>*>(alloc<T>(P, 2 * (size_t)P.nspec * P.H * P.N));
+    // row stride of the matvec spectra: N rounded up to 16 (the other users take stride N)
+    if (P.d == 2) D.spec = reinterpret_cast<cplx<T>*>(alloc<T>(P, 2 * (size_t)P.nspec * P.H * (size_t)((P.N + 15) & ~15)));
     D.pcg = alloc<T>(P, 8 * (size_t)P.Nd);
     D.partial = alloc<T>(P, kMaxPartials);
 }

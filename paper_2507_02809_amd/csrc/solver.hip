@@ -68,7 +68,10 @@ static bool check_opts(const Opts& o) {
         return false;
     }
     if (o.inner_maxit < 1 || o.max_refine < 1) { set_error("opts.inner_maxit and max_refine must be >= 1"); return false; }
-    if (o.precision != TSFDE_FP64 && o.precision != TSFDE_MIXED) { set_error("opts.precision invalid"); return false; }
+    if (o.precision != TSFDE_FP64 && o.precision != TSFDE_MIXED && o.precision != TSFDE_PREC_F32) {
+        set_error("opts.precision invalid");
+        return false;
+    }
     return true;
 }
 
@@ -86,7 +89,7 @@ template <typename T>
 static void apply_A_impl(Problem& P, const T* y, T* z, hipStream_t st) {
     Dev<T>& D = dev<T>(P);
     launch_history_matvec<T>(P, D, y, z, st);
-    launch_toeplitz_matvec<T>(P, D, y, z, st);
+    if (!launch_toeplitz2d_matvec<T>(P, D, y, z, st)) launch_toeplitz_matvec<T>(P, D, y, z, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -350,12 +353,24 @@ static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o,
     const long long n = P.ntot;
     const int maxit = o.maxit > 0 ? o.maxit : (int)std::min<long long>(n, 1000);
     const double t_start = now();
-    if (o.precision == TSFDE_FP64) {
+    if (o.precision == TSFDE_FP64 || o.precision == TSFDE_PREC_F32) {
         SolveOps ops;
         ops.A = [&](const double* v, double* out) { apply_A_impl<double>(P, v, out, st); };
+        Opts o32 = o;
+        o32.inner_tol = std::max(o.inner_tol, kInnerTolF32);
+        Dev<float>& F = P.f32;
+        if (o.precision == TSFDE_PREC_F32 && !F.vecA) {
+            TSFDE_HIP(hipMalloc(&F.vecA, sizeof(float) * n));
+            TSFDE_HIP(hipMalloc(&F.vecB, sizeof(float) * n));
+        }
         ops.M = [&](const double* v, double* out) -> long long {
             if (!o.use_precond) { launch_copy<double>(v, out, n, st); return 0; }
-            return pinv_impl<double>(P, v, out, o, st, true);
+            if (o.precision == TSFDE_FP64) return pinv_impl<double>(P, v, out, o, st, true);
+            // FP32 preconditioner inside the FP64 flexible Krylov solve
+            launch_d2f(v, F.vecA, n, st);
+            const long long it = pinv_impl<float>(P, F.vecA, F.vecB, o32, st, true);
+            launch_f2d(F.vecB, out, n, st);
+            return it;
         };
         double* r = nullptr;
         TSFDE_HIP(hipMalloc(&r, sizeof(double) * n));

@@ -13,7 +13,7 @@ _LIBPATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtsfde.so
 _lib = None
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ENONFINITE, ENOTIMPL = range(7)
-FP64, MIXED = 0, 1
+FP64, MIXED, PREC_F32 = 0, 1, 2
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOCONV", 5: "ENONFINITE", 6: "ENOTIMPL"}
 
 EXPORTED = [
