@@ -29,146 +29,170 @@ constexpr int kMvBlock = 256;
 __host__ __device__ constexpr int mv_stride(int N) { return (N + 15) & ~15; }
 
 template <typename T, int VPT, int LC>
-__global__ __launch_bounds__(kMvBlock) void mv_rows_fwd(const T* __restrict__ y, int N_, int L_,
-                                                        const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ spec) {
+__global__ __launch_bounds__(kMvBlock) void mv_rows_fwd(const T* __restrict__ y, int N, int L_, int nsl,
+                                                        const cplx<T>* __restrict__ tw_g, cplx<T>* __restrict__ spec) {
     extern __shared__ unsigned char smem_raw[];
-    cplx<T>* cbase = reinterpret_cast<cplx<T>*>(smem_raw);
     const int L = LC ? LC : L_;
-    const int N = N_;
+    cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);  // twiddle table, then the groups' sequences
+    cplx<T>* cbase = tw + L;
     const int H = L / 2 + 1, LP = lds_len(L), ns = mv_stride(N);
     const int nthr = L / VPT, gpb = kMvBlock / nthr;
     const int grp = threadIdx.x / nthr, tid = threadIdx.x - grp * nthr;
-    const int ibase = blockIdx.x * 2 * gpb;
-    const int i0 = ibase + 2 * grp;
+    const int nrb = (N + 2 * gpb - 1) / (2 * gpb);
     const long long Nd = (long long)N * N;
-    const T* ys = y + (long long)blockIdx.y * Nd;
-    constexpr int VH = VPT / 2;  // j < N <= L/2 = VH * nthr
-    cplx<T> v[VPT];
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) {
-        const int j = tid + u * nthr;
-        T a0 = T(0), a1 = T(0);
-        if (u < VH && j < N && i0 < N) {
-            a0 = ys[(long long)i0 * N + j];
-            if (i0 + 1 < N) a1 = ys[(long long)(i0 + 1) * N + j];
-        }
-        v[u] = {a0, a1};
-    }
+    for (int k = threadIdx.x; k < L; k += kMvBlock) tw[k] = tw_g[k];
+    __syncthreads();
     cplx<T>* c = cbase + (size_t)grp * LP;
-    fft_x<T, VPT, false, true, false>(v, c, L, tw, tid, nthr);
-    __syncthreads();  // the write-out reads every group's sequence
-    cplx<T>* out = spec + (long long)blockIdx.y * H * ns;
-    for (int idx = threadIdx.x; idx < H * gpb; idx += kMvBlock) {
-        const int k = idx / gpb, g = idx - k * gpb;
-        const int i = ibase + 2 * g;
-        if (i >= N) continue;
-        const cplx<T>* cg = cbase + (size_t)g * LP;
-        const cplx<T> C = cg[lx(k)];
-        const cplx<T> Cm = cg[lx((L - k) & (L - 1))];
-        cplx<T>* dst = out + (long long)k * ns + i;
-        dst[0] = {T(0.5) * (C.x + Cm.x), T(0.5) * (C.y - Cm.y)};
-        if (i + 1 < N) dst[1] = {T(0.5) * (C.y + Cm.y), T(0.5) * (Cm.x - C.x)};
+    constexpr int VH = VPT / 2;  // j < N <= L/2 = VH * nthr
+    for (int blk = blockIdx.x; blk < nrb * nsl; blk += gridDim.x) {  // uniform per workgroup
+        const int slice = blk / nrb;
+        const int ibase = (blk - slice * nrb) * 2 * gpb;
+        const int i0 = ibase + 2 * grp;
+        const T* ys = y + (long long)slice * Nd;
+        cplx<T> v[VPT];
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int j = tid + u * nthr;
+            T a0 = T(0), a1 = T(0);
+            if (u < VH && j < N && i0 < N) {
+                a0 = ys[(long long)i0 * N + j];
+                if (i0 + 1 < N) a1 = ys[(long long)(i0 + 1) * N + j];
+            }
+            v[u] = {a0, a1};
+        }
+        fft_x<T, VPT, false, true, false>(v, c, L, tw, tid, nthr);
+        __syncthreads();  // the write-out reads every group's sequence
+        cplx<T>* out = spec + (long long)slice * H * ns;
+        for (int idx = threadIdx.x; idx < H * gpb; idx += kMvBlock) {
+            const int k = idx / gpb, g = idx - k * gpb;
+            const int i = ibase + 2 * g;
+            if (i >= N) continue;
+            const cplx<T>* cg = cbase + (size_t)g * LP;
+            const cplx<T> C = cg[lx(k)];
+            const cplx<T> Cm = cg[lx((L - k) & (L - 1))];
+            cplx<T>* dst = out + (long long)k * ns + i;
+            dst[0] = {T(0.5) * (C.x + Cm.x), T(0.5) * (C.y - Cm.y)};
+            if (i + 1 < N) dst[1] = {T(0.5) * (C.y + Cm.y), T(0.5) * (Cm.x - C.x)};
+        }
+        __syncthreads();  // the sequences are free for the next rows
     }
 }
 
 template <typename T, int VPT, int LC>
 __global__ __launch_bounds__(kMvBlock) void mv_cols(cplx<T>* __restrict__ spec, int N, int L_, int nrows,
-                                                    const cplx<T>* __restrict__ tw, const T* __restrict__ sym) {
+                                                    const cplx<T>* __restrict__ tw_g, const T* __restrict__ sym) {
+    // the twiddle table sits in LDS in front of the groups' sequences; each workgroup walks over
+    // several spectral rows so that the table is loaded once per workgroup
     extern __shared__ unsigned char smem_raw[];
-    cplx<T>* cbase = reinterpret_cast<cplx<T>*>(smem_raw);
     const int L = LC ? LC : L_;
+    cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* cbase = tw + L;
     const int H = L / 2 + 1, LP = lds_len(L), ns = mv_stride(N);
     const int nthr = L / VPT, gpb = kMvBlock / nthr;
     const int grp = threadIdx.x / nthr, tid = threadIdx.x - grp * nthr;
-    const int rowid = blockIdx.x * gpb + grp;  // (slice, k2) flattened, slice-major
-    const bool valid = rowid < nrows;
-    const int slice = valid ? rowid / H : 0;
-    const int k2 = valid ? rowid - slice * H : 0;
-    cplx<T>* row = spec + ((long long)slice * H + k2) * ns;
-    const T* sy = sym + (long long)k2 * L;
-    constexpr int VH = VPT / 2;
-    cplx<T> v[VPT];
-    T sv[VPT];
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) {
-        const int i = tid + u * nthr;
-        v[u] = (u < VH && valid && i < N) ? row[i] : cplx<T>{T(0), T(0)};
-        sv[u] = sy[i];
-    }
+    for (int k = threadIdx.x; k < L; k += kMvBlock) tw[k] = tw_g[k];
+    __syncthreads();
     cplx<T>* c = cbase + (size_t)grp * LP;
-    fft_x<T, VPT, false, true, true>(v, c, L, tw, tid, nthr);
+    constexpr int VH = VPT / 2;
+    const int stride = gridDim.x * gpb;
+    const int rounds = (nrows + stride - 1) / stride;  // the same for every group (the FFTs hold barriers)
+    for (int rd = 0; rd < rounds; ++rd) {
+        const int rowid = rd * stride + blockIdx.x * gpb + grp;  // (slice, k2) flattened, slice-major
+        const bool valid = rowid < nrows;
+        const int slice = valid ? rowid / H : 0;
+        const int k2 = valid ? rowid - slice * H : 0;
+        cplx<T>* row = spec + ((long long)slice * H + k2) * ns;
+        const T* sy = sym + (long long)k2 * L;
+        cplx<T> v[VPT];
+        T sv[VPT];
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) v[u] = {v[u].x * sv[u], v[u].y * sv[u]};
-    fft_x<T, VPT, true, true, true>(v, c, L, tw, tid, nthr);
-    if (valid) {
-#pragma unroll
-        for (int u = 0; u < VH; ++u) {
+        for (int u = 0; u < VPT; ++u) {
             const int i = tid + u * nthr;
-            if (i < N) row[i] = v[u];
+            v[u] = (u < VH && valid && i < N) ? row[i] : cplx<T>{T(0), T(0)};
+            sv[u] = sy[i];
+        }
+        fft_x<T, VPT, false, true, true>(v, c, L, tw, tid, nthr);
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) v[u] = {v[u].x * sv[u], v[u].y * sv[u]};
+        fft_x<T, VPT, true, true, true>(v, c, L, tw, tid, nthr);
+        if (valid) {
+#pragma unroll
+            for (int u = 0; u < VH; ++u) {
+                const int i = tid + u * nthr;
+                if (i < N) row[i] = v[u];
+            }
         }
     }
 }
 
 template <typename T, int VPT, int LC>
 __global__ __launch_bounds__(kMvBlock) void mv_rows_inv(const cplx<T>* __restrict__ spec, int N, int L_, int slice0,
-                                                        int M, const cplx<T>* __restrict__ tw, T* __restrict__ z,
-                                                        const T* __restrict__ y, const T* __restrict__ g2, T ct, T cf) {
+                                                        int nsl, int M, const cplx<T>* __restrict__ tw_g,
+                                                        T* __restrict__ z, const T* __restrict__ y,
+                                                        const T* __restrict__ g2, T ct, T cf) {
     extern __shared__ unsigned char smem_raw[];
-    cplx<T>* cbase = reinterpret_cast<cplx<T>*>(smem_raw);
     const int L = LC ? LC : L_;
+    cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);  // twiddle table, then the groups' sequences
+    cplx<T>* cbase = tw + L;
     const int H = L / 2 + 1, LP = lds_len(L), ns = mv_stride(N);
     const int nthr = L / VPT, gpb = kMvBlock / nthr;
     const int grp = threadIdx.x / nthr, tid = threadIdx.x - grp * nthr;
-    const int ibase = blockIdx.x * 2 * gpb;
-    const int i0 = ibase + 2 * grp;
-    const bool two = i0 + 1 < N;
+    const int nrb = (N + 2 * gpb - 1) / (2 * gpb);
     const long long Nd = (long long)N * N;
-    const int s = slice0 + blockIdx.y;
-    const bool last = (s == M);
+    for (int k = threadIdx.x; k < L; k += kMvBlock) tw[k] = tw_g[k];
+    __syncthreads();
+    cplx<T>* c = cbase + (size_t)grp * LP;
     constexpr int VH = VPT / 2;
-    // epilogue operands first (their latency overlaps the spectrum loads and the transform)
-    T zo0[VH], zo1[VH], gv0[VH], gv1[VH];
+    for (int blk = blockIdx.x; blk < nrb * nsl; blk += gridDim.x) {  // uniform per workgroup
+        const int sl = blk / nrb;
+        const int ibase = (blk - sl * nrb) * 2 * gpb;
+        const int i0 = ibase + 2 * grp;
+        const bool two = i0 + 1 < N;
+        const int s = slice0 + sl;
+        const bool last = (s == M);
+        // epilogue operands first (their latency overlaps the spectrum loads and the transform)
+        T zo0[VH], zo1[VH], gv0[VH], gv1[VH];
 #pragma unroll
-    for (int u = 0; u < VH; ++u) {
-        const int j = tid + u * nthr;
-        zo0[u] = zo1[u] = gv0[u] = gv1[u] = T(0);
-        if (j < N && i0 < N) {
-            const long long o = (long long)i0 * N + j;
-            const long long gs = (long long)(last ? M - 1 : s) * Nd;
-            gv0[u] = g2[gs + o];
-            zo0[u] = last ? y[gs + o] : z[(long long)s * Nd + o];
-            if (two) {
-                gv1[u] = g2[gs + o + N];
-                zo1[u] = last ? y[gs + o + N] : z[(long long)s * Nd + o + N];
+        for (int u = 0; u < VH; ++u) {
+            const int j = tid + u * nthr;
+            zo0[u] = zo1[u] = gv0[u] = gv1[u] = T(0);
+            if (j < N && i0 < N) {
+                const long long o = (long long)i0 * N + j;
+                const long long gs = (long long)(last ? M - 1 : s) * Nd;
+                gv0[u] = g2[gs + o];
+                zo0[u] = last ? y[gs + o] : z[(long long)s * Nd + o];
+                if (two) {
+                    gv1[u] = g2[gs + o + N];
+                    zo1[u] = last ? y[gs + o + N] : z[(long long)s * Nd + o + N];
+                }
             }
         }
-    }
-    const cplx<T>* sp = spec + (long long)blockIdx.y * H * ns;
-    for (int idx = threadIdx.x; idx < H * gpb; idx += kMvBlock) {
-        const int k = idx / gpb, g = idx - k * gpb;
-        const int i = ibase + 2 * g;
-        cplx<T> Y0 = {T(0), T(0)}, Y1 = {T(0), T(0)};
-        if (i < N) {
-            const cplx<T>* src = sp + (long long)k * ns + i;
-            Y0 = src[0];
-            if (i + 1 < N) Y1 = src[1];
+        const cplx<T>* sp = spec + (long long)sl * H * ns;
+        for (int idx = threadIdx.x; idx < H * gpb; idx += kMvBlock) {
+            const int k = idx / gpb, g = idx - k * gpb;
+            const int i = ibase + 2 * g;
+            cplx<T> Y0 = {T(0), T(0)}, Y1 = {T(0), T(0)};
+            if (i < N) {
+                const cplx<T>* src = sp + (long long)k * ns + i;
+                Y0 = src[0];
+                if (i + 1 < N) Y1 = src[1];
+            }
+            cplx<T>* cg = cbase + (size_t)g * LP;
+            cg[lx(k)] = {Y0.x - Y1.y, Y0.y + Y1.x};
+            if (k > 0 && k < H - 1) cg[lx(L - k)] = {Y0.x + Y1.y, Y1.x - Y0.y};
         }
-        cplx<T>* cg = cbase + (size_t)g * LP;
-        cg[lx(k)] = {Y0.x - Y1.y, Y0.y + Y1.x};
-        if (k > 0 && k < H - 1) cg[lx(L - k)] = {Y0.x + Y1.y, Y1.x - Y0.y};
-    }
-    __syncthreads();
-    cplx<T> v[VPT];
-    cplx<T>* c = cbase + (size_t)grp * LP;
-    fft_x<T, VPT, true, false, true>(v, c, L, tw, tid, nthr);
-    const T cc = last ? cf : ct;
+        __syncthreads();
+        cplx<T> v[VPT];
+        fft_x<T, VPT, true, false, true>(v, c, L, tw, tid, nthr);  // ends with the sequences free
+        const T cc = last ? cf : ct;
 #pragma unroll
-    for (int u = 0; u < VH; ++u) {
-        const int j = tid + u * nthr;
-        if (j < N && i0 < N) {
-            const long long o = (long long)s * Nd + (long long)i0 * N + j;
-            z[o] = zo0[u] + cc * gv0[u] * v[u].x;
-            if (two) z[o + N] = zo1[u] + cc * gv1[u] * v[u].y;
+        for (int u = 0; u < VH; ++u) {
+            const int j = tid + u * nthr;
+            if (j < N && i0 < N) {
+                const long long o = (long long)s * Nd + (long long)i0 * N + j;
+                z[o] = zo0[u] + cc * gv0[u] * v[u].x;
+                if (two) z[o + N] = zo1[u] + cc * gv1[u] * v[u].y;
+            }
         }
     }
 }
@@ -177,18 +201,36 @@ template <typename T, int VPT, int LC>
 static void launch_mv(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t st) {
     const int L = P.L, N = P.N, H = L / 2 + 1;
     const int nthr = L / VPT, gpb = kMvBlock / nthr;
-    const size_t lds = sizeof(cplx<T>) * (size_t)gpb * lds_len(L);
+    const size_t lds = sizeof(cplx<T>) * ((size_t)L + (size_t)gpb * lds_len(L));  // twiddles + sequences
     const int nslices = P.M + 1;
     const int nrb = (N + 2 * gpb - 1) / (2 * gpb);
+    // workgroups loop over the work (the twiddle table is loaded once each): one full wave of
+    // resident workgroups per kernel
+    thread_local int res[3] = {0, 0, 0};
+    thread_local size_t res_lds = 0;  // occupancy depends on the LDS size (L is a run-time value for LC = 0)
+    if (res_lds != lds) {
+        res_lds = lds;
+        int dev = 0, ncu = 0;
+        TSFDE_HIP(hipGetDevice(&dev));
+        TSFDE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        int b0 = 0, b1 = 0, b2 = 0;
+        TSFDE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, mv_rows_fwd<T, VPT, LC>, kMvBlock, lds));
+        TSFDE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, mv_cols<T, VPT, LC>, kMvBlock, lds));
+        TSFDE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, mv_rows_inv<T, VPT, LC>, kMvBlock, lds));
+        res[1] = std::max(1, b1) * ncu;
+        res[2] = std::max(1, b2) * ncu;
+        res[0] = std::max(1, b0) * ncu;
+    }
     for (int s0 = 0; s0 < nslices; s0 += P.nspec) {
         const int nsl = std::min(P.nspec, nslices - s0);
         const T* ys = y + (long long)s0 * P.Nd;
-        hipLaunchKernelGGL((mv_rows_fwd<T, VPT, LC>), dim3(nrb, nsl), dim3(kMvBlock), lds, st, ys, N, L, D.tw, D.spec);
+        hipLaunchKernelGGL((mv_rows_fwd<T, VPT, LC>), dim3(std::min(nrb * nsl, res[0])), dim3(kMvBlock), lds, st, ys,
+                           N, L, nsl, D.tw, D.spec);
         const int nrows = nsl * H;
-        hipLaunchKernelGGL((mv_cols<T, VPT, LC>), dim3((nrows + gpb - 1) / gpb), dim3(kMvBlock), lds, st, D.spec, N, L,
-                           nrows, D.tw, D.sym);
-        hipLaunchKernelGGL((mv_rows_inv<T, VPT, LC>), dim3(nrb, nsl), dim3(kMvBlock), lds, st, D.spec, N, L, s0, P.M,
-                           D.tw, z, y, D.gamma2, T(P.ct), T(P.cf));
+        hipLaunchKernelGGL((mv_cols<T, VPT, LC>), dim3(std::min((nrows + gpb - 1) / gpb, res[1])), dim3(kMvBlock), lds,
+                           st, D.spec, N, L, nrows, D.tw, D.sym);
+        hipLaunchKernelGGL((mv_rows_inv<T, VPT, LC>), dim3(std::min(nrb * nsl, res[2])), dim3(kMvBlock), lds, st,
+                           D.spec, N, L, s0, nsl, P.M, D.tw, z, y, D.gamma2, T(P.ct), T(P.cf));
         TSFDE_HIP(hipGetLastError());
     }
 }
