@@ -34,6 +34,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GMRES solves/sec to 1e-8 rel. f error (d=2,N=255²,M=256); matvec HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+# one FP64 apply_A at c3, bytes at the HBM interface (FETCH_SIZE x 1.996 + WRITE_SIZE x 1.000)
+APPLY_A_TRAFFIC_FP64 = 2380.0e6
+# algorithmic flops of one apply_A at c3: M(M+1)/2 Nd FMA of the history sum (4.28 GFLOP) plus
+# 5 L log2 L flops per length-512 complex FFT: 2 x 257 x 128 row transforms and 2 x 257 x 257
+# column transforms (4.56 GFLOP)
+APPLY_A_GFLOP_FP64 = 8.84
 
 
 def log(msg: str) -> None:
@@ -54,6 +61,9 @@ def parse():
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--matvec-only", action="store_true",
+                    help="only the apply_A timing (FP64, FP32), preceded by one FP64->FP32 conversion of a vector "
+                         "(known bytes: a reference for hardware traffic counters); for profiling")
     return ap.parse_args()
 
 
@@ -88,6 +98,31 @@ def cpu_baseline(inp, outer_iters: int, restarts: int, inner_tol: float) -> dict
             "est_seconds_per_solve": t_solve}
 
 
+def matvec_timing(a, prob, inp, y, y32) -> dict:
+    """HIP-event time of apply_A (FP64 and FP32) on the stream the library launches on, and the
+    throughput in compulsory bytes: y in, z out, gamma1, gamma2."""
+    import torch
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def time_mv(yy, zz):
+        for _ in range(5):
+            prob.apply_A(yy, zz, stream=stream)
+        ev0.record(stream)
+        for _ in range(a.matvec_reps):
+            prob.apply_A(yy, zz, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / a.matvec_reps  # ms
+
+    mv64 = time_mv(y, torch.empty_like(y))
+    mv32 = time_mv(y32, torch.empty_like(y32))
+    n = prob.n_tot
+    bytes64 = 8 * (2 * n + 2 * inp.M * inp.Nd)
+    return {"fp64_ms": mv64, "fp64_GB_s": bytes64 / (mv64 * 1e-3) / 1e9, "fp32_ms": mv32,
+            "fp32_GB_s": (bytes64 / 2) / (mv32 * 1e-3) / 1e9, "algorithmic_bytes_fp64": bytes64}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -102,6 +137,15 @@ def main():
     prob = tsfde.Problem.from_inputs(inp)
     t_setup = time.perf_counter() - t_setup
     log(f"problem created in {t_setup:.2f} s (n_tot = {prob.n_tot})")
+    if a.matvec_only:
+        y = torch.randn(prob.n_tot, dtype=torch.float64, device=dev)
+        y32 = y.float()  # reads 8 n_tot bytes, writes 4 n_tot bytes
+        torch.cuda.synchronize()
+        res = matvec_timing(a, prob, inp, y, y32)
+        log(f"apply_A: fp64 {res['fp64_ms']:.3f} ms ({res['fp64_GB_s']:.0f} GB/s), fp32 {res['fp32_ms']:.3f} ms")
+        prob.close()
+        print(json.dumps({"matvec": res}))
+        return
     # final-time data from the library's forward solve of the direct problem, plus noise
     v = prob.forward_solve(torch.tensor(inp.f_true, device=dev), opts=tsfde.default_opts(inner_tol=1e-12))
     mu = v[(inp.M - 1) * inp.Nd:].cpu().numpy()
@@ -169,30 +213,11 @@ def main():
         }
 
     # structured matvec (FP64 and FP32), HIP events on the stream the library launches on
-    n = prob.n_tot
-    y = torch.randn(n, dtype=torch.float64, device=dev)
-    z = torch.empty_like(y)
-    stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-    def time_mv(yy, zz):
-        for _ in range(5):
-            prob.apply_A(yy, zz, stream=stream)
-        ev0.record(stream)
-        for _ in range(a.matvec_reps):
-            prob.apply_A(yy, zz, stream=stream)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        return ev0.elapsed_time(ev1) / a.matvec_reps  # ms
-
-    mv64 = time_mv(y, z)
-    y32 = y.float()
-    mv32 = time_mv(y32, torch.empty_like(y32))
+    y = torch.randn(prob.n_tot, dtype=torch.float64, device=dev)
+    mvr = matvec_timing(a, prob, inp, y, y.float())
+    mv64, gbs64, mv32, gbs32, bytes64 = (mvr["fp64_ms"], mvr["fp64_GB_s"], mvr["fp32_ms"], mvr["fp32_GB_s"],
+                                         mvr["algorithmic_bytes_fp64"])
     Nd, M = inp.Nd, inp.M
-    bytes64 = 8 * (2 * n + 2 * M * Nd)  # y in, z out, gamma1, gamma2 (compulsory)
-    gbs64 = bytes64 / (mv64 * 1e-3) / 1e9
-    gbs32 = (bytes64 / 2) / (mv32 * 1e-3) / 1e9
-
     log(f"apply_A: fp64 {mv64:.3f} ms ({gbs64:.0f} GB/s), fp32 {mv32:.3f} ms ({gbs32:.0f} GB/s)")
     last = stats[-1]
     out = {
@@ -224,9 +249,14 @@ def main():
         "mixed": mixed,
         "matvec": {"fp64_ms": mv64, "fp64_GB_s": gbs64, "fp32_ms": mv32, "fp32_GB_s": gbs32,
                    "algorithmic_bytes_fp64": bytes64},
-        "roofline": {"kernel": "apply_A (history_matvec + toep2d_rows_fwd + toep2d_cols + toep2d_rows_inv), FP64",
+        # traffic: HBM bytes of one FP64 apply_A from the FETCH_SIZE / WRITE_SIZE counter runs, scaled by
+        # a copy of known size (profiles/c3_apply_A_hbm_counters.md); to be re-measured when the kernels change
+        "roofline": {"kernel": "apply_A (history_matvec + mv_rows_fwd + mv_cols + mv_rows_inv), FP64",
                      "bound": "hbm", "achieved": gbs64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs64 / HBM_PEAK_GBS, "traffic": None},
+                     "frac": gbs64 / HBM_PEAK_GBS, "traffic": APPLY_A_TRAFFIC_FP64},
+        # the same call against the FP64 vector peak: time-history FMAs and the FFTs of the Toeplitz product
+        "alu": {"gflop_per_call": APPLY_A_GFLOP_FP64, "achieved_TFLOP_s": APPLY_A_GFLOP_FP64 / mv64,
+                "peak_TFLOP_s": FP64_PEAK_TFLOPS, "frac": APPLY_A_GFLOP_FP64 / mv64 / FP64_PEAK_TFLOPS},
     }
     if not a.no_cpu_baseline:
         log("timing the CPU oracle sample")
