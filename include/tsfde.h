@@ -48,7 +48,7 @@ typedef enum {
     TSFDE_ENOTIMPL = 6    /* combination not supported by this build               */
 } tsfde_status;
 
-typedef enum { TSFDE_FP64 = 0, TSFDE_MIXED = 1 } tsfde_precision;
+typedef enum { TSFDE_FP64 = 0, TSFDE_MIXED = 1, TSFDE_PREC_F32 = 2 } tsfde_precision;
 
 /* Solver options.  tsfde_default_opts() fills the defaults listed here. */
 typedef struct tsfde_opts {
@@ -59,7 +59,11 @@ typedef struct tsfde_opts {
     int precision;       /* TSFDE_FP64: every operator application in FP64;
                             TSFDE_MIXED: A and P^{-1} inside FGMRES in FP32, the
                             residual b - A x, Arnoldi, Givens and the update in
-                            FP64, closed by iterative refinement        (FP64)  */
+                            FP64, closed by iterative refinement;
+                            TSFDE_PREC_F32: FGMRES, A, Arnoldi and Givens in FP64
+                            and only P^{-1} applied in FP32 (a flexible, inexact
+                            preconditioner; inner_tol is raised to >= 1e-6)
+                                                                        (FP64)  */
     int use_precond;     /* 1: right preconditioning by P of §5.1; 0: none (1)   */
     double inner_tol;    /* relative residual of each diagonal-block solve inside
                             P^{-1} (preconditioned CG)                  (1e-12) */
@@ -67,7 +71,19 @@ typedef struct tsfde_opts {
     double refine_tol;   /* MIXED: relative tolerance of each inner FGMRES
                             sweep on A d = r                            (1e-5)  */
     int max_refine;      /* MIXED: max refinement sweeps                (30)    */
+    int block_solver;    /* TSFDE_BLOCK_CG: each diagonal block of P solved by
+                            tau-preconditioned CG to inner_tol (P of §5.1);
+                            TSFDE_BLOCK_TAU: the T_{n,S} variant of the §5.1
+                            Remark -- B replaced by its tau matrix and the block's
+                            coefficient ratio gamma1/gamma2 frozen at its slice
+                            mean, so each block is solved exactly by sine
+                            transforms (no inner iterations, no warm start).
+                            TSFDE_BLOCK_TAU needs d = 2 and 2(N+1) a power of
+                            two; otherwise the calls return TSFDE_ENOTIMPL
+                                                                        (CG)    */
 } tsfde_opts;
+
+typedef enum { TSFDE_BLOCK_CG = 0, TSFDE_BLOCK_TAU = 1 } tsfde_block_solver;
 
 /* Statistics of a solve.  Times are wall-clock seconds on the host, measured
    around stream-synchronised phases. */

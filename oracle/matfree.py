@@ -11,6 +11,9 @@ paragraphs), in FP64 NumPy.
                 a stated tolerance, for sizes where dense blocks do not fit).
   forward_solve the direct problem A-hat v = z-hat (§6.1): the first S steps of the
                 same forward substitution.
+  T_solve       y = T_{n,S}^{-1} z (§5.1 Remark, with the frozen-coefficient reading of
+                system.dense_T): the same forward substitution, each block solved exactly
+                by the orthonormal DST-I.
 
 The embedding size used here is 2N per direction (the smallest even size
 >= 2N-1); any size >= 2N-1 gives the same product in exact arithmetic.
@@ -20,9 +23,11 @@ from __future__ import annotations
 from typing import Callable, Optional
 
 import numpy as np
+import scipy.fft as sfft
 import scipy.sparse.linalg as spla
 
-from .system import Problem, dense_B
+from . import coeffs
+from .system import Problem, dense_B, tau_sigma
 
 
 # --------------------------------------------------------------------------
@@ -195,3 +200,35 @@ def forward_solve(p: Problem, zhat: np.ndarray, inner: str = "dense",
     forward substitution for P (A-hat is the leading S x S block part of P)."""
     zz = np.concatenate([zhat, np.zeros(p.Nd)])
     return P_solve(p, zz, inner=inner, inner_tol=inner_tol, last_block=False)
+
+
+# --------------------------------------------------------------------------
+# y = T_{n,S}^{-1} z (§5.1 Remark; blocks as in system.dense_T)
+# --------------------------------------------------------------------------
+def T_solve(p: Problem, z: np.ndarray, last_block: bool = True) -> np.ndarray:
+    """Forward substitution with the blocks of T_{n,S}:
+         s = 1..S:  r = (z^(s) - D_1^(s) sum_{m<s} e_{s-m} y^(m)) / gamma2^(s),
+                    y^(s) = S diag(1/(sigma_s + c_t lambda)) S r
+         s = S+1:   y^(S+1) = S diag(1/lambda) S (z^(S+1) - y^(S)) / (c_f gamma2^(S))
+    with S the orthonormal DST-I over every level and lambda the tau eigenvalues of B_n."""
+    S_, Nd = p.S, p.Nd
+    shape = (p.N,) * p.d
+    lam = coeffs.tau_eigenvalues(p.a())
+    sig = tau_sigma(p)
+    e = p.e()
+    Z = z.reshape(-1, Nd)
+    Y = np.zeros((S_ + 1, Nd))
+
+    def dst(v):
+        return sfft.dstn(v.reshape(shape), type=1, norm="ortho")
+
+    for s in range(S_):
+        hist = np.zeros(Nd)
+        for m in range(s):
+            hist += e[s - m] * Y[m]
+        r = (Z[s] - p.gamma1[s] * hist) / p.gamma2[s]
+        Y[s] = dst(dst(r) / (sig[s] + p.c_t * lam)).reshape(-1)
+    if last_block:
+        r = (Z[S_] - Y[S_ - 1]) / (p.c_f * p.gamma2[S_ - 1])
+        Y[S_] = dst(dst(r) / lam).reshape(-1)
+    return Y.reshape(-1)

@@ -19,6 +19,8 @@ from __future__ import annotations
 import dataclasses
 from typing import Optional
 
+import math
+
 import numpy as np
 
 from . import coeffs
@@ -106,11 +108,12 @@ def dense_B(p: Problem) -> np.ndarray:
     return B4.reshape(N * N, N * N)
 
 
-def dense_A(p: Problem) -> np.ndarray:
-    """A_{n,S} of eq. lin-syst (§5), assembled block by block."""
+def dense_A(p: Problem, B: Optional[np.ndarray] = None) -> np.ndarray:
+    """A_{n,S} of eq. lin-syst (§5), assembled block by block.  B overrides the spatial
+    matrix B_n (used to form the paper's T_{n,S}: every B_n replaced by its tau matrix)."""
     Nd, S = p.Nd, p.S
     e = p.e()
-    B = dense_B(p)
+    B = dense_B(p) if B is None else B
     A = np.zeros((p.n_tot, p.n_tot))
     I = np.eye(Nd)
     for s in range(S):  # block row s+1 of the paper
@@ -125,12 +128,53 @@ def dense_A(p: Problem) -> np.ndarray:
     return A
 
 
-def dense_P(p: Problem) -> np.ndarray:
+def dense_P(p: Problem, B: Optional[np.ndarray] = None) -> np.ndarray:
     """P_{n,S} (§5.1): A_{n,S} with the upper-right block column (rows 1..S of the
-    last block column) replaced by zeros."""
-    P = dense_A(p)
+    last block column) replaced by zeros.  B overrides B_n as in dense_A."""
+    P = dense_A(p, B)
     P[:p.S * p.Nd, p.S * p.Nd:] = 0.0
     return P
+
+
+def dst1_matrix(n: int) -> np.ndarray:
+    """The orthonormal DST-I matrix sqrt(2/(n+1)) sin(pi j k/(n+1)), j, k = 1..n (symmetric,
+    its own inverse)."""
+    j = np.arange(1, n + 1)
+    return math.sqrt(2.0 / (n + 1)) * np.sin(np.outer(j, j) * math.pi / (n + 1))
+
+
+def dense_tauB(p: Problem) -> np.ndarray:
+    """tau(B_n), the natural tau matrix of B_n (§5.1 Remark; Bini–Capovani): S diag(lambda) S with
+    S the orthonormal DST-I (tensor product over the d levels) and lambda the truncated symbol
+    (coeffs.tau_eigenvalues)."""
+    from .coeffs import tau_eigenvalues
+    lam = tau_eigenvalues(p.a())
+    S1 = dst1_matrix(p.N)
+    S = S1 if p.d == 1 else np.kron(S1, S1)
+    return S @ np.diag(lam.reshape(-1)) @ S
+
+
+def tau_sigma(p: Problem) -> np.ndarray:
+    """sigma_s = mean over the grid of e_0 gamma1^(s)/gamma2^(s), s = 1..S: the coefficient
+    ratio of block s frozen at its mean (the reading under which T_{n,S} stays fast-invertible
+    for variable coefficients)."""
+    e0 = p.e()[0]
+    return np.array([np.mean(e0 * p.gamma1[s] / p.gamma2[s]) for s in range(p.S)])
+
+
+def dense_T(p: Problem) -> np.ndarray:
+    """T_{n,S} of the §5.1 Remark, with variable coefficients read as follows: P_{n,S} with
+    B_n replaced by tau(B_n) and each diagonal block e_0 D_1 + c_t D_2 B_n replaced by
+    D_2 (sigma_s I + c_t tau(B_n)), sigma_s = mean(e_0 gamma1^(s)/gamma2^(s)).  For constant
+    coefficients this is exactly P_{n,S} with every B_n replaced by tau(B_n)."""
+    Nd, S = p.Nd, p.S
+    T = dense_P(p, dense_tauB(p))
+    tB = dense_tauB(p)
+    sig = tau_sigma(p)
+    I = np.eye(Nd)
+    for s in range(S):
+        T[s * Nd:(s + 1) * Nd, s * Nd:(s + 1) * Nd] = p.gamma2[s][:, None] * (sig[s] * I + p.c_t * tB)
+    return T
 
 
 def rhs_z(p: Problem) -> np.ndarray:

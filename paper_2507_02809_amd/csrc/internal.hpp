@@ -148,7 +148,7 @@ void launch_jacobi_prec(const T* r, T* z, const T* dg, T c, T a0, long long n, T
 bool persistent_supported(const Problem& P);
 template <typename T>
 long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T* z, T* y, double inner_tol,
-                              int inner_maxit, bool last_block, int extrap, hipStream_t st);
+                              int inner_maxit, bool last_block, int extrap, int tblocks, hipStream_t st);
 template <typename T>
 void pinv_persistent_free(void* wptr);
 void set_persistent_blocks(int g);

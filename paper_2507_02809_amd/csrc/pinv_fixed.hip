@@ -10,14 +10,13 @@ bool launch_segments_fixed(Problem& P, const Dev<T>& D, PersistentWork<T>& W, co
     if (P.d != 2 || !P.tau_ok || P.Ld != P.L) return false;
     switch (P.L) {
         case 256:
-            launch_segments<T, 8, SEG_2D_TAU, 256>(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, blocks, st);
+            launch_segments<T, 8, SEG_2D_TAU, 256, false>(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, blocks, st);
             return true;
         case 512:
-            launch_segments<T, 8, SEG_2D_TAU, 512>(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, blocks, st);
+            launch_segments<T, 8, SEG_2D_TAU, 512, false>(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, blocks, st);
             return true;
         case 1024:
-            launch_segments<T, 8, SEG_2D_TAU, 1024>(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, blocks,
-                                                    st);
+            launch_segments<T, 8, SEG_2D_TAU, 1024, false>(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, blocks, st);
             return true;
         default:
             return false;

@@ -785,9 +785,12 @@ __host__ __device__ constexpr int spec_stride(int N) { return (N + 15) & ~15; }
 
 // LC > 0: the transform length is the compile-time constant LC (2D sine-transform path, where
 // L = 2(N + 1)); LC = 0: lengths are taken from the arguments
-template <typename T, int VPT, int MODE, int LC>
+// TB: the tau-block form (each block solved by one application of its frozen-coefficient tau
+// matrix, from zero; 2D tau path only)
+template <typename T, int VPT, int MODE, int LC, bool TB>
 __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int sa, int sb) {
     static_assert(LC == 0 || MODE == SEG_2D_TAU, "a fixed length is provided for the 2D tau path only");
+    static_assert(!TB || MODE == SEG_2D_TAU, "the tau-block form runs on the 2D tau path only");
     PinvArgs<T> a = ain;
     if constexpr (LC > 0) {
         a.d = 2;
@@ -928,7 +931,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
         // hn = sum over the near-history terms m in [sa, s-1) of e_{s-m} y_m
         auto e_load = [&](long long j) -> EIn {
             EIn v;
-            const bool ext = (s >= 2 && !lastrow && a.extrap);
+            const bool ext = (s >= 2 && !lastrow && a.extrap && !TB);
             v.xv = (s > 0) ? a.x[j] : T(0);
             v.rhs_o = (s > 0) ? a.rhs[j] : T(0);
             v.r_o = (s > 0) ? a.r[j] : T(0);
@@ -956,7 +959,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
         };
         // the rest of point j: returns r0 and adds to (r, r), (b, b)
         auto e_store = [&](long long j, const EIn& v, T& rr, T& bb) -> T {
-            const bool ext = (s >= 2 && !lastrow && a.extrap);
+            const bool ext = (s >= 2 && !lastrow && a.extrap && !TB);
             const T yprev = v.xv;
             const T bxprev = (s > 0) ? (v.rhs_o - v.r_o - v.dgp * yprev) / a.ct : T(0);  // B y_{s-1}
             T rhs, x0 = T(0), bx0 = T(0);
@@ -965,7 +968,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
             } else {
                 const T h = v.hn + e1 * yprev;
                 rhs = v.zo - v.dgo * h;
-                if (s >= 1) {
+                if (s >= 1 && !TB) {
                     x0 = ext ? T(2) * yprev - v.ym2 : yprev;
                     bx0 = ext ? T(2) * bxprev - v.bxb : bxprev;
                 }
@@ -1051,6 +1054,37 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
             }
             grid_barrier(a.bar, epoch);
             continue;
+        }
+        if constexpr (TAU2) {
+            if constexpr (TB) {
+                // y_s = M_s^{-1} rhs_s: pass B, then the last sine transform of each row pair straight
+                // into x.  The next step's phase E reads these points in the same thread, so no
+                // device-wide barrier follows.
+                T rzl = T(0);
+                for (int rd = 0; rd < NR; ++rd) {
+                    const int kbase = 2 * (rd * NG + blockIdx.x * gpb);
+                    wg_pass_B<T, VPT>(a, cbase, c, twl, kbase, grp, gpb, sig, cc, scale, tid, nthr, rzl);
+                }
+                grid_barrier(a.bar, epoch);
+                for (int rd = 0; rd < NR; ++rd) {
+                    const int ibase = 2 * (rd * NG + blockIdx.x * gpb);
+                    const int i0 = ibase + 2 * grp;
+                    const bool valid = i0 < N;
+                    g_dst_rows<T, VPT>(a, c, twl, a.t2, a.ns, i0, valid, tid, nthr);
+#pragma unroll
+                    for (int u = 0; u < VPT / 2; ++u) {
+                        const int m = tid + u * nthr;
+                        if (valid && m < N) {
+                            const cplx<T> C = c[lx(m + 1)];
+                            const long long o0 = (long long)i0 * N + m;
+                            a.x[o0] = T(-0.5) * C.y;
+                            if (i0 + 1 < N) a.x[o0 + N] = T(0.5) * C.x;
+                        }
+                    }
+                    __syncthreads();  // the sequences are reused
+                }
+                continue;
+            }
         }
         if (rrt <= a.tol2 * bbt) continue;  // the warm start already meets the tolerance
 
@@ -1195,7 +1229,9 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
         total_it += it;
         }
     }
-    // the segment's last step: y_{sb-1} = x (same pointwise ownership as phase E)
+    // the segment's last step: y_{sb-1} = x (grid-stride ownership: in the tau-block mode x was
+    // last written by row-owning groups, so the grid synchronises first)
+    if constexpr (TB) grid_barrier(a.bar, epoch);
     for (long long j = gtid; j < Nd; j += gthreads) a.y[(long long)(sb - 1) * Nd + j] = a.x[j];
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.iters += total_it;
 }
@@ -1217,7 +1253,7 @@ struct PersistentWork {
 template <typename T>
 void ensure_work(Problem& P, PersistentWork<T>& W);
 
-template <typename T, int VPT, int MODE, int LC>
+template <typename T, int VPT, int MODE, int LC, bool TB>
 void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T* z, T* y, double inner_tol,
                      int inner_maxit, bool last_block, int extrap, int blocks, hipStream_t st) {
     PinvArgs<T> a{};
@@ -1273,7 +1309,7 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
         if (blocks > 0) grid = blocks;
     }
     int per_cu = 0;
-    TSFDE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pinv_segment<T, VPT, MODE, LC>, block, lds));
+    TSFDE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pinv_segment<T, VPT, MODE, LC, TB>, block, lds));
     int dev = 0, ncu = 0;
     TSFDE_HIP(hipGetDevice(&dev));
     TSFDE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1291,13 +1327,17 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
         }
         launch_fill(reinterpret_cast<float*>(W.bar), 1, 0.0f, st);  // zero the barrier counter
         void* args[] = {&a, &sa_, &sb_};
-        TSFDE_HIP(hipLaunchCooperativeKernel((void*)pinv_segment<T, VPT, MODE, LC>, dim3(grid), dim3(block), args, lds, st));
+        TSFDE_HIP(hipLaunchCooperativeKernel((void*)pinv_segment<T, VPT, MODE, LC, TB>, dim3(grid), dim3(block), args, lds, st));
     }
 }
 
-// launches of the fixed-length 2D sine-transform kernels; false if L has no fixed-length kernel
+// launches of the fixed-length 2D sine-transform kernels (CG blocks: pinv_fixed.hip; tau blocks:
+// pinv_fixed_tau.hip); false if L has no fixed-length kernel
 template <typename T>
 bool launch_segments_fixed(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T* z, T* y, double inner_tol,
                            int inner_maxit, bool last_block, int extrap, int blocks, hipStream_t st);
+template <typename T>
+bool launch_segments_fixed_tau(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T* z, T* y, bool last_block,
+                               int blocks, hipStream_t st);
 
 }  // namespace tsfde

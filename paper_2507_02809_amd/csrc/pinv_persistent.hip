@@ -32,7 +32,7 @@ bool persistent_supported(const Problem& P) {
 
 template <typename T>
 long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T* z, T* y, double inner_tol,
-                              int inner_maxit, bool last_block, int extrap, hipStream_t st) {
+                              int inner_maxit, bool last_block, int extrap, int tblocks, hipStream_t st) {
     if (!wptr) wptr = new PersistentWork<T>();
     PersistentWork<T>& W = *static_cast<PersistentWork<T>*>(wptr);
     ensure_work(P, W);
@@ -40,12 +40,21 @@ long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T*
     const int vpt = (L <= 2048) ? 8 : (L == 4096 ? 16 : 32);
     const int mode = (P.d == 1) ? SEG_1D : (P.tau_ok ? SEG_2D_TAU : SEG_2D_DIAG);
     const int blocks = g_blocks_override;
-    if (mode == SEG_2D_TAU && g_fixed_length &&
-        launch_segments_fixed<T>(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, blocks, st)) {
+    if (tblocks) {
+        // tau-block form: no inner iterations, no warm start (the caller has checked the path)
+        if (mode != SEG_2D_TAU) throw HipError{hipErrorNotSupported, "tau-block P^-1 outside the 2D tau path"};
+        if (!(g_fixed_length && launch_segments_fixed_tau<T>(P, D, W, z, y, last_block, blocks, st))) {
+            if (vpt == 8) launch_segments<T, 8, SEG_2D_TAU, 0, true>(P, D, W, z, y, 0.0, 1, last_block, 0, blocks, st);
+            else if (vpt == 16)
+                launch_segments<T, 16, SEG_2D_TAU, 0, true>(P, D, W, z, y, 0.0, 1, last_block, 0, blocks, st);
+            else launch_segments<T, 32, SEG_2D_TAU, 0, true>(P, D, W, z, y, 0.0, 1, last_block, 0, blocks, st);
+        }
+    } else if (mode == SEG_2D_TAU && g_fixed_length &&
+               launch_segments_fixed<T>(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, blocks, st)) {
         // done by a fixed-length kernel
     } else {
 #define TSFDE_SEG(V, B) \
-    launch_segments<T, V, B, 0>(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, blocks, st)
+    launch_segments<T, V, B, 0, false>(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, blocks, st)
 #define TSFDE_SEG_MODES(V)                                       \
     do {                                                         \
         if (mode == SEG_1D) TSFDE_SEG(V, SEG_1D);                \
@@ -80,9 +89,9 @@ void set_persistent_fixed_length(bool on) { g_fixed_length = on; }
 template void ensure_work<double>(Problem&, PersistentWork<double>&);
 template void ensure_work<float>(Problem&, PersistentWork<float>&);
 template long long pinv_persistent_run<double>(Problem&, const Dev<double>&, void*&, const double*, double*, double,
-                                               int, bool, int, hipStream_t);
+                                               int, bool, int, int, hipStream_t);
 template long long pinv_persistent_run<float>(Problem&, const Dev<float>&, void*&, const float*, float*, double, int,
-                                              bool, int, hipStream_t);
+                                              bool, int, int, hipStream_t);
 template void pinv_persistent_free<double>(void*);
 template void pinv_persistent_free<float>(void*);
 

@@ -43,6 +43,7 @@ constexpr double kInnerTolF32 = 1e-6;
 
 struct Opts {
     int restart = 50, maxit = 0, precision = TSFDE_FP64, use_precond = 1, inner_maxit = 200, max_refine = 30;
+    int block_solver = TSFDE_BLOCK_CG;
     double tol = 1e-10, inner_tol = 1e-12, refine_tol = 1e-5;
 };
 
@@ -58,6 +59,7 @@ static Opts get_opts(const tsfde_opts* o) {
     r.inner_maxit = o->inner_maxit;
     r.refine_tol = o->refine_tol;
     r.max_refine = o->max_refine;
+    r.block_solver = o->block_solver;
     return r;
 }
 
@@ -70,6 +72,10 @@ static bool check_opts(const Opts& o) {
     if (o.inner_maxit < 1 || o.max_refine < 1) { set_error("opts.inner_maxit and max_refine must be >= 1"); return false; }
     if (o.precision != TSFDE_FP64 && o.precision != TSFDE_MIXED && o.precision != TSFDE_PREC_F32) {
         set_error("opts.precision invalid");
+        return false;
+    }
+    if (o.block_solver != TSFDE_BLOCK_CG && o.block_solver != TSFDE_BLOCK_TAU) {
+        set_error("opts.block_solver invalid");
         return false;
     }
     return true;
@@ -100,6 +106,14 @@ static int env_int(const char* name, int dflt) {
     return (e && *e) ? std::atoi(e) : dflt;
 }
 
+// the tau-block form runs on the persistent 2D sine-transform path only
+static bool block_solver_supported(const Problem& P, const Opts& o) {
+    if (o.block_solver != TSFDE_BLOCK_TAU || !o.use_precond) return true;
+    if (P.d == 2 && P.tau_ok && persistent_supported(P) && env_int("TSFDE_PINV", 1) != 0) return true;
+    set_error("opts.block_solver = TSFDE_BLOCK_TAU needs d = 2 with 2(N+1) a power of two");
+    return false;
+}
+
 template <typename T>
 static void*& pwork(Problem& P);
 template <>
@@ -121,7 +135,7 @@ static long long pinv_impl(Problem& P, const T* z, T* y, const Opts& o, hipStrea
         set_persistent_blocks(env_int("TSFDE_PINV_BLOCKS", -1));
         set_persistent_fixed_length(env_int("TSFDE_PINV_FIXED", 1) != 0);
         return pinv_persistent_run<T>(P, dev<T>(P), pwork<T>(P), z, y, o.inner_tol, o.inner_maxit, last_block,
-                                      env_int("TSFDE_EXTRAP", 1), st);
+                                      env_int("TSFDE_EXTRAP", 1), o.block_solver == TSFDE_BLOCK_TAU ? 1 : 0, st);
     }
     return pinv_launch<T>(P, z, y, o, st, last_block);
 }
@@ -475,6 +489,7 @@ void tsfde_default_opts(tsfde_opts* o) {
     o->maxit = 0;
     o->tol = 1e-10;
     o->precision = TSFDE_FP64;
+    o->block_solver = TSFDE_BLOCK_CG;
     o->use_precond = 1;
     o->inner_tol = 1e-12;
     o->inner_maxit = 200;
@@ -560,6 +575,7 @@ tsfde_status tsfde_apply_P_inv(tsfde_problem* prob, const double* z, double* y, 
     if (overlap(y, z, sizeof(double) * P.ntot)) { set_error("apply_P_inv: y and z overlap"); return TSFDE_EINVAL; }
     const Opts o = get_opts(opts);
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
     TSFDE_GUARD("apply_P_inv", pinv_impl<double>(P, z, y, o, (hipStream_t)stream, true);)
     return TSFDE_OK;
 }
@@ -571,6 +587,7 @@ tsfde_status tsfde_apply_P_inv_f32(tsfde_problem* prob, const float* z, float* y
     if (overlap(y, z, sizeof(float) * P.ntot)) { set_error("apply_P_inv_f32: y and z overlap"); return TSFDE_EINVAL; }
     Opts o = get_opts(opts);
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
     o.inner_tol = std::max(o.inner_tol, kInnerTolF32);
     TSFDE_GUARD("apply_P_inv_f32", pinv_impl<float>(P, z, y, o, (hipStream_t)stream, true);)
     return TSFDE_OK;
@@ -583,6 +600,7 @@ tsfde_status tsfde_gmres_solve(tsfde_problem* prob, const double* b, double* x, 
     const Opts o = get_opts(opts);
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
     if (b && overlap(b, x, sizeof(double) * P.ntot)) { set_error("gmres_solve: b and x overlap"); return TSFDE_EINVAL; }
+    if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
     tsfde_stats S{};
     tsfde_status rc = TSFDE_OK;
     hipStream_t st = (hipStream_t)stream;
@@ -604,6 +622,7 @@ tsfde_status tsfde_recover_f(tsfde_problem* prob, double* f_out, double* work, c
     Problem& P = *prob->p;
     const Opts o = get_opts(opts);
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
     tsfde_stats S{};
     tsfde_status rc = TSFDE_OK;
     hipStream_t st = (hipStream_t)stream;
@@ -628,8 +647,9 @@ tsfde_status tsfde_forward_solve(tsfde_problem* prob, const double* f, double* v
                                  void* stream) {
     if (!prob || !f || !v) { set_error("forward_solve: NULL argument"); return TSFDE_EINVAL; }
     Problem& P = *prob->p;
-    const Opts o = get_opts(opts);
+    Opts o = get_opts(opts);
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    o.block_solver = TSFDE_BLOCK_CG;  // the direct problem is solved, not preconditioned
     hipStream_t st = (hipStream_t)stream;
     TSFDE_GUARD("forward_solve", {
         double* zh = nullptr;

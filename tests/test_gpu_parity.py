@@ -92,6 +92,10 @@ def test_gmres_fp64_and_mixed_match_dense_lu(dense_case):
         fm, sm = g.recover_f(tsfde.default_opts(tol=1e-12, precision=tsfde.MIXED), raise_noconv=True)
         assert sm.converged == 1 and sm.refinements >= 1
         assert rel_err(fm.cpu().numpy(), f_lu) <= 1e-8
+        # FP64 Krylov solve with the preconditioner applied in FP32: same FP64 residual target
+        fp, sp = g.recover_f(tsfde.default_opts(tol=3e-13, precision=tsfde.PREC_F32), raise_noconv=True)
+        assert sp.converged == 1 and sp.rel_res <= 3e-13
+        assert rel_err(fp.cpu().numpy(), f_lu) <= 1e-10
         # explicit right-hand side and initial guess through gmres_solve
         x, st2 = g.gmres_solve(torch.tensor(b, device=DEV), opts=tsfde.default_opts(tol=3e-13, inner_tol=1e-14))
         assert np.linalg.norm(x.cpu().numpy() - x_lu) <= 1e-10 * np.linalg.norm(x_lu)
@@ -225,3 +229,59 @@ def test_apply_P_inv_full_size_c3_residual():
         if s < p.S:
             py += p.eta * p.q[s] * y[p.S * p.Nd + j]
         assert abs(py - zz[s * p.Nd + j]) <= 1e-8 * np.abs(zz).max(), (s, j)
+
+
+# ---------------------------------------------------------------------------
+# T_{n,S}: the tau-block form of the preconditioner (opts.block_solver = BLOCK_TAU)
+# ---------------------------------------------------------------------------
+def _tau_path(p) -> bool:
+    """The tau-block form runs where the sine-transform path does: d = 2, 2(N+1) a power of two."""
+    n = 2 * (p.N + 1)
+    return p.d == 2 and (n & (n - 1)) == 0
+
+
+def test_apply_P_inv_tau_blocks_matches_dense_T(dense_case):
+    """y = T^{-1} z (each block solved by sine transforms) against LU of the assembled T; other
+    shapes report ENOTIMPL."""
+    inp, p, _, _ = dense_case
+    rng = np.random.default_rng(21)
+    zz = rng.standard_normal(p.n_tot)
+    o = tsfde.default_opts(block_solver=tsfde.BLOCK_TAU)
+    with gpu_problem(inp, p) as g:
+        if not _tau_path(p):
+            with pytest.raises(tsfde.TsfdeError) as ei:
+                g.apply_P_inv(torch.tensor(zz, device=DEV), opts=o)
+            assert ei.value.status == tsfde.ENOTIMPL
+            return
+        y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=o).cpu().numpy()
+        y32 = g.apply_P_inv(torch.tensor(zz, device=DEV, dtype=torch.float32), opts=o).cpu().double().numpy()
+    ref = np.linalg.solve(system.dense_T(p), zz)
+    assert rel_err(y, ref) <= 1e-12
+    assert rel_err(y32, ref) <= 1e-5
+
+
+def test_gmres_tau_blocks_reaches_dense_lu(dense_case):
+    """FGMRES preconditioned by T reaches the same solution as dense LU of A."""
+    inp, p, A, _ = dense_case
+    if not _tau_path(p):
+        pytest.skip("the tau-block form needs d = 2 and 2(N+1) a power of two")
+    x_lu = np.linalg.solve(A, system.rhs_z(p))
+    with gpu_problem(inp, p) as g:
+        f, st = g.recover_f(tsfde.default_opts(tol=3e-13, block_solver=tsfde.BLOCK_TAU), raise_noconv=True)
+        assert st.converged == 1 and st.inner_iters == 0
+        fp, sp = g.recover_f(tsfde.default_opts(tol=3e-13, block_solver=tsfde.BLOCK_TAU,
+                                                precision=tsfde.PREC_F32), raise_noconv=True)
+        assert sp.converged == 1
+    assert rel_err(f.cpu().numpy(), x_lu[p.S * p.Nd:]) <= 1e-10
+    assert rel_err(fp.cpu().numpy(), x_lu[p.S * p.Nd:]) <= 1e-10
+
+
+@pytest.mark.parametrize("fixed", [True, False])
+def test_apply_P_inv_tau_blocks_n127_matches_oracle(monkeypatch, fixed):
+    """N = 127 (fixed-length and run-time-length kernels) against the oracle's matrix-free T^{-1}."""
+    monkeypatch.setenv("TSFDE_PINV_FIXED", "1" if fixed else "0")
+    inp, p, zz, _ = _n127_case()
+    ref = matfree.T_solve(p, zz)
+    with gpu_problem(inp, p) as g:
+        y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=tsfde.default_opts(block_solver=tsfde.BLOCK_TAU))
+    assert rel_err(y.cpu().numpy(), ref) <= 1e-12

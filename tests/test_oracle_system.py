@@ -1,5 +1,6 @@
 """Pins of the oracle's assembly, products and solvers: brute force on tiny inputs,
 invariants of §5, and the printed condition numbers / GMRES iteration counts of §6."""
+import dataclasses
 import math
 import os
 
@@ -222,3 +223,71 @@ def test_paper_2d_gmres_iterations_16_16():
     _, it, _ = krylov.gmres(lambda v: A @ v, system.rhs_z(p), 1e-8, 1000,
                             M_left=lambda v: sl.lu_solve(lu, v))
     assert abs(it - int(r[3])) <= 2
+
+
+# ---------------------------------------------------------------------------
+# T_{n,S} (§5.1 Remark): B_n replaced by its tau matrix
+# ---------------------------------------------------------------------------
+def _hankel_part(a1: np.ndarray) -> np.ndarray:
+    """H of the natural tau splitting T = tau(T) + H for a symmetric Toeplitz matrix with first
+    column a1 (Bini–Capovani), 0-based with k = i + j: H_ij = a_{k+2} for k <= n-3 (upper-left
+    anti-diagonals) and a_{2n-k} for k >= n+1 (lower-right), zero in between."""
+    n = a1.shape[0]
+    H = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            k = i + j
+            if k <= n - 3:
+                H[i, j] = a1[k + 2]
+            elif k >= n + 1:
+                H[i, j] = a1[2 * n - k]
+    return H
+
+
+def test_dense_tauB_is_the_natural_tau_matrix_1d():
+    """1D: dense_tauB = B - H, the natural tau matrix written out from the Toeplitz entries."""
+    p = workloads.problem(inputs.small(1, 17, 4))
+    B = system.dense_B(p)
+    np.testing.assert_allclose(system.dense_tauB(p), B - _hankel_part(p.a()), atol=1e-14)
+
+
+def test_dense_tauB_2d_is_diagonalised_by_the_2d_sine_transform():
+    """2D: tau(B) is diagonalised by S (x) S with the truncated symbol as its eigenvalues (the
+    symbol itself is pinned against the natural tau matrix in test_oracle_coeffs)."""
+    p = workloads.problem(inputs.small(2, 6, 3))
+    tB = system.dense_tauB(p)
+    S1 = system.dst1_matrix(p.N)
+    S = np.kron(S1, S1)
+    D = S @ tB @ S
+    np.testing.assert_allclose(D, np.diag(np.diag(D)), atol=1e-12)
+    np.testing.assert_allclose(np.diag(D), system.coeffs.tau_eigenvalues(p.a()).reshape(-1), rtol=1e-12)
+    np.testing.assert_allclose(tB, tB.T, atol=1e-14)
+
+
+def test_dense_T_constant_coefficients_is_P_with_tau():
+    """For constant gamma1, gamma2 the frozen-coefficient T equals P with every B replaced by
+    tau(B) — the paper's T_{n,S} exactly."""
+    inp = inputs.small(2, 5, 4)
+    p = workloads.problem(inp)
+    p = dataclasses.replace(p, gamma1=np.full_like(p.gamma1, 1.3), gamma2=np.full_like(p.gamma2, 0.7))
+    np.testing.assert_allclose(system.dense_T(p), system.dense_P(p, system.dense_tauB(p)), atol=1e-13)
+
+
+@pytest.mark.parametrize("d,N,M", [(1, 15, 6), (2, 7, 4)])
+def test_T_solve_matches_dense_T(d, N, M):
+    """Matrix-free T_{n,S}^{-1} (DST-I block solves) against LU of the assembled T."""
+    p = workloads.problem(inputs.small(d, N, M))
+    z = np.random.default_rng(3).standard_normal(p.n_tot)
+    np.testing.assert_allclose(matfree.T_solve(p, z), np.linalg.solve(system.dense_T(p), z),
+                               rtol=1e-11, atol=1e-12 * np.abs(z).max())
+
+
+def test_fgmres_with_T_reaches_the_dense_solution():
+    """T_{n,S} as a right preconditioner changes only the path of the Krylov solve."""
+    p = workloads.problem(inputs.small(2, 7, 5))
+    b = system.rhs_z(p)
+    x_lu = np.linalg.solve(system.dense_A(p), b)
+    A = system.dense_A(p)
+    x, its, _ = krylov.fgmres(lambda v: A @ v, lambda v: matfree.T_solve(p, v), b, tol=1e-13, restart=60,
+                              maxit=300)
+    np.testing.assert_allclose(x, x_lu, rtol=1e-9, atol=1e-10 * np.abs(x_lu).max())
