@@ -125,11 +125,15 @@ template <typename T>
 void launch_cg_update_p(T* p, const T* z, const double* scal, long long n, hipStream_t s);
 void launch_cg_scalars(double* scal, int mode, hipStream_t s);
 
-// Arnoldi helpers (FP64)
+// Arnoldi helpers (FP64), 1 <= k <= kArnMaxK basis vectors; partials holds k * nblk doubles
+constexpr int kArnMaxK = 64;
 void launch_multidot(const double* V, long long n, int k, const double* w, double* partials,
                      int nblk, hipStream_t s);
+void launch_cgs_sub_dot(const double* V, long long n, int k, const double* h, double* w, double* partials,
+                        int nblk, hipStream_t s);
+void launch_cgs_sub_norm(const double* V, long long n, int k, const double* h, double* w, double* partials,
+                         int nblk, hipStream_t s);
 void launch_multidot_finish(const double* partials, int nblk, int k, double* h, hipStream_t s);
-void launch_gemv_sub(const double* V, long long n, int k, const double* h, double* w, hipStream_t s);
 void launch_gemv_add(const double* Z, long long n, int k, const double* y, double* x, hipStream_t s);
 void launch_scale(double* v, long long n, const double* num, const double* den, hipStream_t s);
 void launch_axpby(double a, const double* x, double b, const double* y, double* out, long long n,

@@ -3,6 +3,8 @@
 // Arnoldi (classical Gram-Schmidt) reductions and small vector helpers.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace tsfde {
@@ -235,63 +237,196 @@ void launch_fill(float* p, long long n, float v, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Arnoldi helpers (FP64).  multidot: partials[blk][k] = sum over the block's chunk of V[k] . w
+// Arnoldi helpers (FP64): classical Gram-Schmidt with one reorthogonalisation over the basis
+// V[0..k) (k rows of n, row-major), in three passes over V:
+//   multidot       h1 = V^T w
+//   cgs_sub_dot    w -= V h1, then h2 = V^T w, from the same loads of V
+//   cgs_sub_norm   w -= V h2, then ||w||^2
+// Each pass splits n into gridDim.x contiguous chunks, one per block, and writes per-block partial
+// sums partials[t * gridDim.x + block]; multidot_finish adds them in a fixed order.  Row indices past
+// k - 1 are clamped to k - 1 (their coefficients are zero, their sums unused), so that a thread's
+// loads of one element carry no branches and are all in flight together.
 // ---------------------------------------------------------------------------
-constexpr int kMD = 8;  // basis vectors per pass over w
+constexpr int kArnBlock = 256;
 
-__global__ void multidot_k(const double* __restrict__ V, long long n, int k, const double* __restrict__ w,
-                           double* __restrict__ partials) {
-    __shared__ double red[4];
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+    return v;
+}
+
+// h = V^T w: the block's 4 waves split the rows (RT per wave, the last wave's clamped), each wave
+// sweeps the whole chunk and owns its rows' sums, so no block-wide reduction is needed.
+template <int RT>
+__global__ __launch_bounds__(kArnBlock) void multidot_k(const double* __restrict__ V, long long n, int k,
+                                                        const double* __restrict__ w, double* __restrict__ partials) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int t0 = (threadIdx.x / kWave) * RT;
+    if (t0 >= k) return;  // wave-uniform
     const long long chunk = (n + gridDim.x - 1) / gridDim.x;
     const long long lo = (long long)blockIdx.x * chunk;
     const long long hi = min(n, lo + chunk);
-    for (int k0 = 0; k0 < k; k0 += kMD) {
-        double acc[kMD];
+    const double* row[RT];
 #pragma unroll
-        for (int t = 0; t < kMD; ++t) acc[t] = 0.0;
-        const int kk = min(kMD, k - k0);
-        for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-            const double wv = w[i];
+    for (int r = 0; r < RT; ++r) row[r] = V + (long long)min(t0 + r, k - 1) * n;
+    double acc[RT];
 #pragma unroll
-            for (int t = 0; t < kMD; ++t)
-                if (t < kk) acc[t] += V[(long long)(k0 + t) * n + i] * wv;
-        }
-        for (int t = 0; t < kk; ++t) {
-            double s = block_sum(acc[t], red);
-            if (threadIdx.x == 0) partials[(long long)blockIdx.x * k + k0 + t] = s;
-        }
+    for (int r = 0; r < RT; ++r) acc[r] = 0.0;
+    for (long long i = lo + lane; i < hi; i += kWave) {
+        double v[RT];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) v[r] = row[r][i];
+        const double wv = w[i];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) acc[r] += v[r] * wv;
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+        const double sum = wave_sum(acc[r]);
+        if (lane == 0 && t0 + r < k) partials[(long long)(t0 + r) * gridDim.x + blockIdx.x] = sum;
     }
 }
+
+// Sums acc[t] (t < kk) over the block; thread t writes the total to out[t * ostride].
+// red holds (kArnBlock / 64) * KB doubles.
+template <int KB>
+__device__ __forceinline__ void block_sum_multi(const double (&acc)[KB], int kk, double* red, double* out,
+                                                long long ostride) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int t = 0; t < KB; ++t) {
+        if (t < kk) {
+            const double v = wave_sum(acc[t]);
+            if (lane == 0) red[wid * KB + t] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < kk) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < kArnBlock / kWave; ++q) s += red[q * KB + threadIdx.x];
+        out[threadIdx.x * ostride] = s;
+    }
+    __syncthreads();
+}
+
+// Loads h[0..k) into hs[0..KB), zero past k
+template <int KB>
+__device__ __forceinline__ void load_coeffs(const double* h, int k, double* hs) {
+    if ((int)threadIdx.x < KB) hs[threadIdx.x] = (int)threadIdx.x < k ? h[threadIdx.x] : 0.0;
+    __syncthreads();
+}
+
+// w -= V h; then partials of V^T w (the reorthogonalisation's coefficients), k <= KB
+template <int KB>
+__global__ __launch_bounds__(kArnBlock) void cgs_sub_dot_k(const double* __restrict__ V, long long n, int k,
+                                                           const double* __restrict__ h, double* __restrict__ w,
+                                                           double* __restrict__ partials) {
+    __shared__ double red[(kArnBlock / kWave) * KB];
+    __shared__ double hs[KB];
+    load_coeffs<KB>(h, k, hs);
+    const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+    const long long lo = (long long)blockIdx.x * chunk;
+    const long long hi = min(n, lo + chunk);
+    double acc[KB];
+#pragma unroll
+    for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+    for (long long i = lo + threadIdx.x; i < hi; i += kArnBlock) {
+        double v[KB];
+#pragma unroll
+        for (int t = 0; t < KB; ++t) v[t] = V[(long long)min(t, k - 1) * n + i];
+        double s = w[i];
+#pragma unroll
+        for (int t = 0; t < KB; ++t) s -= v[t] * hs[t];
+        w[i] = s;
+#pragma unroll
+        for (int t = 0; t < KB; ++t) acc[t] += v[t] * s;
+    }
+    block_sum_multi<KB>(acc, k, red, partials + blockIdx.x, gridDim.x);
+}
+
+// w -= V h; then the partial sums of w . w, k <= KB
+template <int KB>
+__global__ __launch_bounds__(kArnBlock) void cgs_sub_norm_k(const double* __restrict__ V, long long n, int k,
+                                                            const double* __restrict__ h, double* __restrict__ w,
+                                                            double* __restrict__ partials) {
+    __shared__ double red[kArnBlock / kWave];
+    __shared__ double hs[KB];
+    load_coeffs<KB>(h, k, hs);
+    const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+    const long long lo = (long long)blockIdx.x * chunk;
+    const long long hi = min(n, lo + chunk);
+    double acc = 0.0;
+    for (long long i = lo + threadIdx.x; i < hi; i += kArnBlock) {
+        double v[KB];
+#pragma unroll
+        for (int t = 0; t < KB; ++t) v[t] = V[(long long)min(t, k - 1) * n + i];
+        // keep every load ahead of the dependent chain below
+        __builtin_amdgcn_sched_barrier(0);
+        double s = w[i];
+#pragma unroll
+        for (int t = 0; t < KB; ++t) s -= v[t] * hs[t];
+        w[i] = s;
+        acc += s * s;
+    }
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// Launches KERNEL<X> for the smallest X = STEP, 2 STEP, ..., MAX with X >= need
+template <int X, int STEP, int MAX, typename F>
+static void launch_tier(int need, F&& f) {
+    if constexpr (X >= MAX) {
+        f(std::integral_constant<int, MAX>{});
+    } else {
+        if (need <= X) f(std::integral_constant<int, X>{});
+        else launch_tier<X + STEP, STEP, MAX>(need, f);
+    }
+}
+
+static void check_arnoldi(long long n, int k, int nblk) {
+    if (k < 1 || k > kArnMaxK || nblk < 1 || n < 1)
+        throw HipError{hipErrorInvalidValue, "Arnoldi pass: need 1 <= k <= kArnMaxK, n >= 1, nblk >= 1"};
+}
+static_assert(kArnMaxK == 4 * 16 && kArnMaxK % 8 == 0, "Arnoldi tiers cover kArnMaxK rows");
+
 void launch_multidot(const double* V, long long n, int k, const double* w, double* partials, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL(multidot_k, dim3(nblk), dim3(256), 0, s, V, n, k, w, partials);
+    check_arnoldi(n, k, nblk);
+    launch_tier<1, 1, 16>((k + 3) / 4, [&](auto rt) {
+        hipLaunchKernelGGL(multidot_k<decltype(rt)::value>, dim3(nblk), dim3(kArnBlock), 0, s, V, n, k, w, partials);
+    });
+    TSFDE_HIP(hipGetLastError());
+}
+void launch_cgs_sub_dot(const double* V, long long n, int k, const double* h, double* w, double* partials, int nblk,
+                        hipStream_t s) {
+    check_arnoldi(n, k, nblk);
+    launch_tier<8, 8, kArnMaxK>(k, [&](auto kb) {
+        hipLaunchKernelGGL(cgs_sub_dot_k<decltype(kb)::value>, dim3(nblk), dim3(kArnBlock), 0, s, V, n, k, h, w,
+                           partials);
+    });
+    TSFDE_HIP(hipGetLastError());
+}
+void launch_cgs_sub_norm(const double* V, long long n, int k, const double* h, double* w, double* partials, int nblk,
+                         hipStream_t s) {
+    check_arnoldi(n, k, nblk);
+    launch_tier<8, 8, kArnMaxK>(k, [&](auto kb) {
+        hipLaunchKernelGGL(cgs_sub_norm_k<decltype(kb)::value>, dim3(nblk), dim3(kArnBlock), 0, s, V, n, k, h, w,
+                           partials);
+    });
     TSFDE_HIP(hipGetLastError());
 }
 
-__global__ void multidot_finish_k(const double* __restrict__ partials, int nblk, int k, double* __restrict__ h) {
+// h[t] = sum_b partials[t * nblk + b], one block per t
+__global__ void multidot_finish_k(const double* __restrict__ partials, int nblk, double* __restrict__ h) {
     __shared__ double red[4];
-    for (int t = 0; t < k; ++t) {
-        double acc = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += partials[(long long)b * k + t];
-        double s = block_sum(acc, red);
-        if (threadIdx.x == 0) h[t] = s;
-    }
+    const double* p = partials + (long long)blockIdx.x * nblk;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += p[b];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) h[blockIdx.x] = s;
 }
 void launch_multidot_finish(const double* partials, int nblk, int k, double* h, hipStream_t s) {
-    hipLaunchKernelGGL(multidot_finish_k, dim3(1), dim3(256), 0, s, partials, nblk, k, h);
-    TSFDE_HIP(hipGetLastError());
-}
-
-// w -= V[0..k) h
-__global__ void gemv_sub_k(const double* __restrict__ V, long long n, int k, const double* __restrict__ h,
-                           double* __restrict__ w) {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        double acc = w[i];
-        for (int t = 0; t < k; ++t) acc -= V[(long long)t * n + i] * h[t];
-        w[i] = acc;
-    }
-}
-void launch_gemv_sub(const double* V, long long n, int k, const double* h, double* w, hipStream_t s) {
-    hipLaunchKernelGGL(gemv_sub_k, dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, V, n, k, h, w);
+    hipLaunchKernelGGL(multidot_finish_k, dim3(k), dim3(256), 0, s, partials, nblk, h);
     TSFDE_HIP(hipGetLastError());
 }
 

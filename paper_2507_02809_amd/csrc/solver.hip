@@ -231,6 +231,40 @@ static void ensure_basis(Problem& P, int m) {
     P.basis_m = m;
 }
 
+// h = V[0..k)^T w, in chunks of at most kArnMaxK basis vectors
+static void arn_dot(const double* V, long long n, int k, const double* w, double* partials, int nblk, double* h,
+                    hipStream_t st) {
+    for (int c0 = 0; c0 < k; c0 += kArnMaxK) {
+        const int kc = std::min(kArnMaxK, k - c0);
+        launch_multidot(V + (size_t)c0 * n, n, kc, w, partials, nblk, st);
+        launch_multidot_finish(partials, nblk, kc, h + c0, st);
+    }
+}
+
+// w -= V[0..k) h; the partials then hold the block sums of w . w
+static void arn_sub_norm(const double* V, long long n, int k, const double* h, double* w, double* partials, int nblk,
+                         hipStream_t st) {
+    for (int c0 = 0; c0 < k; c0 += kArnMaxK)
+        launch_cgs_sub_norm(V + (size_t)c0 * n, n, std::min(kArnMaxK, k - c0), h + c0, w, partials, nblk, st);
+}
+
+// Classical Gram-Schmidt of w against V[0..k), repeated once (h1 then h2, the coefficients of the two
+// passes; w ends orthogonal to V and unnormalised, nrm2 = ||w||^2).  Three sweeps over V when k fits
+// one pass of the fused kernels.
+static void cgs2(const double* V, long long n, int k, double* w, double* partials, int nblk, double* h1, double* h2,
+                 double* nrm2, hipStream_t st) {
+    arn_dot(V, n, k, w, partials, nblk, h1, st);
+    if (k <= kArnMaxK) {
+        launch_cgs_sub_dot(V, n, k, h1, w, partials, nblk, st);
+        launch_multidot_finish(partials, nblk, k, h2, st);
+    } else {
+        arn_sub_norm(V, n, k, h1, w, partials, nblk, st);
+        arn_dot(V, n, k, w, partials, nblk, h2, st);
+    }
+    arn_sub_norm(V, n, k, h2, w, partials, nblk, st);
+    launch_multidot_finish(partials, nblk, 1, nrm2, st);
+}
+
 static double dev_dot(Problem& P, const double* a, const double* b, long long n, hipStream_t st) {
     int np = 0;
     launch_dot_partials<double>(a, b, n, P.f64.partial, &np, st);
@@ -248,15 +282,15 @@ static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, d
                   bool exact_final) {
     const long long n = P.ntot;
     ensure_basis(P, restart);
-    const int nblk = 2048;
+    const int nblk = 4096;
     double* partials = nullptr;
-    TSFDE_HIP(hipMalloc(&partials, sizeof(double) * nblk * (restart + 1)));
-    double* hdev = P.dev_scalars + 24;  // up to 32 values... use a dedicated buffer for long restarts
+    TSFDE_HIP(hipMalloc(&partials, sizeof(double) * nblk * kArnMaxK));
+    // hbuf: first-pass coefficients [0, restart + 2), second-pass ones [hs, 2 hs), then ||w||^2
+    const int hs = restart + 2;
     double* hbuf = nullptr;
-    TSFDE_HIP(hipMalloc(&hbuf, sizeof(double) * (restart + 2)));
-    (void)hdev;
+    TSFDE_HIP(hipMalloc(&hbuf, sizeof(double) * (2 * hs + 1)));
     std::vector<double> Hc((size_t)(restart + 1) * restart, 0.0), cs(restart), sn(restart), g(restart + 1), yk(restart);
-    std::vector<double> hcol(restart + 2), hcol2(restart + 2);
+    std::vector<double> hhost(2 * hs + 1);
     const double bnorm = std::sqrt(dev_dot(P, b, b, n, st));
     int its = 0;
     conv = false;
@@ -302,16 +336,11 @@ static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, d
             S.t_matvec += now() - t0;
             t0 = now();
             // classical Gram-Schmidt, twice
-            launch_multidot(P.V, n, j + 1, w, partials, nblk, st);
-            launch_multidot_finish(partials, nblk, j + 1, hbuf, st);
-            launch_gemv_sub(P.V, n, j + 1, hbuf, w, st);
-            TSFDE_HIP(hipMemcpyAsync(hcol.data(), hbuf, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
-            launch_multidot(P.V, n, j + 1, w, partials, nblk, st);
-            launch_multidot_finish(partials, nblk, j + 1, hbuf, st);
-            launch_gemv_sub(P.V, n, j + 1, hbuf, w, st);
-            TSFDE_HIP(hipMemcpyAsync(hcol2.data(), hbuf, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
-            const double hn = std::sqrt(dev_dot(P, w, w, n, st));  // synchronises
-            for (int i = 0; i <= j; ++i) Hc[(size_t)i * restart + j] = hcol[i] + hcol2[i];
+            cgs2(P.V, n, j + 1, w, partials, nblk, hbuf, hbuf + hs, hbuf + 2 * hs, st);
+            TSFDE_HIP(hipMemcpyAsync(hhost.data(), hbuf, sizeof(double) * (2 * hs + 1), hipMemcpyDeviceToHost, st));
+            TSFDE_HIP(hipStreamSynchronize(st));
+            const double hn = std::sqrt(hhost[2 * hs]);
+            for (int i = 0; i <= j; ++i) Hc[(size_t)i * restart + j] = hhost[i] + hhost[hs + i];
             Hc[(size_t)(j + 1) * restart + j] = hn;
             if (hn > 0.0) launch_axpby(1.0 / hn, w, 0.0, w, w, n, st);
             S.t_ortho += now() - t0;

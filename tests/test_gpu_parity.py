@@ -101,6 +101,27 @@ def test_gmres_fp64_and_mixed_match_dense_lu(dense_case):
         assert np.linalg.norm(x.cpu().numpy() - x_lu) <= 1e-10 * np.linalg.norm(x_lu)
 
 
+@pytest.mark.parametrize("restart", [3, 70])
+def test_gmres_unpreconditioned_restarts_match_dense_lu(restart):
+    """Arnoldi without the preconditioner: restart 70 takes the Gram-Schmidt sweeps past 64 basis
+    vectors (split into passes of at most 64), restart 3 restarts many times."""
+    inp = inputs.small(1, 12, 7)
+    p = workloads.with_data(inp)
+    A = system.dense_A(p)
+    b = system.rhs_z(p)
+    x_lu = np.linalg.solve(A, b)
+    with gpu_problem(inp, p) as g:
+        o = tsfde.default_opts(tol=1e-11, use_precond=0, restart=restart, maxit=20000)
+        x, st = g.gmres_solve(torch.tensor(b, device=DEV), opts=o, raise_noconv=True)
+        assert st.converged == 1 and st.rel_res <= 1e-11
+        if restart == 70:
+            assert st.iters > 64
+        else:
+            assert st.restarts >= 2
+        assert np.linalg.norm(A @ x.cpu().numpy() - b) <= 1e-10 * np.linalg.norm(b)
+        assert rel_err(x.cpu().numpy(), x_lu) <= 1e-6
+
+
 def test_forward_solve_matches_oracle():
     inp = inputs.c1()
     p = workloads.problem(inp)
