@@ -98,6 +98,19 @@ def cpu_baseline(inp, outer_iters: int, restarts: int, inner_tol: float) -> dict
             "est_seconds_per_solve": t_solve}
 
 
+def arnoldi_bytes(n: int, iters: int, restart: int) -> float:
+    """HBM bytes the FP64 Arnoldi moves in one solve: per step with k = j + 1 basis vectors, each of
+    the three Gram-Schmidt sweeps reads the k vectors and w, the last two write w, and the
+    normalisation reads and writes w (3k + 7 vectors); per cycle x += Z y reads k + 1 vectors and
+    writes one."""
+    total, left = 0, iters
+    while left > 0:
+        m = min(restart, left)
+        total += sum(3 * (j + 1) + 7 for j in range(m)) + (m + 2)
+        left -= m
+    return 8.0 * n * total
+
+
 def matvec_timing(a, prob, inp, y, y32) -> dict:
     """HIP-event time of apply_A (FP64 and FP32) on the stream the library launches on, and the
     throughput in compulsory bytes: y in, z out, gamma1, gamma2."""
@@ -234,6 +247,7 @@ def main():
     Nd, M = inp.Nd, inp.M
     log(f"apply_A: fp64 {mv64:.3f} ms ({gbs64:.0f} GB/s), fp32 {mv32:.3f} ms ({gbs32:.0f} GB/s)")
     last = stats[-1]
+    arn_bytes = arnoldi_bytes(prob.n_tot, last["iters"], 50)
     out = {
         "metric": METRIC,
         "value": a.steps / dt,
@@ -254,6 +268,9 @@ def main():
         "outer_iters": last["iters"],
         "inner_cg_iters": last["inner_iters"],
         "time_split_s": {"precond": last["t_precond"], "matvec": last["t_matvec"], "ortho": last["t_ortho"]},
+        # the Arnoldi sweeps are HBM-bound: their algorithmic bytes over the measured orthogonalisation time
+        "arnoldi": {"bytes_per_solve": arn_bytes, "GB_s": arn_bytes / last["t_ortho"] / 1e9,
+                    "frac": arn_bytes / last["t_ortho"] / 1e9 / HBM_PEAK_GBS},
         # P^{-1} is latency-bound (a chain of M+1 dependent block solves): per time step
         "p_inv": {"us_per_step": 1e6 * last["t_precond"] / max(1, last["iters"] * (M + 1)),
                   "cg_iters_per_step": last["inner_iters"] / max(1, last["iters"] * (M + 1)),

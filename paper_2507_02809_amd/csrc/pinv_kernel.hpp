@@ -79,15 +79,18 @@ struct PinvArgs {
 };
 
 // Device-wide barrier: arrive on a counter, wait until all blocks of this epoch arrived.  The
-// release/acquire pair at agent scope makes every block's earlier writes visible to every block.
+// release increment and the acquire fence after the wait (both at agent scope) make every block's
+// earlier writes visible to every block; the wait itself polls with relaxed loads, so that the
+// cache invalidation of the acquire happens once per barrier rather than once per poll.
 __device__ __forceinline__ void grid_barrier(unsigned* ctr, unsigned& epoch) {
     __syncthreads();
     if (gridDim.x > 1) {
         epoch += gridDim.x;
         if (threadIdx.x == 0) {
             __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch)
+            while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch)
                 __builtin_amdgcn_s_sleep(1);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
     }
