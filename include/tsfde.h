@@ -197,6 +197,30 @@ tsfde_status tsfde_recover_f(tsfde_problem* prob, double* f_out, double* work,
                              const tsfde_opts* opts, tsfde_stats* stats, void* stream);
 
 /*
+ * Recover f~ for several independent problems (the batched form of
+ * tsfde_recover_f, e.g. many instances, regularisation parameters or data
+ * sets).  Up to max_inflight problems (1..4) are solved at the same time,
+ * each on a non-blocking stream the library creates for it, by as many host
+ * worker threads (the calling thread is one of them).  Because one problem's
+ * preconditioner is a chain of dependent time steps that occupies only a
+ * part of the device, solving several side by side raises the throughput.
+ *   probs   count distinct problem handles (on the current HIP device)
+ *   f_out   count device pointers, f_out[i] receives N_i^d values
+ *   opts    one set of options for all problems (NULL for defaults)
+ *   stats   NULL, or count entries receiving each problem's statistics
+ *   stream  work already queued on it is finished before the batch starts;
+ *           every output is complete when the call returns
+ * Returns EINVAL for a NULL entry, a repeated problem or max_inflight out of
+ * range, ENOTIMPL if the options do not apply to one of the problems, the
+ * first device error by problem index, else ENOCONV if any problem missed
+ * the tolerance (its stats tell which; its f~ is the last iterate).  While a
+ * batch runs, other calls of this library that apply P^-1 wait for it.
+ */
+tsfde_status tsfde_recover_f_batch(tsfde_problem* const* probs, int count, double* const* f_out,
+                                   const tsfde_opts* opts, tsfde_stats* stats, int max_inflight,
+                                   void* stream);
+
+/*
  * Direct problem of §6.1: v = A-hat^{-1} z-hat with z-hat^(s) = b_{s-1} D_1^(s) rho + eta q^(s) f,
  * i.e. the first M steps of the forward substitution (used to synthesise mu).
  *   f    device, N^d        v  device, M N^d (slices v^(1..M)); mu = v^(M)

@@ -46,6 +46,8 @@ struct Dev {
     T* vecB = nullptr;
 };
 
+constexpr int kMaxRestart = 1000;  // largest FGMRES restart length accepted
+constexpr int kArnBlocks = 4096;   // blocks of the Arnoldi sweeps
 constexpr int kEpad = 256;   // leading zeros in epad (covers the history tile overhang)
 constexpr int kMaxPartials = 4096;
 
@@ -74,6 +76,9 @@ struct Problem {
     double* V = nullptr;
     double* Z = nullptr;
     int basis_m = 0;
+    double* arn_part = nullptr;  // Arnoldi block partials [kArnMaxK][kArnBlocks]
+    double* arn_h = nullptr;     // Arnoldi coefficients, 2 (kMaxRestart + 2) + 1
+    double* rwork = nullptr;     // FGMRES residual (n_tot)
     void* pw64 = nullptr;           // persistent P^{-1} work buffers (FP64 / FP32)
     void* pw32 = nullptr;
     double* dev_scalars = nullptr;  // small device scratch (dots, flags)
@@ -156,6 +161,11 @@ long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T*
 template <typename T>
 void pinv_persistent_free(void* wptr);
 void set_persistent_blocks(int g);
+// Batch mode of the calling thread: its persistent kernels are ordinary launches sized so that
+// kMaxInflight of them fit the device together (tsfde_recover_f_batch)
+constexpr int kMaxInflight = 4;
+void set_shared_launch(bool on);
+bool shared_launch();
 void set_persistent_fixed_length(bool on);  // use the fixed-length 2D sine-transform kernels where available
 
 }  // namespace tsfde

@@ -1316,7 +1316,15 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
     int dev = 0, ncu = 0;
     TSFDE_HIP(hipGetDevice(&dev));
     TSFDE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    grid = std::max(1, std::min(grid, per_cu * ncu));
+    if (per_cu < 1) throw HipError{hipErrorInvalidConfiguration, "persistent P^-1: a workgroup does not fit a CU"};
+    // The segment kernel's blocks wait for each other, so all of them must be resident at once.  A
+    // single call launches cooperatively (the runtime checks residency and does not overlap such
+    // launches).  Inside a batch, up to kMaxInflight of these kernels run side by side as ordinary
+    // launches, each limited to 1/kMaxInflight of the device's resident capacity, so that together
+    // they always fit.
+    const bool shared = shared_launch();
+    const int cap = shared ? std::max(1, per_cu * ncu / kMaxInflight) : per_cu * ncu;
+    grid = std::max(1, std::min(grid, cap));
     launch_fill(reinterpret_cast<float*>(W.iters), 2, 0.0f, st);  // zero the iteration counter
     const int s_last = last_block ? P.M : P.M - 1;
     for (int sa = 0; sa <= s_last; sa += kHB) {
@@ -1330,7 +1338,11 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
         }
         launch_fill(reinterpret_cast<float*>(W.bar), 1, 0.0f, st);  // zero the barrier counter
         void* args[] = {&a, &sa_, &sb_};
-        TSFDE_HIP(hipLaunchCooperativeKernel((void*)pinv_segment<T, VPT, MODE, LC, TB>, dim3(grid), dim3(block), args, lds, st));
+        if (shared)
+            TSFDE_HIP(hipLaunchKernel((void*)pinv_segment<T, VPT, MODE, LC, TB>, dim3(grid), dim3(block), args, lds, st));
+        else
+            TSFDE_HIP(hipLaunchCooperativeKernel((void*)pinv_segment<T, VPT, MODE, LC, TB>, dim3(grid), dim3(block), args,
+                                                 lds, st));
     }
 }
 

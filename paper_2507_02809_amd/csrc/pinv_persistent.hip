@@ -1,11 +1,13 @@
 // P^{-1} z with persistent cooperative kernels: work buffers, dispatch, and the kernels whose
 // transform length is a run-time value (the device code is in pinv_kernel.hpp).
+#include <atomic>
+
 #include "pinv_kernel.hpp"
 
 namespace tsfde {
 
-static int g_blocks_override = -1;
-static bool g_fixed_length = true;
+static std::atomic<int> g_blocks_override{-1};
+static std::atomic<bool> g_fixed_length{true};
 
 
 template <typename T>
@@ -82,6 +84,10 @@ void pinv_persistent_free(void* wptr) {
         if (p) (void)hipFree(p);
     delete W;
 }
+
+static thread_local bool t_shared_launch = false;
+void set_shared_launch(bool on) { t_shared_launch = on; }
+bool shared_launch() { return t_shared_launch; }
 
 void set_persistent_blocks(int g) { g_blocks_override = g; }
 void set_persistent_fixed_length(bool on) { g_fixed_length = on; }

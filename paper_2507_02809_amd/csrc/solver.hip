@@ -7,11 +7,17 @@
 //                iterative refinement with an FP64 residual
 //   recover_f    z of eq. lin-syst, solve from x0 = 0, f~ = last block (§5, §6)
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <functional>
+#include <mutex>
+#include <shared_mutex>
+#include <string>
+#include <system_error>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -64,7 +70,7 @@ static Opts get_opts(const tsfde_opts* o) {
 }
 
 static bool check_opts(const Opts& o) {
-    if (o.restart < 1 || o.restart > 1000) { set_error("opts.restart must be in [1, 1000]"); return false; }
+    if (o.restart < 1 || o.restart > kMaxRestart) { set_error("opts.restart must be in [1, 1000]"); return false; }
     if (!(o.tol > 0.0) || !(o.inner_tol > 0.0) || !(o.refine_tol > 0.0)) {
         set_error("opts tolerances must be > 0");
         return false;
@@ -282,13 +288,13 @@ static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, d
                   bool exact_final) {
     const long long n = P.ntot;
     ensure_basis(P, restart);
-    const int nblk = 4096;
-    double* partials = nullptr;
-    TSFDE_HIP(hipMalloc(&partials, sizeof(double) * nblk * kArnMaxK));
+    const int nblk = kArnBlocks;
+    if (!P.arn_part) TSFDE_HIP(hipMalloc(&P.arn_part, sizeof(double) * kArnBlocks * kArnMaxK));
+    if (!P.arn_h) TSFDE_HIP(hipMalloc(&P.arn_h, sizeof(double) * (2 * (kMaxRestart + 2) + 1)));
+    double* partials = P.arn_part;
     // hbuf: first-pass coefficients [0, restart + 2), second-pass ones [hs, 2 hs), then ||w||^2
     const int hs = restart + 2;
-    double* hbuf = nullptr;
-    TSFDE_HIP(hipMalloc(&hbuf, sizeof(double) * (2 * hs + 1)));
+    double* hbuf = P.arn_h;
     std::vector<double> Hc((size_t)(restart + 1) * restart, 0.0), cs(restart), sn(restart), g(restart + 1), yk(restart);
     std::vector<double> hhost(2 * hs + 1);
     const double bnorm = std::sqrt(dev_dot(P, b, b, n, st));
@@ -299,8 +305,6 @@ static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, d
         launch_fill(x, n, 0.0, st);
         conv = true;
         relres = 0.0;
-        (void)hipFree(partials);
-        (void)hipFree(hbuf);
         return 0;
     }
     while (true) {
@@ -387,8 +391,6 @@ static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, d
         }
         ++S.restarts;
     }
-    (void)hipFree(partials);
-    (void)hipFree(hbuf);
     return its;
 }
 
@@ -415,12 +417,10 @@ static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o,
             launch_f2d(F.vecB, out, n, st);
             return it;
         };
-        double* r = nullptr;
-        TSFDE_HIP(hipMalloc(&r, sizeof(double) * n));
+        if (!P.rwork) TSFDE_HIP(hipMalloc(&P.rwork, sizeof(double) * n));
         bool conv = false;
         double rel = 1.0;
-        fgmres(P, ops, b, x, r, o.tol, o.restart, maxit, st, S, conv, rel, true);
-        (void)hipFree(r);
+        fgmres(P, ops, b, x, P.rwork, o.tol, o.restart, maxit, st, S, conv, rel, true);
         S.refinements = 1;
         S.converged = conv ? 1 : 0;
         S.rel_res = rel;
@@ -504,10 +504,36 @@ struct tsfde_problem {
         return TSFDE_ENOMEM;                                                              \
     }
 
+// Calls that launch the persistent P^-1 kernels hold this lock shared; a batch holds it exclusively,
+// so that its ordinary (non-cooperative) persistent launches never share the device with the
+// cooperative launches of another call of this library.
+static std::shared_mutex g_launch_mx;
+using SharedLaunch = std::shared_lock<std::shared_mutex>;
+
 static bool overlap(const void* a, const void* b, size_t bytes) {
     const char* x = static_cast<const char*>(a);
     const char* y = static_cast<const char*>(b);
     return x < y + bytes && y < x + bytes;
+}
+
+// Builds z, solves from x0 = 0 into work (or the problem's buffer) and copies f~ out; synchronises st.
+static tsfde_status recover_impl(Problem& P, double* f_out, double* work, const Opts& o, tsfde_stats& S,
+                                 hipStream_t st) {
+    tsfde_status rc = TSFDE_OK;
+    TSFDE_GUARD("recover_f", {
+        double* x = work;
+        if (!x) {
+            if (!P.xbuf) TSFDE_HIP(hipMalloc(&P.xbuf, sizeof(double) * P.ntot));
+            x = P.xbuf;
+        }
+        launch_fill(x, P.ntot, 0.0, st);
+        launch_build_z(P, P.z_rhs, st);
+        rc = solve(P, P.z_rhs, x, o, S, st);
+        launch_copy<double>(x + (size_t)P.M * P.Nd, f_out, P.Nd, st);
+        TSFDE_HIP(hipStreamSynchronize(st));
+    })
+    if (rc == TSFDE_ENOCONV) set_error("recover_f: tolerance not reached (rel. residual %.3e)", S.rel_res);
+    return rc;
 }
 
 extern "C" {
@@ -605,6 +631,7 @@ tsfde_status tsfde_apply_P_inv(tsfde_problem* prob, const double* z, double* y, 
     const Opts o = get_opts(opts);
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
     if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
+    SharedLaunch lk(g_launch_mx);
     TSFDE_GUARD("apply_P_inv", pinv_impl<double>(P, z, y, o, (hipStream_t)stream, true);)
     return TSFDE_OK;
 }
@@ -618,6 +645,7 @@ tsfde_status tsfde_apply_P_inv_f32(tsfde_problem* prob, const float* z, float* y
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
     if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
     o.inner_tol = std::max(o.inner_tol, kInnerTolF32);
+    SharedLaunch lk(g_launch_mx);
     TSFDE_GUARD("apply_P_inv_f32", pinv_impl<float>(P, z, y, o, (hipStream_t)stream, true);)
     return TSFDE_OK;
 }
@@ -633,6 +661,7 @@ tsfde_status tsfde_gmres_solve(tsfde_problem* prob, const double* b, double* x, 
     tsfde_stats S{};
     tsfde_status rc = TSFDE_OK;
     hipStream_t st = (hipStream_t)stream;
+    SharedLaunch lk(g_launch_mx);
     TSFDE_GUARD("gmres_solve", {
         if (!b) {
             launch_build_z(P, P.z_rhs, st);
@@ -653,23 +682,86 @@ tsfde_status tsfde_recover_f(tsfde_problem* prob, double* f_out, double* work, c
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
     if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
     tsfde_stats S{};
-    tsfde_status rc = TSFDE_OK;
-    hipStream_t st = (hipStream_t)stream;
-    TSFDE_GUARD("recover_f", {
-        double* x = work;
-        if (!x) {
-            if (!P.xbuf) TSFDE_HIP(hipMalloc(&P.xbuf, sizeof(double) * P.ntot));
-            x = P.xbuf;
-        }
-        launch_fill(x, P.ntot, 0.0, st);
-        launch_build_z(P, P.z_rhs, st);
-        rc = solve(P, P.z_rhs, x, o, S, st);
-        launch_copy<double>(x + (size_t)P.M * P.Nd, f_out, P.Nd, st);
-        TSFDE_HIP(hipStreamSynchronize(st));
-    })
+    SharedLaunch lk(g_launch_mx);
+    const tsfde_status rc = recover_impl(P, f_out, work, o, S, (hipStream_t)stream);
     if (stats) *stats = S;
-    if (rc == TSFDE_ENOCONV) set_error("recover_f: tolerance not reached (rel. residual %.3e)", S.rel_res);
     return rc;
+}
+
+tsfde_status tsfde_recover_f_batch(tsfde_problem* const* probs, int count, double* const* f_out,
+                                   const tsfde_opts* opts, tsfde_stats* stats, int max_inflight, void* stream) {
+    if (count < 0 || (count > 0 && (!probs || !f_out))) {
+        set_error("recover_f_batch: count < 0 or NULL arrays");
+        return TSFDE_EINVAL;
+    }
+    if (max_inflight < 1 || max_inflight > kMaxInflight) {
+        set_error("recover_f_batch: max_inflight must be in [1, %d]", kMaxInflight);
+        return TSFDE_EINVAL;
+    }
+    const Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        if (!probs[i] || !f_out[i]) {
+            set_error("recover_f_batch: problem %d or its output is NULL", i);
+            return TSFDE_EINVAL;
+        }
+        for (int j = 0; j < i; ++j)
+            if (probs[j] == probs[i]) {
+                set_error("recover_f_batch: problem %d appears twice (entries %d and %d)", i, j, i);
+                return TSFDE_EINVAL;
+            }
+        if (!block_solver_supported(*probs[i]->p, o)) return TSFDE_ENOTIMPL;
+    }
+    if (count == 0) return TSFDE_OK;
+    std::unique_lock<std::shared_mutex> lk(g_launch_mx);
+    int dev = 0;
+    TSFDE_GUARD("recover_f_batch", {
+        TSFDE_HIP(hipGetDevice(&dev));
+        TSFDE_HIP(hipStreamSynchronize((hipStream_t)stream));
+    })
+    std::vector<tsfde_status> rcs(count, TSFDE_OK);
+    std::vector<std::string> msgs(count);
+    std::vector<tsfde_stats> S(count, tsfde_stats{});
+    std::atomic<int> next{0};
+    // each worker takes the next problem until none is left, on a stream of its own
+    auto worker = [&]() {
+        hipStream_t st = nullptr;
+        hipError_t e = hipSetDevice(dev);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        set_shared_launch(true);
+        for (int i; (i = next.fetch_add(1)) < count;) {
+            if (e != hipSuccess) {
+                rcs[i] = TSFDE_EDEVICE;
+                msgs[i] = std::string("stream creation failed: ") + hipGetErrorString(e);
+                continue;
+            }
+            rcs[i] = recover_impl(*probs[i]->p, f_out[i], nullptr, o, S[i], st);
+            if (rcs[i] != TSFDE_OK) msgs[i] = last_error();
+        }
+        set_shared_launch(false);
+        if (st) (void)hipStreamDestroy(st);
+    };
+    std::vector<std::thread> th;
+    try {
+        for (int t = 1; t < std::min(max_inflight, count); ++t) th.emplace_back(worker);
+    } catch (const std::system_error&) {
+        // fewer workers: the calling thread and those started take every problem
+    }
+    worker();
+    for (auto& t : th) t.join();
+    if (stats)
+        for (int i = 0; i < count; ++i) stats[i] = S[i];
+    for (int i = 0; i < count; ++i)
+        if (rcs[i] != TSFDE_OK && rcs[i] != TSFDE_ENOCONV) {
+            set_error("recover_f_batch: problem %d: %s", i, msgs[i].c_str());
+            return rcs[i];
+        }
+    for (int i = 0; i < count; ++i)
+        if (rcs[i] == TSFDE_ENOCONV) {
+            set_error("recover_f_batch: problem %d: %s", i, msgs[i].c_str());
+            return TSFDE_ENOCONV;
+        }
+    return TSFDE_OK;
 }
 
 tsfde_status tsfde_forward_solve(tsfde_problem* prob, const double* f, double* v, const tsfde_opts* opts,
@@ -680,6 +772,7 @@ tsfde_status tsfde_forward_solve(tsfde_problem* prob, const double* f, double* v
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
     o.block_solver = TSFDE_BLOCK_CG;  // the direct problem is solved, not preconditioned
     hipStream_t st = (hipStream_t)stream;
+    SharedLaunch lk(g_launch_mx);
     TSFDE_GUARD("forward_solve", {
         double* zh = nullptr;
         double* y = nullptr;

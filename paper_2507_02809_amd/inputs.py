@@ -161,9 +161,11 @@ def c2(which: int = 0) -> Inputs:
                      amp1=None, amp2=None, modes=20, name=f"c2{'ab'[which]}")
 
 
-def c3() -> Inputs:
-    """d=2, N=255 per direction, M=256, beta=0.6, omega=1.6, alpha=1e-4, 8x8 sine modes."""
-    return synthetic(2, 255, 256, 0.6, 1.6, 1e-4, config_id=3, modes=8, name="c3")
+def c3(instance: int = 0) -> Inputs:
+    """d=2, N=255 per direction, M=256, beta=0.6, omega=1.6, alpha=1e-4, 8x8 sine modes; further
+    instances draw other source modes and noise."""
+    return synthetic(2, 255, 256, 0.6, 1.6, 1e-4, config_id=3, instance=instance, modes=8,
+                     name="c3" if instance == 0 else f"c3_{instance}")
 
 
 def small(d: int, N: int, M: int, beta: float = 0.5, omega: float = 1.5, alpha: float = 1e-3,

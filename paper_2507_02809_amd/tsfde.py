@@ -21,8 +21,8 @@ EXPORTED = [
     "tsfde_default_opts", "tsfde_create_problem", "tsfde_create_problem_ex", "tsfde_set_mu",
     "tsfde_destroy_problem", "tsfde_vector_length", "tsfde_problem_scalars", "tsfde_get_stencil",
     "tsfde_compute_stencil", "tsfde_apply_A", "tsfde_apply_A_f32", "tsfde_apply_P_inv",
-    "tsfde_apply_P_inv_f32", "tsfde_gmres_solve", "tsfde_recover_f", "tsfde_forward_solve",
-    "tsfde_last_error",
+    "tsfde_apply_P_inv_f32", "tsfde_gmres_solve", "tsfde_recover_f", "tsfde_recover_f_batch",
+    "tsfde_forward_solve", "tsfde_last_error",
 ]
 
 
@@ -77,6 +77,7 @@ def lib():
     L.tsfde_gmres_solve.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_recover_f.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_forward_solve.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
+    L.tsfde_recover_f_batch.argtypes = [pp, i, pp, C.POINTER(Opts), C.POINTER(Stats), i, vp]
     L.tsfde_last_error.argtypes = []
     L.tsfde_last_error.restype = C.c_char_p
     for name in EXPORTED:
@@ -243,3 +244,19 @@ class Problem:
                                          _dptr(v, torch.float64, self.M * self.Nd, "v"),
                                          C.byref(opts) if opts is not None else None, _stream(stream)))
         return v
+
+
+def recover_f_batch(problems, opts: Optional[Opts] = None, max_inflight: int = 2, stream=None,
+                    raise_noconv=False):
+    """tsfde_recover_f_batch: f~ of every problem, up to max_inflight solved side by side.
+    Returns a list of (f, stats)."""
+    import torch
+    n = len(problems)
+    fs = [torch.empty(p.Nd, dtype=torch.float64, device="cuda") for p in problems]
+    hs = (C.c_void_p * max(n, 1))(*[p._h.value for p in problems])
+    fp = (C.c_void_p * max(n, 1))(*[f.data_ptr() for f in fs])
+    st = (Stats * max(n, 1))()
+    rc = lib().tsfde_recover_f_batch(hs, n, fp, C.byref(opts) if opts is not None else None, st, max_inflight,
+                                     _stream(stream))
+    _check(rc, allow=() if raise_noconv else (ENOCONV,))
+    return [(fs[i], st[i]) for i in range(n)]

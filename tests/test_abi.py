@@ -93,3 +93,17 @@ def test_null_arguments_rejected():
     assert lib.tsfde_apply_A(None, None, None, None) == tsfde.EINVAL
     assert lib.tsfde_gmres_solve(None, None, None, None, None, None) == tsfde.EINVAL
     assert lib.tsfde_compute_stencil(2, 8, 2.5, None) == tsfde.EINVAL
+
+
+def test_batch_arguments_checked_before_device_work():
+    lib = tsfde.lib()
+    # argument errors come back before anything touches a device
+    assert lib.tsfde_recover_f_batch(None, 1, None, None, None, 2, None) == tsfde.EINVAL
+    assert lib.tsfde_recover_f_batch(None, -1, None, None, None, 2, None) == tsfde.EINVAL
+    assert "max_inflight" in (lib.tsfde_recover_f_batch(None, 0, None, None, None, 0, None) == tsfde.EINVAL
+                              and tsfde.last_error() or "")
+    assert lib.tsfde_recover_f_batch(None, 0, None, None, None, 5, None) == tsfde.EINVAL
+    # an empty batch is a no-op
+    assert lib.tsfde_recover_f_batch(None, 0, None, None, None, 1, None) == tsfde.OK
+    bad = tsfde.default_opts(restart=0)
+    assert lib.tsfde_recover_f_batch(None, 0, None, C.byref(bad), None, 1, None) == tsfde.EINVAL

@@ -306,3 +306,49 @@ def test_apply_P_inv_tau_blocks_n127_matches_oracle(monkeypatch, fixed):
     with gpu_problem(inp, p) as g:
         y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=tsfde.default_opts(block_solver=tsfde.BLOCK_TAU))
     assert rel_err(y.cpu().numpy(), ref) <= 1e-12
+
+
+BATCH_CASES = [
+    lambda: inputs.small(1, 12, 7),
+    lambda: inputs.small(2, 7, 9, beta=0.3, omega=1.2),
+    lambda: inputs.c1(),
+    lambda: inputs.small(2, 15, 6, beta=0.6, omega=1.6),
+    lambda: inputs.small(2, 31, 5, beta=0.4, omega=1.3),
+]
+
+
+@pytest.mark.parametrize("inflight", [2, 4])
+def test_recover_f_batch_matches_single_solves_and_dense_lu(inflight):
+    """The batch solves each problem exactly as a single call does (same kernels, same reduction
+    order), several at a time on worker streams; each f~ also matches the oracle's dense LU."""
+    cases = [mk() for mk in BATCH_CASES]
+    opts = tsfde.default_opts(tol=1e-11, inner_tol=1e-12, inner_maxit=500)
+    probs, refs = [], []
+    try:
+        for inp in cases:
+            p = workloads.with_data(inp)
+            probs.append(gpu_problem(inp, p))
+            b = system.rhs_z(p)
+            refs.append(np.linalg.solve(system.dense_A(p), b)[p.S * p.Nd:])
+        single = [g.recover_f(opts, raise_noconv=True) for g in probs]
+        out = tsfde.recover_f_batch(probs, opts, max_inflight=inflight, raise_noconv=True)
+        for (f1, s1), (fb, sb), f_lu in zip(single, out, refs):
+            assert sb.converged == 1 and sb.iters == s1.iters
+            assert np.array_equal(fb.cpu().numpy(), f1.cpu().numpy())
+            assert rel_err(fb.cpu().numpy(), f_lu) <= 1e-8
+    finally:
+        for g in probs:
+            g.close()
+
+
+def test_recover_f_batch_rejects_bad_batches():
+    inp = inputs.small(1, 12, 7)
+    p = workloads.with_data(inp)
+    with gpu_problem(inp, p) as g:
+        with pytest.raises(tsfde.TsfdeError) as e:
+            tsfde.recover_f_batch([g, g])
+        assert e.value.status == tsfde.EINVAL and "twice" in str(e.value)
+        with pytest.raises(tsfde.TsfdeError) as e:  # tau blocks need d = 2
+            tsfde.recover_f_batch([g], tsfde.default_opts(block_solver=tsfde.BLOCK_TAU))
+        assert e.value.status == tsfde.ENOTIMPL
+        assert tsfde.recover_f_batch([]) == []
