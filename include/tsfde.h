@@ -199,11 +199,14 @@ tsfde_status tsfde_recover_f(tsfde_problem* prob, double* f_out, double* work,
 /*
  * Recover f~ for several independent problems (the batched form of
  * tsfde_recover_f, e.g. many instances, regularisation parameters or data
- * sets).  Up to max_inflight problems (1..4) are solved at the same time,
+ * sets).  Up to max_inflight problems (1..8) are solved at the same time,
  * each on a non-blocking stream the library creates for it, by as many host
  * worker threads (the calling thread is one of them).  Because one problem's
  * preconditioner is a chain of dependent time steps that occupies only a
  * part of the device, solving several side by side raises the throughput.
+ * Their kernels overlap only as far as the HIP runtime gives the streams
+ * hardware queues of their own: GPU_MAX_HW_QUEUES (4 by default, shared with
+ * every other stream of the process) should be at least max_inflight + 2.
  *   probs   count distinct problem handles (on the current HIP device)
  *   f_out   count device pointers, f_out[i] receives N_i^d values
  *   opts    one set of options for all problems (NULL for defaults)

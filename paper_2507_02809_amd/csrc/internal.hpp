@@ -69,6 +69,11 @@ struct Problem {
     double* d_rho = nullptr;   // [Nd]
     double* d_mu = nullptr;    // [Nd]
     bool tau_ok = false;       // sine-transform preconditioner available (2(N+1) a power of two)
+    // d = 1 with 2(N+1) not a power of two: the inner CG of the persistent P^-1 is preconditioned by
+    // R tau_Nt^{-1} R^T, the tau matrix of the next size Nt = 2^k - 1 > N on the zero-padded residual
+    // (R keeps the first N entries), which is SPD; the circulant embedding is then L = 2 (Nt + 1)
+    bool tau_pad = false;
+    int Nt = 0;                // sine-transform size of the preconditioner (N unless tau_pad)
     double a0 = 0;             // stencil centre a_0 (Jacobi fallback)
     double* z_rhs = nullptr;   // built right-hand side z (FP64, n_tot)
     double* xbuf = nullptr;    // solution buffer for recover_f (n_tot)
@@ -163,7 +168,7 @@ void pinv_persistent_free(void* wptr);
 void set_persistent_blocks(int g);
 // Batch mode of the calling thread: its persistent kernels are ordinary launches sized so that
 // kMaxInflight of them fit the device together (tsfde_recover_f_batch)
-constexpr int kMaxInflight = 4;
+constexpr int kMaxInflight = 8;
 void set_shared_launch(bool on);
 bool shared_launch();
 void set_persistent_fixed_length(bool on);  // use the fixed-length 2D sine-transform kernels where available

@@ -55,6 +55,7 @@ struct PinvArgs {
     int ns;  // row stride of the transposed 2D intermediates spec, t1, t2 (N rounded up to 16)
     long long Nd;
     int use_tau;  // 1: tau (sine transform) preconditioner, 0: diagonal
+    int Nt;       // size of the sine transform: N, or (d = 1) the padded size with L = 2 (Nt + 1)
     int extrap;   // 1: linear extrapolation of the warm start in time
     const T* z;
     T* y;
@@ -354,8 +355,9 @@ __device__ __forceinline__ void g_rows_inv(const PinvArgs<T>& a, cplx<T>* c, con
     __syncthreads();
 }
 
-// Sine transform (DST-I via the odd extension of length L = 2(N+1)) of rows (i0, i1) of `in`, with
-// the two rows packed as real + i*imag; afterwards c[lx(k+1)] = -2i DST(row i0)_k + 2 DST(row i1)_k.
+// Sine transform (DST-I of size L/2 - 1 via the odd extension of length L) of rows (i0, i1) of `in`
+// (N entries each, zero-padded when L/2 - 1 > N), with the two rows packed as real + i*imag;
+// afterwards c[lx(k+1)] = -2i DST(row i0)_k + 2 DST(row i1)_k.
 // With upd, first x += alpha p and in -= alpha q on those rows (accumulating (in, in)).
 // d = 1: a single row.
 template <typename T, int VPT>
@@ -363,7 +365,7 @@ __device__ __forceinline__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, con
                            int tid, int nthr, bool upd, T alpha, T& rr) {
     const int N = a.N, L = a.L;
     const bool two = (a.d == 2) && (i0 + 1 < N);
-    constexpr int VH = VPT / 2;  // the sine transform has L = 2(N + 1), so m < N < L/2 = VH * nthr
+    constexpr int VH = VPT / 2;  // the odd extension's first half: m < L/2 = VH * nthr, and N < L/2
     T v0[VH], v1[VH];
     if (upd) {
         T q0[VH], q1[VH], x0[VH], x1[VH], pp0[VH], pp1[VH];
@@ -413,18 +415,15 @@ __device__ __forceinline__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, con
             }
         }
     }
+    // odd extension of length L: position m + 1 holds x_m and position L - 1 - m holds -x_m for
+    // m < L/2 (zero past the data, m >= N: the padded entries and position L/2), position 0 is zero
 #pragma unroll
     for (int u = 0; u < VH; ++u) {
         const int m = tid + u * nthr;
-        if (m < N) {
-            c[lx(m + 1)] = {v0[u], v1[u]};
-            c[lx(L - m - 1)] = {-v0[u], -v1[u]};
-        }
+        c[lx(m + 1)] = {v0[u], v1[u]};
+        c[lx(L - m - 1)] = {-v0[u], -v1[u]};
     }
-    if (tid == 0) {
-        c[lx(0)] = {T(0), T(0)};
-        c[lx(N + 1)] = {T(0), T(0)};
-    }
+    if (tid == 0) c[lx(0)] = {T(0), T(0)};
     __syncthreads();
     fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
 }
@@ -799,6 +798,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
         a.d = 2;
         a.L = LC;
         a.N = LC / 2 - 1;
+        a.Nt = LC / 2 - 1;
         a.H = LC / 2 + 1;
         a.Nd = (long long)(LC / 2 - 1) * (LC / 2 - 1);
         a.ns = spec_stride(LC / 2 - 1);
@@ -831,7 +831,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
     const int NR = (NP + NG - 1) / NG;       // rounds over row pairs
     const int NC = (a.H + NG - 1) / NG;      // rounds over spectral rows
     const T* e = a.epad + kEpad;
-    const T scale = two_d ? T(4.0 / ((double)(N + 1) * (N + 1))) : T(2.0 / (N + 1));
+    const T scale = two_d ? T(4.0 / ((double)(N + 1) * (N + 1))) : T(2.0 / (a.Nt + 1));
     unsigned epoch = 0;
     long long total_it = 0;
 
@@ -848,30 +848,32 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
             if (a.use_tau) {
                 const bool act = gg == 0;
                 g_dst_load<T, VPT>(a, c, twl, a.r, N, 0, act, tid, nthr, upd, alpha, rr);
+                // sine-transform coefficients k < Nt (the transform size; Nt >= N)
+                const int Nt = a.Nt;
                 T hv[VPT], tv[VPT], rv[VPT];
 #pragma unroll
                 for (int u = 0; u < VPT; ++u) {
                     const int k = tid + u * nthr;
-                    tv[u] = (k < N) ? a.tau[k] : T(1);
+                    tv[u] = (k < Nt) ? a.tau[k] : T(1);
                     rv[u] = (act && k < N) ? a.r[k] : T(0);
                 }
 #pragma unroll
                 for (int u = 0; u < VPT; ++u) {
                     const int k = tid + u * nthr;
-                    hv[u] = (k < N) ? T(-0.5) * c[lx(k + 1)].y * scale / (sig + cc * tv[u]) : T(0);
+                    hv[u] = (k < Nt) ? T(-0.5) * c[lx(k + 1)].y * scale / (sig + cc * tv[u]) : T(0);
                 }
                 __syncthreads();
 #pragma unroll
                 for (int u = 0; u < VPT; ++u) {
                     const int k = tid + u * nthr;
-                    if (k < N) {
+                    if (k < Nt) {
                         c[lx(k + 1)] = {hv[u], T(0)};
                         c[lx(a.L - k - 1)] = {-hv[u], T(0)};
                     }
                 }
                 if (tid == 0) {
                     c[lx(0)] = {T(0), T(0)};
-                    c[lx(N + 1)] = {T(0), T(0)};
+                    c[lx(Nt + 1)] = {T(0), T(0)};
                 }
                 __syncthreads();
                 fft_lds<T, VPT, false>(c, a.L, twl, tid, nthr);
@@ -1266,7 +1268,8 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
     a.L = P.L;
     a.H = P.H;
     a.Nd = P.Nd;
-    a.use_tau = P.tau_ok ? 1 : 0;
+    a.use_tau = (P.tau_ok || P.tau_pad) ? 1 : 0;
+    a.Nt = P.Nt;
     a.extrap = extrap;
     a.z = z;
     a.y = y;

@@ -368,10 +368,21 @@ tsfde_status create(int d, int N, int M, double T, double beta, double omega, do
         P->eta = std::pow(P->dt, beta) * std::tgamma(2.0 - beta);
         P->ct = P->eta / std::pow(P->h, omega);
         P->cf = alpha / std::pow(P->h, omega);
-        P->L = L;
-        P->H = L / 2 + 1;
         P->Ld = is_pow2(2LL * (N + 1)) && 2 * (N + 1) <= 8192 ? 2 * (N + 1) : 0;
         P->tau_ok = P->Ld > 0;
+        P->Nt = N;
+        if (d == 1 && !P->tau_ok) {
+            int Ld = 4;
+            while (Ld < 2 * (N + 1)) Ld *= 2;
+            if (Ld <= 8192) {
+                P->tau_pad = true;
+                P->Nt = Ld / 2 - 1;
+                P->Ld = Ld;
+                L = std::max(L, Ld);  // one transform length serves the Toeplitz product and the sine transform
+            }
+        }
+        P->L = L;
+        P->H = L / 2 + 1;
         P->gamma1_h.assign(gamma1, gamma1 + MN);
         P->gamma2_h.assign(gamma2, gamma2 + MN);
         P->q_h.assign(q, q + M);
@@ -413,6 +424,12 @@ tsfde_status create(int d, int N, int M, double T, double beta, double omega, do
         if (P->tau_ok) {
             twd = twiddles(P->Ld);
             tau = tau_eigs(d, N, P->stencil);
+        } else if (P->tau_pad) {
+            // the stencil continued to Nt entries (the problem's own entries first)
+            std::vector<double> ext(P->Nt);
+            stencil_1d(P->Nt, omega, ext.data());
+            std::copy(P->stencil.begin(), P->stencil.end(), ext.begin());
+            tau = tau_eigs(1, P->Nt, ext);
         }
         P->nspec = (d == 2) ? M + 1 : 0;
         build_dev<double>(*P, P->f64, dg, epad, sym, tw, twd, tau);

@@ -168,6 +168,27 @@ def c3(instance: int = 0) -> Inputs:
                      name="c3" if instance == 0 else f"c3_{instance}")
 
 
+C4_SIZE = 64
+
+
+def c4(instance: int) -> Inputs:
+    """Instance k of the mixed batch of 64 (a stand-in for many independent problems): even k in
+    d = 1 with N ~ U[127, 2047], odd k in d = 2 with N ~ U[31, 127]; M ~ U[64, 512],
+    beta ~ U(0.2, 0.9), omega ~ U(1.1, 1.9), alpha log-uniform on [1e-5, 1e-2], coefficient
+    amplitudes ~ U(0.1, 0.5)."""
+    if not 0 <= instance < C4_SIZE:
+        raise ValueError(f"c4 instance must be in [0, {C4_SIZE})")
+    rng = np.random.default_rng([SEED_BASE, 4, 1000 + instance])
+    d = 1 + instance % 2
+    N = int(rng.integers(127, 2048)) if d == 1 else int(rng.integers(31, 128))
+    M = int(rng.integers(64, 513))
+    beta = float(rng.uniform(0.2, 0.9))
+    omega = float(rng.uniform(1.1, 1.9))
+    alpha = float(10.0 ** rng.uniform(-5.0, -2.0))
+    return synthetic(d, N, M, beta, omega, alpha, config_id=4, instance=instance, amp1=None, amp2=None,
+                     modes=min(8, N), name=f"c4_{instance}")
+
+
 def small(d: int, N: int, M: int, beta: float = 0.5, omega: float = 1.5, alpha: float = 1e-3,
           instance: int = 0) -> Inputs:
     """A small instance of the same family for parity tests (seeded by its shape)."""

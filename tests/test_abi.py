@@ -102,7 +102,7 @@ def test_batch_arguments_checked_before_device_work():
     assert lib.tsfde_recover_f_batch(None, -1, None, None, None, 2, None) == tsfde.EINVAL
     assert "max_inflight" in (lib.tsfde_recover_f_batch(None, 0, None, None, None, 0, None) == tsfde.EINVAL
                               and tsfde.last_error() or "")
-    assert lib.tsfde_recover_f_batch(None, 0, None, None, None, 5, None) == tsfde.EINVAL
+    assert lib.tsfde_recover_f_batch(None, 0, None, None, None, 9, None) == tsfde.EINVAL
     # an empty batch is a no-op
     assert lib.tsfde_recover_f_batch(None, 0, None, None, None, 1, None) == tsfde.OK
     bad = tsfde.default_opts(restart=0)

@@ -352,3 +352,29 @@ def test_recover_f_batch_rejects_bad_batches():
             tsfde.recover_f_batch([g], tsfde.default_opts(block_solver=tsfde.BLOCK_TAU))
         assert e.value.status == tsfde.ENOTIMPL
         assert tsfde.recover_f_batch([]) == []
+
+
+@pytest.mark.parametrize("N", [12, 64, 100, 300])
+def test_apply_P_inv_1d_padded_tau_matches_dense(N, pinv_path):
+    """d = 1 with 2(N+1) not a power of two: the persistent kernel preconditions its block CG with
+    the tau matrix of the next size 2^k - 1 on the zero-padded residual (N = 64 also doubles the
+    circulant embedding to that transform length).  P^{-1} still matches dense P, and the block
+    CG needs far fewer iterations than the diagonal preconditioner of the multi-launch path."""
+    pinv_path(True)
+    inp = inputs.small(1, N, 6, beta=0.7, omega=1.8)
+    p = workloads.with_data(inp)
+    P = system.dense_P(p)
+    A = system.dense_A(p)
+    rng = np.random.default_rng(N)
+    zz = rng.standard_normal(p.n_tot)
+    with gpu_problem(inp, p) as g:
+        y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=tsfde.default_opts(inner_tol=1e-13, inner_maxit=500))
+        assert rel_err(y.cpu().numpy(), np.linalg.solve(P, zz)) <= 1e-9
+        o = tsfde.default_opts(tol=1e-11, inner_tol=1e-8, inner_maxit=500)
+        b = system.rhs_z(p)
+        x, st = g.gmres_solve(torch.tensor(b, device=DEV), opts=o, raise_noconv=True)
+        assert np.linalg.norm(A @ x.cpu().numpy() - b) <= 1e-10 * np.linalg.norm(b)
+        pinv_path(False)
+        _, st_diag = g.gmres_solve(torch.tensor(b, device=DEV), opts=o, raise_noconv=True)
+    if N >= 64:
+        assert 3 * st.inner_iters < st_diag.inner_iters, (st.inner_iters, st_diag.inner_iters)
