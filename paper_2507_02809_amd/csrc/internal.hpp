@@ -69,9 +69,10 @@ struct Problem {
     double* d_rho = nullptr;   // [Nd]
     double* d_mu = nullptr;    // [Nd]
     bool tau_ok = false;       // sine-transform preconditioner available (2(N+1) a power of two)
-    // d = 1 with 2(N+1) not a power of two: the inner CG of the persistent P^-1 is preconditioned by
-    // R tau_Nt^{-1} R^T, the tau matrix of the next size Nt = 2^k - 1 > N on the zero-padded residual
-    // (R keeps the first N entries), which is SPD; the circulant embedding is then L = 2 (Nt + 1)
+    // 2(N+1) not a power of two: the inner CG of the persistent P^-1 is preconditioned by
+    // R tau_Nt^{-1} R^T, the tau matrix of the next size Nt = 2^k - 1 > N per direction on the
+    // zero-padded residual (R keeps the first N entries per direction), which is SPD; the circulant
+    // embedding is then L = 2 (Nt + 1)
     bool tau_pad = false;
     int Nt = 0;                // sine-transform size of the preconditioner (N unless tau_pad)
     double a0 = 0;             // stencil centre a_0 (Jacobi fallback)

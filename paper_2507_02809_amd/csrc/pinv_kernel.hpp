@@ -55,7 +55,8 @@ struct PinvArgs {
     int ns;  // row stride of the transposed 2D intermediates spec, t1, t2 (N rounded up to 16)
     long long Nd;
     int use_tau;  // 1: tau (sine transform) preconditioner, 0: diagonal
-    int Nt;       // size of the sine transform: N, or (d = 1) the padded size with L = 2 (Nt + 1)
+    int Nt;       // size of the sine transform: N, or the padded size with L = 2 (Nt + 1)
+    int nt;       // 2D: row stride of the sine-transform intermediates t1 [Nt][nt], t2 [N][nt]
     int extrap;   // 1: linear extrapolation of the warm start in time
     const T* z;
     T* y;
@@ -428,24 +429,25 @@ __device__ __forceinline__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, con
     fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
 }
 
-// Sine transform of rows (i0, i0 + 1) of `in` (row stride ld), packed as real + i*imag: the odd
-// extension of length L = 2(N+1) is loaded from global memory straight into the FFT's register
-// layout (thread tid: positions tid + u nthr), so only the transform's own exchanges use LDS.
+// Sine transform (size L/2 - 1) of rows (i0, i0 + 1) of `in` (n entries each, zero-padded up to
+// L/2 - 1; row stride ld; the second row exists when i0 + 1 < nrow), packed as real + i*imag: the
+// odd extension of length L is loaded from global memory straight into the FFT's register layout
+// (thread tid: positions tid + u nthr), so only the transform's own exchanges use LDS.
 // Afterwards c[lx(k+1)] = -2i DST(row i0)_k + 2 DST(row i0+1)_k.  The LDS sequence must be free.
 template <typename T, int VPT>
 __device__ __forceinline__ void g_dst_rows(const PinvArgs<T>& a, cplx<T>* c, const cplx<T>* tw, const T* in, int ld,
-                                           int i0, bool valid, int tid, int nthr) {
-    const int N = a.N, L = a.L;
-    const bool two = i0 + 1 < N;
+                                           int n, int nrow, int i0, bool valid, int tid, int nthr) {
+    const int L = a.L;
+    const bool two = i0 + 1 < nrow;
     cplx<T> v[VPT];
 #pragma unroll
     for (int u = 0; u < VPT; ++u) {
         const int p = tid + u * nthr;
         T x0 = T(0), x1 = T(0);
         if (valid) {
-            // position p holds x_{p-1} (1 <= p <= N), -x_{L-1-p} (N+2 <= p <= L-1), else 0
-            const bool lo = (p >= 1 && p <= N);
-            const bool hi = (p >= N + 2);
+            // position p holds x_{p-1} (1 <= p <= n), -x_{L-1-p} (L-n <= p <= L-1), else 0
+            const bool lo = (p >= 1 && p <= n);
+            const bool hi = (p >= L - n);
             if (lo || hi) {
                 const int m = lo ? p - 1 : L - 1 - p;
                 const long long o = (long long)i0 * ld + m;
@@ -490,18 +492,20 @@ __device__ __forceinline__ void wg_write_spec(const PinvArgs<T>& a, const cplx<T
 }
 
 // after each group's sine-transform FFT (c[k+1] = -2i DST(row 2g) + 2 DST(row 2g+1)):
-// out[k][ibase + 2g (+1)] = DST of the pair's rows at k
+// out[k][ibase + 2g (+1)] = DST of the pair's rows at k, for k < nk and rows below nrow
+// (row stride a.nt)
 template <typename T>
-__device__ __forceinline__ void wg_write_T(const PinvArgs<T>& a, const cplx<T>* cbase, T* out, int ibase, int gpb) {
-    const int N = a.N, LP = lds_len(a.L);
-    for (int idx = threadIdx.x; idx < N * gpb; idx += blockDim.x) {
+__device__ __forceinline__ void wg_write_T(const PinvArgs<T>& a, const cplx<T>* cbase, T* out, int ibase, int gpb,
+                                           int nk, int nrow) {
+    const int LP = lds_len(a.L);
+    for (int idx = threadIdx.x; idx < nk * gpb; idx += blockDim.x) {
         const int k = idx / gpb, g = idx - k * gpb;
         const int i = ibase + 2 * g;
-        if (i >= N) continue;
+        if (i >= nrow) continue;
         const cplx<T> C = cbase[(size_t)g * LP + lx(k + 1)];
-        T* dst = out + (long long)k * a.ns + i;
+        T* dst = out + (long long)k * a.nt + i;
         dst[0] = T(-0.5) * C.y;
-        if (i + 1 < N) dst[1] = T(0.5) * C.x;
+        if (i + 1 < nrow) dst[1] = T(0.5) * C.x;
     }
 }
 
@@ -532,34 +536,34 @@ __device__ __forceinline__ void wg_load_spec(const PinvArgs<T>& a, cplx<T>* cbas
 template <typename T, int VPT>
 __device__ __forceinline__ void wg_pass_B(const PinvArgs<T>& a, cplx<T>* cbase, cplx<T>* c, const cplx<T>* tw, int kbase, int grp,
                           int gpb, T sig, T cc, T scale, int tid, int nthr, T& rz) {
-    const int N = a.N;
+    // rows k0, k0 + 1 of t1 (first-transform frequencies, Nt of them) hold N values each
+    const int N = a.N, Nt = a.Nt;
     const int k0 = kbase + 2 * grp;
-    const bool valid = k0 < N;
-    const bool two = k0 + 1 < N;
+    const bool valid = k0 < Nt;
+    const bool two = k0 + 1 < Nt;
     constexpr bool PREF = VPT <= 8;  // prefetch the epilogue operands before the transform
-    constexpr int VH = VPT / 2;      // k1 < N < L/2 = VH * nthr
+    constexpr int VH = VPT / 2;      // k1 < Nt < L/2 = VH * nthr
     T tv0[VH], tv1[VH];
     auto load_tau = [&](int u) {
         const int k1 = tid + u * nthr;
         tv0[u] = tv1[u] = T(1);
-        if (valid && k1 < N) {
-            tv0[u] = a.tau[(long long)k0 * N + k1];
-            if (two) tv1[u] = a.tau[(long long)(k0 + 1) * N + k1];
+        if (valid && k1 < Nt) {
+            tv0[u] = a.tau[(long long)k0 * Nt + k1];
+            if (two) tv1[u] = a.tau[(long long)(k0 + 1) * Nt + k1];
         }
     };
     if constexpr (PREF) {
 #pragma unroll
         for (int u = 0; u < VH; ++u) load_tau(u);
     }
-    T dummy = T(0);
-    g_dst_rows<T, VPT>(a, c, tw, a.t1, a.ns, k0, valid, tid, nthr);
+    g_dst_rows<T, VPT>(a, c, tw, a.t1, a.nt, N, Nt, k0, valid, tid, nthr);
     T hv0[VH], hv1[VH];
 #pragma unroll
     for (int u = 0; u < VH; ++u) {
         const int k1 = tid + u * nthr;
         hv0[u] = hv1[u] = T(0);
         if constexpr (!PREF) load_tau(u);
-        if (valid && k1 < N) {
+        if (valid && k1 < Nt) {
             const cplx<T> C = c[lx(k1 + 1)];
             const T y0 = T(-0.5) * C.y, y1 = T(0.5) * C.x;
             hv0[u] = y0 * scale / (sig + cc * tv0[u]);
@@ -574,18 +578,19 @@ __device__ __forceinline__ void wg_pass_B(const PinvArgs<T>& a, cplx<T>* cbase, 
 #pragma unroll
     for (int u = 0; u < VH; ++u) {
         const int k1 = tid + u * nthr;
-        if (k1 < N) {
+        if (k1 < Nt) {
             c[lx(k1 + 1)] = {hv0[u], hv1[u]};
             c[lx(a.L - k1 - 1)] = {-hv0[u], -hv1[u]};
         }
     }
     if (tid == 0) {
         c[lx(0)] = {T(0), T(0)};
-        c[lx(N + 1)] = {T(0), T(0)};
+        c[lx(Nt + 1)] = {T(0), T(0)};
     }
     __syncthreads();
     fft_lds<T, VPT, false>(c, a.L, tw, tid, nthr);
-    wg_write_T(a, cbase, a.t2, kbase, gpb);
+    // back in space along the columns: rows i < N of t2, columns k0, k0 + 1
+    wg_write_T(a, cbase, a.t2, kbase, gpb, N, Nt);
     __syncthreads();
 }
 
@@ -620,8 +625,7 @@ __device__ __forceinline__ void wg_pass_DF(const PinvArgs<T>& a, cplx<T>* cbase,
 #pragma unroll
         for (int u = 0; u < VH; ++u) load_pd(u);
     }
-    T dummy = T(0);
-    g_dst_rows<T, VPT>(a, c, tw, a.t2, a.ns, i0, valid, tid, nthr);
+    g_dst_rows<T, VPT>(a, c, tw, a.t2, a.nt, a.Nt, N, i0, valid, tid, nthr);
     T pn0[VH], pn1[VH];
 #pragma unroll
     for (int u = 0; u < VH; ++u) {
@@ -748,23 +752,19 @@ __device__ __forceinline__ void wg_pass_IUA(const PinvArgs<T>& a, cplx<T>* cbase
             r0[u] = r1[u] = T(0);
         }
     }
-    // pass A on the updated rows: odd extension, FFT, DST rows -> t1 (transposed); the sequence is
-    // free (the inverse transform left its output in registers)
+    // pass A on the updated rows: odd extension (zero for m >= N, so the padded entries and the
+    // middle position L/2), FFT, DST rows -> t1 (transposed); the sequence is free (the inverse
+    // transform left its output in registers)
 #pragma unroll
     for (int u = 0; u < VH; ++u) {
         const int m = tid + u * nthr;
-        if (m < N) {
-            c[lx(m + 1)] = {r0[u], r1[u]};
-            c[lx(L - m - 1)] = {-r0[u], -r1[u]};
-        }
+        c[lx(m + 1)] = {r0[u], r1[u]};
+        c[lx(L - m - 1)] = {-r0[u], -r1[u]};
     }
-    if (tid == 0) {
-        c[lx(0)] = {T(0), T(0)};
-        c[lx(N + 1)] = {T(0), T(0)};
-    }
+    if (tid == 0) c[lx(0)] = {T(0), T(0)};
     __syncthreads();
     fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
-    wg_write_T(a, cbase, a.t1, ibase, gpb);
+    wg_write_T(a, cbase, a.t1, ibase, gpb, a.Nt, N);
     __syncthreads();
 }
 
@@ -802,6 +802,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
         a.H = LC / 2 + 1;
         a.Nd = (long long)(LC / 2 - 1) * (LC / 2 - 1);
         a.ns = spec_stride(LC / 2 - 1);
+        a.nt = a.ns;
     }
     extern __shared__ unsigned char smem_raw[];
     __shared__ double red[kSegBlock / 64 * 2];
@@ -830,8 +831,9 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
     const int NP = two_d ? (N + 1) / 2 : 1;  // row pairs (2D)
     const int NR = (NP + NG - 1) / NG;       // rounds over row pairs
     const int NC = (a.H + NG - 1) / NG;      // rounds over spectral rows
+    const int NRB = ((a.Nt + 1) / 2 + NG - 1) / NG;  // rounds over frequency pairs of the sine transform
     const T* e = a.epad + kEpad;
-    const T scale = two_d ? T(4.0 / ((double)(N + 1) * (N + 1))) : T(2.0 / (a.Nt + 1));
+    const T scale = two_d ? T(4.0 / ((double)(a.Nt + 1) * (a.Nt + 1))) : T(2.0 / (a.Nt + 1));
     unsigned epoch = 0;
     long long total_it = 0;
 
@@ -1016,26 +1018,22 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                         }
 #pragma unroll
                         for (int du = 0; du < EB; ++du) {
+                            // m < L/2: zero past the data (padded entries, position L/2)
                             const int m = tid + (u0 + du) * nthr;
-                            if (m < N) {
-                                T r0 = T(0), r1 = T(0);
-                                if (valid) {
-                                    const long long j0 = (long long)i0 * N + m;
-                                    r0 = e_store(j0, v[du][0], rr, bb);
-                                    if (two) r1 = e_store(j0 + N, v[du][1], rr, bb);
-                                }
-                                c[lx(m + 1)] = {r0, r1};
-                                c[lx(a.L - m - 1)] = {-r0, -r1};
+                            T r0 = T(0), r1 = T(0);
+                            if (valid && m < N) {
+                                const long long j0 = (long long)i0 * N + m;
+                                r0 = e_store(j0, v[du][0], rr, bb);
+                                if (two) r1 = e_store(j0 + N, v[du][1], rr, bb);
                             }
+                            c[lx(m + 1)] = {r0, r1};
+                            c[lx(a.L - m - 1)] = {-r0, -r1};
                         }
                     }
-                    if (tid == 0) {
-                        c[lx(0)] = {T(0), T(0)};
-                        c[lx(N + 1)] = {T(0), T(0)};
-                    }
+                    if (tid == 0) c[lx(0)] = {T(0), T(0)};
                     __syncthreads();
                     fft_lds<T, VPT, false>(c, a.L, twl, tid, nthr);
-                    wg_write_T(a, cbase, a.t1, ibase, gpb);
+                    wg_write_T(a, cbase, a.t1, ibase, gpb, a.Nt, N);
                     __syncthreads();
                 }
             } else {
@@ -1066,7 +1064,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                 // into x.  The next step's phase E reads these points in the same thread, so no
                 // device-wide barrier follows.
                 T rzl = T(0);
-                for (int rd = 0; rd < NR; ++rd) {
+                for (int rd = 0; rd < NRB; ++rd) {
                     const int kbase = 2 * (rd * NG + blockIdx.x * gpb);
                     wg_pass_B<T, VPT>(a, cbase, c, twl, kbase, grp, gpb, sig, cc, scale, tid, nthr, rzl);
                 }
@@ -1075,7 +1073,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                     const int ibase = 2 * (rd * NG + blockIdx.x * gpb);
                     const int i0 = ibase + 2 * grp;
                     const bool valid = i0 < N;
-                    g_dst_rows<T, VPT>(a, c, twl, a.t2, a.ns, i0, valid, tid, nthr);
+                    g_dst_rows<T, VPT>(a, c, twl, a.t2, a.nt, a.Nt, N, i0, valid, tid, nthr);
 #pragma unroll
                     for (int u = 0; u < VPT / 2; ++u) {
                         const int m = tid + u * nthr;
@@ -1098,7 +1096,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
             // z0 = M^{-1} r0: pass A ran with phase E; pass B (with (r, z))
             {
                 T rzl = T(0);
-                for (int rd = 0; rd < NR; ++rd) {
+                for (int rd = 0; rd < NRB; ++rd) {
                     const int kbase = 2 * (rd * NG + blockIdx.x * gpb);
                     wg_pass_B<T, VPT>(a, cbase, c, twl, kbase, grp, gpb, sig, cc, scale, tid, nthr, rzl);
                 }
@@ -1137,7 +1135,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                 rrt = tot[SL_RR];
                 if (rrt <= a.tol2 * bbt || it >= a.maxit || !(rrt == rrt)) break;
                 T rzl = T(0);
-                for (int rd = 0; rd < NR; ++rd) {
+                for (int rd = 0; rd < NRB; ++rd) {
                     const int kbase = 2 * (rd * NG + blockIdx.x * gpb);
                     wg_pass_B<T, VPT>(a, cbase, c, twl, kbase, grp, gpb, sig, cc, scale, tid, nthr, rzl);
                 }
@@ -1297,8 +1295,9 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
     a.bxb = b + 6 * Nd;
     a.hacc = b + 7 * Nd;
     a.ns = spec_stride(P.N);
-    a.t1 = W.tt;
-    a.t2 = W.tt ? W.tt + (long long)P.N * a.ns : nullptr;
+    a.nt = spec_stride(P.Nt);
+    a.t1 = W.tt;                                                   // [Nt][nt]
+    a.t2 = W.tt ? W.tt + (long long)P.Nt * a.nt : nullptr;  // [N][nt]
     a.spec = W.spec;
     a.part = W.part;
     a.bar = W.bar;

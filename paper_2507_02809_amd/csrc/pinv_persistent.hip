@@ -13,10 +13,11 @@ static std::atomic<bool> g_fixed_length{true};
 template <typename T>
 void ensure_work(Problem& P, PersistentWork<T>& W) {
     if (W.buf) return;
-    const size_t ns = (size_t)spec_stride(P.N);
+    const size_t ns = (size_t)spec_stride(P.N), nt = (size_t)spec_stride(P.Nt);
     TSFDE_HIP(hipMalloc(&W.buf, sizeof(T) * (size_t)(7 + kHB) * P.Nd));
     if (P.d == 2) {
-        TSFDE_HIP(hipMalloc(&W.tt, sizeof(T) * 2 * (size_t)P.N * ns));
+        // sine-transform intermediates t1 [Nt][nt] and t2 [N][nt]; half spectra [H][ns]
+        TSFDE_HIP(hipMalloc(&W.tt, sizeof(T) * ((size_t)P.Nt + P.N) * nt));
         TSFDE_HIP(hipMalloc(&W.spec, sizeof(cplx<T>) * (size_t)P.H * ns));
     }
     TSFDE_HIP(hipMalloc(&W.part, sizeof(double) * 1024 * kNPart));
@@ -40,7 +41,7 @@ long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T*
     ensure_work(P, W);
     const int L = P.L;
     const int vpt = (L <= 2048) ? 8 : (L == 4096 ? 16 : 32);
-    const int mode = (P.d == 1) ? SEG_1D : (P.tau_ok ? SEG_2D_TAU : SEG_2D_DIAG);
+    const int mode = (P.d == 1) ? SEG_1D : ((P.tau_ok || P.tau_pad) ? SEG_2D_TAU : SEG_2D_DIAG);
     const int blocks = g_blocks_override;
     if (tblocks) {
         // tau-block form: no inner iterations, no warm start (the caller has checked the path)

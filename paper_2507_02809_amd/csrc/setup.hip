@@ -371,7 +371,7 @@ tsfde_status create(int d, int N, int M, double T, double beta, double omega, do
         P->Ld = is_pow2(2LL * (N + 1)) && 2 * (N + 1) <= 8192 ? 2 * (N + 1) : 0;
         P->tau_ok = P->Ld > 0;
         P->Nt = N;
-        if (d == 1 && !P->tau_ok) {
+        if (!P->tau_ok) {
             int Ld = 4;
             while (Ld < 2 * (N + 1)) Ld *= 2;
             if (Ld <= 8192) {
@@ -425,11 +425,21 @@ tsfde_status create(int d, int N, int M, double T, double beta, double omega, do
             twd = twiddles(P->Ld);
             tau = tau_eigs(d, N, P->stencil);
         } else if (P->tau_pad) {
-            // the stencil continued to Nt entries (the problem's own entries first)
-            std::vector<double> ext(P->Nt);
-            stencil_1d(P->Nt, omega, ext.data());
-            std::copy(P->stencil.begin(), P->stencil.end(), ext.begin());
-            tau = tau_eigs(1, P->Nt, ext);
+            // the stencil continued to Nt entries per direction (the problem's own entries first)
+            const int Nt = P->Nt;
+            if (d == 1) {
+                std::vector<double> ext(Nt);
+                stencil_1d(Nt, omega, ext.data());
+                std::copy(P->stencil.begin(), P->stencil.end(), ext.begin());
+                tau = tau_eigs(1, Nt, ext);
+            } else {
+                std::vector<double> ext((size_t)Nt * Nt);
+                stencil_2d(Nt, omega, ext.data());
+                for (int l1 = 0; l1 < N; ++l1)
+                    std::copy(P->stencil.begin() + (size_t)l1 * N, P->stencil.begin() + (size_t)(l1 + 1) * N,
+                              ext.begin() + (size_t)l1 * Nt);
+                tau = tau_eigs(2, Nt, ext);
+            }
         }
         P->nspec = (d == 2) ? M + 1 : 0;
         build_dev<double>(*P, P->f64, dg, epad, sym, tw, twd, tau);

@@ -36,7 +36,7 @@ def rel_err(a, b):
 SMALL_DENSE = [
     ("1d_12x7", lambda: inputs.small(1, 12, 7)),
     ("1d_c1", lambda: inputs.c1()),
-    ("2d_6x5_jacobi", lambda: inputs.small(2, 6, 5, beta=0.6, omega=1.6)),
+    ("2d_6x5_padded_tau", lambda: inputs.small(2, 6, 5, beta=0.6, omega=1.6)),
     ("2d_7x9", lambda: inputs.small(2, 7, 9, beta=0.3, omega=1.2)),
 ]
 
@@ -378,3 +378,29 @@ def test_apply_P_inv_1d_padded_tau_matches_dense(N, pinv_path):
         _, st_diag = g.gmres_solve(torch.tensor(b, device=DEV), opts=o, raise_noconv=True)
     if N >= 64:
         assert 3 * st.inner_iters < st_diag.inner_iters, (st.inner_iters, st_diag.inner_iters)
+
+
+@pytest.mark.parametrize("N", [6, 12, 16, 20])
+def test_apply_P_inv_2d_padded_tau_matches_dense(N, pinv_path):
+    """d = 2 with 2(N+1) not a power of two: the fused tau-preconditioned CG of the persistent kernel
+    runs with sine transforms of the next size 2^k - 1 per direction on zero-padded rows and columns
+    (N = 16 also doubles the circulant embedding).  P^{-1} matches dense P, and FGMRES through it
+    needs far fewer block-CG iterations than with the diagonal preconditioner."""
+    pinv_path(True)
+    inp = inputs.small(2, N, 4, beta=0.6, omega=1.8)
+    p = workloads.with_data(inp)
+    P = system.dense_P(p)
+    A = system.dense_A(p)
+    rng = np.random.default_rng(100 + N)
+    zz = rng.standard_normal(p.n_tot)
+    with gpu_problem(inp, p) as g:
+        y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=tsfde.default_opts(inner_tol=1e-13, inner_maxit=500))
+        assert rel_err(y.cpu().numpy(), np.linalg.solve(P, zz)) <= 1e-9
+        o = tsfde.default_opts(tol=1e-11, inner_tol=1e-8, inner_maxit=500)
+        b = system.rhs_z(p)
+        x, st = g.gmres_solve(torch.tensor(b, device=DEV), opts=o, raise_noconv=True)
+        assert np.linalg.norm(A @ x.cpu().numpy() - b) <= 1e-10 * np.linalg.norm(b)
+        pinv_path(False)
+        _, st_diag = g.gmres_solve(torch.tensor(b, device=DEV), opts=o, raise_noconv=True)
+    if N >= 12:
+        assert 2 * st.inner_iters < st_diag.inner_iters, (st.inner_iters, st_diag.inner_iters)
