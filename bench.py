@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=2,
                     help="instances of the workload solved side by side by tsfde_recover_f_batch (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c4", action="store_true", help="skip the mixed batch of 64 independent problems")
     ap.add_argument("--matvec-only", action="store_true",
                     help="only the apply_A timing (FP64, FP32), preceded by one FP64->FP32 conversion of a vector "
                          "(known bytes: a reference for hardware traffic counters); for profiling")
@@ -269,6 +270,39 @@ def main():
         for pk in probs[1:]:
             pk.close()
 
+    # the mixed batch of 64 independent problems (d = 1 and 2, uneven shapes and parameters), all
+    # solved by one tsfde_recover_f_batch call with 8 in flight (a first, untimed call allocates the
+    # problems' Krylov bases and work buffers)
+    mixed_batch = None
+    if not a.no_c4:
+        t0 = time.perf_counter()
+        cprobs = []
+        for k in range(inputs.C4_SIZE):
+            ik = inputs.c4(k)
+            pk = tsfde.Problem.from_inputs(ik)
+            vk = pk.forward_solve(torch.tensor(ik.f_true, device=dev), opts=tsfde.default_opts(inner_tol=1e-12))
+            pk.set_mu(ik.noisy(vk[(ik.M - 1) * ik.Nd:].cpu().numpy()))
+            cprobs.append(pk)
+        t_c4 = time.perf_counter() - t0
+        log(f"mixed batch: {len(cprobs)} problems set up in {t_c4:.1f} s")
+        oc4 = tsfde.default_opts(tol=1e-8, inner_tol=a.inner_tol, maxit=500)
+        tsfde.recover_f_batch(cprobs, oc4, max_inflight=8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = tsfde.recover_f_batch(cprobs, oc4, max_inflight=8)
+        torch.cuda.synchronize()
+        dtc = time.perf_counter() - t0
+        its = [st.iters for _, st in outs]
+        log(f"mixed batch: {len(cprobs)} solves in {dtc:.2f} s ({len(cprobs) / dtc:.2f} problems/s)")
+        mixed_batch = {"problems": len(cprobs), "instances_in_flight": 8, "problems_per_s": len(cprobs) / dtc,
+                       "s_per_batch": dtc, "tol": 1e-8, "inner_tol": a.inner_tol,
+                       "converged": int(sum(st.converged for _, st in outs)),
+                       "max_rel_res": max(st.rel_res for _, st in outs),
+                       "outer_iters_min_mean_max": [min(its), float(np.mean(its)), max(its)],
+                       "n_tot_total": int(sum(p.n_tot for p in cprobs)), "setup_s": t_c4}
+        for pk in cprobs:
+            pk.close()
+
     # structured matvec (FP64 and FP32), HIP events on the stream the library launches on
     y = torch.randn(prob.n_tot, dtype=torch.float64, device=dev)
     mvr = matvec_timing(a, prob, inp, y, y.float())
@@ -312,6 +346,9 @@ def main():
         "tau_blocks_preconditioner": tau_forms,
         # independent instances of the workload solved side by side (tsfde_recover_f_batch)
         "batched": batched,
+        # 64 independent problems of uneven shapes: even k d = 1, N ~ U[127, 2047]; odd k d = 2,
+        # N ~ U[31, 127]; M ~ U[64, 512]; beta, omega, alpha drawn per problem
+        "mixed_batch": mixed_batch,
         "matvec": {"fp64_ms": mv64, "fp64_GB_s": gbs64, "fp32_ms": mv32, "fp32_GB_s": gbs32,
                    "algorithmic_bytes_fp64": bytes64},
         # traffic: HBM bytes of one FP64 apply_A from the FETCH_SIZE / WRITE_SIZE counter runs, scaled by

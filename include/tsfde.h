@@ -205,8 +205,8 @@ tsfde_status tsfde_recover_f(tsfde_problem* prob, double* f_out, double* work,
  * preconditioner is a chain of dependent time steps that occupies only a
  * part of the device, solving several side by side raises the throughput.
  * Their kernels overlap only as far as the HIP runtime gives the streams
- * hardware queues of their own: GPU_MAX_HW_QUEUES (4 by default, shared with
- * every other stream of the process) should be at least max_inflight + 2.
+ * hardware queues of their own (GPU_MAX_HW_QUEUES, 4 by default, shared with
+ * every other stream of the process).
  *   probs   count distinct problem handles (on the current HIP device)
  *   f_out   count device pointers, f_out[i] receives N_i^d values
  *   opts    one set of options for all problems (NULL for defaults)

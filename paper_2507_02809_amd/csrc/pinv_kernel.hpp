@@ -1322,10 +1322,10 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
     // The segment kernel's blocks wait for each other, so all of them must be resident at once.  A
     // single call launches cooperatively (the runtime checks residency and does not overlap such
     // launches).  Inside a batch, up to kMaxInflight of these kernels run side by side as ordinary
-    // launches, each limited to 1/kMaxInflight of the device's resident capacity, so that together
-    // they always fit.
+    // launches, each limited to ncu / kMaxInflight blocks: even if every block of every such kernel
+    // occupied a CU of its own (kernels of different shapes need not pack together), they fit.
     const bool shared = shared_launch();
-    const int cap = shared ? std::max(1, per_cu * ncu / kMaxInflight) : per_cu * ncu;
+    const int cap = shared ? std::max(1, ncu / kMaxInflight) : per_cu * ncu;
     grid = std::max(1, std::min(grid, cap));
     launch_fill(reinterpret_cast<float*>(W.iters), 2, 0.0f, st);  // zero the iteration counter
     const int s_last = last_block ? P.M : P.M - 1;

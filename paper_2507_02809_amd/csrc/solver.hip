@@ -722,6 +722,11 @@ tsfde_status tsfde_recover_f_batch(tsfde_problem* const* probs, int count, doubl
     std::vector<tsfde_status> rcs(count, TSFDE_OK);
     std::vector<std::string> msgs(count);
     std::vector<tsfde_stats> S(count, tsfde_stats{});
+    // largest problems first (by unknowns), so that a long solve does not start last
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return probs[x]->p->ntot > probs[y]->p->ntot; });
     std::atomic<int> next{0};
     // each worker takes the next problem until none is left, on a stream of its own
     auto worker = [&]() {
@@ -729,7 +734,8 @@ tsfde_status tsfde_recover_f_batch(tsfde_problem* const* probs, int count, doubl
         hipError_t e = hipSetDevice(dev);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
         set_shared_launch(true);
-        for (int i; (i = next.fetch_add(1)) < count;) {
+        for (int t; (t = next.fetch_add(1)) < count;) {
+            const int i = order[t];
             if (e != hipSuccess) {
                 rcs[i] = TSFDE_EDEVICE;
                 msgs[i] = std::string("stream creation failed: ") + hipGetErrorString(e);
