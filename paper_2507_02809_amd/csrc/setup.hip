@@ -368,11 +368,12 @@ tsfde_status create(int d, int N, int M, double T, double beta, double omega, do
         P->eta = std::pow(P->dt, beta) * std::tgamma(2.0 - beta);
         P->ct = P->eta / std::pow(P->h, omega);
         P->cf = alpha / std::pow(P->h, omega);
-        P->Ld = is_pow2(2LL * (N + 1)) && 2 * (N + 1) <= 8192 ? 2 * (N + 1) : 0;
+        // the sine transforms run as FFTs of at least 8 points (the shortest transform the kernels take)
+        P->Ld = is_pow2(2LL * (N + 1)) && 2 * (N + 1) >= 8 && 2 * (N + 1) <= 8192 ? 2 * (N + 1) : 0;
         P->tau_ok = P->Ld > 0;
         P->Nt = N;
         if (!P->tau_ok) {
-            int Ld = 4;
+            int Ld = 8;
             while (Ld < 2 * (N + 1)) Ld *= 2;
             if (Ld <= 8192) {
                 P->tau_pad = true;

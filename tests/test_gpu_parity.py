@@ -404,3 +404,23 @@ def test_apply_P_inv_2d_padded_tau_matches_dense(N, pinv_path):
         _, st_diag = g.gmres_solve(torch.tensor(b, device=DEV), opts=o, raise_noconv=True)
     if N >= 12:
         assert 2 * st.inner_iters < st_diag.inner_iters, (st.inner_iters, st_diag.inner_iters)
+
+
+@pytest.mark.parametrize("d,N,M", [(1, 1, 1), (1, 2, 1), (1, 3, 2), (1, 5, 1), (2, 1, 1), (2, 2, 3), (2, 3, 1),
+                                   (2, 4, 2)])
+def test_degenerate_shapes_match_dense(d, N, M):
+    """One time step, one or a few grid points (transforms of length 8, single-thread transform
+    groups): A y, P^{-1} z and the recovered f~ against the oracle's dense matrices."""
+    inp = inputs.small(d, N, M, beta=0.55, omega=1.45)
+    p = workloads.with_data(inp)
+    A, P = system.dense_A(p), system.dense_P(p)
+    rng = np.random.default_rng(1000 + 100 * d + 10 * N + M)
+    y = rng.standard_normal(p.n_tot)
+    b = system.rhs_z(p)
+    with gpu_problem(inp, p) as g:
+        z = g.apply_A(torch.tensor(y, device=DEV)).cpu().numpy()
+        assert rel_err(z, A @ y) <= 1e-13
+        w = g.apply_P_inv(torch.tensor(y, device=DEV), opts=tsfde.default_opts(inner_tol=1e-14, inner_maxit=500))
+        assert rel_err(w.cpu().numpy(), np.linalg.solve(P, y)) <= 1e-10
+        f, st = g.recover_f(tsfde.default_opts(tol=1e-12, inner_tol=1e-14, inner_maxit=500), raise_noconv=True)
+        assert rel_err(f.cpu().numpy(), np.linalg.solve(A, b)[p.S * p.Nd:]) <= 1e-9
