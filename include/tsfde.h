@@ -231,6 +231,51 @@ tsfde_status tsfde_recover_f_batch(tsfde_problem* const* probs, int count, doubl
 tsfde_status tsfde_forward_solve(tsfde_problem* prob, const double* f, double* v,
                                  const tsfde_opts* opts, void* stream);
 
+/*
+ * Transposed problem (gradients of f~ with respect to the data and the
+ * regularisation parameter).  With w^(s) = gamma1^(s) .* lam^(s) and the
+ * blocks of A (§5, eq. lin-syst) transposed (B is symmetric):
+ *   (A^T lam)^(s) = e_0 w^(s) + sum_{r>s, r<=M} e_{r-s} w^(r) + [s = M] lam^(M+1)
+ *                   + (eta/h^omega) B (gamma2^(s) .* lam^(s)),           s = 1..M
+ *   (A^T lam)^(M+1) = -eta sum_s q^(s) lam^(s) + c_f B (gamma2^(M) .* lam^(M+1))
+ * (1-based slices as in §5; the history sum runs backwards in time).
+ * lam, z, g: device, (M+1) N^d, layout of every solution vector.
+ */
+tsfde_status tsfde_apply_AT(tsfde_problem* prob, const double* lam, double* z, void* stream);
+
+/*
+ * lam = P^{-T} g: backward substitution over the block rows of P^T (§5.1
+ * transposed): the last block c_f B D_2^(M) lam^(M+1) = g^(M+1), then for
+ * s = M..1 the block (e_0 D_1^(s) + (eta/h^omega) B D_2^(s)) lam^(s) = r^(s),
+ * solved in u = D_2^(s) lam^(s) by the same SPD block CG as P^{-1}
+ * (opts.inner_tol, opts.inner_maxit; FP64, one launch per CG phase).
+ * g and lam must not overlap.
+ */
+tsfde_status tsfde_apply_PT_inv(tsfde_problem* prob, const double* g, double* lam,
+                                const tsfde_opts* opts, void* stream);
+
+/*
+ * Solve A^T lam = g by flexible GMRES right-preconditioned by P^{-T} (FP64;
+ * opts.precision and opts.block_solver do not apply).  lam holds the initial
+ * guess.  Returns ENOCONV if opts.tol was not reached.
+ */
+tsfde_status tsfde_adjoint_solve(tsfde_problem* prob, const double* g, double* lam,
+                                 const tsfde_opts* opts, tsfde_stats* stats, void* stream);
+
+/*
+ * Vector-Jacobian product of f~ = R A^{-1} z (R: the last block) for a loss
+ * with gradient gf = dL/df~ (device, N^d), given the solution y of A y = z
+ * (device, (M+1) N^d, e.g. the `work` buffer of tsfde_recover_f):
+ *   lam = A^{-T} [0; gf]                           (tsfde_adjoint_solve)
+ *   grad_mu    = lam^(M+1)                         (z^(M+1) = mu_eps)
+ *   grad_alpha = -lam^T (dA/dalpha) y = -(c_f/alpha) lam^(M+1) . (gamma2^(M) .* B y^(M+1))
+ * grad_mu: device N^d or NULL; grad_alpha: HOST double or NULL.  Allocates
+ * three work vectors for the call.
+ */
+tsfde_status tsfde_recover_f_vjp(tsfde_problem* prob, const double* y, const double* gf,
+                                 double* grad_mu, double* grad_alpha, const tsfde_opts* opts,
+                                 tsfde_stats* stats, void* stream);
+
 /* Last error message of the calling thread ("" if none). */
 const char* tsfde_last_error(void);
 

@@ -1,0 +1,48 @@
+"""Oracle of the transposed problem (test infrastructure only: the HIP library never imports it).
+
+The gradients of the recovered source f~ = R A^{-1} z (R keeps the last block, §5 eq. lin-syst)
+with respect to the final-time data mu_eps and the regularisation parameter alpha (§3), by the
+adjoint method written out with dense matrices:
+    lam = A^{-T} R^T g,   dL/dmu = lam^(S+1)   (z^(S+1) = mu_eps, the other blocks of z do not
+                                                depend on mu),
+    dL/dalpha = -lam^T (dA/dalpha) y,  where only c_f = alpha / h^omega depends on alpha, so
+                dA/dalpha is zero except its last diagonal block (c_f/alpha) D_2^(S) B.
+P^{-T} is the transpose of the block lower-triangular P of §5.1, applied by a dense solve."""
+from __future__ import annotations
+
+import numpy as np
+
+from .system import Problem, dense_A, dense_B, dense_P, rhs_z
+
+
+def apply_AT(p: Problem, lam: np.ndarray) -> np.ndarray:
+    """A^T lam with A assembled densely."""
+    return dense_A(p).T @ lam
+
+
+def PT_solve(p: Problem, g: np.ndarray) -> np.ndarray:
+    """P^{-T} g by a dense solve."""
+    return np.linalg.solve(dense_P(p).T, g)
+
+
+def adjoint_solve(p: Problem, g: np.ndarray) -> np.ndarray:
+    """A^{-T} g by a dense solve."""
+    return np.linalg.solve(dense_A(p).T, g)
+
+
+def dA_dalpha(p: Problem) -> np.ndarray:
+    """dA/dalpha: (c_f/alpha) D_2^(S) B in the last diagonal block, zero elsewhere."""
+    D = np.zeros((p.n_tot, p.n_tot))
+    S, Nd = p.S, p.Nd
+    D[S * Nd:, S * Nd:] = (p.c_f / p.alpha) * p.gamma2[S - 1][:, None] * dense_B(p)
+    return D
+
+
+def vjp(p: Problem, gf: np.ndarray):
+    """(dL/dmu, dL/dalpha) for a loss L(f~) with dL/df~ = gf, and the solution y of A y = z."""
+    A = dense_A(p)
+    y = np.linalg.solve(A, rhs_z(p))
+    g = np.zeros(p.n_tot)
+    g[p.S * p.Nd:] = gf
+    lam = np.linalg.solve(A.T, g)
+    return lam[p.S * p.Nd:].copy(), float(-lam @ (dA_dalpha(p) @ y)), y

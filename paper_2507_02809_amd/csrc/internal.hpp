@@ -85,6 +85,7 @@ struct Problem {
     double* arn_part = nullptr;  // Arnoldi block partials [kArnMaxK][kArnBlocks]
     double* arn_h = nullptr;     // Arnoldi coefficients, 2 (kMaxRestart + 2) + 1
     double* rwork = nullptr;     // FGMRES residual (n_tot)
+    double* adj_u = nullptr;     // adjoint work: gamma2-scaled slices (n_tot)
     void* pw64 = nullptr;           // persistent P^{-1} work buffers (FP64 / FP32)
     void* pw32 = nullptr;
     double* dev_scalars = nullptr;  // small device scratch (dots, flags)
@@ -96,11 +97,15 @@ struct Problem {
 template <typename T>
 void launch_history_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s);
 
-// d = 2 matvec Toeplitz part with workgroup-coalesced transposes; false if the shape is not covered
+// Toeplitz part of the matvec: z_s += c_t gamma2_s .* (B y_s) (s < M) and
+// z_M = c_f gamma2_{M-1} .* (B y_M) + ylast (ylast null: y_{M-1}; D.gamma2 null: ones).
+// d = 2 with workgroup-coalesced transposes (false if the shape is not covered), or the general path
 template <typename T>
-bool launch_toeplitz2d_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s);
+bool launch_toeplitz2d_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s,
+                              const T* ylast = nullptr);
 template <typename T>
-void launch_toeplitz_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s);
+void launch_toeplitz_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s,
+                            const T* ylast = nullptr);
 
 // q = dg .* p + c * B p  (single slice, dg may be null), with per-block partials of (p, q)
 template <typename T>
@@ -117,6 +122,16 @@ void launch_tau_prec(const Problem& P, const Dev<T>& D, const T* r, T* z, T sigm
 template <typename T>
 void launch_step_rhs(const Problem& P, const Dev<T>& D, const T* z, const T* y, int s, T* rhs,
                      T scale_last, hipStream_t st);
+
+// transposed operators (kernels.hip): the history, diagonal and f-row terms of A^T lam; the
+// gamma2 scaling of all slices (only < 0), or of one slice `in` into slice `only` of out (inverse:
+// division); the backward-substitution right-hand side
+template <typename T>
+void launch_history_adj(const Problem& P, const Dev<T>& D, const T* lam, T* z, hipStream_t s);
+template <typename T>
+void launch_scale_g2(const Problem& P, const Dev<T>& D, const T* in, T* out, int only, bool inverse, hipStream_t s);
+template <typename T>
+void launch_adj_step_rhs(const Problem& P, const Dev<T>& D, const T* g, const T* lam, int m, T* rhs, hipStream_t s);
 
 // BLAS-1 helpers
 template <typename T>

@@ -100,6 +100,105 @@ void launch_step_rhs(const Problem& P, const Dev<T>& D, const T* z, const T* y, 
 }
 
 // ---------------------------------------------------------------------------
+// Transposed operators (adjoint problem).  With w_s = gamma1^(s) .* lam^(s):
+//   (A^T lam)^(m) = e_0 w_m + sum_{s=m+1}^{M-1} e_{s-m} w_s + [m = M-1] lam^(M)
+//                   + c_t B (gamma2^(m) .* lam^(m))                          (m < M)
+//   (A^T lam)^(M) = -eta sum_{s<M} q_s lam^(s) + c_f B (gamma2^(M-1) .* lam^(M))
+// history_adj writes every term but the B products.  One thread per point; the outputs are taken
+// kAdjTile time levels at a time (their sums in registers) while the inputs s >= m0 stream past.
+// ---------------------------------------------------------------------------
+constexpr int kAdjTile = 32;
+static_assert(kAdjTile <= kEpad, "the tile overhang reads the leading zeros of epad");
+
+template <typename T>
+__global__ __launch_bounds__(256) void history_adj(const T* __restrict__ lam, T* __restrict__ z,
+                                                   const T* __restrict__ g1, const T* __restrict__ epad,
+                                                   const T* __restrict__ q, T eta, long long Nd, int M) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= Nd) return;
+    const T* e = epad + kEpad;  // e[k] = 0 for -kEpad <= k < 0
+    T fr = T(0);
+    for (int s = 0; s < M; ++s) fr += q[s] * lam[(long long)s * Nd + j];
+    z[(long long)M * Nd + j] = -eta * fr;
+    for (int m0 = 0; m0 < M; m0 += kAdjTile) {
+        T acc[kAdjTile];
+#pragma unroll
+        for (int t = 0; t < kAdjTile; ++t) acc[t] = T(0);
+        for (int s = m0; s < M; ++s) {
+            const long long o = (long long)s * Nd + j;
+            const T w = g1[o] * lam[o];
+#pragma unroll
+            for (int t = 0; t < kAdjTile; ++t) acc[t] += e[s - m0 - t] * w;  // zero for s < m0 + t
+        }
+#pragma unroll
+        for (int t = 0; t < kAdjTile; ++t) {
+            const int m = m0 + t;
+            if (m < M) z[(long long)m * Nd + j] = acc[t] + (m == M - 1 ? lam[(long long)M * Nd + j] : T(0));
+        }
+    }
+}
+
+template <typename T>
+void launch_history_adj(const Problem& P, const Dev<T>& D, const T* lam, T* z, hipStream_t s) {
+    hipLaunchKernelGGL(history_adj<T>, dim3((unsigned)((P.Nd + 255) / 256)), dim3(256), 0, s, lam, z, D.gamma1,
+                       D.epad, D.q, T(P.eta), P.Nd, P.M);
+    TSFDE_HIP(hipGetLastError());
+}
+
+// only < 0: out^(s) = gamma2^(s) .* in^(s) for s < M and out^(M) = gamma2^(M-1) .* in^(M) (the inputs of
+// the B products of A^T).  only >= 0: `in` is one slice and out^(only) = in (./ or .*) the gamma2 of
+// that slice (gamma2^(M-1) for only = M).
+template <typename T>
+__global__ void scale_g2_k(const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ g2, long long Nd, int M,
+                           int only, bool inverse) {
+    const long long n = (only >= 0) ? Nd : (long long)(M + 1) * Nd;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const long long k = (only >= 0) ? (long long)only * Nd + i : i;  // index in the full vector
+        const long long sl = k / Nd, j = k - sl * Nd;
+        const T g = g2[(sl < M ? sl : M - 1) * Nd + j];
+        const T v = in[(only >= 0) ? i : k];
+        out[k] = inverse ? v / g : v * g;
+    }
+}
+
+template <typename T>
+void launch_scale_g2(const Problem& P, const Dev<T>& D, const T* in, T* out, int only, bool inverse, hipStream_t s) {
+    const long long n = (only >= 0) ? P.Nd : P.ntot;
+    hipLaunchKernelGGL(scale_g2_k<T>, dim3((unsigned)std::max(1LL, std::min<long long>((n + 255) / 256, 16384))),
+                       dim3(256), 0, s, in, out, D.gamma2, P.Nd, P.M, only, inverse);
+    TSFDE_HIP(hipGetLastError());
+}
+
+// right-hand side of backward-substitution step m (0-based) for P^T lam = g, in the variable u = gamma2 .* lam:
+//   m < M : rhs = g^(m) - sum_{s=m+1}^{M-1} e_{s-m} gamma1^(s) .* lam^(s) - [m = M-1] lam^(M)
+//   m = M : rhs = g^(M) / c_f
+template <typename T>
+__global__ void adj_step_rhs(const T* __restrict__ g, const T* __restrict__ lam, const T* __restrict__ g1,
+                             const T* __restrict__ epad, int m, int M, long long Nd, T cf, T* __restrict__ rhs) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= Nd) return;
+    if (m == M) {
+        rhs[j] = g[(long long)M * Nd + j] / cf;
+        return;
+    }
+    const T* e = epad + kEpad;
+    T h = T(0);
+    for (int s = m + 1; s < M; ++s) {
+        const long long o = (long long)s * Nd + j;
+        h += e[s - m] * g1[o] * lam[o];
+    }
+    if (m == M - 1) h += lam[(long long)M * Nd + j];
+    rhs[j] = g[(long long)m * Nd + j] - h;
+}
+
+template <typename T>
+void launch_adj_step_rhs(const Problem& P, const Dev<T>& D, const T* g, const T* lam, int m, T* rhs, hipStream_t st) {
+    hipLaunchKernelGGL(adj_step_rhs<T>, dim3((unsigned)((P.Nd + 255) / 256)), dim3(256), 0, st, g, lam, D.gamma1,
+                       D.epad, m, P.M, P.Nd, T(P.cf), rhs);
+    TSFDE_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -549,6 +648,11 @@ void launch_jacobi_prec(const T* r, T* z, const T* dg, T c, T a0, long long n, T
 // explicit instantiations
 namespace tsfde {
 template void launch_history_matvec<double>(const Problem&, const Dev<double>&, const double*, double*, hipStream_t);
+template void launch_history_adj<double>(const Problem&, const Dev<double>&, const double*, double*, hipStream_t);
+template void launch_scale_g2<double>(const Problem&, const Dev<double>&, const double*, double*, int, bool,
+                                      hipStream_t);
+template void launch_adj_step_rhs<double>(const Problem&, const Dev<double>&, const double*, const double*, int,
+                                          double*, hipStream_t);
 template void launch_history_matvec<float>(const Problem&, const Dev<float>&, const float*, float*, hipStream_t);
 template void launch_step_rhs<double>(const Problem&, const Dev<double>&, const double*, const double*, int, double*,
                                       double, hipStream_t);

@@ -295,7 +295,7 @@ void free_problem(Problem* P) {
     free_dev(P->f32);
     pinv_persistent_free<double>(P->pw64);
     pinv_persistent_free<float>(P->pw32);
-    void* ptrs[] = {P->d_bw, P->d_rho, P->d_mu, P->z_rhs, P->xbuf, P->V, P->Z, P->arn_part, P->arn_h, P->rwork,
+    void* ptrs[] = {P->d_bw, P->d_rho, P->d_mu, P->z_rhs, P->xbuf, P->V, P->Z, P->arn_part, P->arn_h, P->rwork, P->adj_u,
                     P->dev_scalars};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);

@@ -146,25 +146,70 @@ static long long pinv_impl(Problem& P, const T* z, T* y, const Opts& o, hipStrea
     return pinv_launch<T>(P, z, y, o, st, last_block);
 }
 
+// One diagonal block by preconditioned CG, one kernel launch per CG phase and the convergence test on
+// the host: (dg + c B) x = rhs (dg null: c B x = rhs) from the initial x, to relative residual
+// inner_tol; the preconditioner is the tau matrix (sigma I + c tau(B)) when the sine transform is
+// available, else the diagonal.  Returns the CG iterations.
+template <typename T>
+static long long block_cg(Problem& P, Dev<T>& D, const T* rhs, T* x, const T* dg, T c, T sigma, const Opts& o,
+                          hipStream_t st) {
+    const long long Nd = P.Nd;
+    T* r = D.pcg + Nd;
+    T* zz = D.pcg + 2 * Nd;
+    T* p = D.pcg + 3 * Nd;
+    T* q = D.pcg + 4 * Nd;
+    double* scal = P.dev_scalars;
+    double* hs = P.host_scalars;
+    const double tol2 = o.inner_tol * o.inner_tol;
+    long long total = 0;
+    int np = 0;
+    auto prec = [&](const T* rin, T* zout) {
+        if (P.tau_ok) launch_tau_prec<T>(P, D, rin, zout, sigma, c, D.partial, &np, st);
+        else launch_jacobi_prec<T>(rin, zout, dg, c, T(P.a0), Nd, D.partial, &np, st);
+    };
+    // r = rhs - A_s x ; ||r||^2 ; ||rhs||^2
+    launch_spd_apply<T>(P, D, x, q, dg, c, D.partial, &np, st);
+    launch_sub_partials<T>(rhs, q, r, Nd, D.partial, &np, st);
+    launch_sum_partials(D.partial, np, scal + 3, st);
+    launch_dot_partials<T>(rhs, rhs, Nd, D.partial, &np, st);
+    launch_sum_partials(D.partial, np, scal + 8, st);
+    TSFDE_HIP(hipMemcpyAsync(hs, scal, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+    TSFDE_HIP(hipStreamSynchronize(st));
+    const double bb = hs[8];
+    double rr = hs[3];
+    if (!(bb > 0.0)) {
+        launch_fill(x, Nd, T(0), st);
+    } else if (rr > tol2 * bb) {
+        prec(r, zz);
+        launch_sum_partials(D.partial, np, scal + 0, st);
+        launch_copy<T>(zz, p, Nd, st);
+        for (int it = 1; it <= o.inner_maxit; ++it) {
+            launch_spd_apply<T>(P, D, p, q, dg, c, D.partial, &np, st);
+            launch_sum_partials(D.partial, np, scal + 1, st);
+            launch_cg_scalars(scal, 0, st);
+            launch_cg_update_xr<T>(x, r, p, q, scal, Nd, D.partial, &np, st);
+            launch_sum_partials(D.partial, np, scal + 3, st);
+            TSFDE_HIP(hipMemcpyAsync(hs + 3, scal + 3, sizeof(double), hipMemcpyDeviceToHost, st));
+            TSFDE_HIP(hipStreamSynchronize(st));
+            ++total;
+            rr = hs[3];
+            if (rr <= tol2 * bb || !std::isfinite(rr)) break;
+            prec(r, zz);
+            launch_sum_partials(D.partial, np, scal + 5, st);
+            launch_cg_scalars(scal, 1, st);
+            launch_cg_update_p<T>(p, zz, scal, Nd, st);
+        }
+    }
+    return total;
+}
+
 template <typename T>
 static long long pinv_launch(Problem& P, const T* z, T* y, const Opts& o, hipStream_t st, bool last_block) {
     Dev<T>& D = dev<T>(P);
     const long long Nd = P.Nd;
     T* x = D.pcg;
-    T* r = x + Nd;
-    T* zz = x + 2 * Nd;
-    T* p = x + 3 * Nd;
-    T* q = x + 4 * Nd;
     T* rhs = x + 7 * Nd;
-    double* scal = P.dev_scalars;
-    double* hs = P.host_scalars;
     long long total = 0;
-    const double tol2 = o.inner_tol * o.inner_tol;
-    int np = 0;
-    auto prec = [&](const T* rin, T* zout, const T* dg, T c, T sigma) {
-        if (P.tau_ok) launch_tau_prec<T>(P, D, rin, zout, sigma, c, D.partial, &np, st);
-        else launch_jacobi_prec<T>(rin, zout, dg, c, T(P.a0), Nd, D.partial, &np, st);
-    };
     const int last = last_block ? P.M : P.M - 1;
     for (int s = 0; s <= last; ++s) {
         launch_step_rhs<T>(P, D, z, y, s, rhs, T(P.cf), st);
@@ -173,40 +218,46 @@ static long long pinv_launch(Problem& P, const T* z, T* y, const Opts& o, hipStr
         const T sigma = (s < P.M) ? T(P.sigma[s]) : T(0);
         if (s > 0 && s < P.M) launch_copy<T>(y + (long long)(s - 1) * Nd, x, Nd, st);
         else launch_fill(x, Nd, T(0), st);
-        // r = rhs - A_s x ; ||r||^2 ; ||rhs||^2
-        launch_spd_apply<T>(P, D, x, q, dg, c, D.partial, &np, st);
-        launch_sub_partials<T>(rhs, q, r, Nd, D.partial, &np, st);
-        launch_sum_partials(D.partial, np, scal + 3, st);
-        launch_dot_partials<T>(rhs, rhs, Nd, D.partial, &np, st);
-        launch_sum_partials(D.partial, np, scal + 8, st);
-        TSFDE_HIP(hipMemcpyAsync(hs, scal, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
-        TSFDE_HIP(hipStreamSynchronize(st));
-        const double bb = hs[8];
-        double rr = hs[3];
-        if (!(bb > 0.0)) {
-            launch_fill(x, Nd, T(0), st);
-        } else if (rr > tol2 * bb) {
-            prec(r, zz, dg, c, sigma);
-            launch_sum_partials(D.partial, np, scal + 0, st);
-            launch_copy<T>(zz, p, Nd, st);
-            for (int it = 1; it <= o.inner_maxit; ++it) {
-                launch_spd_apply<T>(P, D, p, q, dg, c, D.partial, &np, st);
-                launch_sum_partials(D.partial, np, scal + 1, st);
-                launch_cg_scalars(scal, 0, st);
-                launch_cg_update_xr<T>(x, r, p, q, scal, Nd, D.partial, &np, st);
-                launch_sum_partials(D.partial, np, scal + 3, st);
-                TSFDE_HIP(hipMemcpyAsync(hs + 3, scal + 3, sizeof(double), hipMemcpyDeviceToHost, st));
-                TSFDE_HIP(hipStreamSynchronize(st));
-                ++total;
-                rr = hs[3];
-                if (rr <= tol2 * bb || !std::isfinite(rr)) break;
-                prec(r, zz, dg, c, sigma);
-                launch_sum_partials(D.partial, np, scal + 5, st);
-                launch_cg_scalars(scal, 1, st);
-                launch_cg_update_p<T>(p, zz, scal, Nd, st);
-            }
-        }
+        total += block_cg<T>(P, D, rhs, x, dg, c, sigma, o, st);
         launch_copy<T>(x, y + (long long)s * Nd, Nd, st);
+    }
+    return total;
+}
+
+// ---------------------------------------------------------------------------
+// Transposed problem: A^T lam and P^{-T} g (FP64)
+// ---------------------------------------------------------------------------
+static void apply_AT_impl(Problem& P, const double* lam, double* z, hipStream_t st) {
+    Dev<double>& D = P.f64;
+    if (!P.adj_u) TSFDE_HIP(hipMalloc(&P.adj_u, sizeof(double) * P.ntot));
+    launch_scale_g2<double>(P, D, lam, P.adj_u, -1, false, st);
+    launch_history_adj<double>(P, D, lam, z, st);
+    // B products of the gamma2-scaled slices added with weight c_t (c_f for the last); the last
+    // slice keeps its f-row terms (ylast = z^(M) itself)
+    Dev<double> Dn = D;
+    Dn.gamma2 = nullptr;
+    const double* ylast = z + (size_t)P.M * P.Nd;
+    if (!launch_toeplitz2d_matvec<double>(P, Dn, P.adj_u, z, st, ylast))
+        launch_toeplitz_matvec<double>(P, Dn, P.adj_u, z, st, ylast);
+}
+
+// lam = P^{-T} g by backward substitution over the block rows of P^T (block upper triangular): block
+// m solves (e_0 D_1 + c_t B D_2) lam^(m) = r, i.e. the SPD system (dg + c_t B) u = r for u = D_2 lam^(m)
+// (the last block: c_f B D_2^(M-1) lam^(M) = g^(M)).  Returns CG iterations.
+static long long ptinv_launch(Problem& P, const double* g, double* lam, const Opts& o, hipStream_t st) {
+    Dev<double>& D = P.f64;
+    const long long Nd = P.Nd;
+    double* x = D.pcg;
+    double* rhs = x + 7 * Nd;
+    long long total = 0;
+    for (int m = P.M; m >= 0; --m) {
+        launch_adj_step_rhs<double>(P, D, g, lam, m, rhs, st);
+        const double* dg = (m < P.M) ? D.dg + (long long)m * Nd : nullptr;
+        const double c = (m < P.M) ? P.ct : 1.0;
+        const double sigma = (m < P.M) ? P.sigma[m] : 0.0;
+        if (m >= P.M - 1) launch_fill(x, Nd, 0.0, st);  // else warm start from u of block m + 1
+        total += block_cg<double>(P, D, rhs, x, dg, c, sigma, o, st);
+        launch_scale_g2<double>(P, D, x, lam, m, true, st);
     }
     return total;
 }
@@ -480,6 +531,33 @@ static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o,
     TSFDE_HIP(hipStreamSynchronize(st));
     S.t_total = now() - t_start;
     return S.converged ? TSFDE_OK : TSFDE_ENOCONV;
+}
+
+// A^T lam = g by FGMRES right-preconditioned with P^{-T} (FP64; block solves by CG to inner_tol);
+// lam holds the initial guess
+static tsfde_status adjoint_impl(Problem& P, const double* g, double* lam, const Opts& o, tsfde_stats& S,
+                                 hipStream_t st) {
+    const long long n = P.ntot;
+    const int maxit = o.maxit > 0 ? o.maxit : (int)std::min<long long>(n, 1000);
+    const double t_start = now();
+    SolveOps ops;
+    ops.A = [&](const double* v, double* out) { apply_AT_impl(P, v, out, st); };
+    ops.M = [&](const double* v, double* out) -> long long {
+        if (!o.use_precond) {
+            launch_copy<double>(v, out, n, st);
+            return 0;
+        }
+        return ptinv_launch(P, v, out, o, st);
+    };
+    if (!P.rwork) TSFDE_HIP(hipMalloc(&P.rwork, sizeof(double) * n));
+    bool conv = false;
+    double rel = 1.0;
+    fgmres(P, ops, g, lam, P.rwork, o.tol, o.restart, maxit, st, S, conv, rel, true);
+    S.refinements = 1;
+    S.converged = conv ? 1 : 0;
+    S.rel_res = rel;
+    S.t_total = now() - t_start;
+    return conv ? TSFDE_OK : TSFDE_ENOCONV;
 }
 
 }  // namespace tsfde
@@ -792,6 +870,85 @@ tsfde_status tsfde_forward_solve(tsfde_problem* prob, const double* f, double* v
         (void)hipFree(y);
     })
     return TSFDE_OK;
+}
+
+tsfde_status tsfde_apply_AT(tsfde_problem* prob, const double* lam, double* z, void* stream) {
+    if (!prob || !lam || !z) { set_error("apply_AT: NULL argument"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    if (overlap(lam, z, sizeof(double) * P.ntot)) { set_error("apply_AT: lam and z overlap"); return TSFDE_EINVAL; }
+    TSFDE_GUARD("apply_AT", apply_AT_impl(P, lam, z, (hipStream_t)stream);)
+    return TSFDE_OK;
+}
+
+tsfde_status tsfde_apply_PT_inv(tsfde_problem* prob, const double* g, double* lam, const tsfde_opts* opts,
+                                void* stream) {
+    if (!prob || !g || !lam) { set_error("apply_PT_inv: NULL argument"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    if (overlap(g, lam, sizeof(double) * P.ntot)) { set_error("apply_PT_inv: g and lam overlap"); return TSFDE_EINVAL; }
+    const Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    TSFDE_GUARD("apply_PT_inv", {
+        ptinv_launch(P, g, lam, o, st);
+        TSFDE_HIP(hipStreamSynchronize(st));
+    })
+    return TSFDE_OK;
+}
+
+tsfde_status tsfde_adjoint_solve(tsfde_problem* prob, const double* g, double* lam, const tsfde_opts* opts,
+                                 tsfde_stats* stats, void* stream) {
+    if (!prob || !g || !lam) { set_error("adjoint_solve: NULL argument"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    if (overlap(g, lam, sizeof(double) * P.ntot)) { set_error("adjoint_solve: g and lam overlap"); return TSFDE_EINVAL; }
+    const Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    tsfde_stats S{};
+    tsfde_status rc = TSFDE_OK;
+    TSFDE_GUARD("adjoint_solve", rc = adjoint_impl(P, g, lam, o, S, (hipStream_t)stream);)
+    if (stats) *stats = S;
+    if (rc == TSFDE_ENOCONV) set_error("adjoint_solve: tolerance not reached (rel. residual %.3e)", S.rel_res);
+    return rc;
+}
+
+tsfde_status tsfde_recover_f_vjp(tsfde_problem* prob, const double* y, const double* gf, double* grad_mu,
+                                 double* grad_alpha, const tsfde_opts* opts, tsfde_stats* stats, void* stream) {
+    if (!prob || !y || !gf) { set_error("recover_f_vjp: NULL argument"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    const Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    const long long n = P.ntot, Nd = P.Nd, last = (long long)P.M * P.Nd;
+    hipStream_t st = (hipStream_t)stream;
+    tsfde_stats S{};
+    tsfde_status rc = TSFDE_OK;
+    TSFDE_GUARD("recover_f_vjp", {
+        double* w = nullptr;  // g = [0; gf], lam, then v = [0; y^(M)] and A v
+        TSFDE_HIP(hipMalloc(&w, sizeof(double) * 3 * n));
+        double* g = w;
+        double* lam = w + n;
+        double* v = w + 2 * n;
+        launch_fill(g, n, 0.0, st);
+        launch_copy<double>(gf, g + last, Nd, st);
+        launch_fill(lam, n, 0.0, st);
+        try {
+            rc = adjoint_impl(P, g, lam, o, S, st);
+            if (grad_mu) launch_copy<double>(lam + last, grad_mu, Nd, st);
+            if (grad_alpha) {
+                // dA/dalpha y = (1/alpha) (A [0; y^(M)])^(M): only c_f = alpha/h^omega depends on alpha
+                launch_fill(v, n, 0.0, st);
+                launch_copy<double>(y + last, v + last, Nd, st);
+                apply_A_impl<double>(P, v, g, st);
+                *grad_alpha = -dev_dot(P, lam + last, g + last, Nd, st) / P.alpha;
+            }
+            TSFDE_HIP(hipStreamSynchronize(st));
+        } catch (...) {
+            (void)hipFree(w);
+            throw;
+        }
+        (void)hipFree(w);
+    })
+    if (stats) *stats = S;
+    if (rc == TSFDE_ENOCONV) set_error("recover_f_vjp: adjoint tolerance not reached (rel. residual %.3e)", S.rel_res);
+    return rc;
 }
 
 const char* tsfde_last_error(void) { return last_error(); }

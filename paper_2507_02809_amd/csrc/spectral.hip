@@ -24,9 +24,10 @@ enum Epi : int { EPI_MATVEC = 0, EPI_SPD = 1 };
 
 template <typename T>
 struct EpiArgs {
-    // EPI_MATVEC: slice s < M: z[s] += ct * gamma2[s] .* u;  s == M: z[M] = cf * gamma2[M-1] .* u + y[M-1]
+    // EPI_MATVEC: slice s < M: z[s] += ct * gamma2[s] .* u;  s == M: z[M] = cf * gamma2[M-1] .* u + ylast
+    // (ylast = y[M-1] for A; gamma2 null stands for ones)
     T* z;
-    const T* y;
+    const T* ylast;
     const T* gamma2;
     T ct, cf;
     int M;
@@ -44,11 +45,11 @@ __device__ __forceinline__ T epi_apply(const EpiArgs<T>& a, int mode, int slice,
     if (mode == EPI_MATVEC) {
         if (slice < a.M) {
             const long long o = (long long)slice * Nd + idx;
-            a.z[o] = a.z[o] + a.ct * a.gamma2[o] * u;
+            a.z[o] = a.z[o] + a.ct * (a.gamma2 ? a.gamma2[o] : T(1)) * u;
         } else {
             const long long o = (long long)a.M * Nd + idx;
             const long long g = (long long)(a.M - 1) * Nd + idx;
-            a.z[o] = a.cf * a.gamma2[g] * u + a.y[g];
+            a.z[o] = a.cf * (a.gamma2 ? a.gamma2[g] : T(1)) * u + a.ylast[idx];
         }
         return T(0);
     } else {
@@ -310,10 +311,10 @@ static int pick_vpt(int L) {
     }
 
 template <typename T>
-void launch_toeplitz_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s) {
+void launch_toeplitz_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s, const T* ylast) {
     EpiArgs<T> ea{};
     ea.z = z;
-    ea.y = y;
+    ea.ylast = ylast ? ylast : y + (long long)(P.M - 1) * P.Nd;
     ea.gamma2 = D.gamma2;
     ea.ct = T(P.ct);
     ea.cf = T(P.cf);
@@ -407,8 +408,10 @@ void launch_tau_prec(const Problem& P, const Dev<T>& D, const T* r, T* z, T sigm
     TSFDE_HIP(hipGetLastError());
 }
 
-template void launch_toeplitz_matvec<double>(const Problem&, const Dev<double>&, const double*, double*, hipStream_t);
-template void launch_toeplitz_matvec<float>(const Problem&, const Dev<float>&, const float*, float*, hipStream_t);
+template void launch_toeplitz_matvec<double>(const Problem&, const Dev<double>&, const double*, double*, hipStream_t,
+                                             const double*);
+template void launch_toeplitz_matvec<float>(const Problem&, const Dev<float>&, const float*, float*, hipStream_t,
+                                            const float*);
 template void launch_spd_apply<double>(const Problem&, const Dev<double>&, const double*, double*, const double*,
                                        double, double*, int*, hipStream_t);
 template void launch_spd_apply<float>(const Problem&, const Dev<float>&, const float*, float*, const float*, float,

@@ -15,7 +15,8 @@
 //              each group re-packs its pair into one Hermitian-completed spectrum, the inverse
 //              FFT leaves the pair's rows in registers, and the epilogue adds c_t gamma2 .* (B y)
 //              to the history part already in z (slice s < M), or writes
-//              z_M = c_f gamma2_{M-1} .* (B f) + y_{M-1}.
+//              z_M = c_f gamma2_{M-1} .* (B f) + ylast, ylast = y_{M-1} for A (a null gamma2
+//              stands for ones: the transposed operator applies B to gamma2-scaled slices).
 //
 // The transform length is a template constant for L = 512 (the C3 size), a run-time value
 // otherwise.  Requires N <= L/2 (the embedding has L >= 2N).
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(kMvBlock) void mv_cols(cplx<T>* __restrict__ spec, 
 template <typename T, int VPT, int LC>
 __global__ __launch_bounds__(kMvBlock) void mv_rows_inv(const cplx<T>* __restrict__ spec, int N, int L_, int slice0,
                                                         int nsl, int M, const cplx<T>* __restrict__ tw_g,
-                                                        T* __restrict__ z, const T* __restrict__ y,
+                                                        T* __restrict__ z, const T* __restrict__ ylast,
                                                         const T* __restrict__ g2, T ct, T cf) {
     extern __shared__ unsigned char smem_raw[];
     const int L = LC ? LC : L_;
@@ -159,11 +160,11 @@ __global__ __launch_bounds__(kMvBlock) void mv_rows_inv(const cplx<T>* __restric
             if (j < N && i0 < N) {
                 const long long o = (long long)i0 * N + j;
                 const long long gs = (long long)(last ? M - 1 : s) * Nd;
-                gv0[u] = g2[gs + o];
-                zo0[u] = last ? y[gs + o] : z[(long long)s * Nd + o];
+                gv0[u] = g2 ? g2[gs + o] : T(1);
+                zo0[u] = last ? ylast[o] : z[(long long)s * Nd + o];
                 if (two) {
-                    gv1[u] = g2[gs + o + N];
-                    zo1[u] = last ? y[gs + o + N] : z[(long long)s * Nd + o + N];
+                    gv1[u] = g2 ? g2[gs + o + N] : T(1);
+                    zo1[u] = last ? ylast[o + N] : z[(long long)s * Nd + o + N];
                 }
             }
         }
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(kMvBlock) void mv_rows_inv(const cplx<T>* __restric
 }
 
 template <typename T, int VPT, int LC>
-static void launch_mv(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t st) {
+static void launch_mv(const Problem& P, const Dev<T>& D, const T* y, T* z, const T* ylast, hipStream_t st) {
     const int L = P.L, N = P.N, H = L / 2 + 1;
     const int nthr = L / VPT, gpb = kMvBlock / nthr;
     const size_t lds = sizeof(cplx<T>) * ((size_t)L + (size_t)gpb * lds_len(L));  // twiddles + sequences
@@ -230,21 +231,23 @@ static void launch_mv(const Problem& P, const Dev<T>& D, const T* y, T* z, hipSt
         hipLaunchKernelGGL((mv_cols<T, VPT, LC>), dim3(std::min((nrows + gpb - 1) / gpb, res[1])), dim3(kMvBlock), lds,
                            st, D.spec, N, L, nrows, D.tw, D.sym);
         hipLaunchKernelGGL((mv_rows_inv<T, VPT, LC>), dim3(std::min(nrb * nsl, res[2])), dim3(kMvBlock), lds, st,
-                           D.spec, N, L, s0, nsl, P.M, D.tw, z, y, D.gamma2, T(P.ct), T(P.cf));
+                           D.spec, N, L, s0, nsl, P.M, D.tw, z, ylast, D.gamma2, T(P.ct), T(P.cf));
         TSFDE_HIP(hipGetLastError());
     }
 }
 
 template <typename T>
-bool launch_toeplitz2d_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t st) {
+bool launch_toeplitz2d_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t st,
+                              const T* ylast) {
     if (P.d != 2 || 2 * P.N > P.L) return false;
     const int L = P.L;
+    if (!ylast) ylast = y + (long long)(P.M - 1) * P.Nd;
     if (L == 512) {
-        launch_mv<T, 8, 512>(P, D, y, z, st);
+        launch_mv<T, 8, 512>(P, D, y, z, ylast, st);
     } else if (L >= 16 && L <= 2048) {
-        launch_mv<T, 8, 0>(P, D, y, z, st);
+        launch_mv<T, 8, 0>(P, D, y, z, ylast, st);
     } else if (L == 4096) {
-        launch_mv<T, 16, 0>(P, D, y, z, st);
+        launch_mv<T, 16, 0>(P, D, y, z, ylast, st);
     } else {
         return false;
     }
@@ -252,7 +255,8 @@ bool launch_toeplitz2d_matvec(const Problem& P, const Dev<T>& D, const T* y, T* 
 }
 
 template bool launch_toeplitz2d_matvec<double>(const Problem&, const Dev<double>&, const double*, double*,
-                                               hipStream_t);
-template bool launch_toeplitz2d_matvec<float>(const Problem&, const Dev<float>&, const float*, float*, hipStream_t);
+                                               hipStream_t, const double*);
+template bool launch_toeplitz2d_matvec<float>(const Problem&, const Dev<float>&, const float*, float*, hipStream_t,
+                                              const float*);
 
 }  // namespace tsfde

@@ -22,7 +22,8 @@ EXPORTED = [
     "tsfde_destroy_problem", "tsfde_vector_length", "tsfde_problem_scalars", "tsfde_get_stencil",
     "tsfde_compute_stencil", "tsfde_apply_A", "tsfde_apply_A_f32", "tsfde_apply_P_inv",
     "tsfde_apply_P_inv_f32", "tsfde_gmres_solve", "tsfde_recover_f", "tsfde_recover_f_batch",
-    "tsfde_forward_solve", "tsfde_last_error",
+    "tsfde_forward_solve", "tsfde_apply_AT", "tsfde_apply_PT_inv", "tsfde_adjoint_solve",
+    "tsfde_recover_f_vjp", "tsfde_last_error",
 ]
 
 
@@ -78,6 +79,10 @@ def lib():
     L.tsfde_recover_f.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_forward_solve.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
     L.tsfde_recover_f_batch.argtypes = [pp, i, pp, C.POINTER(Opts), C.POINTER(Stats), i, vp]
+    L.tsfde_apply_AT.argtypes = [vp, vp, vp, vp]
+    L.tsfde_apply_PT_inv.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
+    L.tsfde_adjoint_solve.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
+    L.tsfde_recover_f_vjp.argtypes = [vp, vp, vp, vp, dp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_last_error.argtypes = []
     L.tsfde_last_error.restype = C.c_char_p
     for name in EXPORTED:
@@ -237,6 +242,47 @@ class Problem:
         _check(rc, allow=() if raise_noconv else (ENOCONV,))
         return f, st
 
+    def apply_AT(self, lam, z=None, stream=None):
+        import torch
+        if z is None:
+            z = torch.empty_like(lam)
+        _check(lib().tsfde_apply_AT(self._h, _dptr(lam, torch.float64, self.n_tot, "lam"),
+                                    _dptr(z, torch.float64, self.n_tot, "z"), _stream(stream)))
+        return z
+
+    def apply_PT_inv(self, g, lam=None, opts: Optional[Opts] = None, stream=None):
+        import torch
+        if lam is None:
+            lam = torch.empty_like(g)
+        _check(lib().tsfde_apply_PT_inv(self._h, _dptr(g, torch.float64, self.n_tot, "g"),
+                                        _dptr(lam, torch.float64, self.n_tot, "lam"),
+                                        C.byref(opts) if opts is not None else None, _stream(stream)))
+        return lam
+
+    def adjoint_solve(self, g, lam=None, opts: Optional[Opts] = None, stream=None, raise_noconv=False):
+        import torch
+        if lam is None:
+            lam = torch.zeros_like(g)
+        st = Stats()
+        rc = lib().tsfde_adjoint_solve(self._h, _dptr(g, torch.float64, self.n_tot, "g"),
+                                       _dptr(lam, torch.float64, self.n_tot, "lam"),
+                                       C.byref(opts) if opts is not None else None, C.byref(st), _stream(stream))
+        _check(rc, allow=() if raise_noconv else (ENOCONV,))
+        return lam, st
+
+    def recover_f_vjp(self, y, gf, opts: Optional[Opts] = None, stream=None, raise_noconv=False):
+        """(grad_mu, grad_alpha, stats) of L(f~) with dL/df~ = gf, given the solution y of A y = z."""
+        import torch
+        gmu = torch.empty(self.Nd, dtype=torch.float64, device="cuda")
+        ga = C.c_double(0.0)
+        st = Stats()
+        rc = lib().tsfde_recover_f_vjp(self._h, _dptr(y, torch.float64, self.n_tot, "y"),
+                                       _dptr(gf, torch.float64, self.Nd, "gf"), _dptr(gmu, torch.float64, self.Nd, "gmu"),
+                                       C.byref(ga), C.byref(opts) if opts is not None else None, C.byref(st),
+                                       _stream(stream))
+        _check(rc, allow=() if raise_noconv else (ENOCONV,))
+        return gmu, ga.value, st
+
     def forward_solve(self, f, opts: Optional[Opts] = None, stream=None):
         import torch
         v = torch.empty(self.M * self.Nd, dtype=torch.float64, device="cuda")
@@ -260,3 +306,30 @@ def recover_f_batch(problems, opts: Optional[Opts] = None, max_inflight: int = 2
                                      _stream(stream))
     _check(rc, allow=() if raise_noconv else (ENOCONV,))
     return [(fs[i], st[i]) for i in range(n)]
+
+
+def recover_f_autograd(problem: "Problem", mu, opts: Optional[Opts] = None, adjoint_opts: Optional[Opts] = None):
+    """f~ as a differentiable function of the final-time data mu_eps (a device FP64 tensor of N^d
+    values): the forward pass sets mu and runs tsfde_recover_f, the backward pass runs
+    tsfde_recover_f_vjp (the adjoint solve).  The problem's alpha gradient of the last backward pass
+    is left in problem.last_grad_alpha."""
+    import torch
+
+    class _RecoverF(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, m):
+            problem.set_mu(m.detach().cpu().numpy())
+            y = torch.empty(problem.n_tot, dtype=torch.float64, device="cuda")
+            f, _ = problem.recover_f(opts, work=y, raise_noconv=True)
+            ctx.save_for_backward(y)
+            return f
+
+        @staticmethod
+        def backward(ctx, gf):
+            (y,) = ctx.saved_tensors
+            gmu, ga, _ = problem.recover_f_vjp(y, gf.contiguous().to(torch.float64), adjoint_opts,
+                                               raise_noconv=True)
+            problem.last_grad_alpha = ga
+            return gmu
+
+    return _RecoverF.apply(mu)

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 import scipy.linalg as sl
 
-from oracle import matfree, system, workloads
+from oracle import adjoint, matfree, system, workloads
 from paper_2507_02809_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -424,3 +424,84 @@ def test_degenerate_shapes_match_dense(d, N, M):
         assert rel_err(w.cpu().numpy(), np.linalg.solve(P, y)) <= 1e-10
         f, st = g.recover_f(tsfde.default_opts(tol=1e-12, inner_tol=1e-14, inner_maxit=500), raise_noconv=True)
         assert rel_err(f.cpu().numpy(), np.linalg.solve(A, b)[p.S * p.Nd:]) <= 1e-9
+
+
+# ---------------------------------------------------------------------------
+# transposed problem (gradients)
+# ---------------------------------------------------------------------------
+def test_apply_AT_and_PT_inv_match_dense(dense_case):
+    inp, p, A, P = dense_case
+    rng = np.random.default_rng(31)
+    lam = rng.standard_normal(p.n_tot)
+    with gpu_problem(inp, p) as g:
+        z = g.apply_AT(torch.tensor(lam, device=DEV)).cpu().numpy()
+        assert rel_err(z, A.T @ lam) <= 1e-13
+        w = g.apply_PT_inv(torch.tensor(lam, device=DEV), opts=tsfde.default_opts(inner_tol=1e-14, inner_maxit=500))
+        assert rel_err(w.cpu().numpy(), np.linalg.solve(P.T, lam)) <= 1e-10
+
+
+@pytest.mark.parametrize("shape", [(1, 100, 70), (2, 13, 70), (2, 31, 20), (2, 64, 9)])
+def test_apply_AT_adjoint_identity_ragged(shape):
+    """<A x, w> (oracle, FFT matvec) = <x, A^T w> (library) at sizes past the dense oracle: several
+    history tiles with ragged tails, and the doubled embedding of N = 64."""
+    d, N, M = shape
+    inp = inputs.small(d, N, M, beta=0.7, omega=1.8)
+    p = workloads.problem(inp, mu=np.zeros(inp.Nd))
+    rng = np.random.default_rng(32)
+    with gpu_problem(inp, p) as g:
+        for _ in range(2):
+            x = rng.standard_normal(p.n_tot)
+            w = rng.standard_normal(p.n_tot)
+            lhs = float(matfree.matvec(p, x) @ w)
+            rhs = float(x @ g.apply_AT(torch.tensor(w, device=DEV)).cpu().numpy())
+            assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(matfree.matvec(p, x)) * np.linalg.norm(w)
+
+
+def test_apply_AT_full_size_c3_adjoint_identity():
+    """c3 (d = 2, N = 255, M = 256): <A x, w> = <x, A^T w> with both products on the GPU."""
+    inp = inputs.c3()
+    with tsfde.Problem.from_inputs(inp) as g:
+        gen = torch.Generator(device=DEV).manual_seed(33)
+        x = torch.randn(g.n_tot, dtype=torch.float64, device=DEV, generator=gen)
+        w = torch.randn(g.n_tot, dtype=torch.float64, device=DEV, generator=gen)
+        ax = g.apply_A(x)
+        lhs = float(torch.dot(ax, w))
+        rhs = float(torch.dot(x, g.apply_AT(w)))
+        assert abs(lhs - rhs) <= 1e-12 * float(ax.norm() * w.norm())
+
+
+def test_adjoint_solve_and_vjp_match_oracle(dense_case):
+    inp, p, A, _ = dense_case
+    rng = np.random.default_rng(34)
+    gf = rng.standard_normal(p.Nd)
+    gmu_ref, ga_ref, y_ref = adjoint.vjp(p, gf)
+    gvec = np.zeros(p.n_tot)
+    gvec[p.S * p.Nd:] = gf
+    # 3e-13: near the attainable FP64 residual of these systems
+    o = tsfde.default_opts(tol=3e-13, inner_tol=1e-12, inner_maxit=500)
+    with gpu_problem(inp, p) as g:
+        lam, st = g.adjoint_solve(torch.tensor(gvec, device=DEV), opts=o, raise_noconv=True)
+        assert st.converged == 1
+        assert rel_err(lam.cpu().numpy(), np.linalg.solve(A.T, gvec)) <= 1e-9
+        y = torch.empty(p.n_tot, dtype=torch.float64, device=DEV)
+        g.recover_f(o, work=y, raise_noconv=True)
+        assert rel_err(y.cpu().numpy(), y_ref) <= 1e-9
+        gmu, ga, _ = g.recover_f_vjp(y, torch.tensor(gf, device=DEV), opts=o, raise_noconv=True)
+    assert rel_err(gmu.cpu().numpy(), gmu_ref) <= 1e-9
+    assert ga == pytest.approx(ga_ref, rel=1e-8)
+
+
+def test_recover_f_autograd_gradient_in_mu():
+    """torch.autograd through recover_f: the gradient of ||f~ - f_true||^2 in mu against the oracle."""
+    inp = inputs.small(2, 7, 9, beta=0.3, omega=1.2)
+    p = workloads.with_data(inp)
+    f_ref = np.linalg.solve(system.dense_A(p), system.rhs_z(p))[p.S * p.Nd:]
+    gmu_ref, ga_ref, _ = adjoint.vjp(p, 2.0 * (f_ref - inp.f_true))
+    o = tsfde.default_opts(tol=3e-13, inner_tol=1e-12, inner_maxit=500)
+    with gpu_problem(inp, p) as g:
+        mu = torch.tensor(p.mu, device=DEV, requires_grad=True)
+        f = tsfde.recover_f_autograd(g, mu, opts=o, adjoint_opts=o)
+        loss = ((f - torch.tensor(inp.f_true, device=DEV)) ** 2).sum()
+        (gmu,) = torch.autograd.grad(loss, mu)
+        assert rel_err(gmu.cpu().numpy(), gmu_ref) <= 1e-8
+        assert g.last_grad_alpha == pytest.approx(ga_ref, rel=1e-7)
