@@ -64,6 +64,7 @@ def parse():
                     help="instances of the workload solved side by side by tsfde_recover_f_batch (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c4", action="store_true", help="skip the mixed batch of 64 independent problems")
+    ap.add_argument("--no-grad", action="store_true", help="skip the gradient (adjoint) measurement")
     ap.add_argument("--matvec-only", action="store_true",
                     help="only the apply_A timing (FP64, FP32), preceded by one FP64->FP32 conversion of a vector "
                          "(known bytes: a reference for hardware traffic counters); for profiling")
@@ -303,6 +304,41 @@ def main():
         for pk in cprobs:
             pk.close()
 
+    # gradients of L = ||f~ - f_true||^2 in mu and alpha (recover_f, then the adjoint solve of
+    # tsfde_recover_f_vjp) on the gradient workload's instance, to the same FGMRES tolerance both ways
+    gradients = None
+    if not a.no_grad:
+        i5 = inputs.c5(0)
+        p5 = tsfde.Problem.from_inputs(i5)
+        v5 = p5.forward_solve(torch.tensor(i5.f_true, device=dev), opts=tsfde.default_opts(inner_tol=1e-12))
+        p5.set_mu(i5.noisy(v5[(i5.M - 1) * i5.Nd:].cpu().numpy()))
+        ft = torch.tensor(i5.f_true, device=dev)
+        y5 = torch.empty(p5.n_tot, dtype=torch.float64, device=dev)
+
+        def grad_pass(o):
+            f5, s1 = p5.recover_f(o, work=y5)
+            gm, ga, s2 = p5.recover_f_vjp(y5, (2.0 * (f5 - ft)).contiguous(), o)
+            return gm, ga, s1, s2
+
+        o_ref = tsfde.default_opts(tol=1e-11, inner_tol=1e-12, maxit=500)
+        gm_ref, ga_ref, _, _ = grad_pass(o_ref)
+        o5 = tsfde.default_opts(tol=1e-8, inner_tol=a.inner_tol, maxit=500)
+        grad_pass(o5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            gm, ga, s1, s2 = grad_pass(o5)
+        torch.cuda.synchronize()
+        dtg = time.perf_counter() - t0
+        egm = float((gm - gm_ref).norm() / gm_ref.norm())
+        log(f"gradients: {a.steps} passes in {dtg:.2f} s, grad_mu rel. diff {egm:.1e} vs tol 1e-11")
+        gradients = {"workload": "d=2, N=127, M=128, beta=0.5, omega=1.5, alpha=1e-3 (seeded inputs c5)",
+                     "passes_per_s": a.steps / dtg, "s_per_pass": dtg / a.steps, "tol": 1e-8,
+                     "inner_tol": a.inner_tol, "forward_outer_iters": s1.iters, "adjoint_outer_iters": s2.iters,
+                     "adjoint_s": s2.t_total, "grad_mu_rel_diff_vs_tight": egm,
+                     "grad_alpha_rel_diff_vs_tight": abs(ga - ga_ref) / abs(ga_ref)}
+        p5.close()
+
     # structured matvec (FP64 and FP32), HIP events on the stream the library launches on
     y = torch.randn(prob.n_tot, dtype=torch.float64, device=dev)
     mvr = matvec_timing(a, prob, inp, y, y.float())
@@ -349,6 +385,8 @@ def main():
         # 64 independent problems of uneven shapes: even k d = 1, N ~ U[127, 2047]; odd k d = 2,
         # N ~ U[31, 127]; M ~ U[64, 512]; beta, omega, alpha drawn per problem
         "mixed_batch": mixed_batch,
+        # one gradient pass: recover_f then the adjoint solve for d||f~ - f_true||^2 / d(mu, alpha)
+        "gradients": gradients,
         "matvec": {"fp64_ms": mv64, "fp64_GB_s": gbs64, "fp32_ms": mv32, "fp32_GB_s": gbs32,
                    "algorithmic_bytes_fp64": bytes64},
         # traffic: HBM bytes of one FP64 apply_A from the FETCH_SIZE / WRITE_SIZE counter runs, scaled by

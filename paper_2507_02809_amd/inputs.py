@@ -189,6 +189,13 @@ def c4(instance: int) -> Inputs:
                      modes=min(8, N), name=f"c4_{instance}")
 
 
+def c5(instance: int = 0) -> Inputs:
+    """The gradient workload's instance: d = 2, N = 127 per direction, M = 128, beta = 0.5,
+    omega = 1.5, alpha = 1e-3, coefficient amplitudes ~ U(0.1, 0.5), 8 x 8 sine modes."""
+    return synthetic(2, 127, 128, 0.5, 1.5, 1e-3, config_id=5, instance=instance, amp1=None, amp2=None,
+                     modes=8, name=f"c5_{instance}")
+
+
 def small(d: int, N: int, M: int, beta: float = 0.5, omega: float = 1.5, alpha: float = 1e-3,
           instance: int = 0) -> Inputs:
     """A small instance of the same family for parity tests (seeded by its shape)."""
