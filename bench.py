@@ -304,7 +304,7 @@ def main():
         for pk in cprobs:
             pk.close()
 
-    # gradients of L = ||f~ - f_true||^2 in mu and alpha (recover_f, then the adjoint solve of
+    # gradients of L = ||f~ - f_true||^2 in mu, alpha and the gamma2 samples (recover_f, then the adjoint solve of
     # tsfde_recover_f_vjp) on the gradient workload's instance, to the same FGMRES tolerance both ways
     gradients = None
     if not a.no_grad:
@@ -317,7 +317,7 @@ def main():
 
         def grad_pass(o):
             f5, s1 = p5.recover_f(o, work=y5)
-            gm, ga, s2 = p5.recover_f_vjp(y5, (2.0 * (f5 - ft)).contiguous(), o)
+            gm, ga, _, s2 = p5.recover_f_vjp(y5, (2.0 * (f5 - ft)).contiguous(), o, gamma2=True)
             return gm, ga, s1, s2
 
         o_ref = tsfde.default_opts(tol=1e-11, inner_tol=1e-12, maxit=500)

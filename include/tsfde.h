@@ -269,12 +269,16 @@ tsfde_status tsfde_adjoint_solve(tsfde_problem* prob, const double* g, double* l
  *   lam = A^{-T} [0; gf]                           (tsfde_adjoint_solve)
  *   grad_mu    = lam^(M+1)                         (z^(M+1) = mu_eps)
  *   grad_alpha = -lam^T (dA/dalpha) y = -(c_f/alpha) lam^(M+1) . (gamma2^(M) .* B y^(M+1))
- * grad_mu: device N^d or NULL; grad_alpha: HOST double or NULL.  Allocates
- * three work vectors for the call.
+ *   grad_gamma2^(s) = -(eta/h^omega) lam^(s) .* B y^(s),  s = 1..M, and for s = M also
+ *                     -c_f lam^(M+1) .* B y^(M+1)   (gamma2^(s) enters the diagonal blocks and,
+ *                     at s = M, the last one)
+ * grad_mu: device N^d or NULL; grad_alpha: HOST double or NULL; grad_gamma2:
+ * device M N^d (slice-major like gamma2) or NULL.  Allocates three work vectors
+ * for the call.
  */
 tsfde_status tsfde_recover_f_vjp(tsfde_problem* prob, const double* y, const double* gf,
-                                 double* grad_mu, double* grad_alpha, const tsfde_opts* opts,
-                                 tsfde_stats* stats, void* stream);
+                                 double* grad_mu, double* grad_alpha, double* grad_gamma2,
+                                 const tsfde_opts* opts, tsfde_stats* stats, void* stream);
 
 /* Last error message of the calling thread ("" if none). */
 const char* tsfde_last_error(void);

@@ -46,3 +46,21 @@ def vjp(p: Problem, gf: np.ndarray):
     g[p.S * p.Nd:] = gf
     lam = np.linalg.solve(A.T, g)
     return lam[p.S * p.Nd:].copy(), float(-lam @ (dA_dalpha(p) @ y)), y
+
+
+def grad_gamma2(p: Problem, gf: np.ndarray) -> np.ndarray:
+    """dL/dgamma2 (S x N^d, the gamma2 samples at t_1..t_S): gamma2^(s) multiplies the B term of
+    diagonal block s (coefficient c_t) and, for s = S, also that of the last block (coefficient c_f),
+    so dL/dgamma2^(s) = -c_t lam^(s) .* B y^(s) - [s = S] c_f lam^(S+1) .* B y^(S+1)."""
+    A = dense_A(p)
+    B = dense_B(p)
+    S, Nd = p.S, p.Nd
+    y = np.linalg.solve(A, rhs_z(p)).reshape(S + 1, Nd)
+    g = np.zeros(p.n_tot)
+    g[S * Nd:] = gf
+    lam = np.linalg.solve(A.T, g).reshape(S + 1, Nd)
+    G = np.empty((S, Nd))
+    for s in range(S):
+        G[s] = -p.c_t * lam[s] * (B @ y[s])
+    G[S - 1] -= p.c_f * lam[S] * (B @ y[S])
+    return G

@@ -132,6 +132,8 @@ template <typename T>
 void launch_scale_g2(const Problem& P, const Dev<T>& D, const T* in, T* out, int only, bool inverse, hipStream_t s);
 template <typename T>
 void launch_adj_step_rhs(const Problem& P, const Dev<T>& D, const T* g, const T* lam, int m, T* rhs, hipStream_t s);
+// G (M N^d) = dL/dgamma2 from lam and v = (c_t B y^(s), s < M; c_f B y^(M))
+void launch_gamma2_grad(const Problem& P, const double* lam, const double* v, double* G, hipStream_t s);
 
 // BLAS-1 helpers
 template <typename T>

@@ -191,6 +191,24 @@ __global__ void adj_step_rhs(const T* __restrict__ g, const T* __restrict__ lam,
     rhs[j] = g[(long long)m * Nd + j] - h;
 }
 
+// dL/dgamma2 from lam and v = (c_t B y^(s) for s < M, c_f B y^(M)):
+//   G^(s) = -lam^(s) .* v^(s) (s < M), and G^(M-1) -= lam^(M) .* v^(M)
+__global__ void gamma2_grad_k(const double* __restrict__ lam, const double* __restrict__ v, double* __restrict__ G,
+                              long long Nd, int M) {
+    const long long n = (long long)M * Nd;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        double g = -lam[i] * v[i];
+        if (i >= (long long)(M - 1) * Nd) g -= lam[i + Nd] * v[i + Nd];
+        G[i] = g;
+    }
+}
+void launch_gamma2_grad(const Problem& P, const double* lam, const double* v, double* G, hipStream_t st) {
+    const long long n = (long long)P.M * P.Nd;
+    hipLaunchKernelGGL(gamma2_grad_k, dim3((unsigned)std::max(1LL, std::min<long long>((n + 255) / 256, 16384))),
+                       dim3(256), 0, st, lam, v, G, P.Nd, P.M);
+    TSFDE_HIP(hipGetLastError());
+}
+
 template <typename T>
 void launch_adj_step_rhs(const Problem& P, const Dev<T>& D, const T* g, const T* lam, int m, T* rhs, hipStream_t st) {
     hipLaunchKernelGGL(adj_step_rhs<T>, dim3((unsigned)((P.Nd + 255) / 256)), dim3(256), 0, st, g, lam, D.gamma1,

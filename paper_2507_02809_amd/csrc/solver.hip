@@ -911,7 +911,8 @@ tsfde_status tsfde_adjoint_solve(tsfde_problem* prob, const double* g, double* l
 }
 
 tsfde_status tsfde_recover_f_vjp(tsfde_problem* prob, const double* y, const double* gf, double* grad_mu,
-                                 double* grad_alpha, const tsfde_opts* opts, tsfde_stats* stats, void* stream) {
+                                 double* grad_alpha, double* grad_gamma2, const tsfde_opts* opts, tsfde_stats* stats,
+                                 void* stream) {
     if (!prob || !y || !gf) { set_error("recover_f_vjp: NULL argument"); return TSFDE_EINVAL; }
     Problem& P = *prob->p;
     const Opts o = get_opts(opts);
@@ -932,6 +933,16 @@ tsfde_status tsfde_recover_f_vjp(tsfde_problem* prob, const double* y, const dou
         try {
             rc = adjoint_impl(P, g, lam, o, S, st);
             if (grad_mu) launch_copy<double>(lam + last, grad_mu, Nd, st);
+            if (grad_gamma2) {
+                // v = (c_t B y^(s), c_f B y^(M)): the matvec's B kernels with unit gamma2 into a zero
+                // vector, the last row adding the (zero) first slice of g instead of y^(M-1)
+                Dev<double> Dn = P.f64;
+                Dn.gamma2 = nullptr;
+                launch_fill(v, n, 0.0, st);
+                if (!launch_toeplitz2d_matvec<double>(P, Dn, y, v, st, g))
+                    launch_toeplitz_matvec<double>(P, Dn, y, v, st, g);
+                launch_gamma2_grad(P, lam, v, grad_gamma2, st);
+            }
             if (grad_alpha) {
                 // dA/dalpha y = (1/alpha) (A [0; y^(M)])^(M): only c_f = alpha/h^omega depends on alpha
                 launch_fill(v, n, 0.0, st);

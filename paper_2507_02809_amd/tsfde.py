@@ -82,7 +82,7 @@ def lib():
     L.tsfde_apply_AT.argtypes = [vp, vp, vp, vp]
     L.tsfde_apply_PT_inv.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
     L.tsfde_adjoint_solve.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
-    L.tsfde_recover_f_vjp.argtypes = [vp, vp, vp, vp, dp, C.POINTER(Opts), C.POINTER(Stats), vp]
+    L.tsfde_recover_f_vjp.argtypes = [vp, vp, vp, vp, dp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_last_error.argtypes = []
     L.tsfde_last_error.restype = C.c_char_p
     for name in EXPORTED:
@@ -270,17 +270,22 @@ class Problem:
         _check(rc, allow=() if raise_noconv else (ENOCONV,))
         return lam, st
 
-    def recover_f_vjp(self, y, gf, opts: Optional[Opts] = None, stream=None, raise_noconv=False):
-        """(grad_mu, grad_alpha, stats) of L(f~) with dL/df~ = gf, given the solution y of A y = z."""
+    def recover_f_vjp(self, y, gf, opts: Optional[Opts] = None, stream=None, raise_noconv=False,
+                      gamma2=False):
+        """(grad_mu, grad_alpha, stats) of L(f~) with dL/df~ = gf, given the solution y of A y = z;
+        with gamma2=True, (grad_mu, grad_alpha, grad_gamma2 [M, N^d], stats)."""
         import torch
         gmu = torch.empty(self.Nd, dtype=torch.float64, device="cuda")
+        gg2 = torch.empty(self.M * self.Nd, dtype=torch.float64, device="cuda") if gamma2 else None
         ga = C.c_double(0.0)
         st = Stats()
         rc = lib().tsfde_recover_f_vjp(self._h, _dptr(y, torch.float64, self.n_tot, "y"),
                                        _dptr(gf, torch.float64, self.Nd, "gf"), _dptr(gmu, torch.float64, self.Nd, "gmu"),
-                                       C.byref(ga), C.byref(opts) if opts is not None else None, C.byref(st),
-                                       _stream(stream))
+                                       C.byref(ga), _dptr(gg2, torch.float64, self.M * self.Nd, "gg2") if gamma2 else None,
+                                       C.byref(opts) if opts is not None else None, C.byref(st), _stream(stream))
         _check(rc, allow=() if raise_noconv else (ENOCONV,))
+        if gamma2:
+            return gmu, ga.value, gg2.view(self.M, self.Nd), st
         return gmu, ga.value, st
 
     def forward_solve(self, f, opts: Optional[Opts] = None, stream=None):

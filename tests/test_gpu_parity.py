@@ -487,8 +487,11 @@ def test_adjoint_solve_and_vjp_match_oracle(dense_case):
         g.recover_f(o, work=y, raise_noconv=True)
         assert rel_err(y.cpu().numpy(), y_ref) <= 1e-9
         gmu, ga, _ = g.recover_f_vjp(y, torch.tensor(gf, device=DEV), opts=o, raise_noconv=True)
+        gmu2, ga2, gg2, _ = g.recover_f_vjp(y, torch.tensor(gf, device=DEV), opts=o, raise_noconv=True, gamma2=True)
     assert rel_err(gmu.cpu().numpy(), gmu_ref) <= 1e-9
     assert ga == pytest.approx(ga_ref, rel=1e-8)
+    assert rel_err(gmu2.cpu().numpy(), gmu_ref) <= 1e-9 and ga2 == pytest.approx(ga_ref, rel=1e-8)
+    assert rel_err(gg2.cpu().numpy(), adjoint.grad_gamma2(p, gf)) <= 1e-8
 
 
 def test_recover_f_autograd_gradient_in_mu():

@@ -74,3 +74,25 @@ def test_PT_solve_inverts_the_transposed_block_triangle(prob):
     # P^T is block upper triangular: nothing below the diagonal blocks
     for s in range(S + 1):
         assert not PT[(s + 1) * Nd:, s * Nd:(s + 1) * Nd].any()
+
+
+def test_grad_gamma2_matches_central_differences(prob):
+    """Sampled entries of dL/dgamma2 against central differences of gf . f~ in that one sample
+    (including the last time level, where gamma2 also scales the final-condition block)."""
+    rng = np.random.default_rng(9)
+    gf = rng.standard_normal(prob.Nd)
+    G = adjoint.grad_gamma2(prob, gf)
+    S, Nd = prob.S, prob.Nd
+    # samples where the gradient is well above the finite differences' rounding noise
+    samples = [(s, int(np.argmax(np.abs(G[s])))) for s in (0, S // 2, S - 1)]
+    big = np.flatnonzero(np.abs(G[S - 1]) > 0.1 * np.abs(G[S - 1]).max())
+    samples.append((S - 1, int(big[len(big) // 2])))
+    for s, j in samples:
+        h = 1e-6 * prob.gamma2[s, j]
+        vals = []
+        for sign in (1, -1):
+            g2 = prob.gamma2.copy()
+            g2[s, j] += sign * h
+            vals.append(gf @ f_tilde(dataclasses.replace(prob, gamma2=g2)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert G[s, j] == pytest.approx(fd, rel=1e-5)
