@@ -13,48 +13,64 @@ namespace tsfde {
 // z^(s) = gamma1^(s) .* sum_{m=1}^{s} e_{s-m} y^(m) - eta q^(s) y^(M+1),  s = 1..M
 // (0-based here: s = 0..M-1, y[M] is f~).
 //
-// One workgroup = 64 spatial points (one per lane) x 64 output steps (16 per wave).
-// The input steps are staged through LDS 16 at a time; e_{s-m} is wave-uniform, so
-// the weights come from the scalar cache.  epad holds kEpad zeros before e_0 so that
-// e_{s-m} with m > s reads a zero.
+// One workgroup = 64 spatial points (one per lane) x 16 NW output steps (16 per wave, NW waves);
+// every input step is read once per 16 NW outputs.  The input steps are staged through
+// LDS 16 at a time, double-buffered: the loads of the next 16 steps are in flight while the
+// current ones are used, and one barrier per stage suffices.  e_{s-m} is wave-uniform, so the
+// weights come from the scalar cache; epad holds kEpad zeros before e_0 so that e_{s-m} with
+// m > s reads a zero.  A wave skips the stages that lie entirely after its outputs.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void history_matvec(const T* __restrict__ y, T* __restrict__ z,
-                                                      const T* __restrict__ g1, const T* __restrict__ epad,
-                                                      const T* __restrict__ q, T eta, long long Nd, int M) {
-    __shared__ T tile[16][64];
+constexpr int kHistStage = 16;  // input steps per stage (and output steps per wave)
+
+template <typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void history_matvec(const T* __restrict__ y, T* __restrict__ z,
+                                                          const T* __restrict__ g1, const T* __restrict__ epad,
+                                                          const T* __restrict__ q, T eta, long long Nd, int M) {
+    constexpr int NT = 64 * NW;                        // threads
+    constexpr int PER = kHistStage * 64 / NT;          // staged values per thread and stage
+    static_assert(PER >= 1 && PER * NT == kHistStage * 64, "one stage is 16 steps x 64 points");
+    __shared__ T tile[2][kHistStage][64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long long j = (long long)blockIdx.x * 64 + lane;
-    const int s0 = blockIdx.y * 64;
-    const int sw = s0 + wave * 16;
-    const int s_end = min(s0 + 64, M);
-    T acc[16];
+    const int s0 = blockIdx.y * (kHistStage * NW);
+    const int sw = s0 + wave * kHistStage;
+    const int s_end = min(s0 + kHistStage * NW, M);  // inputs m < s_end contribute
+    const int nstage = (s_end + kHistStage - 1) / kHistStage;
+    T acc[kHistStage];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = T(0);
-    for (int m0 = 0; m0 < s_end; m0 += 16) {
-        __syncthreads();
-        for (int t = threadIdx.x; t < 16 * 64; t += 256) {
-            const int mm = t >> 6, jj = t & 63;
-            const long long jg = (long long)blockIdx.x * 64 + jj;
-            const int m = m0 + mm;
-            tile[mm][jj] = (m < s_end && jg < Nd) ? y[(long long)m * Nd + jg] : T(0);
+    for (int i = 0; i < kHistStage; ++i) acc[i] = T(0);
+    // thread t stages rows mm = t / 64 + (NT / 64) r of a stage, point column lane
+    T pre[PER];
+    auto stage_load = [&](int m0) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int m = m0 + (int)(threadIdx.x >> 6) + NW * r;
+            pre[r] = (m < s_end && j < Nd) ? y[(long long)m * Nd + j] : T(0);
         }
-        __syncthreads();
-        if (m0 <= sw + 15) {
+    };
+    stage_load(0);
+    for (int t = 0; t < nstage; ++t) {
+        const int buf = t & 1;
+#pragma unroll
+        for (int r = 0; r < PER; ++r) tile[buf][(threadIdx.x >> 6) + NW * r][lane] = pre[r];
+        __syncthreads();  // stage t visible; every wave is past stage t - 1, so buffer buf ^ 1 is free
+        const int m0 = t * kHistStage;
+        if (t + 1 < nstage) stage_load(m0 + kHistStage);
+        if (sw < M && m0 <= sw + kHistStage - 1) {  // (sw < M keeps the weight reads inside epad)
             const T* ew = epad + kEpad + sw - m0;
 #pragma unroll
-            for (int mm = 0; mm < 16; ++mm) {
-                const T yv = tile[mm][lane];
+            for (int mm = 0; mm < kHistStage; ++mm) {
+                const T yv = tile[buf][mm][lane];
 #pragma unroll
-                for (int i = 0; i < 16; ++i) acc[i] += ew[i - mm] * yv;
+                for (int i = 0; i < kHistStage; ++i) acc[i] += ew[i - mm] * yv;
             }
         }
     }
     if (j < Nd) {
         const T f = y[(long long)M * Nd + j];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < kHistStage; ++i) {
             const int s = sw + i;
             if (s < M) z[(long long)s * Nd + j] = g1[(long long)s * Nd + j] * acc[i] - eta * q[s] * f;
         }
@@ -63,8 +79,12 @@ __global__ __launch_bounds__(256) void history_matvec(const T* __restrict__ y, T
 
 template <typename T>
 void launch_history_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s) {
-    dim3 grid((unsigned)((P.Nd + 63) / 64), (unsigned)((P.M + 63) / 64));
-    hipLaunchKernelGGL(history_matvec<T>, grid, dim3(256), 0, s, y, z, D.gamma1, D.epad, D.q, T(P.eta), P.Nd, P.M);
+    // 4 waves (64 output steps per workgroup): measured at c3 as fast as 8 waves and faster than 16
+    // (FP64 134 us against 135 and 181 us), with the most workgroups for short histories
+    constexpr int NW = 4;
+    dim3 grid((unsigned)((P.Nd + 63) / 64), (unsigned)((P.M + NW * kHistStage - 1) / (NW * kHistStage)));
+    hipLaunchKernelGGL((history_matvec<T, NW>), grid, dim3(64 * NW), 0, s, y, z, D.gamma1, D.epad, D.q, T(P.eta),
+                       P.Nd, P.M);
     TSFDE_HIP(hipGetLastError());
 }
 
