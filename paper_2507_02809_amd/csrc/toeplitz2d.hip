@@ -45,22 +45,31 @@ __global__ __launch_bounds__(kMvBlock) void mv_rows_fwd(const T* __restrict__ y,
     __syncthreads();
     cplx<T>* c = cbase + (size_t)grp * LP;
     constexpr int VH = VPT / 2;  // j < N <= L/2 = VH * nthr
+    // the rows of the next block are loaded while the current block is transformed (barriers wait
+    // for LDS operations only, so the loads stay in flight)
+    T p0[VH], p1[VH];
+    auto load_rows = [&](int b) {
+        const int sl = b / nrb;
+        const int i0 = (b - sl * nrb) * 2 * gpb + 2 * grp;
+        const T* ys = y + (long long)sl * Nd;
+#pragma unroll
+        for (int u = 0; u < VH; ++u) {
+            const int j = tid + u * nthr;
+            p0[u] = p1[u] = T(0);
+            if (j < N && i0 < N) {
+                p0[u] = ys[(long long)i0 * N + j];
+                if (i0 + 1 < N) p1[u] = ys[(long long)(i0 + 1) * N + j];
+            }
+        }
+    };
+    if (blockIdx.x < nrb * nsl) load_rows(blockIdx.x);
     for (int blk = blockIdx.x; blk < nrb * nsl; blk += gridDim.x) {  // uniform per workgroup
         const int slice = blk / nrb;
         const int ibase = (blk - slice * nrb) * 2 * gpb;
-        const int i0 = ibase + 2 * grp;
-        const T* ys = y + (long long)slice * Nd;
         cplx<T> v[VPT];
 #pragma unroll
-        for (int u = 0; u < VPT; ++u) {
-            const int j = tid + u * nthr;
-            T a0 = T(0), a1 = T(0);
-            if (u < VH && j < N && i0 < N) {
-                a0 = ys[(long long)i0 * N + j];
-                if (i0 + 1 < N) a1 = ys[(long long)(i0 + 1) * N + j];
-            }
-            v[u] = {a0, a1};
-        }
+        for (int u = 0; u < VPT; ++u) v[u] = (u < VH) ? cplx<T>{p0[u], p1[u]} : cplx<T>{T(0), T(0)};
+        if (blk + (int)gridDim.x < nrb * nsl) load_rows(blk + gridDim.x);
         fft_x<T, VPT, false, true, false>(v, c, L, tw, tid, nthr);
         __syncthreads();  // the write-out reads every group's sequence
         cplx<T>* out = spec + (long long)slice * H * ns;
@@ -97,21 +106,39 @@ __global__ __launch_bounds__(kMvBlock) void mv_cols(cplx<T>* __restrict__ spec, 
     constexpr int VH = VPT / 2;
     const int stride = gridDim.x * gpb;
     const int rounds = (nrows + stride - 1) / stride;  // the same for every group (the FFTs hold barriers)
+    // the next round's row and symbol are loaded while the current row is transformed (barriers
+    // wait for LDS operations only, so the loads stay in flight)
+    cplx<T> pv[VH];
+    T ps[VPT];
+    auto load_row = [&](int r) {
+        const int rowid = r * stride + blockIdx.x * gpb + grp;  // (slice, k2) flattened, slice-major
+        const bool ok = rowid < nrows;
+        const int sl = ok ? rowid / H : 0;
+        const int kk = ok ? rowid - sl * H : 0;
+        const cplx<T>* rw = spec + ((long long)sl * H + kk) * ns;
+        const T* sy = sym + (long long)kk * L;
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int i = tid + u * nthr;
+            if (u < VH) pv[u] = (ok && i < N) ? rw[i] : cplx<T>{T(0), T(0)};
+            ps[u] = sy[i];
+        }
+    };
+    if (rounds > 0) load_row(0);
     for (int rd = 0; rd < rounds; ++rd) {
         const int rowid = rd * stride + blockIdx.x * gpb + grp;  // (slice, k2) flattened, slice-major
         const bool valid = rowid < nrows;
         const int slice = valid ? rowid / H : 0;
         const int k2 = valid ? rowid - slice * H : 0;
         cplx<T>* row = spec + ((long long)slice * H + k2) * ns;
-        const T* sy = sym + (long long)k2 * L;
         cplx<T> v[VPT];
         T sv[VPT];
 #pragma unroll
         for (int u = 0; u < VPT; ++u) {
-            const int i = tid + u * nthr;
-            v[u] = (u < VH && valid && i < N) ? row[i] : cplx<T>{T(0), T(0)};
-            sv[u] = sy[i];
+            v[u] = (u < VH) ? pv[u] : cplx<T>{T(0), T(0)};
+            sv[u] = ps[u];
         }
+        if (rd + 1 < rounds) load_row(rd + 1);
         fft_x<T, VPT, false, true, true>(v, c, L, tw, tid, nthr);
 #pragma unroll
         for (int u = 0; u < VPT; ++u) v[u] = {v[u].x * sv[u], v[u].y * sv[u]};
