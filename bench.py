@@ -216,16 +216,18 @@ def main():
         run(op, 1)
         dtp, errp, stp = run(op, a.steps)
         log(f"fp64 Krylov + fp32 P^-1: tol {tolp:g}, {a.steps} solves in {dtp:.2f} s, max f error {max(errp):.2e}")
-        om = tsfde.default_opts(tol=0.1 * a.target, precision=tsfde.MIXED, inner_tol=1e-6, maxit=300)
+        tolm = a.tol if a.tol > 0 else calibrate(tsfde.MIXED)
+        om = tsfde.default_opts(tol=tolm, precision=tsfde.MIXED, inner_tol=a.inner_tol, maxit=300)
         run(om, 1)
         dtm, errm, stm = run(om, a.steps)
-        log(f"fp32 operators + fp64 refinement: {a.steps} solves in {dtm:.2f} s, max f error {max(errm):.2e}")
+        log(f"fp32 operators + fp64 refinement: tol {tolm:g}, {a.steps} solves in {dtm:.2f} s, "
+            f"max f error {max(errm):.2e}")
         mixed = {
             "fp32_preconditioner": {"solves_per_s": a.steps / dtp, "ms_per_solve": 1e3 * dtp / a.steps,
                                     "f_rel_err": max(errp), "tol": tolp, "inner_tol": a.inner_tol,
                                     "outer_iters": stp[-1]["iters"], "inner_cg_iters": stp[-1]["inner_iters"]},
             "fp32_operators_refinement": {"solves_per_s": a.steps / dtm, "ms_per_solve": 1e3 * dtm / a.steps,
-                                          "f_rel_err": max(errm), "tol": 0.1 * a.target,
+                                          "f_rel_err": max(errm), "tol": tolm, "inner_tol": a.inner_tol,
                                           "outer_iters": stm[-1]["iters"], "refinements": stm[-1]["refinements"],
                                           "inner_cg_iters": stm[-1]["inner_iters"]},
         }
