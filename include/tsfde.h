@@ -140,6 +140,11 @@ tsfde_status tsfde_create_problem_ex(int d, int N, int M, double T, double beta,
 /* Replace mu_eps (host [N^d]) without rebuilding the problem. */
 tsfde_status tsfde_set_mu(tsfde_problem* prob, const double* mu);
 
+/* Replace the regularisation parameter alpha (> 0; §3): only c_f = alpha/h^omega
+ * of the last block row changes, so nothing is rebuilt (a sweep over alpha
+ * for a parameter choice rule reuses one problem). */
+tsfde_status tsfde_set_alpha(tsfde_problem* prob, double alpha);
+
 void tsfde_destroy_problem(tsfde_problem* prob);
 
 /* (M+1) * N^d, the length of y and z. */

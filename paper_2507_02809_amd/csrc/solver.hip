@@ -656,6 +656,15 @@ tsfde_status tsfde_set_mu(tsfde_problem* prob, const double* mu) {
     return set_mu(prob->p, mu);
 }
 
+tsfde_status tsfde_set_alpha(tsfde_problem* prob, double alpha) {
+    if (!prob) { set_error("set_alpha: NULL problem"); return TSFDE_EINVAL; }
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) { set_error("set_alpha: need alpha > 0"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    P.alpha = alpha;  // only the final-condition block's coefficient depends on alpha
+    P.cf = alpha / std::pow(P.h, P.omega);
+    return TSFDE_OK;
+}
+
 void tsfde_destroy_problem(tsfde_problem* prob) {
     if (!prob) return;
     free_problem(prob->p);

@@ -18,7 +18,7 @@ BLOCK_CG, BLOCK_TAU = 0, 1
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOCONV", 5: "ENONFINITE", 6: "ENOTIMPL"}
 
 EXPORTED = [
-    "tsfde_default_opts", "tsfde_create_problem", "tsfde_create_problem_ex", "tsfde_set_mu",
+    "tsfde_default_opts", "tsfde_create_problem", "tsfde_create_problem_ex", "tsfde_set_mu", "tsfde_set_alpha",
     "tsfde_destroy_problem", "tsfde_vector_length", "tsfde_problem_scalars", "tsfde_get_stencil",
     "tsfde_compute_stencil", "tsfde_apply_A", "tsfde_apply_A_f32", "tsfde_apply_P_inv",
     "tsfde_apply_P_inv_f32", "tsfde_gmres_solve", "tsfde_recover_f", "tsfde_recover_f_batch",
@@ -64,6 +64,7 @@ def lib():
     L.tsfde_create_problem.argtypes = [i, i, i, d, d, d, d, dp, dp, dp, dp, dp, pp]
     L.tsfde_create_problem_ex.argtypes = [i, i, i, d, d, d, d, dp, dp, dp, dp, dp, d, dp, pp]
     L.tsfde_set_mu.argtypes = [vp, dp]
+    L.tsfde_set_alpha.argtypes = [vp, d]
     L.tsfde_destroy_problem.argtypes = [vp]
     L.tsfde_destroy_problem.restype = None
     L.tsfde_vector_length.argtypes = [vp]
@@ -165,6 +166,7 @@ class Problem:
         _check(L.tsfde_create_problem_ex(d, N, M, T, beta, omega, alpha, *args, length, st_ptr, C.byref(h)))
         self._h = h
         self.n_tot = int(L.tsfde_vector_length(h))
+        self.mu_host = np.zeros(Nd) if mu is None else np.asarray(mu, dtype=np.float64).reshape(-1).copy()
 
     @classmethod
     def from_inputs(cls, inp, mu=None, stencil=None):
@@ -191,6 +193,10 @@ class Problem:
     def set_mu(self, mu):
         arr, ptr = _host(mu, self.Nd, "mu")
         _check(lib().tsfde_set_mu(self._h, ptr))
+        self.mu_host = arr
+
+    def set_alpha(self, alpha: float):
+        _check(lib().tsfde_set_alpha(self._h, float(alpha)))
 
     def scalars(self) -> dict:
         out = (C.c_double * 6)()
@@ -338,3 +344,29 @@ def recover_f_autograd(problem: "Problem", mu, opts: Optional[Opts] = None, adjo
             return gmu
 
     return _RecoverF.apply(mu)
+
+
+def discrepancy_curve(problem: "Problem", alphas, opts: Optional[Opts] = None, fwd_opts: Optional[Opts] = None):
+    """Morozov's discrepancy of the quasi-boundary-value reconstruction for each alpha: with f_alpha
+    recovered from the problem's data mu_eps (tsfde_recover_f after tsfde_set_alpha), the direct
+    problem is solved for f_alpha (tsfde_forward_solve) and ||v^(M)(f_alpha) - mu_eps||_2 returned.
+    The problem keeps the last alpha of the sweep.  Returns (residuals, list of f_alpha)."""
+    import torch
+    mu = torch.tensor(problem.mu_host, device="cuda") if hasattr(problem, "mu_host") else None
+    if mu is None:
+        raise ValueError("the problem's data were not set through set_mu")
+    res, fs = [], []
+    for a in alphas:
+        problem.set_alpha(a)
+        f, _ = problem.recover_f(opts, raise_noconv=True)
+        v = problem.forward_solve(f, opts=fwd_opts)
+        res.append(float((v[(problem.M - 1) * problem.Nd:] - mu).norm()))
+        fs.append(f)
+    return res, fs
+
+
+def select_alpha(alphas, residuals, delta: float, tau: float = 1.1):
+    """The discrepancy principle: the largest alpha whose residual is at most tau * delta (delta the
+    noise norm ||mu_eps - mu||); None if no alpha of the grid qualifies."""
+    ok = [a for a, r in zip(alphas, residuals) if r <= tau * delta]
+    return max(ok) if ok else None

@@ -508,3 +508,22 @@ def test_recover_f_autograd_gradient_in_mu():
         (gmu,) = torch.autograd.grad(loss, mu)
         assert rel_err(gmu.cpu().numpy(), gmu_ref) <= 1e-8
         assert g.last_grad_alpha == pytest.approx(ga_ref, rel=1e-7)
+
+
+def test_discrepancy_sweep_matches_oracle():
+    """set_alpha + recover_f + forward_solve over an alpha grid: the discrepancies against the
+    oracle's dense solves, and the same alpha chosen by the discrepancy principle."""
+    from oracle import discrepancy
+    inp = inputs.small(2, 7, 9, beta=0.3, omega=1.2)
+    p = workloads.with_data(inp)
+    alphas = list(np.logspace(-7, -2, 6))
+    ref = discrepancy.residuals(p, alphas)
+    mu0 = discrepancy.forward_data(p, inp.f_true)
+    delta = float(np.linalg.norm(p.mu - mu0))
+    o = tsfde.default_opts(tol=3e-13, inner_tol=1e-13, inner_maxit=500)
+    fo = tsfde.default_opts(inner_tol=1e-13, inner_maxit=500)
+    with gpu_problem(inp, p) as g:
+        res, _ = tsfde.discrepancy_curve(g, alphas, opts=o, fwd_opts=fo)
+    for r, rr in zip(res, ref):
+        assert r == pytest.approx(rr, rel=1e-7)
+    assert tsfde.select_alpha(alphas, res, delta) == discrepancy.select(alphas, ref, delta)
