@@ -285,6 +285,20 @@ tsfde_status tsfde_recover_f_vjp(tsfde_problem* prob, const double* y, const dou
                                  double* grad_mu, double* grad_alpha, double* grad_gamma2,
                                  const tsfde_opts* opts, tsfde_stats* stats, void* stream);
 
+/*
+ * Spectral estimate of the preconditioned operator: k steps of Arnoldi
+ * (classical Gram-Schmidt applied twice, as in the solver) on A P^{-1} from b
+ * (device, (M+1) N^d; NULL for z of eq. lin-syst), with P^{-1} applied as in
+ * tsfde_gmres_solve (opts.use_precond = 0: A itself).  H (host) receives the
+ * (k+1) x k upper Hessenberg matrix, row-major; *steps the steps taken (fewer
+ * than k after an exact breakdown).  The eigenvalues of its leading steps x
+ * steps block are Ritz values of A P^{-1}, which has the spectrum of P^{-1} A
+ * (§5.1: P^{-1} A - I has rank at most N^d, so its eigenvalues cluster at 1).
+ * Uses the problem's Krylov basis storage; 1 <= k <= 1000.
+ */
+tsfde_status tsfde_arnoldi(tsfde_problem* prob, const double* b, int k, double* H, int* steps,
+                           const tsfde_opts* opts, void* stream);
+
 /* Last error message of the calling thread ("" if none). */
 const char* tsfde_last_error(void);
 

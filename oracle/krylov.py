@@ -130,3 +130,25 @@ def fgmres(A: Callable, M: Callable, b: np.ndarray, tol: float, restart: int, ma
                 break
         yk = np.linalg.solve(np.triu(H[:k, :k]), g[:k])
         x = x + Z[:k].T @ yk
+
+
+def arnoldi_cgs2(op: Callable, b: np.ndarray, k: int):
+    """k steps of Arnoldi on op from b, classical Gram-Schmidt applied twice (the solver's
+    orthogonalisation).  Returns (H, V): H (k+1) x k upper Hessenberg, V n x (k+1) orthonormal,
+    op(V[:, :k]) = V H."""
+    n = b.shape[0]
+    V = np.zeros((n, k + 1))
+    H = np.zeros((k + 1, k))
+    V[:, 0] = b / np.linalg.norm(b)
+    for j in range(k):
+        w = op(V[:, j])
+        h1 = V[:, :j + 1].T @ w
+        w = w - V[:, :j + 1] @ h1
+        h2 = V[:, :j + 1].T @ w
+        w = w - V[:, :j + 1] @ h2
+        H[:j + 1, j] = h1 + h2
+        H[j + 1, j] = np.linalg.norm(w)
+        if H[j + 1, j] == 0.0:
+            return H[:j + 2, :j + 1], V[:, :j + 2]
+        V[:, j + 1] = w / H[j + 1, j]
+    return H, V

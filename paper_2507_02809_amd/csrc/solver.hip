@@ -445,6 +445,41 @@ static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, d
     return its;
 }
 
+// k steps of Arnoldi (classical Gram-Schmidt twice) on the right-preconditioned operator A M from b;
+// H receives the (k+1) x k Hessenberg matrix row-major (host).  Returns the steps taken (fewer than k
+// on an exact breakdown).  The eigenvalues of its leading square part are Ritz values of A M, i.e.
+// of M A (the same spectrum).
+static int arnoldi_impl(Problem& P, const SolveOps& ops, const double* b, int k, double* H, hipStream_t st) {
+    const long long n = P.ntot;
+    ensure_basis(P, k);
+    const int nblk = kArnBlocks;
+    if (!P.arn_part) TSFDE_HIP(hipMalloc(&P.arn_part, sizeof(double) * kArnBlocks * kArnMaxK));
+    if (!P.arn_h) TSFDE_HIP(hipMalloc(&P.arn_h, sizeof(double) * (2 * (kMaxRestart + 2) + 1)));
+    const int hs = k + 2;
+    double* hbuf = P.arn_h;
+    std::vector<double> hhost(2 * hs + 1);
+    std::fill(H, H + (size_t)(k + 1) * k, 0.0);
+    const double bnorm = std::sqrt(dev_dot(P, b, b, n, st));
+    if (!(bnorm > 0.0)) return 0;
+    launch_axpby(1.0 / bnorm, b, 0.0, b, P.V, n, st);
+    for (int j = 0; j < k; ++j) {
+        double* vj = P.V + (size_t)j * n;
+        double* zj = P.Z + (size_t)j * n;
+        double* w = P.V + (size_t)(j + 1) * n;
+        ops.M(vj, zj);
+        ops.A(zj, w);
+        cgs2(P.V, n, j + 1, w, P.arn_part, nblk, hbuf, hbuf + hs, hbuf + 2 * hs, st);
+        TSFDE_HIP(hipMemcpyAsync(hhost.data(), hbuf, sizeof(double) * (2 * hs + 1), hipMemcpyDeviceToHost, st));
+        TSFDE_HIP(hipStreamSynchronize(st));
+        const double hn = std::sqrt(hhost[2 * hs]);
+        for (int i = 0; i <= j; ++i) H[(size_t)i * k + j] = hhost[i] + hhost[hs + i];
+        H[(size_t)(j + 1) * k + j] = hn;
+        if (!(hn > 0.0)) return j + 1;
+        launch_axpby(1.0 / hn, w, 0.0, w, w, n, st);
+    }
+    return k;
+}
+
 static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o, tsfde_stats& S, hipStream_t st) {
     const long long n = P.ntot;
     const int maxit = o.maxit > 0 ? o.maxit : (int)std::min<long long>(n, 1000);
@@ -969,6 +1004,38 @@ tsfde_status tsfde_recover_f_vjp(tsfde_problem* prob, const double* y, const dou
     if (stats) *stats = S;
     if (rc == TSFDE_ENOCONV) set_error("recover_f_vjp: adjoint tolerance not reached (rel. residual %.3e)", S.rel_res);
     return rc;
+}
+
+tsfde_status tsfde_arnoldi(tsfde_problem* prob, const double* b, int k, double* H, int* steps,
+                           const tsfde_opts* opts, void* stream) {
+    if (!prob || !H) { set_error("arnoldi: NULL argument"); return TSFDE_EINVAL; }
+    if (k < 1 || k > kMaxRestart) { set_error("arnoldi: need 1 <= k <= %d", kMaxRestart); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    const Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
+    hipStream_t st = (hipStream_t)stream;
+    const long long n = P.ntot;
+    SharedLaunch lk(g_launch_mx);
+    int done = 0;
+    TSFDE_GUARD("arnoldi", {
+        SolveOps ops;
+        ops.A = [&](const double* v, double* out) { apply_A_impl<double>(P, v, out, st); };
+        ops.M = [&](const double* v, double* out) -> long long {
+            if (!o.use_precond) {
+                launch_copy<double>(v, out, n, st);
+                return 0;
+            }
+            return pinv_impl<double>(P, v, out, o, st, true);
+        };
+        if (!b) {
+            launch_build_z(P, P.z_rhs, st);
+            b = P.z_rhs;
+        }
+        done = arnoldi_impl(P, ops, b, k, H, st);
+    })
+    if (steps) *steps = done;
+    return TSFDE_OK;
 }
 
 const char* tsfde_last_error(void) { return last_error(); }

@@ -23,7 +23,7 @@ EXPORTED = [
     "tsfde_compute_stencil", "tsfde_apply_A", "tsfde_apply_A_f32", "tsfde_apply_P_inv",
     "tsfde_apply_P_inv_f32", "tsfde_gmres_solve", "tsfde_recover_f", "tsfde_recover_f_batch",
     "tsfde_forward_solve", "tsfde_apply_AT", "tsfde_apply_PT_inv", "tsfde_adjoint_solve",
-    "tsfde_recover_f_vjp", "tsfde_last_error",
+    "tsfde_recover_f_vjp", "tsfde_arnoldi", "tsfde_last_error",
 ]
 
 
@@ -81,6 +81,7 @@ def lib():
     L.tsfde_forward_solve.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
     L.tsfde_recover_f_batch.argtypes = [pp, i, pp, C.POINTER(Opts), C.POINTER(Stats), i, vp]
     L.tsfde_apply_AT.argtypes = [vp, vp, vp, vp]
+    L.tsfde_arnoldi.argtypes = [vp, vp, i, dp, C.POINTER(C.c_int), C.POINTER(Opts), vp]
     L.tsfde_apply_PT_inv.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
     L.tsfde_adjoint_solve.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_recover_f_vjp.argtypes = [vp, vp, vp, vp, dp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
@@ -294,6 +295,17 @@ class Problem:
             return gmu, ga.value, gg2.view(self.M, self.Nd), st
         return gmu, ga.value, st
 
+    def arnoldi(self, k: int, b=None, opts: Optional[Opts] = None, stream=None):
+        """(H, steps): the (steps+1) x steps Hessenberg matrix of Arnoldi on A P^{-1} from b (default z)."""
+        import torch
+        H = np.zeros((k + 1) * k)
+        steps = C.c_int(0)
+        bp = _dptr(b, torch.float64, self.n_tot, "b") if b is not None else None
+        _check(lib().tsfde_arnoldi(self._h, bp, int(k), H.ctypes.data_as(C.POINTER(C.c_double)), C.byref(steps),
+                                   C.byref(opts) if opts is not None else None, _stream(stream)))
+        m = steps.value
+        return H.reshape(k + 1, k)[:m + 1, :m], m
+
     def forward_solve(self, f, opts: Optional[Opts] = None, stream=None):
         import torch
         v = torch.empty(self.M * self.Nd, dtype=torch.float64, device="cuda")
@@ -370,3 +382,9 @@ def select_alpha(alphas, residuals, delta: float, tau: float = 1.1):
     noise norm ||mu_eps - mu||); None if no alpha of the grid qualifies."""
     ok = [a for a, r in zip(alphas, residuals) if r <= tau * delta]
     return max(ok) if ok else None
+
+
+def ritz_values(H):
+    """Eigenvalues of the leading square block of an Arnoldi Hessenberg matrix."""
+    m = H.shape[1]
+    return np.linalg.eigvals(H[:m, :m])

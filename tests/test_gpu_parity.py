@@ -527,3 +527,28 @@ def test_discrepancy_sweep_matches_oracle():
     for r, rr in zip(res, ref):
         assert r == pytest.approx(rr, rel=1e-7)
     assert tsfde.select_alpha(alphas, res, delta) == discrepancy.select(alphas, ref, delta)
+
+
+def test_arnoldi_hessenberg_matches_oracle(dense_case):
+    """tsfde_arnoldi on A P^{-1} from z against the oracle's Arnoldi (classical Gram-Schmidt twice)
+    on the dense operator."""
+    from oracle import krylov
+    inp, p, A, P = dense_case
+    k = min(10, p.n_tot - 1)
+    H_ref, _ = krylov.arnoldi_cgs2(lambda v: A @ np.linalg.solve(P, v), system.rhs_z(p), k)
+    with gpu_problem(inp, p) as g:
+        H, m = g.arnoldi(k, opts=tsfde.default_opts(inner_tol=1e-14, inner_maxit=500))
+    assert m == H_ref.shape[1]
+    assert np.abs(H - H_ref).max() <= 1e-9 * np.abs(H_ref).max()
+
+
+def test_arnoldi_ritz_values_are_eigenvalues_of_preconditioned_matrix():
+    """A P^{-1} = I + rank N^d: N^d + 1 Arnoldi steps give eigenvalues of P^{-1} A."""
+    inp = inputs.small(1, 6, 5)
+    p = workloads.with_data(inp)
+    A, P = system.dense_A(p), system.dense_P(p)
+    ev = np.linalg.eigvals(np.linalg.solve(P, A))
+    with gpu_problem(inp, p) as g:
+        H, m = g.arnoldi(p.Nd + 1, opts=tsfde.default_opts(inner_tol=1e-14, inner_maxit=500))
+    for r in tsfde.ritz_values(H):
+        assert np.min(np.abs(ev - r)) <= 1e-6 * max(1.0, abs(r))
