@@ -81,9 +81,22 @@ typedef struct tsfde_opts {
                             TSFDE_BLOCK_TAU needs d = 2 and 2(N+1) a power of
                             two; otherwise the calls return TSFDE_ENOTIMPL
                                                                         (CG)    */
+    int warm_start;      /* initial guess of each block CG in P^{-1} from the
+                            solution of the previous time levels:
+                            TSFDE_WARM_PREVIOUS (y^(s-1)), TSFDE_WARM_LINEAR
+                            (2 y^(s-1) - y^(s-2)), TSFDE_WARM_QUADRATIC,
+                            TSFDE_WARM_HALF (1.5 y^(s-1) - 0.5 y^(s-2)).  The
+                            persistent P^{-1} applies it; the multi-launch path
+                            always starts from y^(s-1)              (LINEAR) */
 } tsfde_opts;
 
 typedef enum { TSFDE_BLOCK_CG = 0, TSFDE_BLOCK_TAU = 1 } tsfde_block_solver;
+typedef enum {
+    TSFDE_WARM_PREVIOUS = 0,
+    TSFDE_WARM_LINEAR = 1,
+    TSFDE_WARM_QUADRATIC = 2,
+    TSFDE_WARM_HALF = 3
+} tsfde_warm_start;
 
 /* Statistics of a solve.  Times are wall-clock seconds on the host, measured
    around stream-synchronised phases. */

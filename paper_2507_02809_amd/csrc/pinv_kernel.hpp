@@ -57,7 +57,7 @@ struct PinvArgs {
     int use_tau;  // 1: tau (sine transform) preconditioner, 0: diagonal
     int Nt;       // size of the sine transform: N, or the padded size with L = 2 (Nt + 1)
     int nt;       // 2D: row stride of the sine-transform intermediates t1 [Nt][nt], t2 [N][nt]
-    int extrap;   // 1: linear extrapolation of the warm start in time
+    int extrap;   // block CG initial guess: 0 previous level, 1 linear, 2 quadratic, 3 half-linear extrapolation
     const T* z;
     T* y;
     const T* g1;
@@ -72,7 +72,7 @@ struct PinvArgs {
     double tol2;
     int maxit;
     // work (Nd each unless noted)
-    T *x, *r, *zz, *p, *q, *t1, *t2, *rhs, *bxb;
+    T *x, *r, *zz, *p, *q, *t1, *t2, *rhs, *bxb, *bxb2;  // bxb, bxb2: B y_{s-2}, B y_{s-3} (warm start)
     T* hacc;           // [kHB][Nd]: w_s of the segment's steps (far history folded into the rhs)
     cplx<T>* spec;     // [H][ns]
     double* part;      // [G][kNPart]
@@ -926,7 +926,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
         // extrapolation in time) and r0 = rhs - A_s x0 are stored; returns r0 and adds to (r, r), (b, b).
         const int nnear = s - sa;  // near-history terms m in [sa, s)
         struct EIn {
-            T xv, rhs_o, r_o, dgp, bxb, ym2, zo, g2o, dgo, hn;
+            T xv, rhs_o, r_o, dgp, bxb, bxb2, ym2, ym3, zo, g2o, dgo, hn;
         };
         // weights of the near-history terms y_{sa+i}, i < kHB, of this step (zero for absent terms),
         // read once per step so that no load of a point waits on a weight
@@ -939,12 +939,15 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
         auto e_load = [&](long long j) -> EIn {
             EIn v;
             const bool ext = (s >= 2 && !lastrow && a.extrap && !TB);
+            const bool ext2 = (s >= 3 && !lastrow && a.extrap == 2 && !TB);
             v.xv = (s > 0) ? a.x[j] : T(0);
             v.rhs_o = (s > 0) ? a.rhs[j] : T(0);
             v.r_o = (s > 0) ? a.r[j] : T(0);
             v.dgp = (s > 0) ? a.dg[(long long)(s - 1) * Nd + j] : T(0);
-            v.bxb = (s >= 2 && !lastrow) ? a.bxb[j] : T(0);
+            v.bxb = ext ? a.bxb[j] : T(0);
             v.ym2 = ext ? a.y[(long long)(s - 2) * Nd + j] : T(0);
+            v.ym3 = ext2 ? a.y[(long long)(s - 3) * Nd + j] : T(0);
+            v.bxb2 = ext2 ? a.bxb2[j] : T(0);
             // s < M: w_s (far history folded in) and dg_s = gamma1_s/gamma2_s (e_0 = 1);
             // s = M: z_M and gamma2_{M-1}
             v.zo = lastrow ? a.z[(long long)M * Nd + j] : a.hacc[(long long)(s - sa) * Nd + j];
@@ -967,6 +970,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
         // the rest of point j: returns r0 and adds to (r, r), (b, b)
         auto e_store = [&](long long j, const EIn& v, T& rr, T& bb) -> T {
             const bool ext = (s >= 2 && !lastrow && a.extrap && !TB);
+            const bool ext2 = (s >= 3 && !lastrow && a.extrap == 2 && !TB);
             const T yprev = v.xv;
             const T bxprev = (s > 0) ? (v.rhs_o - v.r_o - v.dgp * yprev) / a.ct : T(0);  // B y_{s-1}
             T rhs, x0 = T(0), bx0 = T(0);
@@ -976,13 +980,23 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                 const T h = v.hn + e1 * yprev;
                 rhs = v.zo - v.dgo * h;
                 if (s >= 1 && !TB) {
-                    x0 = ext ? T(2) * yprev - v.ym2 : yprev;
-                    bx0 = ext ? T(2) * bxprev - v.bxb : bxprev;
+                    // linear (or, extrap = 2, quadratic) extrapolation in time of y and B y
+                    if (ext2) {
+                        x0 = T(3) * (yprev - v.ym2) + v.ym3;
+                        bx0 = T(3) * (bxprev - v.bxb) + v.bxb2;
+                    } else {
+                        const T th = (a.extrap == 3) ? T(0.5) : T(1);  // 3: half the linear step
+                        x0 = ext ? yprev + th * (yprev - v.ym2) : yprev;
+                        bx0 = ext ? bxprev + th * (bxprev - v.bxb) : bxprev;
+                    }
                 }
             }
             const T rv = rhs - (v.dgo * x0 + cc * bx0);
             if (s > 0) a.y[(long long)(s - 1) * Nd + j] = yprev;
-            if (s >= 1 && !lastrow) a.bxb[j] = bxprev;  // B y_{s-1} is "B y_{s-2}" next step
+            if (s >= 1 && !lastrow && a.extrap && !TB) {
+                a.bxb[j] = bxprev;  // B y_{s-1} is "B y_{s-2}" next step
+                if (a.extrap == 2) a.bxb2[j] = v.bxb;  // and B y_{s-2} is "B y_{s-3}"
+            }
             a.rhs[j] = rhs;
             a.x[j] = x0;
             a.r[j] = rv;
@@ -1244,7 +1258,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
 // ---------------------------------------------------------------------------
 template <typename T>
 struct PersistentWork {
-    T* buf = nullptr;       // x r zz p q rhs bxb: 7 Nd, then hacc: kHB Nd
+    T* buf = nullptr;       // x r zz p q rhs bxb bxb2: 8 Nd, then hacc: kHB Nd
     T* tt = nullptr;        // t1, t2: N ns each (2D)
     cplx<T>* spec = nullptr;  // [H][ns] (2D)
     double* part = nullptr;
@@ -1293,7 +1307,8 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
     a.q = b + 4 * Nd;
     a.rhs = b + 5 * Nd;
     a.bxb = b + 6 * Nd;
-    a.hacc = b + 7 * Nd;
+    a.bxb2 = b + 7 * Nd;
+    a.hacc = b + 8 * Nd;
     a.ns = spec_stride(P.N);
     a.nt = spec_stride(P.Nt);
     a.t1 = W.tt;                                                   // [Nt][nt]

@@ -14,7 +14,7 @@ template <typename T>
 void ensure_work(Problem& P, PersistentWork<T>& W) {
     if (W.buf) return;
     const size_t ns = (size_t)spec_stride(P.N), nt = (size_t)spec_stride(P.Nt);
-    TSFDE_HIP(hipMalloc(&W.buf, sizeof(T) * (size_t)(7 + kHB) * P.Nd));
+    TSFDE_HIP(hipMalloc(&W.buf, sizeof(T) * (size_t)(8 + kHB) * P.Nd));
     if (P.d == 2) {
         // sine-transform intermediates t1 [Nt][nt] and t2 [N][nt]; half spectra [H][ns]
         TSFDE_HIP(hipMalloc(&W.tt, sizeof(T) * ((size_t)P.Nt + P.N) * nt));
@@ -25,7 +25,7 @@ void ensure_work(Problem& P, PersistentWork<T>& W) {
     TSFDE_HIP(hipMalloc(&W.iters, sizeof(long long)));
     TSFDE_HIP(hipMalloc(&W.sigma, sizeof(double) * P.M));
     TSFDE_HIP(hipMemcpy(W.sigma, P.sigma.data(), sizeof(double) * P.M, hipMemcpyHostToDevice));
-    TSFDE_HIP(hipMemset(W.buf, 0, sizeof(T) * (size_t)(7 + kHB) * P.Nd));
+    TSFDE_HIP(hipMemset(W.buf, 0, sizeof(T) * (size_t)(8 + kHB) * P.Nd));
 }
 
 bool persistent_supported(const Problem& P) {

@@ -49,7 +49,7 @@ constexpr double kInnerTolF32 = 1e-6;
 
 struct Opts {
     int restart = 50, maxit = 0, precision = TSFDE_FP64, use_precond = 1, inner_maxit = 200, max_refine = 30;
-    int block_solver = TSFDE_BLOCK_CG;
+    int block_solver = TSFDE_BLOCK_CG, warm_start = TSFDE_WARM_LINEAR;
     double tol = 1e-10, inner_tol = 1e-12, refine_tol = 1e-5;
 };
 
@@ -66,6 +66,7 @@ static Opts get_opts(const tsfde_opts* o) {
     r.refine_tol = o->refine_tol;
     r.max_refine = o->max_refine;
     r.block_solver = o->block_solver;
+    r.warm_start = o->warm_start;
     return r;
 }
 
@@ -78,6 +79,10 @@ static bool check_opts(const Opts& o) {
     if (o.inner_maxit < 1 || o.max_refine < 1) { set_error("opts.inner_maxit and max_refine must be >= 1"); return false; }
     if (o.precision != TSFDE_FP64 && o.precision != TSFDE_MIXED && o.precision != TSFDE_PREC_F32) {
         set_error("opts.precision invalid");
+        return false;
+    }
+    if (o.warm_start < TSFDE_WARM_PREVIOUS || o.warm_start > TSFDE_WARM_HALF) {
+        set_error("opts.warm_start invalid");
         return false;
     }
     if (o.block_solver != TSFDE_BLOCK_CG && o.block_solver != TSFDE_BLOCK_TAU) {
@@ -136,12 +141,13 @@ template <typename T>
 static long long pinv_impl(Problem& P, const T* z, T* y, const Opts& o, hipStream_t st, bool last_block) {
     // TSFDE_PINV=0 selects the multi-launch path; TSFDE_PINV_BLOCKS overrides the grid size;
     // TSFDE_PINV_FIXED=0 keeps the 2D sine-transform path on its run-time-length kernel;
-    // TSFDE_EXTRAP=0 disables the linear-in-time warm start
+    // TSFDE_EXTRAP overrides opts.warm_start (the block CG's initial guess)
     if (env_int("TSFDE_PINV", 1) != 0 && persistent_supported(P)) {
         set_persistent_blocks(env_int("TSFDE_PINV_BLOCKS", -1));
         set_persistent_fixed_length(env_int("TSFDE_PINV_FIXED", 1) != 0);
         return pinv_persistent_run<T>(P, dev<T>(P), pwork<T>(P), z, y, o.inner_tol, o.inner_maxit, last_block,
-                                      env_int("TSFDE_EXTRAP", 1), o.block_solver == TSFDE_BLOCK_TAU ? 1 : 0, st);
+                                      env_int("TSFDE_EXTRAP", o.warm_start), o.block_solver == TSFDE_BLOCK_TAU ? 1 : 0,
+                                      st);
     }
     return pinv_launch<T>(P, z, y, o, st, last_block);
 }
@@ -658,6 +664,7 @@ void tsfde_default_opts(tsfde_opts* o) {
     o->tol = 1e-10;
     o->precision = TSFDE_FP64;
     o->block_solver = TSFDE_BLOCK_CG;
+    o->warm_start = TSFDE_WARM_LINEAR;
     o->use_precond = 1;
     o->inner_tol = 1e-12;
     o->inner_maxit = 200;

@@ -15,6 +15,7 @@ _lib = None
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ENONFINITE, ENOTIMPL = range(7)
 FP64, MIXED, PREC_F32 = 0, 1, 2
 BLOCK_CG, BLOCK_TAU = 0, 1
+WARM_PREVIOUS, WARM_LINEAR, WARM_QUADRATIC, WARM_HALF = 0, 1, 2, 3
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOCONV", 5: "ENONFINITE", 6: "ENOTIMPL"}
 
 EXPORTED = [
@@ -30,7 +31,8 @@ EXPORTED = [
 class Opts(C.Structure):
     _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("tol", C.c_double), ("precision", C.c_int),
                 ("use_precond", C.c_int), ("inner_tol", C.c_double), ("inner_maxit", C.c_int),
-                ("refine_tol", C.c_double), ("max_refine", C.c_int), ("block_solver", C.c_int)]
+                ("refine_tol", C.c_double), ("max_refine", C.c_int), ("block_solver", C.c_int),
+                ("warm_start", C.c_int)]
 
 
 class Stats(C.Structure):

@@ -33,6 +33,7 @@ def test_default_opts():
     o = tsfde.default_opts()
     assert (o.restart, o.maxit, o.tol, o.precision, o.use_precond) == (50, 0, 1e-10, 0, 1)
     assert o.inner_tol == 1e-12 and o.inner_maxit == 200
+    assert o.block_solver == tsfde.BLOCK_CG and o.warm_start == tsfde.WARM_LINEAR
 
 
 @pytest.mark.parametrize("omega", [1.2, 1.5, 1.8])

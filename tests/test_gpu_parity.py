@@ -180,16 +180,17 @@ def test_library_stencil_used_by_problem():
 
 @pytest.fixture
 def pinv_path(monkeypatch):
-    def set_path(persistent: bool, extrap: bool = True):
+    def set_path(persistent: bool, extrap: int = 0):
         monkeypatch.setenv("TSFDE_PINV", "1" if persistent else "0")
-        monkeypatch.setenv("TSFDE_EXTRAP", "1" if extrap else "0")
+        monkeypatch.setenv("TSFDE_EXTRAP", str(int(extrap)))
     return set_path
 
 
-@pytest.mark.parametrize("persistent,extrap", [(True, True), (True, False), (False, True)])
+@pytest.mark.parametrize("persistent,extrap", [(True, 0), (True, 1), (True, 2), (True, 3), (False, 0)])
 def test_apply_P_inv_paths_match_dense(dense_case, pinv_path, persistent, extrap):
     """Both implementations of the forward substitution (one persistent cooperative kernel, or one
-    launch per CG phase), with and without the extrapolated warm start, against dense P^{-1}."""
+    launch per CG phase), with each initial guess of the block CG (previous time level; linear,
+    quadratic, half-linear extrapolation), against dense P^{-1}."""
     pinv_path(persistent, extrap)
     inp, p, _, P = dense_case
     rng = np.random.default_rng(16)
