@@ -36,7 +36,7 @@ METRIC = "GMRES solves/sec to 1e-8 rel. f error (d=2,N=255²,M=256); matvec HBM 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 # one FP64 apply_A at c3, bytes at the HBM interface (FETCH_SIZE x 1.996 + WRITE_SIZE x 1.000)
-APPLY_A_TRAFFIC_FP64 = 2380.1e6
+APPLY_A_TRAFFIC_FP64 = 2396.2e6
 # algorithmic flops of one apply_A at c3: M(M+1)/2 Nd FMA of the history sum (4.28 GFLOP) plus
 # 5 L log2 L flops per length-512 complex FFT: 2 x 257 x 128 row transforms and 2 x 257 x 257
 # column transforms (4.56 GFLOP)
