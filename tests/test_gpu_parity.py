@@ -553,3 +553,33 @@ def test_arnoldi_ritz_values_are_eigenvalues_of_preconditioned_matrix():
         H, m = g.arnoldi(p.Nd + 1, opts=tsfde.default_opts(inner_tol=1e-14, inner_maxit=500))
     for r in tsfde.ritz_values(H):
         assert np.min(np.abs(ev - r)) <= 1e-6 * max(1.0, abs(r))
+
+
+@pytest.mark.parametrize("d,N,M", [(1, 40, 70), (2, 15, 33)])
+def test_apply_A_time_operator_exact_on_linear_in_t(d, N, M):
+    """The L1 time operator is exact on functions linear in t (closed form, not the oracle): with
+    y_s = psi (a + b t_s) and f~ = 0, (A y)_s minus its spatial part, divided by gamma1_s, equals
+    psi (b_{s-1} a + b dt s^{1-beta}).  The spatial part c_t gamma2_s .* B psi (a + b t_s) uses
+    B psi from the last block row of A [0; psi], which is c_f gamma2_M .* B psi."""
+    inp = inputs.small(d, N, M, beta=0.45, omega=1.5)
+    Nd, dt, beta = inp.Nd, inp.T / M, inp.beta
+    rng = np.random.default_rng(41)
+    psi = rng.standard_normal(Nd)
+    a, b = 0.7, -1.3
+    t = dt * np.arange(1, M + 1)
+    y = np.zeros((M + 1) * Nd)
+    for s in range(M):
+        y[s * Nd:(s + 1) * Nd] = psi * (a + b * t[s])
+    e_last = np.zeros((M + 1) * Nd)
+    e_last[M * Nd:] = psi
+    with tsfde.Problem.from_inputs(inp) as g:
+        sc = g.scalars()
+        z = g.apply_A(torch.tensor(y, device=DEV)).cpu().numpy().reshape(M + 1, Nd)
+        zl = g.apply_A(torch.tensor(e_last, device=DEV)).cpu().numpy().reshape(M + 1, Nd)
+    Bpsi = zl[M] / (sc["c_f"] * inp.gamma2[M - 1])
+    s1 = np.arange(1, M + 1)
+    bw = s1 ** (1 - beta) - (s1 - 1) ** (1 - beta)  # b_{s-1}
+    for s in range(M):
+        hist = (z[s] - sc["c_t"] * inp.gamma2[s] * (a + b * t[s]) * Bpsi) / inp.gamma1[s]
+        ref = psi * (bw[s] * a + b * dt * (s + 1) ** (1 - beta))
+        assert np.abs(hist - ref).max() <= 1e-10 * np.abs(psi).max() * (1 + sc["c_t"]), s
