@@ -343,7 +343,31 @@ def main():
                      "inner_tol": a.inner_tol, "forward_outer_iters": s1.iters, "adjoint_outer_iters": s2.iters,
                      "adjoint_s": s2.t_total, "grad_mu_rel_diff_vs_tight": egm,
                      "grad_alpha_rel_diff_vs_tight": abs(ga - ga_ref) / abs(ga_ref)}
-        p5.close()
+        # a batch of 16 instances: forward batch, then the gradient batch on the problems' own solutions
+        gprobs, fts = [p5], [ft]
+        for k in range(1, 16):
+            ik = inputs.c5(k)
+            pk = tsfde.Problem.from_inputs(ik)
+            vk = pk.forward_solve(torch.tensor(ik.f_true, device=dev), opts=tsfde.default_opts(inner_tol=1e-12))
+            pk.set_mu(ik.noisy(vk[(ik.M - 1) * ik.Nd:].cpu().numpy()))
+            gprobs.append(pk)
+            fts.append(torch.tensor(ik.f_true, device=dev))
+
+        def grad_batch():
+            outs = tsfde.recover_f_batch(gprobs, o5, max_inflight=8)
+            gfs = [(2.0 * (f - t)).contiguous() for (f, _), t in zip(outs, fts)]
+            return tsfde.recover_f_vjp_batch(gprobs, gfs, opts=o5, max_inflight=8, gamma2=True)
+
+        grad_batch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        grad_batch()
+        torch.cuda.synchronize()
+        dtb = time.perf_counter() - t0
+        log(f"gradients: batch of 16 in {dtb:.2f} s ({16 / dtb:.2f} passes/s)")
+        gradients["batch_of_16"] = {"instances_in_flight": 8, "passes_per_s": 16 / dtb, "s_per_batch": dtb}
+        for pk in gprobs:
+            pk.close()
 
     # structured matvec (FP64 and FP32), HIP events on the stream the library launches on
     y = torch.randn(prob.n_tot, dtype=torch.float64, device=dev)

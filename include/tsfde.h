@@ -299,6 +299,23 @@ tsfde_status tsfde_recover_f_vjp(tsfde_problem* prob, const double* y, const dou
                                  const tsfde_opts* opts, tsfde_stats* stats, void* stream);
 
 /*
+ * tsfde_recover_f_vjp for several problems side by side, as tsfde_recover_f_batch
+ * runs tsfde_recover_f (same worker streams, ordering, limits and status rules).
+ *   ys           count device solutions of A y = z, or NULL (or a NULL entry) for
+ *                the solution the problem's last tsfde_recover_f without a work
+ *                buffer left in its internal buffer (EINVAL if there is none)
+ *   gfs          count device gradients dL/df~ (N_i^d)
+ *   grad_mu      NULL, or count device outputs (N_i^d; NULL entries skip)
+ *   grad_alpha   NULL, or a HOST array of count doubles
+ *   grad_gamma2  NULL, or count device outputs (M_i N_i^d; NULL entries skip)
+ */
+tsfde_status tsfde_recover_f_vjp_batch(tsfde_problem* const* probs, int count,
+                                       const double* const* ys, const double* const* gfs,
+                                       double* const* grad_mu, double* grad_alpha,
+                                       double* const* grad_gamma2, const tsfde_opts* opts,
+                                       tsfde_stats* stats, int max_inflight, void* stream);
+
+/*
  * Spectral estimate of the preconditioned operator: k steps of Arnoldi
  * (classical Gram-Schmidt applied twice, as in the solver) on A P^{-1} from b
  * (device, (M+1) N^d; NULL for z of eq. lin-syst), with P^{-1} applied as in

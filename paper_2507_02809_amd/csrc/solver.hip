@@ -655,6 +655,131 @@ static tsfde_status recover_impl(Problem& P, double* f_out, double* work, const 
     return rc;
 }
 
+// The vector-Jacobian product of f~ (see tsfde_recover_f_vjp); synchronises st.
+static tsfde_status vjp_impl(Problem& P, const double* y, const double* gf, double* grad_mu, double* grad_alpha,
+                             double* grad_gamma2, const Opts& o, tsfde_stats& S, hipStream_t st) {
+    const long long n = P.ntot, Nd = P.Nd, last = (long long)P.M * P.Nd;
+    tsfde_status rc = TSFDE_OK;
+    TSFDE_GUARD("recover_f_vjp", {
+        double* w = nullptr;  // g = [0; gf], lam, then v = [0; y^(M)] and A v
+        TSFDE_HIP(hipMalloc(&w, sizeof(double) * 3 * n));
+        double* g = w;
+        double* lam = w + n;
+        double* v = w + 2 * n;
+        launch_fill(g, n, 0.0, st);
+        launch_copy<double>(gf, g + last, Nd, st);
+        launch_fill(lam, n, 0.0, st);
+        try {
+            rc = adjoint_impl(P, g, lam, o, S, st);
+            if (grad_mu) launch_copy<double>(lam + last, grad_mu, Nd, st);
+            if (grad_gamma2) {
+                // v = (c_t B y^(s), c_f B y^(M)): the matvec's B kernels with unit gamma2 into a zero
+                // vector, the last row adding the (zero) first slice of g instead of y^(M-1)
+                Dev<double> Dn = P.f64;
+                Dn.gamma2 = nullptr;
+                launch_fill(v, n, 0.0, st);
+                if (!launch_toeplitz2d_matvec<double>(P, Dn, y, v, st, g))
+                    launch_toeplitz_matvec<double>(P, Dn, y, v, st, g);
+                launch_gamma2_grad(P, lam, v, grad_gamma2, st);
+            }
+            if (grad_alpha) {
+                // dA/dalpha y = (1/alpha) (A [0; y^(M)])^(M): only c_f = alpha/h^omega depends on alpha
+                launch_fill(v, n, 0.0, st);
+                launch_copy<double>(y + last, v + last, Nd, st);
+                apply_A_impl<double>(P, v, g, st);
+                *grad_alpha = -dev_dot(P, lam + last, g + last, Nd, st) / P.alpha;
+            }
+            TSFDE_HIP(hipStreamSynchronize(st));
+        } catch (...) {
+            (void)hipFree(w);
+            throw;
+        }
+        (void)hipFree(w);
+    })
+    if (rc == TSFDE_ENOCONV) set_error("recover_f_vjp: adjoint tolerance not reached (rel. residual %.3e)", S.rel_res);
+    return rc;
+}
+
+// Runs fn(i, problem i, its stats, a stream) for every problem of a batch, up to max_inflight at once,
+// each worker thread on a non-blocking stream of its own, largest problems first; the persistent
+// kernels of the workers are ordinary launches sized to fit together (set_shared_launch).  Checks the
+// batch, holds the launch lock exclusively, and returns the first device error by index, else
+// TSFDE_ENOCONV if any problem missed its tolerance.
+template <typename F>
+static tsfde_status run_batch(const char* name, tsfde_problem* const* probs, int count, const Opts& o,
+                              tsfde_stats* stats, int max_inflight, void* stream, F&& fn) {
+    if (max_inflight < 1 || max_inflight > kMaxInflight) {
+        set_error("%s: max_inflight must be in [1, %d]", name, kMaxInflight);
+        return TSFDE_EINVAL;
+    }
+    for (int i = 0; i < count; ++i) {
+        if (!probs[i]) {
+            set_error("%s: problem %d is NULL", name, i);
+            return TSFDE_EINVAL;
+        }
+        for (int j = 0; j < i; ++j)
+            if (probs[j] == probs[i]) {
+                set_error("%s: problem %d appears twice (entries %d and %d)", name, i, j, i);
+                return TSFDE_EINVAL;
+            }
+        if (!block_solver_supported(*probs[i]->p, o)) return TSFDE_ENOTIMPL;
+    }
+    if (count == 0) return TSFDE_OK;
+    std::unique_lock<std::shared_mutex> lk(g_launch_mx);
+    int dev = 0;
+    TSFDE_GUARD(name, {
+        TSFDE_HIP(hipGetDevice(&dev));
+        TSFDE_HIP(hipStreamSynchronize((hipStream_t)stream));
+    })
+    std::vector<tsfde_status> rcs(count, TSFDE_OK);
+    std::vector<std::string> msgs(count);
+    std::vector<tsfde_stats> S(count, tsfde_stats{});
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return probs[x]->p->ntot > probs[y]->p->ntot; });
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+        hipStream_t st = nullptr;
+        hipError_t e = hipSetDevice(dev);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        set_shared_launch(true);
+        for (int t; (t = next.fetch_add(1)) < count;) {
+            const int i = order[t];
+            if (e != hipSuccess) {
+                rcs[i] = TSFDE_EDEVICE;
+                msgs[i] = std::string("stream creation failed: ") + hipGetErrorString(e);
+                continue;
+            }
+            rcs[i] = fn(i, *probs[i]->p, S[i], st);
+            if (rcs[i] != TSFDE_OK) msgs[i] = last_error();
+        }
+        set_shared_launch(false);
+        if (st) (void)hipStreamDestroy(st);
+    };
+    std::vector<std::thread> th;
+    try {
+        for (int t = 1; t < std::min(max_inflight, count); ++t) th.emplace_back(worker);
+    } catch (const std::system_error&) {
+        // fewer workers: the calling thread and those started take every problem
+    }
+    worker();
+    for (auto& t : th) t.join();
+    if (stats)
+        for (int i = 0; i < count; ++i) stats[i] = S[i];
+    for (int i = 0; i < count; ++i)
+        if (rcs[i] != TSFDE_OK && rcs[i] != TSFDE_ENOCONV) {
+            set_error("%s: problem %d: %s", name, i, msgs[i].c_str());
+            return rcs[i];
+        }
+    for (int i = 0; i < count; ++i)
+        if (rcs[i] == TSFDE_ENOCONV) {
+            set_error("%s: problem %d: %s", name, i, msgs[i].c_str());
+            return TSFDE_ENOCONV;
+        }
+    return TSFDE_OK;
+}
+
 extern "C" {
 
 void tsfde_default_opts(tsfde_opts* o) {
@@ -823,80 +948,45 @@ tsfde_status tsfde_recover_f_batch(tsfde_problem* const* probs, int count, doubl
         set_error("recover_f_batch: count < 0 or NULL arrays");
         return TSFDE_EINVAL;
     }
-    if (max_inflight < 1 || max_inflight > kMaxInflight) {
-        set_error("recover_f_batch: max_inflight must be in [1, %d]", kMaxInflight);
+    const Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    for (int i = 0; i < count; ++i)
+        if (!f_out[i]) {
+            set_error("recover_f_batch: output %d is NULL", i);
+            return TSFDE_EINVAL;
+        }
+    return run_batch("recover_f_batch", probs, count, o, stats, max_inflight, stream,
+                     [&](int i, Problem& P, tsfde_stats& S, hipStream_t st) {
+                         return recover_impl(P, f_out[i], nullptr, o, S, st);
+                     });
+}
+
+tsfde_status tsfde_recover_f_vjp_batch(tsfde_problem* const* probs, int count, const double* const* ys,
+                                       const double* const* gfs, double* const* grad_mu, double* grad_alpha,
+                                       double* const* grad_gamma2, const tsfde_opts* opts, tsfde_stats* stats,
+                                       int max_inflight, void* stream) {
+    if (count < 0 || (count > 0 && (!probs || !gfs))) {
+        set_error("recover_f_vjp_batch: count < 0 or NULL arrays");
         return TSFDE_EINVAL;
     }
     const Opts o = get_opts(opts);
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
     for (int i = 0; i < count; ++i) {
-        if (!probs[i] || !f_out[i]) {
-            set_error("recover_f_batch: problem %d or its output is NULL", i);
+        if (!gfs[i]) {
+            set_error("recover_f_vjp_batch: gf %d is NULL", i);
             return TSFDE_EINVAL;
         }
-        for (int j = 0; j < i; ++j)
-            if (probs[j] == probs[i]) {
-                set_error("recover_f_batch: problem %d appears twice (entries %d and %d)", i, j, i);
-                return TSFDE_EINVAL;
-            }
-        if (!block_solver_supported(*probs[i]->p, o)) return TSFDE_ENOTIMPL;
+        if (probs && probs[i] && !(ys && ys[i]) && !probs[i]->p->xbuf) {
+            set_error("recover_f_vjp_batch: problem %d has no solution (no ys and no earlier recover_f)", i);
+            return TSFDE_EINVAL;
+        }
     }
-    if (count == 0) return TSFDE_OK;
-    std::unique_lock<std::shared_mutex> lk(g_launch_mx);
-    int dev = 0;
-    TSFDE_GUARD("recover_f_batch", {
-        TSFDE_HIP(hipGetDevice(&dev));
-        TSFDE_HIP(hipStreamSynchronize((hipStream_t)stream));
-    })
-    std::vector<tsfde_status> rcs(count, TSFDE_OK);
-    std::vector<std::string> msgs(count);
-    std::vector<tsfde_stats> S(count, tsfde_stats{});
-    // largest problems first (by unknowns), so that a long solve does not start last
-    std::vector<int> order(count);
-    for (int i = 0; i < count; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return probs[x]->p->ntot > probs[y]->p->ntot; });
-    std::atomic<int> next{0};
-    // each worker takes the next problem until none is left, on a stream of its own
-    auto worker = [&]() {
-        hipStream_t st = nullptr;
-        hipError_t e = hipSetDevice(dev);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-        set_shared_launch(true);
-        for (int t; (t = next.fetch_add(1)) < count;) {
-            const int i = order[t];
-            if (e != hipSuccess) {
-                rcs[i] = TSFDE_EDEVICE;
-                msgs[i] = std::string("stream creation failed: ") + hipGetErrorString(e);
-                continue;
-            }
-            rcs[i] = recover_impl(*probs[i]->p, f_out[i], nullptr, o, S[i], st);
-            if (rcs[i] != TSFDE_OK) msgs[i] = last_error();
-        }
-        set_shared_launch(false);
-        if (st) (void)hipStreamDestroy(st);
-    };
-    std::vector<std::thread> th;
-    try {
-        for (int t = 1; t < std::min(max_inflight, count); ++t) th.emplace_back(worker);
-    } catch (const std::system_error&) {
-        // fewer workers: the calling thread and those started take every problem
-    }
-    worker();
-    for (auto& t : th) t.join();
-    if (stats)
-        for (int i = 0; i < count; ++i) stats[i] = S[i];
-    for (int i = 0; i < count; ++i)
-        if (rcs[i] != TSFDE_OK && rcs[i] != TSFDE_ENOCONV) {
-            set_error("recover_f_batch: problem %d: %s", i, msgs[i].c_str());
-            return rcs[i];
-        }
-    for (int i = 0; i < count; ++i)
-        if (rcs[i] == TSFDE_ENOCONV) {
-            set_error("recover_f_batch: problem %d: %s", i, msgs[i].c_str());
-            return TSFDE_ENOCONV;
-        }
-    return TSFDE_OK;
+    return run_batch("recover_f_vjp_batch", probs, count, o, stats, max_inflight, stream,
+                     [&](int i, Problem& P, tsfde_stats& S, hipStream_t st) {
+                         return vjp_impl(P, (ys && ys[i]) ? ys[i] : P.xbuf, gfs[i], grad_mu ? grad_mu[i] : nullptr,
+                                         grad_alpha ? grad_alpha + i : nullptr,
+                                         grad_gamma2 ? grad_gamma2[i] : nullptr, o, S, st);
+                     });
 }
 
 tsfde_status tsfde_forward_solve(tsfde_problem* prob, const double* f, double* v, const tsfde_opts* opts,
@@ -968,48 +1058,9 @@ tsfde_status tsfde_recover_f_vjp(tsfde_problem* prob, const double* y, const dou
     Problem& P = *prob->p;
     const Opts o = get_opts(opts);
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
-    const long long n = P.ntot, Nd = P.Nd, last = (long long)P.M * P.Nd;
-    hipStream_t st = (hipStream_t)stream;
     tsfde_stats S{};
-    tsfde_status rc = TSFDE_OK;
-    TSFDE_GUARD("recover_f_vjp", {
-        double* w = nullptr;  // g = [0; gf], lam, then v = [0; y^(M)] and A v
-        TSFDE_HIP(hipMalloc(&w, sizeof(double) * 3 * n));
-        double* g = w;
-        double* lam = w + n;
-        double* v = w + 2 * n;
-        launch_fill(g, n, 0.0, st);
-        launch_copy<double>(gf, g + last, Nd, st);
-        launch_fill(lam, n, 0.0, st);
-        try {
-            rc = adjoint_impl(P, g, lam, o, S, st);
-            if (grad_mu) launch_copy<double>(lam + last, grad_mu, Nd, st);
-            if (grad_gamma2) {
-                // v = (c_t B y^(s), c_f B y^(M)): the matvec's B kernels with unit gamma2 into a zero
-                // vector, the last row adding the (zero) first slice of g instead of y^(M-1)
-                Dev<double> Dn = P.f64;
-                Dn.gamma2 = nullptr;
-                launch_fill(v, n, 0.0, st);
-                if (!launch_toeplitz2d_matvec<double>(P, Dn, y, v, st, g))
-                    launch_toeplitz_matvec<double>(P, Dn, y, v, st, g);
-                launch_gamma2_grad(P, lam, v, grad_gamma2, st);
-            }
-            if (grad_alpha) {
-                // dA/dalpha y = (1/alpha) (A [0; y^(M)])^(M): only c_f = alpha/h^omega depends on alpha
-                launch_fill(v, n, 0.0, st);
-                launch_copy<double>(y + last, v + last, Nd, st);
-                apply_A_impl<double>(P, v, g, st);
-                *grad_alpha = -dev_dot(P, lam + last, g + last, Nd, st) / P.alpha;
-            }
-            TSFDE_HIP(hipStreamSynchronize(st));
-        } catch (...) {
-            (void)hipFree(w);
-            throw;
-        }
-        (void)hipFree(w);
-    })
+    const tsfde_status rc = vjp_impl(P, y, gf, grad_mu, grad_alpha, grad_gamma2, o, S, (hipStream_t)stream);
     if (stats) *stats = S;
-    if (rc == TSFDE_ENOCONV) set_error("recover_f_vjp: adjoint tolerance not reached (rel. residual %.3e)", S.rel_res);
     return rc;
 }
 

@@ -24,7 +24,7 @@ EXPORTED = [
     "tsfde_compute_stencil", "tsfde_apply_A", "tsfde_apply_A_f32", "tsfde_apply_P_inv",
     "tsfde_apply_P_inv_f32", "tsfde_gmres_solve", "tsfde_recover_f", "tsfde_recover_f_batch",
     "tsfde_forward_solve", "tsfde_apply_AT", "tsfde_apply_PT_inv", "tsfde_adjoint_solve",
-    "tsfde_recover_f_vjp", "tsfde_arnoldi", "tsfde_last_error",
+    "tsfde_recover_f_vjp", "tsfde_recover_f_vjp_batch", "tsfde_arnoldi", "tsfde_last_error",
 ]
 
 
@@ -84,6 +84,7 @@ def lib():
     L.tsfde_recover_f_batch.argtypes = [pp, i, pp, C.POINTER(Opts), C.POINTER(Stats), i, vp]
     L.tsfde_apply_AT.argtypes = [vp, vp, vp, vp]
     L.tsfde_arnoldi.argtypes = [vp, vp, i, dp, C.POINTER(C.c_int), C.POINTER(Opts), vp]
+    L.tsfde_recover_f_vjp_batch.argtypes = [pp, i, pp, pp, pp, dp, pp, C.POINTER(Opts), C.POINTER(Stats), i, vp]
     L.tsfde_apply_PT_inv.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
     L.tsfde_adjoint_solve.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_recover_f_vjp.argtypes = [vp, vp, vp, vp, dp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
@@ -384,6 +385,31 @@ def select_alpha(alphas, residuals, delta: float, tau: float = 1.1):
     noise norm ||mu_eps - mu||); None if no alpha of the grid qualifies."""
     ok = [a for a, r in zip(alphas, residuals) if r <= tau * delta]
     return max(ok) if ok else None
+
+
+def recover_f_vjp_batch(problems, gfs, ys=None, opts: Optional[Opts] = None, max_inflight: int = 2,
+                        gamma2=False, stream=None, raise_noconv=False):
+    """tsfde_recover_f_vjp_batch: per problem (grad_mu, grad_alpha[, grad_gamma2], stats); ys None uses
+    each problem's solution from its last recover_f without a work buffer."""
+    import torch
+    n = len(problems)
+    gmu = [torch.empty(p.Nd, dtype=torch.float64, device="cuda") for p in problems]
+    gg2 = [torch.empty(p.M * p.Nd, dtype=torch.float64, device="cuda") for p in problems] if gamma2 else None
+    ga = np.zeros(max(n, 1))
+    arr = lambda ptrs: (C.c_void_p * max(n, 1))(*ptrs)
+    hs = arr([p._h.value for p in problems])
+    yp = arr([_dptr(y, torch.float64, p.n_tot, "y").value for y, p in zip(ys, problems)]) if ys is not None else None
+    gp = arr([_dptr(g, torch.float64, p.Nd, "gf").value for g, p in zip(gfs, problems)])
+    mp = arr([t.data_ptr() for t in gmu])
+    g2p = arr([t.data_ptr() for t in gg2]) if gamma2 else None
+    st = (Stats * max(n, 1))()
+    rc = lib().tsfde_recover_f_vjp_batch(hs, n, yp, gp, mp, ga.ctypes.data_as(C.POINTER(C.c_double)), g2p,
+                                         C.byref(opts) if opts is not None else None, st, max_inflight,
+                                         _stream(stream))
+    _check(rc, allow=() if raise_noconv else (ENOCONV,))
+    if gamma2:
+        return [(gmu[i], float(ga[i]), gg2[i].view(problems[i].M, problems[i].Nd), st[i]) for i in range(n)]
+    return [(gmu[i], float(ga[i]), st[i]) for i in range(n)]
 
 
 def ritz_values(H):

@@ -583,3 +583,31 @@ def test_apply_A_time_operator_exact_on_linear_in_t(d, N, M):
         hist = (z[s] - sc["c_t"] * inp.gamma2[s] * (a + b * t[s]) * Bpsi) / inp.gamma1[s]
         ref = psi * (bw[s] * a + b * dt * (s + 1) ** (1 - beta))
         assert np.abs(hist - ref).max() <= 1e-10 * np.abs(psi).max() * (1 + sc["c_t"]), s
+
+
+def test_recover_f_vjp_batch_matches_single_calls():
+    """Forward batch, then the gradient batch on the problems' own solutions: the same numbers as one
+    problem at a time (same kernels and reduction order), and the oracle's gradients."""
+    cases = [inputs.small(1, 12, 7), inputs.small(2, 7, 9, beta=0.3, omega=1.2), inputs.small(2, 15, 6)]
+    o = tsfde.default_opts(tol=3e-13, inner_tol=1e-12, inner_maxit=500)
+    rng = np.random.default_rng(51)
+    probs, gfs, refs = [], [], []
+    try:
+        for inp in cases:
+            p = workloads.with_data(inp)
+            probs.append(gpu_problem(inp, p))
+            gf = rng.standard_normal(p.Nd)
+            gfs.append(torch.tensor(gf, device=DEV))
+            refs.append(adjoint.vjp(p, gf))
+        tsfde.recover_f_batch(probs, o, max_inflight=3, raise_noconv=True)
+        out = tsfde.recover_f_vjp_batch(probs, gfs, opts=o, max_inflight=3, gamma2=True, raise_noconv=True)
+        for g, gf, (gm_b, ga_b, gg_b, _), (gm_ref, ga_ref, _) in zip(probs, gfs, out, refs):
+            y = torch.empty(g.n_tot, dtype=torch.float64, device=DEV)
+            g.recover_f(o, work=y, raise_noconv=True)
+            gm, ga, gg, _ = g.recover_f_vjp(y, gf, opts=o, raise_noconv=True, gamma2=True)
+            assert torch.equal(gm, gm_b) and ga == ga_b and torch.equal(gg, gg_b)
+            assert rel_err(gm_b.cpu().numpy(), gm_ref) <= 1e-9
+            assert ga_b == pytest.approx(ga_ref, rel=1e-8)
+    finally:
+        for g in probs:
+            g.close()
