@@ -6,6 +6,10 @@
 //                twice, Givens rotations on the host in FP64; MIXED precision wraps it in
 //                iterative refinement with an FP64 residual
 //   recover_f    z of eq. lin-syst, solve from x0 = 0, f~ = last block (§5, §6)
+//   batches      several problems side by side on worker streams (recover_f, its gradient)
+//   transposed   A^T lam, P^{-T} g by backward substitution, the adjoint solve and the
+//                vector-Jacobian product of f~ in mu, alpha and the gamma2 samples
+//   arnoldi      the Hessenberg matrix of Arnoldi on A P^{-1} (spectral estimates)
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -274,13 +278,6 @@ static long long ptinv_launch(Problem& P, const double* g, double* lam, const Op
 struct SolveOps {
     std::function<void(const double*, double*)> A;     // out = A v
     std::function<long long(const double*, double*)> M; // out = M v (returns inner iterations)
-};
-
-struct Basis {
-    double* V;
-    double* Z;
-    double* partials;
-    int nblk;
 };
 
 static void ensure_basis(Problem& P, int m) {
