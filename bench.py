@@ -424,6 +424,8 @@ def main():
                    "algorithmic_bytes_fp64": bytes64},
         # traffic: HBM bytes of one FP64 apply_A from the FETCH_SIZE / WRITE_SIZE counter runs, scaled by
         # a copy of known size (profiles/c3_apply_A_hbm_counters.md); to be re-measured when the kernels change
+        # P^-1 (pinv_segment) takes most of the solve time but is a dependent chain of small phases
+        # (latency-bound, reported in p_inv); the roofline object covers the structured matvec
         "roofline": {"kernel": "apply_A (history_matvec + mv_rows_fwd + mv_cols + mv_rows_inv), FP64",
                      "bound": "hbm", "achieved": gbs64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs64 / HBM_PEAK_GBS, "traffic": APPLY_A_TRAFFIC_FP64},
