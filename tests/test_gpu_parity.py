@@ -611,3 +611,21 @@ def test_recover_f_vjp_batch_matches_single_calls():
     finally:
         for g in probs:
             g.close()
+
+
+def test_nonconvergence_reports_enoconv_and_the_last_iterate():
+    """maxit reached: TSFDE_ENOCONV, converged = 0, the iterate's true residual is the reported one
+    and below the starting residual (GMRES minimises it over the Krylov space)."""
+    inp = inputs.small(1, 12, 7)
+    p = workloads.with_data(inp)
+    A = system.dense_A(p)
+    b = system.rhs_z(p)
+    with gpu_problem(inp, p) as g:
+        o = tsfde.default_opts(tol=1e-12, use_precond=0, maxit=3)
+        with pytest.raises(tsfde.TsfdeError) as e:
+            g.gmres_solve(torch.tensor(b, device=DEV), opts=o, raise_noconv=True)
+        assert e.value.status == tsfde.ENOCONV
+        x, st = g.gmres_solve(torch.tensor(b, device=DEV), opts=o)
+        assert st.converged == 0 and st.iters == 3
+        rel = np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b)
+        assert rel == pytest.approx(st.rel_res, rel=1e-6) and rel < 1.0
