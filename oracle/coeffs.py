@@ -227,3 +227,22 @@ def tau_eigenvalues(a: np.ndarray) -> np.ndarray:
     if d == 1:
         return Cm.T @ a
     return Cm.T @ a @ Cm
+
+
+def strang_first_column(a: np.ndarray) -> np.ndarray:
+    """First column of Strang's circulant s(B) of the (multilevel) symmetric Toeplitz matrix with
+    stencil a (§5.1 Remark, the Strang preconditioner): along every level the central diagonals of
+    B are kept and wrapped around the circle, c_l = a_l for 0 <= l <= n//2 and c_l = a_{n-l} for
+    n//2 < l < n.  Shape (n,)*d like a."""
+    n = a.shape[0]
+    l = np.arange(n)
+    f = np.where(l <= n // 2, l, n - l)
+    if a.ndim == 1:
+        return a[f]
+    return a[f[:, None], f[None, :]]
+
+
+def strang_eigenvalues(a: np.ndarray) -> np.ndarray:
+    """Eigenvalues of s(B): the d-dimensional DFT of its first column, index k the frequency of
+    the Fourier vector exp(2 pi i k.j / n) (real because the column is even along every level)."""
+    return np.fft.fftn(strang_first_column(a)).real

@@ -14,6 +14,8 @@ paragraphs), in FP64 NumPy.
   T_solve       y = T_{n,S}^{-1} z (§5.1 Remark, with the frozen-coefficient reading of
                 system.dense_T): the same forward substitution, each block solved exactly
                 by the orthonormal DST-I.
+  S_solve       y = S_{n,S}^{-1} z (§5.1 Remark, Strang blocks under the same reading,
+                system.dense_S): each block solved exactly by the d-dimensional FFT.
 
 The embedding size used here is 2N per direction (the smallest even size
 >= 2N-1); any size >= 2N-1 gives the same product in exact arithmetic.
@@ -231,4 +233,32 @@ def T_solve(p: Problem, z: np.ndarray, last_block: bool = True) -> np.ndarray:
     if last_block:
         r = (Z[S_] - Y[S_ - 1]) / (p.c_f * p.gamma2[S_ - 1])
         Y[S_] = dst(dst(r) / lam).reshape(-1)
+    return Y.reshape(-1)
+
+
+def S_solve(p: Problem, z: np.ndarray, last_block: bool = True) -> np.ndarray:
+    """Forward substitution with the blocks of S_{n,S}: as T_solve, with the block solves
+         s = 1..S:  y^(s) = F^{-1} diag(1/(sigma_s + c_t lambda)) F r
+         s = S+1:   y^(S+1) = F^{-1} diag(1/lambda) F (z^(S+1) - y^(S)) / (c_f gamma2^(S))
+    where F is the d-dimensional DFT and lambda the eigenvalues of Strang's circulant s(B_n)."""
+    S_, Nd = p.S, p.Nd
+    shape = (p.N,) * p.d
+    lam = coeffs.strang_eigenvalues(p.a())
+    sig = tau_sigma(p)
+    e = p.e()
+    Z = z.reshape(-1, Nd)
+    Y = np.zeros((S_ + 1, Nd))
+
+    def solve(r, diag):
+        return np.fft.ifftn(np.fft.fftn(r.reshape(shape)) / diag).real.reshape(-1)
+
+    for s in range(S_):
+        hist = np.zeros(Nd)
+        for m in range(s):
+            hist += e[s - m] * Y[m]
+        r = (Z[s] - p.gamma1[s] * hist) / p.gamma2[s]
+        Y[s] = solve(r, sig[s] + p.c_t * lam)
+    if last_block:
+        r = (Z[S_] - Y[S_ - 1]) / (p.c_f * p.gamma2[S_ - 1])
+        Y[S_] = solve(r, lam)
     return Y.reshape(-1)

@@ -177,6 +177,33 @@ def dense_T(p: Problem) -> np.ndarray:
     return T
 
 
+def dense_strangB(p: Problem) -> np.ndarray:
+    """s(B_n), Strang's circulant (§5.1 Remark): along every level the entry at lag l is
+    c_{l mod n} of coeffs.strang_first_column, i.e. a d-level circulant."""
+    from .coeffs import strang_first_column
+    c = strang_first_column(p.a())
+    N = p.N
+    i = np.arange(N)
+    lag = (i[:, None] - i[None, :]) % N
+    if p.d == 1:
+        return c[lag]
+    return c[lag[:, None, :, None], lag[None, :, None, :]].reshape(N * N, N * N)
+
+
+def dense_S(p: Problem) -> np.ndarray:
+    """S_{n,S} of the §5.1 Remark under the reading of dense_T: P_{n,S} with B_n replaced by
+    s(B_n) and each diagonal block replaced by D_2 (sigma_s I + c_t s(B_n)).  For constant
+    coefficients this is exactly P_{n,S} with every B_n replaced by s(B_n)."""
+    Nd, S = p.Nd, p.S
+    sB = dense_strangB(p)
+    Sm = dense_P(p, sB)
+    sig = tau_sigma(p)
+    I = np.eye(Nd)
+    for s in range(S):
+        Sm[s * Nd:(s + 1) * Nd, s * Nd:(s + 1) * Nd] = p.gamma2[s][:, None] * (sig[s] * I + p.c_t * sB)
+    return Sm
+
+
 def rhs_z(p: Problem) -> np.ndarray:
     """z of eq. lin-syst: z^(s) = b_{s-1} D_1^(s) rho for s = 1..S, z^(S+1) = mu_eps."""
     b = p.b()

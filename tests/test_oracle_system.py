@@ -291,3 +291,61 @@ def test_fgmres_with_T_reaches_the_dense_solution():
     x, its, _ = krylov.fgmres(lambda v: A @ v, lambda v: matfree.T_solve(p, v), b, tol=1e-13, restart=60,
                               maxit=300)
     np.testing.assert_allclose(x, x_lu, rtol=1e-9, atol=1e-10 * np.abs(x_lu).max())
+
+
+@pytest.mark.parametrize("d,N", [(1, 9), (1, 10), (2, 5), (2, 6)])
+def test_dense_strangB_is_a_symmetric_circulant_keeping_the_central_diagonals(d, N):
+    """s(B) is a d-level circulant, symmetric, and equal to B wherever every per-level lag is at
+    most N//2 (Strang's construction), checked entry by entry against dense_B."""
+    p = workloads.problem(inputs.small(d, N, 2))
+    C = system.dense_strangB(p)
+    B = system.dense_B(p)
+    np.testing.assert_allclose(C, C.T, atol=0)
+    idx = np.indices((N,) * d).reshape(d, -1).T  # multi-index of every row, last level fastest
+    for r in range(0, C.shape[0], 3):
+        for c in range(C.shape[1]):
+            lag = np.abs(idx[r] - idx[c])
+            if np.all(lag <= N // 2):
+                assert C[r, c] == B[r, c]
+            shifted = ((idx[r] + 1) % N, (idx[c] + 1) % N)  # one step along every level
+            rr = np.ravel_multi_index(tuple(shifted[0]), (N,) * d)
+            cc = np.ravel_multi_index(tuple(shifted[1]), (N,) * d)
+            assert C[rr, cc] == C[r, c]
+
+
+@pytest.mark.parametrize("d,N", [(1, 9), (1, 10), (2, 6), (2, 7)])
+def test_strang_eigenvalues_match_a_dense_eigensolver(d, N):
+    """The DFT eigenvalues of s(B) against LAPACK's symmetric eigensolver on the assembled matrix."""
+    p = workloads.problem(inputs.small(d, N, 2))
+    lam = np.sort(system.coeffs.strang_eigenvalues(p.a()).reshape(-1))
+    ref = np.linalg.eigvalsh(system.dense_strangB(p))
+    np.testing.assert_allclose(lam, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    assert lam.min() > 0.0  # s(B) of the fractional stencil is SPD
+
+
+def test_dense_S_constant_coefficients_is_P_with_strang():
+    """For constant gamma1, gamma2 the frozen-coefficient S equals P with every B replaced by
+    s(B) — the paper's S_{n,S} exactly."""
+    p = workloads.problem(inputs.small(2, 5, 4))
+    p = dataclasses.replace(p, gamma1=np.full_like(p.gamma1, 1.3), gamma2=np.full_like(p.gamma2, 0.7))
+    np.testing.assert_allclose(system.dense_S(p), system.dense_P(p, system.dense_strangB(p)), atol=1e-13)
+
+
+@pytest.mark.parametrize("d,N,M", [(1, 15, 6), (1, 12, 5), (2, 7, 4), (2, 6, 3)])
+def test_S_solve_matches_dense_S(d, N, M):
+    """Matrix-free S_{n,S}^{-1} (FFT block solves) against LU of the assembled S."""
+    p = workloads.problem(inputs.small(d, N, M))
+    z = np.random.default_rng(4).standard_normal(p.n_tot)
+    np.testing.assert_allclose(matfree.S_solve(p, z), np.linalg.solve(system.dense_S(p), z),
+                               rtol=1e-11, atol=1e-12 * np.abs(z).max())
+
+
+def test_fgmres_with_S_reaches_the_dense_solution():
+    """S_{n,S} as a right preconditioner changes only the path of the Krylov solve."""
+    p = workloads.problem(inputs.small(2, 7, 5))
+    b = system.rhs_z(p)
+    A = system.dense_A(p)
+    x_lu = np.linalg.solve(A, b)
+    x, its, _ = krylov.fgmres(lambda v: A @ v, lambda v: matfree.S_solve(p, v), b, tol=1e-13, restart=60,
+                              maxit=300)
+    np.testing.assert_allclose(x, x_lu, rtol=1e-9, atol=1e-10 * np.abs(x_lu).max())
