@@ -249,6 +249,17 @@ def main():
             tau_forms[name] = {"solves_per_s": a.steps / dtt, "ms_per_solve": 1e3 * dtt / a.steps,
                                "f_rel_err": max(errt), "tol": tolt, "outer_iters": stt[-1]["iters"]}
 
+    # the S_{n,S} form (B replaced by Strang's circulant, blocks solved by Hartley transforms): one
+    # solve at the FP64 T_{n,S} tolerance; it needs about four times the outer iterations
+    strang_form = None
+    if tau_forms:
+        tols = tau_forms["fp64"]["tol"]
+        osg = tsfde.default_opts(tol=tols, maxit=500, block_solver=tsfde.BLOCK_STRANG)
+        dts, errs_s, sts = run(osg, 1)
+        log(f"S_n,S (fp64): tol {tols:g}, 1 solve in {dts:.2f} s, f error {errs_s[0]:.2e}, {sts[-1]['iters']} iterations")
+        strang_form = {"solves_per_s": 1.0 / dts, "ms_per_solve": 1e3 * dts, "f_rel_err": errs_s[0], "tol": tols,
+                       "outer_iters": sts[-1]["iters"]}
+
     # throughput with several instances in flight: the same workload with other source modes and
     # noise, all solved by one tsfde_recover_f_batch call at the tolerance calibrated above
     batched = None
@@ -413,6 +424,8 @@ def main():
         "mixed": mixed,
         # the paper's T_{n,S} (B replaced by its tau matrix; block coefficient ratio frozen at its mean)
         "tau_blocks_preconditioner": tau_forms,
+        # the paper's S_{n,S} (B replaced by Strang's circulant; same frozen-coefficient reading)
+        "strang_blocks_preconditioner": strang_form,
         # independent instances of the workload solved side by side (tsfde_recover_f_batch)
         "batched": batched,
         # 64 independent problems of uneven shapes: even k d = 1, N ~ U[127, 2047]; odd k d = 2,

@@ -79,7 +79,15 @@ typedef struct tsfde_opts {
                             mean, so each block is solved exactly by sine
                             transforms (no inner iterations, no warm start).
                             TSFDE_BLOCK_TAU needs d = 2 and 2(N+1) a power of
-                            two; otherwise the calls return TSFDE_ENOTIMPL
+                            two; otherwise the calls return TSFDE_ENOTIMPL.
+                            TSFDE_BLOCK_STRANG: the S_{n,S} variant of the same
+                            Remark -- B replaced by Strang's circulant (the
+                            central diagonals of B wrapped around, per level),
+                            the ratio frozen as above, each block solved exactly
+                            by real Hartley transforms of any size N (d = 1, 2;
+                            ENOTIMPL if N is too large for the transform passes,
+                            about N > 1200 in 2D, or if that circulant is not
+                            positive definite)
                                                                         (CG)    */
     int warm_start;      /* initial guess of each block CG in P^{-1} from the
                             solution of the previous time levels:
@@ -90,7 +98,7 @@ typedef struct tsfde_opts {
                             always starts from y^(s-1)              (LINEAR) */
 } tsfde_opts;
 
-typedef enum { TSFDE_BLOCK_CG = 0, TSFDE_BLOCK_TAU = 1 } tsfde_block_solver;
+typedef enum { TSFDE_BLOCK_CG = 0, TSFDE_BLOCK_TAU = 1, TSFDE_BLOCK_STRANG = 2 } tsfde_block_solver;
 typedef enum {
     TSFDE_WARM_PREVIOUS = 0,
     TSFDE_WARM_LINEAR = 1,

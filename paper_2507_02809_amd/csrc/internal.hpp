@@ -47,6 +47,7 @@ struct Dev {
 };
 
 constexpr int kMaxRestart = 1000;  // largest FGMRES restart length accepted
+constexpr int kHB = 16;            // time steps per history block of the forward substitution
 constexpr int kArnBlocks = 4096;   // blocks of the Arnoldi sweeps
 constexpr int kEpad = 256;   // leading zeros in epad (covers the history tile overhang)
 constexpr int kMaxPartials = 4096;
@@ -86,6 +87,11 @@ struct Problem {
     double* arn_h = nullptr;     // Arnoldi coefficients, 2 (kMaxRestart + 2) + 1
     double* rwork = nullptr;     // FGMRES residual (n_tot)
     double* adj_u = nullptr;     // adjoint work: gamma2-scaled slices (n_tot)
+    // Strang blocks (S_{n,S}), built on first use: [N] cas table then [Nd] eigenvalues of s(B)
+    double* strang64 = nullptr;
+    float* strang32 = nullptr;
+    double strang_min = 0;       // smallest eigenvalue of s(B)
+    double* strang_hist = nullptr;  // kHB slices: far history of one block of steps (FP64, or FP32 in place)
     void* pw64 = nullptr;           // persistent P^{-1} work buffers (FP64 / FP32)
     void* pw32 = nullptr;
     double* dev_scalars = nullptr;  // small device scratch (dots, flags)
@@ -189,6 +195,20 @@ void set_persistent_blocks(int g);
 constexpr int kMaxInflight = 8;
 void set_shared_launch(bool on);
 bool shared_launch();
-void set_persistent_fixed_length(bool on);  // use the fixed-length 2D sine-transform kernels where available
+void set_persistent_fixed_length(bool on);
+
+// S_{n,S} (strang.hip): the cas table and eigenvalues of Strang's circulant (setup.hip; returns the
+// smallest eigenvalue); whether the Hartley passes fit the LDS; the tables on the device (first
+// use); y = S^{-1} z by forward substitution with one exact circulant solve per block
+double strang_tables(const Problem& P, std::vector<double>& cas, std::vector<double>& lam);
+bool strang_supported(const Problem& P);
+void ensure_strang(Problem& P);
+template <typename T>
+void pinv_strang(Problem& P, const Dev<T>& D, const T* z, T* y, bool last_block, hipStream_t st);
+// w[i] = (z_s - gamma1_s sum_{m < sa} e_{s-m} y_m) / gamma2_s for s = sa + i, i < cnt <= kHB
+// (pinv_persistent.hip; the far part of the history, shared with the persistent P^-1)
+template <typename T>
+void launch_far_history(const Problem& P, const Dev<T>& D, const T* y, T* w, const T* z, int sa, int cnt,
+                        hipStream_t st);  // use the fixed-length 2D sine-transform kernels where available
 
 }  // namespace tsfde

@@ -43,7 +43,6 @@
 
 namespace tsfde {
 
-constexpr int kHB = 16;    // steps per segment (history block)
 static_assert(kHB <= 64, "the weight table e carries 64 trailing zeros for the history tiles");
 constexpr int kNPart = 6;  // reduction slots per workgroup
 // (r,r) (rhs,rhs) (r,z) (p,q) (p,dg p) (p,B p)

@@ -87,6 +87,15 @@ void pinv_persistent_free(void* wptr) {
 }
 
 static thread_local bool t_shared_launch = false;
+template <typename T>
+void launch_far_history(const Problem& P, const Dev<T>& D, const T* y, T* w, const T* z, int sa, int cnt,
+                        hipStream_t st) {
+    if (cnt < 1 || cnt > kHB || sa + cnt > P.M) throw HipError{hipErrorInvalidValue, "far_history step range"};
+    hipLaunchKernelGGL(far_history<T>, dim3((unsigned)((P.Nd + 63) / 64)), dim3(256), 0, st, y, w, D.epad, z,
+                       D.gamma1, D.gamma2, sa, cnt, P.Nd);
+    TSFDE_HIP(hipGetLastError());
+}
+
 void set_shared_launch(bool on) { t_shared_launch = on; }
 bool shared_launch() { return t_shared_launch; }
 
@@ -99,6 +108,10 @@ template long long pinv_persistent_run<double>(Problem&, const Dev<double>&, voi
                                                int, bool, int, int, hipStream_t);
 template long long pinv_persistent_run<float>(Problem&, const Dev<float>&, void*&, const float*, float*, double, int,
                                               bool, int, int, hipStream_t);
+template void launch_far_history<double>(const Problem&, const Dev<double>&, const double*, double*, const double*, int,
+                                         int, hipStream_t);
+template void launch_far_history<float>(const Problem&, const Dev<float>&, const float*, float*, const float*, int, int,
+                                        hipStream_t);
 template void pinv_persistent_free<double>(void*);
 template void pinv_persistent_free<float>(void*);
 

@@ -228,6 +228,49 @@ static std::vector<double> tau_eigs(int d, int N, const std::vector<double>& a) 
     return t;
 }
 
+// Strang's circulant s(B) (§5.1 Remark): first column c_l = a_{f(l)} per level with f(l) = l for
+// l <= N/2 and N - l above (the central diagonals wrapped around).  cas[m] = cos + sin of 2 pi m/N,
+// lam[k1][k2] = sum_l c[l1][l2] cos(2 pi l1 k1/N) cos(2 pi l2 k2/N), its eigenvalues in the Hartley
+// basis (1D: lam[k]); returns the smallest eigenvalue.  The sums cancel heavily at the smallest
+// eigenvalues (the stencil's entries nearly sum to zero), so they are accumulated in long double.
+double strang_tables(const Problem& P, std::vector<double>& cas, std::vector<double>& lam) {
+    const int N = P.N;
+    std::vector<long double> ct(N);
+    for (int m = 0; m < N; ++m) ct[m] = std::cos(2.0L * (long double)M_PI * (long double)m / (long double)N);
+    cas.resize(N);
+    for (int m = 0; m < N; ++m) cas[m] = std::cos(2.0 * M_PI * m / N) + std::sin(2.0 * M_PI * m / N);
+    auto f = [N](int l) { return l <= N / 2 ? l : N - l; };
+    auto cosk = [&](long long l, long long k) { return ct[(l * k) % N]; };
+    const std::vector<double>& a = P.stencil;
+    if (P.d == 1) {
+        lam.assign(N, 0.0);
+        for (int k = 0; k < N; ++k) {
+            long double acc = 0.0L;
+            for (int l = 0; l < N; ++l) acc += (long double)a[f(l)] * cosk(l, k);
+            lam[k] = (double)acc;
+        }
+    } else {
+        std::vector<long double> G((size_t)N * N);  // G[l1][k2]
+        parallel_for(N, [&](long long l1) {
+            const double* row = a.data() + (size_t)f((int)l1) * N;
+            for (int k2 = 0; k2 < N; ++k2) {
+                long double acc = 0.0L;
+                for (int l2 = 0; l2 < N; ++l2) acc += (long double)row[f(l2)] * cosk(l2, k2);
+                G[(size_t)l1 * N + k2] = acc;
+            }
+        });
+        lam.assign((size_t)N * N, 0.0);
+        parallel_for(N, [&](long long k1) {
+            for (int k2 = 0; k2 < N; ++k2) {
+                long double acc = 0.0L;
+                for (int l1 = 0; l1 < N; ++l1) acc += cosk(l1, k1) * G[(size_t)l1 * N + k2];
+                lam[(size_t)k1 * N + k2] = (double)acc;
+            }
+        });
+    }
+    return *std::min_element(lam.begin(), lam.end());
+}
+
 static std::vector<double> twiddles(int L) {
     std::vector<double> t(2 * (size_t)L);
     for (int m = 0; m < L; ++m) {
@@ -296,7 +339,7 @@ void free_problem(Problem* P) {
     pinv_persistent_free<double>(P->pw64);
     pinv_persistent_free<float>(P->pw32);
     void* ptrs[] = {P->d_bw, P->d_rho, P->d_mu, P->z_rhs, P->xbuf, P->V, P->Z, P->arn_part, P->arn_h, P->rwork, P->adj_u,
-                    P->dev_scalars};
+                    P->dev_scalars, P->strang64, P->strang32, P->strang_hist};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (P->host_scalars) (void)hipHostFree(P->host_scalars);

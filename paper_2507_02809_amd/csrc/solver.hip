@@ -89,7 +89,7 @@ static bool check_opts(const Opts& o) {
         set_error("opts.warm_start invalid");
         return false;
     }
-    if (o.block_solver != TSFDE_BLOCK_CG && o.block_solver != TSFDE_BLOCK_TAU) {
+    if (o.block_solver != TSFDE_BLOCK_CG && o.block_solver != TSFDE_BLOCK_TAU && o.block_solver != TSFDE_BLOCK_STRANG) {
         set_error("opts.block_solver invalid");
         return false;
     }
@@ -121,9 +121,29 @@ static int env_int(const char* name, int dflt) {
     return (e && *e) ? std::atoi(e) : dflt;
 }
 
-// the tau-block form runs on the persistent 2D sine-transform path only
-static bool block_solver_supported(const Problem& P, const Opts& o) {
-    if (o.block_solver != TSFDE_BLOCK_TAU || !o.use_precond) return true;
+// the tau-block form runs on the persistent 2D sine-transform path only; the Strang form needs its
+// Hartley passes to fit the LDS and Strang's circulant of the stencil to be positive definite (its
+// tables are built here on first use)
+static bool block_solver_supported(Problem& P, const Opts& o) {
+    if (!o.use_precond || o.block_solver == TSFDE_BLOCK_CG) return true;
+    if (o.block_solver == TSFDE_BLOCK_STRANG) {
+        if (!strang_supported(P)) {
+            set_error("opts.block_solver = TSFDE_BLOCK_STRANG: N = %d is too large for the transform passes", P.N);
+            return false;
+        }
+        try {
+            ensure_strang(P);
+        } catch (const HipError& e) {
+            set_error("opts.block_solver = TSFDE_BLOCK_STRANG: %s failed: %s", e.where.c_str(), hipGetErrorString(e.code));
+            return false;
+        }
+        if (!(P.strang_min > 0.0)) {
+            set_error("opts.block_solver = TSFDE_BLOCK_STRANG: Strang's circulant of the stencil is not positive "
+                      "definite (smallest eigenvalue %g)", P.strang_min);
+            return false;
+        }
+        return true;
+    }
     if (P.d == 2 && P.tau_ok && persistent_supported(P) && env_int("TSFDE_PINV", 1) != 0) return true;
     set_error("opts.block_solver = TSFDE_BLOCK_TAU needs d = 2 with 2(N+1) a power of two");
     return false;
@@ -146,6 +166,10 @@ static long long pinv_impl(Problem& P, const T* z, T* y, const Opts& o, hipStrea
     // TSFDE_PINV=0 selects the multi-launch path; TSFDE_PINV_BLOCKS overrides the grid size;
     // TSFDE_PINV_FIXED=0 keeps the 2D sine-transform path on its run-time-length kernel;
     // TSFDE_EXTRAP overrides opts.warm_start (the block CG's initial guess)
+    if (o.block_solver == TSFDE_BLOCK_STRANG) {
+        pinv_strang<T>(P, dev<T>(P), z, y, last_block, st);
+        return 0;
+    }
     if (env_int("TSFDE_PINV", 1) != 0 && persistent_supported(P)) {
         set_persistent_blocks(env_int("TSFDE_PINV_BLOCKS", -1));
         set_persistent_fixed_length(env_int("TSFDE_PINV_FIXED", 1) != 0);

@@ -1,0 +1,238 @@
+// S_{n,S} of the §5.1 Remark: the forward substitution of P with every B replaced by Strang's
+// circulant s(B) (per level, the central diagonals of B wrapped around the circle) and the
+// coefficient ratio of each diagonal block frozen at its slice mean sigma_s, the reading under
+// which T_{n,S} is built as well:
+//   s < M:  (sigma_s I + c_t s(B)) y_s = (z_s - gamma1_s sum_{m<s} e_{s-m} y_m) / gamma2_s
+//   s = M:  s(B) y_M = (z_M - y_{M-1}) / (c_f gamma2_{M-1}).
+//
+// A d-level symmetric circulant whose first column c is even along every level is diagonalised by
+// the real Hartley transform of size N per level: with H[j][k] = cas(2 pi j k / N), cas = cos + sin,
+// H H = N I and
+//   s(B) = (H x H) diag(lambda) (H x H) / N^d,
+//   lambda[k1][k2] = sum_{l1,l2} c[l1][l2] cos(2 pi l1 k1 / N) cos(2 pi l2 k2 / N)
+// (the cos-sin cross terms cancel by the evenness of c), so every block is solved exactly by two
+// transforms around a diagonal scaling, with no inner iterations.  N is arbitrary (it need not give
+// a power-of-two FFT), so each level's transform is a dense pass: N multiply-adds per output, the
+// cas table (N values, index j k mod N) and the workgroup's input rows held in LDS.  Every pass
+// transforms the fast index of its input and writes its output transposed, so the 2D solve is four
+// passes of one kernel and returns to the slice layout [i1][i2].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace tsfde {
+
+constexpr int kCasK = 64;      // outputs per workgroup along the transformed index (one per lane)
+constexpr int kCasRows = 4;    // rows per workgroup, one per wave
+constexpr int kCasU = 8;       // unrolled steps of the inner sum
+constexpr int kLdsBytes = 160 * 1024;
+
+// Where the first pass of a block solve takes its right-hand side from:
+//   NEAR: x = w[j] - dg_s[j] sum_{sa <= m < s} e_{s-m} y_m[j], w the far-history slice of step s
+//         (dg = e_0 gamma1 / gamma2 with e_0 = 1), i.e. (z_s - gamma1_s sum_{m<s} e_{s-m} y_m) / gamma2_s;
+//   LAST: x = (z_M - y_{M-1}) / (c_f gamma2_{M-1});
+//   otherwise x = in[j] (scaled by the eigenvalue factor when lam is given).
+enum CasSrc : int { SRC_IN = 0, SRC_NEAR = 1, SRC_LAST = 2 };
+template <typename T>
+struct RhsArgs {
+    int mode = SRC_IN;
+    int sa = 0, s = 0;
+    const T* dg = nullptr;  // dg_s (NEAR); gamma2_{M-1} (LAST)
+    const T* y = nullptr;   // the solution so far
+    const T* e = nullptr;   // e_0.. (offset into the zero-padded weight table)
+    const T* z = nullptr;   // z_M (LAST)
+    T cf = T(1);
+    long long Nd = 0;
+};
+
+template <typename T>
+__device__ __forceinline__ T rhs_value(const RhsArgs<T>& ra, const T* __restrict__ in, long long g) {
+    if (ra.mode == SRC_NEAR) {
+        T h = T(0);
+        // at most kHB - 1 near terms; their loads are independent and issued together
+#pragma unroll
+        for (int t = 1; t < kHB; ++t) {
+            const int m = ra.s - t;
+            if (m >= ra.sa) h += ra.e[t] * ra.y[(long long)m * ra.Nd + g];
+        }
+        return in[g] - ra.dg[g] * h;
+    }
+    if (ra.mode == SRC_LAST) return (ra.z[g] - ra.y[(long long)(ra.s - 1) * ra.Nd + g]) / (ra.cf * ra.dg[g]);
+    return in[g];
+}
+
+// out[k][r] = sum_j x[r][j] cas[(j k) mod N] for r < nrow, k < N, with x[r][j] the right-hand side
+// value of point r N + j (rhs_value) times (lam ? scale / (sigma + c lam[r][j]) : 1).
+template <typename T>
+__global__ __launch_bounds__(256) void cas_pass(const T* __restrict__ in, T* __restrict__ out,
+                                                const T* __restrict__ cas, const T* __restrict__ lam, T sigma,
+                                                T c, T scale, int N, int nrow, RhsArgs<T> ra) {
+    extern __shared__ double cas_lds_raw[];
+    T* ct = reinterpret_cast<T*>(cas_lds_raw);  // [N]
+    T* xs = ct + N;                              // [nr][N]
+    const int r0 = blockIdx.y * kCasRows;
+    const int nr = min(kCasRows, nrow - r0);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) ct[i] = cas[i];
+    const long long base = (long long)r0 * N;
+    for (int i = threadIdx.x; i < nr * N; i += blockDim.x) {
+        T v = rhs_value(ra, in, base + i);
+        if (lam) v *= scale / (sigma + c * lam[base + i]);
+        xs[i] = v;
+    }
+    __syncthreads();
+    const int k = blockIdx.x * kCasK + (threadIdx.x & (kCasK - 1));
+    const int r = threadIdx.x / kCasK;  // one row per wave
+    if (k >= N || r >= nr) return;
+    const T* x = xs + r * N;
+    // the j loop in chunks of kCasU: the chunk's table indices (j k mod N) come from a short VALU
+    // chain, so its LDS reads are independent and in flight together, and kCasU partial sums break
+    // the multiply-add dependence
+    T acc[kCasU];
+#pragma unroll
+    for (int u = 0; u < kCasU; ++u) acc[u] = T(0);
+    int idx = 0;  // j k mod N
+    int j = 0;
+    for (; j + kCasU <= N; j += kCasU) {
+        int id[kCasU];
+        id[0] = idx;
+#pragma unroll
+        for (int u = 1; u < kCasU; ++u) {
+            const int t = id[u - 1] + k;
+            id[u] = t >= N ? t - N : t;
+        }
+        T cv[kCasU], xv[kCasU];
+#pragma unroll
+        for (int u = 0; u < kCasU; ++u) {
+            cv[u] = ct[id[u]];
+            xv[u] = x[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < kCasU; ++u) acc[u] += xv[u] * cv[u];
+        const int t = id[kCasU - 1] + k;
+        idx = t >= N ? t - N : t;
+    }
+    for (; j < N; ++j) {
+        acc[0] += x[j] * ct[idx];
+        idx += k;
+        if (idx >= N) idx -= N;
+    }
+    T sum = T(0);
+#pragma unroll
+    for (int u = 0; u < kCasU; ++u) sum += acc[u];
+    out[(long long)k * nrow + r0 + r] = sum;
+}
+
+static size_t cas_lds_bytes(int N, int nrow, size_t elem) {
+    return (size_t)(1 + std::min(kCasRows, nrow)) * N * elem;
+}
+
+bool strang_supported(const Problem& P) {
+    const int nrow = P.d == 2 ? P.N : 1;
+    return cas_lds_bytes(P.N, nrow, sizeof(double)) <= (size_t)kLdsBytes;
+}
+
+template <typename T>
+static void cas_launch(const T* in, T* out, const T* cas, const T* lam, T sigma, T c, T scale, int N, int nrow,
+                       hipStream_t st, const RhsArgs<T>& ra = RhsArgs<T>()) {
+    const dim3 grid((unsigned)((N + kCasK - 1) / kCasK), (unsigned)((nrow + kCasRows - 1) / kCasRows));
+    const size_t lds = cas_lds_bytes(N, nrow, sizeof(T));
+    hipLaunchKernelGGL(cas_pass<T>, grid, dim3(256), lds, st, in, out, cas, lam, sigma, c, scale, N, nrow, ra);
+    TSFDE_HIP(hipGetLastError());
+}
+
+template <typename T>
+static T* strang_table(Problem& P);
+template <>
+double* strang_table<double>(Problem& P) { return P.strang64; }
+template <>
+float* strang_table<float>(Problem& P) { return P.strang32; }
+
+// The cas table and the eigenvalues of s(B), computed on first use: [N] cas(2 pi m / N), then
+// [Nd] lambda (2D: [k1][k2], k2 the frequency of the fast index).
+void ensure_strang(Problem& P) {
+    if (P.strang64) return;
+    std::vector<double> cas, lam;
+    const double lmin = strang_tables(P, cas, lam);
+    std::vector<double> t(cas);
+    t.insert(t.end(), lam.begin(), lam.end());
+    std::vector<float> t32(t.begin(), t.end());
+    double* d64 = nullptr;
+    float* d32 = nullptr;
+    TSFDE_HIP(hipMalloc(&d64, sizeof(double) * t.size()));
+    if (hipMalloc(&d32, sizeof(float) * t32.size()) != hipSuccess) {
+        (void)hipFree(d64);
+        throw HipError{hipErrorOutOfMemory, "hipMalloc(strang32)"};
+    }
+    TSFDE_HIP(hipMemcpy(d64, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice));
+    TSFDE_HIP(hipMemcpy(d32, t32.data(), sizeof(float) * t32.size(), hipMemcpyHostToDevice));
+    double* hist = nullptr;
+    if (hipMalloc(&hist, sizeof(double) * (size_t)kHB * P.Nd) != hipSuccess) {
+        (void)hipFree(d64);
+        (void)hipFree(d32);
+        throw HipError{hipErrorOutOfMemory, "hipMalloc(strang_hist)"};
+    }
+    P.strang64 = d64;
+    P.strang32 = d32;
+    P.strang_hist = hist;
+    P.strang_min = lmin;
+    P.bytes += (sizeof(double) + sizeof(float)) * t.size() + sizeof(double) * (size_t)kHB * P.Nd;
+}
+
+// The steps run in blocks of kHB: one bandwidth-bound kernel folds the history of all earlier blocks
+// into the block's right-hand sides, and each step's first transform pass adds the (< kHB) near terms
+// while loading its rows.
+template <typename T>
+void pinv_strang(Problem& P, const Dev<T>& D, const T* z, T* y, bool last_block, hipStream_t st) {
+    ensure_strang(P);
+    const T* cas = strang_table<T>(P);
+    const T* lam = cas + P.N;
+    const long long Nd = P.Nd;
+    const int N = P.N;
+    const int nrow = P.d == 2 ? N : 1;
+    T* t1 = D.pcg + 5 * Nd;
+    T* t2 = D.pcg + 6 * Nd;
+    T* hist = reinterpret_cast<T*>(P.strang_hist);
+    const T inv = T(1.0 / (double)Nd);  // (H x H)^2 = N^d I
+    const int last = last_block ? P.M : P.M - 1;
+    for (int sa = 0; sa <= last; sa += kHB) {
+        const int cnt = std::min(kHB, P.M - sa);
+        if (cnt > 0) launch_far_history<T>(P, D, y, hist, z, sa, cnt, st);
+        for (int s = sa; s <= std::min(sa + kHB - 1, last); ++s) {
+            RhsArgs<T> ra;
+            ra.sa = sa;
+            ra.s = s;
+            ra.y = y;
+            ra.e = D.epad + kEpad;
+            ra.Nd = Nd;
+            const T* in = nullptr;
+            if (s < P.M) {
+                ra.mode = SRC_NEAR;
+                ra.dg = D.dg + (long long)s * Nd;
+                in = hist + (long long)(s - sa) * Nd;
+            } else {
+                ra.mode = SRC_LAST;
+                ra.dg = D.gamma2 + (long long)(P.M - 1) * Nd;
+                ra.z = z + (long long)P.M * Nd;
+                ra.cf = T(P.cf);
+            }
+            const T sigma = (s < P.M) ? T(P.sigma[s]) : T(0);
+            const T c = (s < P.M) ? T(P.ct) : T(1);
+            T* ys = y + (long long)s * Nd;
+            cas_launch<T>(in, t1, cas, nullptr, T(0), T(0), T(1), N, nrow, st, ra);  // [i1][i2] -> [k2][i1]
+            if (P.d == 1) {
+                cas_launch<T>(t1, ys, cas, lam, sigma, c, inv, N, 1, st);
+            } else {
+                cas_launch<T>(t1, t2, cas, nullptr, T(0), T(0), T(1), N, N, st);  // -> [k1][k2]
+                cas_launch<T>(t2, t1, cas, lam, sigma, c, inv, N, N, st);         // scaled, -> [m2][k1]
+                cas_launch<T>(t1, ys, cas, nullptr, T(0), T(0), T(1), N, N, st);  // -> [m1][m2]
+            }
+        }
+    }
+}
+
+template void pinv_strang<double>(Problem&, const Dev<double>&, const double*, double*, bool, hipStream_t);
+template void pinv_strang<float>(Problem&, const Dev<float>&, const float*, float*, bool, hipStream_t);
+
+}  // namespace tsfde

@@ -14,7 +14,7 @@ _lib = None
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ENONFINITE, ENOTIMPL = range(7)
 FP64, MIXED, PREC_F32 = 0, 1, 2
-BLOCK_CG, BLOCK_TAU = 0, 1
+BLOCK_CG, BLOCK_TAU, BLOCK_STRANG = 0, 1, 2
 WARM_PREVIOUS, WARM_LINEAR, WARM_QUADRATIC, WARM_HALF = 0, 1, 2, 3
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOCONV", 5: "ENONFINITE", 6: "ENOTIMPL"}
 

@@ -309,6 +309,73 @@ def test_apply_P_inv_tau_blocks_n127_matches_oracle(monkeypatch, fixed):
     assert rel_err(y.cpu().numpy(), ref) <= 1e-12
 
 
+# ---------------------------------------------------------------------------
+# S_{n,S}: the Strang-block form of the preconditioner (opts.block_solver = BLOCK_STRANG)
+# ---------------------------------------------------------------------------
+def test_apply_P_inv_strang_blocks_matches_dense_S(dense_case):
+    """y = S^{-1} z (each block solved by Hartley transforms) against LU of the assembled S, in
+    FP64 and FP32; every shape (any N, d = 1, 2) is covered."""
+    inp, p, _, _ = dense_case
+    rng = np.random.default_rng(23)
+    zz = rng.standard_normal(p.n_tot)
+    o = tsfde.default_opts(block_solver=tsfde.BLOCK_STRANG)
+    with gpu_problem(inp, p) as g:
+        y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=o).cpu().numpy()
+        y32 = g.apply_P_inv(torch.tensor(zz, device=DEV, dtype=torch.float32), opts=o).cpu().double().numpy()
+    ref = np.linalg.solve(system.dense_S(p), zz)
+    assert rel_err(y, ref) <= 1e-12
+    assert rel_err(y32, ref) <= 1e-5
+
+
+def test_gmres_strang_blocks_reaches_dense_lu(dense_case):
+    """FGMRES preconditioned by S reaches the same solution as dense LU of A, with no inner
+    iterations; also with S^{-1} applied in FP32."""
+    inp, p, A, _ = dense_case
+    x_lu = np.linalg.solve(A, system.rhs_z(p))
+    with gpu_problem(inp, p) as g:
+        f, st = g.recover_f(tsfde.default_opts(tol=3e-13, block_solver=tsfde.BLOCK_STRANG), raise_noconv=True)
+        assert st.converged == 1 and st.inner_iters == 0
+        fp, sp = g.recover_f(tsfde.default_opts(tol=3e-13, block_solver=tsfde.BLOCK_STRANG,
+                                                precision=tsfde.PREC_F32), raise_noconv=True)
+        assert sp.converged == 1
+    assert rel_err(f.cpu().numpy(), x_lu[p.S * p.Nd:]) <= 1e-10
+    assert rel_err(fp.cpu().numpy(), x_lu[p.S * p.Nd:]) <= 1e-10
+
+
+@pytest.mark.parametrize("d,N,M", [(1, 700, 5), (2, 100, 4), (2, 255, 3)])
+def test_apply_P_inv_strang_blocks_matches_oracle(d, N, M):
+    """Several transform tiles with ragged tails (64 outputs and 4 rows per workgroup, sums unrolled by 8), up to the
+    255 x 255 slices of the headline workload, against the oracle's FFT forward substitution.
+
+    Bound: the smallest eigenvalues of s(B) come from sums that cancel down to lambda_max / cond;
+    the oracle's FFT gets them to about eps log2(N^d) lambda_max absolute, i.e. eps log2(N^d) cond
+    relative, and the solve's dominant components inherit that (the library sums in extended
+    precision).  8 eps log2(N^d) cond, at least 1e-12."""
+    inp = inputs.small(d, N, M, beta=0.6, omega=1.7)
+    p = workloads.problem(inp, mu=np.zeros(inp.Nd))
+    zz = np.random.default_rng(29).standard_normal(p.n_tot)
+    ref = matfree.S_solve(p, zz)
+    lam = system.coeffs.strang_eigenvalues(p.a())
+    tol = max(1e-12, 8 * np.finfo(float).eps * np.log2(p.Nd) * lam.max() / lam.min())
+    with gpu_problem(inp, p) as g:
+        y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=tsfde.default_opts(block_solver=tsfde.BLOCK_STRANG))
+    assert rel_err(y.cpu().numpy(), ref) <= tol
+
+
+def test_strang_blocks_reject_an_indefinite_circulant():
+    """A stencil whose Strang circulant is not positive definite is refused with ENOTIMPL before
+    anything is launched (its block solves would divide by a zero or negative eigenvalue)."""
+    inp = inputs.small(1, 9, 3)
+    p = workloads.problem(inp, mu=np.zeros(inp.Nd))
+    bad = p.a().copy()
+    bad[1:] = -bad[0]  # row sums far below zero
+    zz = np.ones(p.n_tot)
+    with tsfde.Problem.from_inputs(inp, mu=p.mu, stencil=bad) as g:
+        with pytest.raises(tsfde.TsfdeError) as ei:
+            g.apply_P_inv(torch.tensor(zz, device=DEV), opts=tsfde.default_opts(block_solver=tsfde.BLOCK_STRANG))
+        assert ei.value.status == tsfde.ENOTIMPL
+
+
 BATCH_CASES = [
     lambda: inputs.small(1, 12, 7),
     lambda: inputs.small(2, 7, 9, beta=0.3, omega=1.2),
