@@ -85,9 +85,8 @@ typedef struct tsfde_opts {
                             central diagonals of B wrapped around, per level),
                             the ratio frozen as above, each block solved exactly
                             by real Hartley transforms of any size N (d = 1, 2;
-                            ENOTIMPL if N is too large for the transform passes,
-                            about N > 1200 in 2D, or if that circulant is not
-                            positive definite)
+                            ENOTIMPL if that circulant is not positive definite,
+                            which a user-supplied stencil can cause)
                                                                         (CG)    */
     int warm_start;      /* initial guess of each block CG in P^{-1} from the
                             solution of the previous time levels:

@@ -409,6 +409,28 @@ def test_recover_f_batch_matches_single_solves_and_dense_lu(inflight):
             g.close()
 
 
+def test_recover_f_batch_strang_blocks_matches_single_solves():
+    """S_{n,S}-preconditioned solves in a batch (worker streams, 3 in flight) give bit for bit the
+    single-call results, and each f~ matches the oracle's dense LU."""
+    cases = [mk() for mk in BATCH_CASES]
+    opts = tsfde.default_opts(tol=1e-11, maxit=400, block_solver=tsfde.BLOCK_STRANG)
+    probs, refs = [], []
+    try:
+        for inp in cases:
+            p = workloads.with_data(inp)
+            probs.append(gpu_problem(inp, p))
+            refs.append(np.linalg.solve(system.dense_A(p), system.rhs_z(p))[p.S * p.Nd:])
+        single = [g.recover_f(opts, raise_noconv=True) for g in probs]
+        out = tsfde.recover_f_batch(probs, opts, max_inflight=3, raise_noconv=True)
+        for (f1, s1), (fb, sb), f_lu in zip(single, out, refs):
+            assert sb.converged == 1 and sb.iters == s1.iters and sb.inner_iters == 0
+            assert np.array_equal(fb.cpu().numpy(), f1.cpu().numpy())
+            assert rel_err(fb.cpu().numpy(), f_lu) <= 1e-8
+    finally:
+        for g in probs:
+            g.close()
+
+
 def test_recover_f_batch_rejects_bad_batches():
     inp = inputs.small(1, 12, 7)
     p = workloads.with_data(inp)
