@@ -362,6 +362,19 @@ def test_apply_P_inv_strang_blocks_matches_oracle(d, N, M):
     assert rel_err(y.cpu().numpy(), ref) <= tol
 
 
+@pytest.mark.parametrize("d,N,M", [(1, 1, 3), (2, 1, 2), (1, 2, 4), (2, 2, 3), (2, 9, 1)])
+def test_apply_P_inv_strang_blocks_degenerate_shapes(d, N, M):
+    """One or two points per direction (a single-entry circulant, a 2 x 2 one) and a single time
+    level, against LU of the assembled S."""
+    inp = inputs.small(d, N, M)
+    p = workloads.problem(inp, mu=np.zeros(inp.Nd))
+    zz = np.random.default_rng(31).standard_normal(p.n_tot)
+    ref = np.linalg.solve(system.dense_S(p), zz)
+    with gpu_problem(inp, p) as g:
+        y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=tsfde.default_opts(block_solver=tsfde.BLOCK_STRANG))
+    assert rel_err(y.cpu().numpy(), ref) <= 1e-12
+
+
 def test_strang_blocks_reject_an_indefinite_circulant():
     """A stencil whose Strang circulant is not positive definite is refused with ENOTIMPL before
     anything is launched (its block solves would divide by a zero or negative eigenvalue)."""
