@@ -253,6 +253,24 @@ def test_apply_P_inv_full_size_c3_residual():
         assert abs(py - zz[s * p.Nd + j]) <= 1e-8 * np.abs(zz).max(), (s, j)
 
 
+def test_gmres_full_size_c3_true_residual():
+    """The headline solve at full size (d=2, N=255^2, M=256) in the benchmark's configuration
+    (FGMRES(50), tol 1e-7, block CG to 0.1 from the previous time level), checked through the
+    oracle: its FFT matvec gives the true relative residual ||z - A x|| / ||z||, which must meet
+    the tolerance and agree with the library's own FP64 figure."""
+    inp = inputs.c3()
+    p = workloads.problem(inp, mu=1e-3 * np.asarray(inp.f_true))
+    opts = tsfde.default_opts(tol=1e-7, inner_tol=0.1, maxit=300, warm_start=tsfde.WARM_PREVIOUS)
+    with gpu_problem(inp, p) as g:
+        x, st = g.gmres_solve(opts=opts, raise_noconv=True)
+        x = x.cpu().numpy()
+    z = system.rhs_z(p)
+    res = float(np.linalg.norm(z - matfree.matvec(p, x)) / np.linalg.norm(z))
+    assert st.converged == 1
+    assert res <= 1.05e-7
+    assert abs(res - st.rel_res) <= 1e-3 * res
+
+
 # ---------------------------------------------------------------------------
 # T_{n,S}: the tau-block form of the preconditioner (opts.block_solver = BLOCK_TAU)
 # ---------------------------------------------------------------------------
