@@ -253,12 +253,14 @@ def test_apply_P_inv_full_size_c3_residual():
         assert abs(py - zz[s * p.Nd + j]) <= 1e-8 * np.abs(zz).max(), (s, j)
 
 
-def test_gmres_full_size_c3_true_residual():
-    """The headline solve at full size (d=2, N=255^2, M=256) in the benchmark's configuration
-    (FGMRES(50), tol 1e-7, block CG to 0.1 from the previous time level), checked through the
-    oracle: its FFT matvec gives the true relative residual ||z - A x|| / ||z||, which must meet
-    the tolerance and agree with the library's own FP64 figure."""
-    inp = inputs.c3()
+@pytest.mark.parametrize("which", ["c3", "c2a"])
+def test_gmres_full_size_true_residual(which):
+    """Solves at full size (c3: the headline d=2, N=255^2, M=256; c2a: d=1, N=4095, M=1024) in the
+    benchmark's configuration (FGMRES(50), tol 1e-7, block CG to 0.1 from the previous time
+    level), checked through the oracle: its FFT matvec gives the true relative residual
+    ||z - A x|| / ||z||, which must meet the tolerance and agree with the library's own FP64
+    figure."""
+    inp = inputs.c3() if which == "c3" else inputs.c2(0)
     p = workloads.problem(inp, mu=1e-3 * np.asarray(inp.f_true))
     opts = tsfde.default_opts(tol=1e-7, inner_tol=0.1, maxit=300, warm_start=tsfde.WARM_PREVIOUS)
     with gpu_problem(inp, p) as g:
