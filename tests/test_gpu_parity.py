@@ -593,6 +593,41 @@ def test_apply_AT_full_size_c3_adjoint_identity():
         assert abs(lhs - rhs) <= 1e-12 * float(ax.norm() * w.norm())
 
 
+def test_vjp_full_size_c5_through_the_oracle():
+    """The gradient workload at full size (d = 2, N = 127, M = 128), checked with the oracle's FFT
+    matvec.  With r_lam = A^T lam - g and r_x = A x - z the two solves' residuals (g = R^T gf,
+    z = R^T mu since rho = 0):
+      <lam, A y> - <g, y> = <r_lam, y>                                   (random y)
+      <g, x> - <lam, z>   = <lam, r_x> - <r_lam, x>,  <g, x> = gf . f~,  <lam, z> = grad_mu . mu
+    so both gaps are bounded by the solve tolerance times the norms involved (plus rounding of the
+    inner products, 64 eps times the same norms)."""
+    inp = inputs.c5()
+    mu = 1e-3 * np.asarray(inp.f_true)
+    p = workloads.problem(inp, mu=mu)
+    assert not np.any(p.rho)
+    rng = np.random.default_rng(35)
+    gf = rng.standard_normal(p.Nd)
+    gvec = np.zeros(p.n_tot)
+    gvec[p.S * p.Nd:] = gf
+    tol = 1e-11
+    eps = np.finfo(float).eps
+    o = tsfde.default_opts(tol=tol, maxit=400)
+    with gpu_problem(inp, p) as g:
+        lam, st = g.adjoint_solve(torch.tensor(gvec, device=DEV), opts=o, raise_noconv=True)
+        x, sx = g.gmres_solve(opts=o, raise_noconv=True)
+        gmu, _, sv = g.recover_f_vjp(x, torch.tensor(gf, device=DEV), opts=o, raise_noconv=True)
+        lam, x, gmu = lam.cpu().numpy(), x.cpu().numpy(), gmu.cpu().numpy()
+    assert rel_err(gmu, lam[p.S * p.Nd:]) <= 1e-8  # the VJP's adjoint is this adjoint solve
+    ng, nl, nx, nz = (np.linalg.norm(v) for v in (gvec, lam, x, mu))
+    for _ in range(2):
+        y = rng.standard_normal(p.n_tot)
+        ay = matfree.matvec(p, y)
+        gap = float(lam @ ay - gvec @ y)
+        assert abs(gap) <= 2 * tol * ng * np.linalg.norm(y) + 64 * eps * (nl * np.linalg.norm(ay) + ng * np.linalg.norm(y))
+    lhs, rhs = float(gf @ x[p.S * p.Nd:]), float(gmu @ mu)
+    assert abs(lhs - rhs) <= 2 * tol * (ng * nx + nl * nz) + 64 * eps * (ng * nx + nl * nz)
+
+
 def test_adjoint_solve_and_vjp_match_oracle(dense_case):
     inp, p, A, _ = dense_case
     rng = np.random.default_rng(34)
