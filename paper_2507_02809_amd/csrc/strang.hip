@@ -63,6 +63,46 @@ __device__ __forceinline__ T rhs_value(const RhsArgs<T>& ra, const T* __restrict
     return in[g];
 }
 
+// sum_{j0 <= j < j1} x[j] ct[(j k) mod N].  The sum runs in chunks of kCasU: the chunk's table
+// indices come from a short VALU chain, so its LDS reads are independent and in flight together,
+// and kCasU partial sums break the multiply-add dependence.
+template <typename T>
+__device__ __forceinline__ T cas_sum(const T* x, const T* ct, int N, int k, int j0, int j1) {
+    T acc[kCasU];
+#pragma unroll
+    for (int u = 0; u < kCasU; ++u) acc[u] = T(0);
+    int idx = (int)(((long long)j0 * k) % N);  // j k mod N
+    int j = j0;
+    for (; j + kCasU <= j1; j += kCasU) {
+        int id[kCasU];
+        id[0] = idx;
+#pragma unroll
+        for (int u = 1; u < kCasU; ++u) {
+            const int t = id[u - 1] + k;
+            id[u] = t >= N ? t - N : t;
+        }
+        T cv[kCasU], xv[kCasU];
+#pragma unroll
+        for (int u = 0; u < kCasU; ++u) {
+            cv[u] = ct[id[u]];
+            xv[u] = x[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < kCasU; ++u) acc[u] += xv[u] * cv[u];
+        const int t = id[kCasU - 1] + k;
+        idx = t >= N ? t - N : t;
+    }
+    for (; j < j1; ++j) {
+        acc[0] += x[j] * ct[idx];
+        idx += k;
+        if (idx >= N) idx -= N;
+    }
+    T sum = T(0);
+#pragma unroll
+    for (int u = 0; u < kCasU; ++u) sum += acc[u];
+    return sum;
+}
+
 // out[k][r] = sum_j x[r][j] cas[(j k) mod N] for r < nrow, k < N, with x[r][j] the right-hand side
 // value of point r N + j (rhs_value) times (lam ? scale / (sigma + c lam[r][j]) : 1).
 template <typename T>
@@ -83,44 +123,23 @@ __global__ __launch_bounds__(256) void cas_pass(const T* __restrict__ in, T* __r
     }
     __syncthreads();
     const int k = blockIdx.x * kCasK + (threadIdx.x & (kCasK - 1));
-    const int r = threadIdx.x / kCasK;  // one row per wave
+    const int w = threadIdx.x / kCasK;
+    if (nrow == 1) {
+        // a single row (d = 1): the four waves split the sum over j and add their partial sums
+        __shared__ T part[4][kCasK];
+        const int span = (N + 3) / 4;
+        const int j0 = min(N, w * span), j1 = min(N, j0 + span);
+        part[w][threadIdx.x & (kCasK - 1)] = k < N ? cas_sum(xs, ct, N, k, j0, j1) : T(0);
+        __syncthreads();
+        if (w == 0 && k < N) {
+            const int l = threadIdx.x;
+            out[k] = (part[0][l] + part[1][l]) + (part[2][l] + part[3][l]);
+        }
+        return;
+    }
+    const int r = w;  // one row per wave
     if (k >= N || r >= nr) return;
-    const T* x = xs + r * N;
-    // the j loop in chunks of kCasU: the chunk's table indices (j k mod N) come from a short VALU
-    // chain, so its LDS reads are independent and in flight together, and kCasU partial sums break
-    // the multiply-add dependence
-    T acc[kCasU];
-#pragma unroll
-    for (int u = 0; u < kCasU; ++u) acc[u] = T(0);
-    int idx = 0;  // j k mod N
-    int j = 0;
-    for (; j + kCasU <= N; j += kCasU) {
-        int id[kCasU];
-        id[0] = idx;
-#pragma unroll
-        for (int u = 1; u < kCasU; ++u) {
-            const int t = id[u - 1] + k;
-            id[u] = t >= N ? t - N : t;
-        }
-        T cv[kCasU], xv[kCasU];
-#pragma unroll
-        for (int u = 0; u < kCasU; ++u) {
-            cv[u] = ct[id[u]];
-            xv[u] = x[j + u];
-        }
-#pragma unroll
-        for (int u = 0; u < kCasU; ++u) acc[u] += xv[u] * cv[u];
-        const int t = id[kCasU - 1] + k;
-        idx = t >= N ? t - N : t;
-    }
-    for (; j < N; ++j) {
-        acc[0] += x[j] * ct[idx];
-        idx += k;
-        if (idx >= N) idx -= N;
-    }
-    T sum = T(0);
-#pragma unroll
-    for (int u = 0; u < kCasU; ++u) sum += acc[u];
+    const T sum = cas_sum(xs + r * N, ct, N, k, 0, N);
     out[(long long)k * nrow + r0 + r] = sum;
 }
 
