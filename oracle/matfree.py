@@ -18,10 +18,13 @@ paragraphs), in FP64 NumPy.
                 system.dense_S): each block solved exactly by the d-dimensional FFT.
 
 The embedding size used here is 2N per direction (the smallest even size
->= 2N-1); any size >= 2N-1 gives the same product in exact arithmetic.
+>= 2N-1); any size >= 2N-1 gives the same product in exact arithmetic.  The
+transforms are SciPy's real FFTs on all host cores (WORKERS); the time-history
+sums are products with the lower-triangular Toeplitz matrix of the e_m weights.
 """
 from __future__ import annotations
 
+import os
 from typing import Callable, Optional
 
 import numpy as np
@@ -30,6 +33,8 @@ import scipy.sparse.linalg as spla
 
 from . import coeffs
 from .system import Problem, dense_B, tau_sigma
+
+WORKERS = os.cpu_count() or 1  # threads of the FFTs (scipy.fft workers)
 
 
 # --------------------------------------------------------------------------
@@ -60,18 +65,30 @@ def circulant_symbol(p: Problem) -> np.ndarray:
 
 def apply_B(p: Problem, v: np.ndarray, symbol: Optional[np.ndarray] = None) -> np.ndarray:
     """B v for v of shape (..., Nd): zero-pad each direction to 2N, multiply by the circulant
-    symbol in Fourier space, crop (§5, matvec step 1(b))."""
+    symbol in Fourier space, crop (§5, matvec step 1(b)).  v is real and the symbol is real and
+    even, so the half spectrum of the real transform carries the whole product."""
     if symbol is None:
         symbol = circulant_symbol(p)
     N = p.N
+    L = 2 * N
     lead = v.shape[:-1]
     if p.d == 1:
-        V = np.fft.fft(v, n=2 * N, axis=-1)
-        return np.fft.ifft(V * symbol, axis=-1).real[..., :N]
+        V = sfft.rfft(v, n=L, axis=-1, workers=WORKERS)
+        return sfft.irfft(V * symbol[:N + 1], n=L, axis=-1, workers=WORKERS)[..., :N]
     vv = v.reshape(lead + (N, N))
-    V = np.fft.fft2(vv, s=(2 * N, 2 * N), axes=(-2, -1))
-    out = np.fft.ifft2(V * symbol, axes=(-2, -1)).real[..., :N, :N]
+    V = sfft.rfftn(vv, s=(L, L), axes=(-2, -1), workers=WORKERS)
+    out = sfft.irfftn(V * symbol[:, :N + 1], s=(L, L), axes=(-2, -1), workers=WORKERS)[..., :N, :N]
     return out.reshape(lead + (N * N,))
+
+
+def history_matrix(p: Problem) -> np.ndarray:
+    """The S x S lower-triangular Toeplitz matrix E with E[s, m] = e_{s-m} (m <= s): block (s, m)
+    of the time part of A is e_{s-m} D_1^(s) (§5, eq. lin-syst), so the history sums of all
+    slices are D_1 (E Y)."""
+    e = p.e()
+    s = np.arange(p.S)
+    lag = s[:, None] - s[None, :]
+    return np.where(lag >= 0, e[np.clip(lag, 0, None)], 0.0)
 
 
 # --------------------------------------------------------------------------
@@ -87,16 +104,13 @@ def matvec(p: Problem, y: np.ndarray, symbol: Optional[np.ndarray] = None) -> np
          z^(S+1) = (lambda/h^omega) D_2^(S) B y^(S+1) + y^(S)."""
     S, Nd = p.S, p.Nd
     Y = y.reshape(S + 1, Nd)
-    e = p.e()
     if symbol is None:
         symbol = circulant_symbol(p)
     BY = apply_B(p, Y, symbol)
+    W = history_matrix(p) @ Y[:S]  # W[s] = sum_{m <= s} e_{s-m} y^(m)
     Z = np.empty_like(Y)
     for s in range(S):
-        w = np.zeros(Nd)
-        for m in range(s + 1):
-            w += e[s - m] * Y[m]
-        Z[s] = p.gamma1[s] * w + p.c_t * p.gamma2[s] * BY[s] - p.eta * p.q[s] * Y[S]
+        Z[s] = p.gamma1[s] * W[s] + p.c_t * p.gamma2[s] * BY[s] - p.eta * p.q[s] * Y[S]
     Z[S] = p.c_f * p.gamma2[S - 1] * BY[S] + Y[S - 1]
     return Z.reshape(-1)
 
@@ -152,6 +166,20 @@ def _cg(apply: Callable, rhs: np.ndarray, x0: np.ndarray, tol: float, maxit: int
     return x, maxit
 
 
+def tau_block_preconditioner(p: Problem, sigma: float, c: float) -> Callable:
+    """r -> (sigma I + c tau(B))^{-1} r with tau(B) = S diag(lambda) S, S the orthonormal DST-I over
+    every level (§5.1 Remark): an SPD approximation of the block sigma I + c B, used only to speed up
+    the CG of P_solve (the block system and its solution are unchanged)."""
+    lam = coeffs.tau_eigenvalues(p.a())
+    shape = (p.N,) * p.d
+    diag = sigma + c * lam
+
+    def apply(r):
+        t = sfft.dstn(r.reshape(shape), type=1, norm="ortho", workers=WORKERS)
+        return sfft.dstn(t / diag, type=1, norm="ortho", workers=WORKERS).reshape(-1)
+    return apply
+
+
 def P_solve(p: Problem, z: np.ndarray, inner: str = "dense", inner_tol: float = 1e-14,
             inner_maxit: int = 2000, last_block: bool = True) -> np.ndarray:
     """y = P_{n,S}^{-1} z by the forward substitution of §5.1:
@@ -161,7 +189,9 @@ def P_solve(p: Problem, z: np.ndarray, inner: str = "dense", inner_tol: float = 
     inner = 'dense': each block solved by LU of the assembled block (the paper's backslash);
     inner = 'cg':    each block solved by CG on the SPD form (D_2^-1 D_1 e_0 + c_t B) y = D_2^-1 r
                      (respectively B y = r / (c_f gamma_2)) to relative residual inner_tol —
-                     an approximation of P^{-1}, used only where dense blocks do not fit."""
+                     an approximation of P^{-1}, used only where dense blocks do not fit;
+    inner = 'pcg':   the same CG preconditioned by the tau matrix of the block with its diagonal
+                     frozen at the slice mean (tau_block_preconditioner), for the large sizes."""
     S, Nd = p.S, p.Nd
     Z = z.reshape(-1, Nd)
     e = p.e()
@@ -174,9 +204,7 @@ def P_solve(p: Problem, z: np.ndarray, inner: str = "dense", inner_tol: float = 
     for s in range(S):
         r = Z[s].copy()
         if s > 0:
-            hist = np.zeros(Nd)
-            for m in range(s):
-                hist += e[s - m] * Y[m]
+            hist = e[s:0:-1] @ Y[:s]  # sum_{m < s} e_{s-m} y^(m)
             r -= p.gamma1[s] * hist
         if inner == "dense":
             K = e[0] * np.diag(p.gamma1[s]) + p.c_t * p.gamma2[s][:, None] * B
@@ -184,15 +212,17 @@ def P_solve(p: Problem, z: np.ndarray, inner: str = "dense", inner_tol: float = 
         else:
             dg = e[0] * p.gamma1[s] / p.gamma2[s]
             x0 = Y[s - 1] if s > 0 else np.zeros(Nd)
+            prec = tau_block_preconditioner(p, float(np.mean(dg)), p.c_t) if inner == "pcg" else None
             Y[s], _ = _cg(lambda v: dg * v + p.c_t * Bop(v), r / p.gamma2[s], x0,
-                          inner_tol, inner_maxit)
+                          inner_tol, inner_maxit, prec)
     if not last_block:
         return Y[:S].reshape(-1)
     r = Z[S] - Y[S - 1]
     if inner == "dense":
         Y[S] = np.linalg.solve(p.c_f * p.gamma2[S - 1][:, None] * B, r)
     else:
-        Y[S], _ = _cg(Bop, r / (p.c_f * p.gamma2[S - 1]), np.zeros(Nd), inner_tol, inner_maxit)
+        prec = tau_block_preconditioner(p, 0.0, 1.0) if inner == "pcg" else None
+        Y[S], _ = _cg(Bop, r / (p.c_f * p.gamma2[S - 1]), np.zeros(Nd), inner_tol, inner_maxit, prec)
     return Y.reshape(-1)
 
 
