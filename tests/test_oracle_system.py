@@ -64,6 +64,31 @@ def test_A_time_structure_exact_on_linear_in_t(small1d):
 
 
 @pytest.mark.parametrize("which", ["small1d", "small2d"])
+def test_rhs_rho_term_completes_the_L1_formula(which, request):
+    """The initial state rho = v^(0) enters z^(s) = b_{s-1} D_1^(s) rho (§5, eq. lin-syst): with
+    rho = a psi and v^(s) = psi (a + c t_s), f~ = 0, block row s of A y - z minus its spatial
+    part c_t D_2^(s) B v^(s) is the L1 formula (§4, eq. L1-formula) applied to a + c t with its
+    v^(0) term, which is exact on functions linear in t: D_1^(s) psi c dt s^(1-beta)."""
+    p0 = request.getfixturevalue(which)
+    rng = np.random.default_rng(3)
+    psi = rng.standard_normal(p0.Nd)
+    a, c = 1.9, -0.8
+    p = dataclasses.replace(p0, rho=a * psi)
+    t = p.dt * np.arange(1, p.S + 1)
+    Y = np.zeros((p.S + 1, p.Nd))
+    Y[:p.S] = np.outer(a + c * t, psi)
+    R = (matfree.matvec(p, Y.ravel()) - system.rhs_z(p)).reshape(p.S + 1, p.Nd)
+    BY = matfree.apply_B(p, Y[:p.S])
+    for s in range(p.S):
+        hist = R[s] - p.c_t * p.gamma2[s] * BY[s]
+        expect = p.gamma1[s] * psi * c * p.dt * (s + 1) ** (1 - p.beta)
+        np.testing.assert_allclose(hist, expect, rtol=0, atol=1e-12 * np.abs(psi).max())
+    # without the rho term of z the a-part of the L1 formula would remain: a b_{s-1} D_1 psi
+    R0 = (matfree.matvec(p, Y.ravel()) - system.rhs_z(dataclasses.replace(p, rho=0 * psi))).reshape(p.S + 1, p.Nd)
+    assert np.abs(R0[p.S - 1] - R[p.S - 1]).max() > 0.1 * a * np.abs(psi).max() * p.b()[p.S - 1]
+
+
+@pytest.mark.parametrize("which", ["small1d", "small2d"])
 def test_matvec_matches_dense(which, request):
     p = request.getfixturevalue(which)
     A = system.dense_A(p)
