@@ -192,6 +192,14 @@ tsfde_status tsfde_apply_A(tsfde_problem* prob, const double* y, double* z, void
 tsfde_status tsfde_apply_A_f32(tsfde_problem* prob, const float* y, float* z, void* stream);
 
 /*
+ * Persistent kernels.  P^{-1} runs as persistent grids whose workgroups wait for each other at
+ * device-wide barriers.  Every such grid of the process takes its share of the device's CU slots
+ * before it starts and gives it back when it has finished, so that grids running side by side on
+ * different streams or host threads are always resident together (a call waits on the host while
+ * the slots are taken).  A barrier wait is bounded (TSFDE_BARRIER_TIMEOUT_US, default 5 s): if it
+ * expires, every workgroup leaves the grid normally and the call returns TSFDE_EDEVICE.  The entry
+ * points that apply P^{-1} synchronise their stream.
+ *
  * y ~= P^{-1} z by the forward substitution of §5.1: for s = 1..M solve
  * (e_0 D_1^(s) + (eta/h^omega) D_2^(s) B) y^(s) = z^(s) - D_1^(s) sum_{m<s} e_{s-m} y^(m),
  * then (alpha/h^omega) D_2^(M) B y^(M+1) = z^(M+1) - y^(M).  Each block is solved by
@@ -241,8 +249,7 @@ tsfde_status tsfde_recover_f(tsfde_problem* prob, double* f_out, double* work,
  * Returns EINVAL for a NULL entry, a repeated problem or max_inflight out of
  * range, ENOTIMPL if the options do not apply to one of the problems, the
  * first device error by problem index, else ENOCONV if any problem missed
- * the tolerance (its stats tell which; its f~ is the last iterate).  While a
- * batch runs, other calls of this library that apply P^-1 wait for it.
+ * the tolerance (its stats tell which; its f~ is the last iterate).
  */
 tsfde_status tsfde_recover_f_batch(tsfde_problem* const* probs, int count, double* const* f_out,
                                    const tsfde_opts* opts, tsfde_stats* stats, int max_inflight,
@@ -298,8 +305,8 @@ tsfde_status tsfde_adjoint_solve(tsfde_problem* prob, const double* g, double* l
  *                     -c_f lam^(M+1) .* B y^(M+1)   (gamma2^(s) enters the diagonal blocks and,
  *                     at s = M, the last one)
  * grad_mu: device N^d or NULL; grad_alpha: HOST double or NULL; grad_gamma2:
- * device M N^d (slice-major like gamma2) or NULL.  Allocates three work vectors
- * for the call.
+ * device M N^d (slice-major like gamma2) or NULL.  The first call allocates
+ * three work vectors of (M+1) N^d that the problem keeps.
  */
 tsfde_status tsfde_recover_f_vjp(tsfde_problem* prob, const double* y, const double* gf,
                                  double* grad_mu, double* grad_alpha, double* grad_gamma2,

@@ -67,6 +67,7 @@ struct Problem {
     Dev<float> f32;
     bool have_f32 = false;
     double* d_bw = nullptr;    // [M] b_0..b_{M-1}
+    double* d_sigma = nullptr; // [M] sigma_s, the slice mean of e_0 gamma1 / gamma2 (tau preconditioner shift)
     double* d_rho = nullptr;   // [Nd]
     double* d_mu = nullptr;    // [Nd]
     bool tau_ok = false;       // sine-transform preconditioner available (2(N+1) a power of two)
@@ -87,6 +88,8 @@ struct Problem {
     double* arn_h = nullptr;     // Arnoldi coefficients, 2 (kMaxRestart + 2) + 1
     double* rwork = nullptr;     // FGMRES residual (n_tot)
     double* adj_u = nullptr;     // adjoint work: gamma2-scaled slices (n_tot)
+    double* refine_work = nullptr;  // MIXED refinement: residual, correction, inner FGMRES residual (3 n_tot)
+    double* vjp_work = nullptr;     // vector-Jacobian product: [0; gf], lam, a scratch vector (3 n_tot)
     // Strang blocks (S_{n,S}), built on first use: [N] cas table then [Nd] eigenvalues of s(B)
     double* strang64 = nullptr;
     float* strang32 = nullptr;
@@ -193,6 +196,8 @@ void set_persistent_blocks(int g);
 // Batch mode of the calling thread: its persistent kernels are ordinary launches sized so that
 // kMaxInflight of them fit the device together (tsfde_recover_f_batch)
 constexpr int kMaxInflight = 8;
+// XCDs of the device (MI355X: 8 XCDs of 32 CUs); the workgroups of a dispatch are dealt to them in turn
+constexpr int kXcds = 8;
 void set_shared_launch(bool on);
 bool shared_launch();
 void set_persistent_fixed_length(bool on);

@@ -1,10 +1,10 @@
-// P^{-1} z with persistent cooperative kernels (§5.1 'Implementation': forward substitution over
+// P^{-1} z with persistent kernels (§5.1 'Implementation': forward substitution over
 // the time steps; each diagonal block solved by preconditioned CG on its symmetrised form).
 //
 // The forward substitution is a chain of M+1 dependent solves on one spatial slice each, and every
 // CG iteration is a handful of small transforms and two reductions.  Launching those as separate
 // kernels costs microseconds per launch plus a host round trip per convergence test, so here a
-// cooperative grid of G workgroups runs a segment of up to kHB consecutive steps, separating
+// persistent grid of G workgroups runs a segment of up to kHB consecutive steps, separating
 // phases with a device-wide barrier and taking every convergence decision on the device: all
 // workgroups reduce the same partial sums in the same order and take the same branch.
 //
@@ -40,6 +40,7 @@
 
 #include "fft.hpp"
 #include "internal.hpp"
+#include "residency.hpp"
 
 namespace tsfde {
 
@@ -75,7 +76,8 @@ struct PinvArgs {
     T* hacc;           // [kHB][Nd]: w_s of the segment's steps (far history folded into the rhs)
     cplx<T>* spec;     // [H][ns]
     double* part;      // [G][kNPart]
-    unsigned* bar;     // barrier counter, zero at launch
+    unsigned* bar;     // [0] barrier counter, zero at launch; [1] abort word (see grid_barrier)
+    unsigned long long bar_ticks;  // longest barrier wait, in wall-clock periods
     long long* iters;  // accumulated CG iterations
 };
 
@@ -83,14 +85,30 @@ struct PinvArgs {
 // release increment and the acquire fence after the wait (both at agent scope) make every block's
 // earlier writes visible to every block; the wait itself polls with relaxed loads, so that the
 // cache invalidation of the acquire happens once per barrier rather than once per poll.
-__device__ __forceinline__ void grid_barrier(unsigned* ctr, unsigned& epoch) {
+//
+// The wait is bounded.  bar[0] is the arrival counter and bar[1] an abort word: a block that has
+// waited longer than `ticks` periods of the constant wall clock sets the abort word, and from then
+// on every barrier of the launch (and of the later segment launches of the same P^-1, which keep
+// the word) returns at once.  The grid then runs its remaining, bounded loops on meaningless
+// values and exits normally; the host finds the word set and reports an error.  A wait can only
+// last that long when the grid's workgroups are not all resident at once.
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned long long ticks, unsigned& epoch) {
     __syncthreads();
     if (gridDim.x > 1) {
         epoch += gridDim.x;
         if (threadIdx.x == 0) {
-            __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch)
-                __builtin_amdgcn_s_sleep(1);
+            __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+                const unsigned long long t0 = (unsigned long long)wall_clock64();
+                while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+                    if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+                    if ((unsigned long long)wall_clock64() - t0 > ticks) {
+                        __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
@@ -915,7 +933,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
             } else {
                 put_partial(a.part, SL_RZ, rzl, red);
             }
-            grid_barrier(a.bar, epoch);
+            grid_barrier(a.bar, a.bar_ticks, epoch);
             gather_totals(a.part, tot);
         };
 
@@ -1057,7 +1075,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                 const T vv[2] = {rr, bb};
                 put_partials<2>(a.part, sl, vv, red);
             }
-            grid_barrier(a.bar, epoch);
+            grid_barrier(a.bar, a.bar_ticks, epoch);
             gather_totals<(1u << SL_RR) | (1u << SL_BB)>(a.part, tot);
         }
         const double bbt = tot[SL_BB];
@@ -1068,7 +1086,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                 a.x[j] = T(0);
                 a.r[j] = T(0);
             }
-            grid_barrier(a.bar, epoch);
+            grid_barrier(a.bar, a.bar_ticks, epoch);
             continue;
         }
         if constexpr (TAU2) {
@@ -1081,7 +1099,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                     const int kbase = 2 * (rd * NG + blockIdx.x * gpb);
                     wg_pass_B<T, VPT>(a, cbase, c, twl, kbase, grp, gpb, sig, cc, scale, tid, nthr, rzl);
                 }
-                grid_barrier(a.bar, epoch);
+                grid_barrier(a.bar, a.bar_ticks, epoch);
                 for (int rd = 0; rd < NR; ++rd) {
                     const int ibase = 2 * (rd * NG + blockIdx.x * gpb);
                     const int i0 = ibase + 2 * grp;
@@ -1114,7 +1132,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                     wg_pass_B<T, VPT>(a, cbase, c, twl, kbase, grp, gpb, sig, cc, scale, tid, nthr, rzl);
                 }
                 put_partial(a.part, SL_RZ, rzl, red);
-                grid_barrier(a.bar, epoch);
+                grid_barrier(a.bar, a.bar_ticks, epoch);
                 gather_totals<1u << SL_RZ>(a.part, tot);
             }
             double rz = tot[SL_RZ];
@@ -1127,13 +1145,13 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                     wg_pass_DF<T, VPT>(a, cbase, c, twl, ibase, grp, gpb, beta, dg, tid, nthr, pdp);
                 }
                 put_partial(a.part, SL_PD, pdp, red);
-                grid_barrier(a.bar, epoch);
+                grid_barrier(a.bar, a.bar_ticks, epoch);
                 for (int rd = 0; rd < NC; ++rd) {
                     const int k2 = rd * NG + gg;
                     g_cols_pbp<T, VPT>(a, c, twl, k2, k2 < a.H, tid, nthr, pbp);
                 }
                 put_partial(a.part, SL_PB, pbp, red);
-                grid_barrier(a.bar, epoch);
+                grid_barrier(a.bar, a.bar_ticks, epoch);
                 gather_totals<(1u << SL_PD) | (1u << SL_PB)>(a.part, tot);
                 const double pqt = tot[SL_PD] + (double)cc * tot[SL_PB];
                 const T alpha = T(pqt != 0.0 ? rz / pqt : 0.0);
@@ -1142,7 +1160,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                     wg_pass_IUA<T, VPT>(a, cbase, c, twl, ibase, grp, gpb, dg, cc, alpha, tid, nthr, rr);
                 }
                 put_partial(a.part, SL_RR, rr, red);
-                grid_barrier(a.bar, epoch);
+                grid_barrier(a.bar, a.bar_ticks, epoch);
                 gather_totals<1u << SL_RR>(a.part, tot);
                 ++it;
                 rrt = tot[SL_RR];
@@ -1153,7 +1171,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                     wg_pass_B<T, VPT>(a, cbase, c, twl, kbase, grp, gpb, sig, cc, scale, tid, nthr, rzl);
                 }
                 put_partial(a.part, SL_RZ, rzl, red);
-                grid_barrier(a.bar, epoch);
+                grid_barrier(a.bar, a.bar_ticks, epoch);
                 gather_totals<1u << SL_RZ>(a.part, tot);
                 const double rz_new = tot[SL_RZ];
                 beta = T(rz != 0.0 ? rz_new / rz : 0.0);
@@ -1174,12 +1192,12 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                     const int pr = rd * NG + gg;
                     g_rows_fwd<T, VPT>(a, c, twl, pr, pr < NP, beta, tid, nthr);
                 }
-                grid_barrier(a.bar, epoch);
+                grid_barrier(a.bar, a.bar_ticks, epoch);
                 for (int rd = 0; rd < NC; ++rd) {
                     const int k2 = rd * NG + gg;
                     g_cols<T, VPT>(a, c, twl, k2, k2 < a.H, tid, nthr);
                 }
-                grid_barrier(a.bar, epoch);
+                grid_barrier(a.bar, a.bar_ticks, epoch);
                 for (int rd = 0; rd < NR; ++rd) {
                     const int pr = rd * NG + gg;
                     g_rows_inv<T, VPT>(a, c, twl, pr, pr < NP, dg, cc, tid, nthr, pq);
@@ -1229,7 +1247,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                 __syncthreads();
             }
             put_partial(a.part, SL_PQ, pq, red);
-            grid_barrier(a.bar, epoch);
+            grid_barrier(a.bar, a.bar_ticks, epoch);
             gather_totals(a.part, tot);
             const double pqt = tot[SL_PQ];
             const T alpha = T(pqt != 0.0 ? rz / pqt : 0.0);
@@ -1247,7 +1265,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
     }
     // the segment's last step: y_{sb-1} = x (grid-stride ownership: in the tau-block mode x was
     // last written by row-owning groups, so the grid synchronises first)
-    if constexpr (TB) grid_barrier(a.bar, epoch);
+    if constexpr (TB) grid_barrier(a.bar, a.bar_ticks, epoch);
     for (long long j = gtid; j < Nd; j += gthreads) a.y[(long long)(sb - 1) * Nd + j] = a.x[j];
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.iters += total_it;
 }
@@ -1261,10 +1279,15 @@ struct PersistentWork {
     T* tt = nullptr;        // t1, t2: N ns each (2D)
     cplx<T>* spec = nullptr;  // [H][ns] (2D)
     double* part = nullptr;
-    unsigned* bar = nullptr;
+    unsigned* bar = nullptr;  // [0] barrier counter, [1] abort word
     long long* iters = nullptr;
-    double* sigma = nullptr;
+    ResidencyTicket ticket;   // CU slots of the grid while its segments run
 };
+
+// the device's pool of CU slots for persistent grids, and the longest barrier wait in wall-clock
+// periods (pinv_persistent.hip)
+ResidencyBudget& residency_budget(int dev, int ncu);
+unsigned long long barrier_ticks(int dev);
 
 template <typename T>
 void ensure_work(Problem& P, PersistentWork<T>& W);
@@ -1291,7 +1314,7 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
     a.sym = D.sym;
     a.tau = D.tau;
     a.tw = D.tw;
-    a.sigma = W.sigma;
+    a.sigma = P.d_sigma;
     a.ct = T(P.ct);
     a.cf = T(P.cf);
     a.a0 = T(P.a0);
@@ -1333,14 +1356,17 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
     TSFDE_HIP(hipGetDevice(&dev));
     TSFDE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     if (per_cu < 1) throw HipError{hipErrorInvalidConfiguration, "persistent P^-1: a workgroup does not fit a CU"};
-    // The segment kernel's blocks wait for each other, so all of them must be resident at once.  A
-    // single call launches cooperatively (the runtime checks residency and does not overlap such
-    // launches).  Inside a batch, up to kMaxInflight of these kernels run side by side as ordinary
-    // launches, each limited to ncu / kMaxInflight blocks: even if every block of every such kernel
-    // occupied a CU of its own (kernels of different shapes need not pack together), they fit.
-    const bool shared = shared_launch();
-    const int cap = shared ? std::max(1, ncu / kMaxInflight) : per_cu * ncu;
+    // The segment kernel's workgroups wait for each other, so all of them must be resident at once,
+    // also beside the persistent grids of other streams: the grid is sized to its share of the
+    // device's CU slots and holds them (W.ticket) until the host has seen the last segment finish
+    // (residency.hpp).  Inside a batch, where up to kMaxInflight problems run side by side, a grid is
+    // further limited to ncu / kMaxInflight workgroups, so that that many fit together.
+    ResidencyBudget& pool = residency_budget(dev, ncu);
+    int cap = std::min(per_cu * ncu, residency_max_grid(pool.total(), kXcds));
+    if (shared_launch()) cap = std::min(cap, std::max(1, ncu / kMaxInflight));
     grid = std::max(1, std::min(grid, cap));
+    a.bar_ticks = barrier_ticks(dev);
+    W.ticket.hold(&pool, residency_slots(grid, kXcds));
     launch_fill(reinterpret_cast<float*>(W.iters), 2, 0.0f, st);  // zero the iteration counter
     const int s_last = last_block ? P.M : P.M - 1;
     for (int sa = 0; sa <= s_last; sa += kHB) {
@@ -1354,11 +1380,7 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
         }
         launch_fill(reinterpret_cast<float*>(W.bar), 1, 0.0f, st);  // zero the barrier counter
         void* args[] = {&a, &sa_, &sb_};
-        if (shared)
-            TSFDE_HIP(hipLaunchKernel((void*)pinv_segment<T, VPT, MODE, LC, TB>, dim3(grid), dim3(block), args, lds, st));
-        else
-            TSFDE_HIP(hipLaunchCooperativeKernel((void*)pinv_segment<T, VPT, MODE, LC, TB>, dim3(grid), dim3(block), args,
-                                                 lds, st));
+        TSFDE_HIP(hipLaunchKernel((void*)pinv_segment<T, VPT, MODE, LC, TB>, dim3(grid), dim3(block), args, lds, st));
     }
 }
 

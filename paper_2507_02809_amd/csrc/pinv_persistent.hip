@@ -1,6 +1,8 @@
-// P^{-1} z with persistent cooperative kernels: work buffers, dispatch, and the kernels whose
+// P^{-1} z with persistent kernels: work buffers, dispatch, and the kernels whose
 // transform length is a run-time value (the device code is in pinv_kernel.hpp).
 #include <atomic>
+#include <cstdlib>
+#include <mutex>
 
 #include "pinv_kernel.hpp"
 
@@ -8,6 +10,24 @@ namespace tsfde {
 
 static std::atomic<int> g_blocks_override{-1};
 static std::atomic<bool> g_fixed_length{true};
+
+ResidencyBudget& residency_budget(int dev, int ncu) {
+    constexpr int kMaxDev = 64;
+    static ResidencyBudget pools[kMaxDev];
+    static std::once_flag once[kMaxDev];
+    if (dev < 0 || dev >= kMaxDev) throw HipError{hipErrorInvalidDevice, "persistent P^-1: device index"};
+    std::call_once(once[dev], [&] { pools[dev].reset(std::max(1, ncu / kXcds)); });
+    return pools[dev];
+}
+
+// longest wait at a device-wide barrier: TSFDE_BARRIER_TIMEOUT_US microseconds (default 5 s)
+unsigned long long barrier_ticks(int dev) {
+    int khz = 0;
+    TSFDE_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    const char* e = std::getenv("TSFDE_BARRIER_TIMEOUT_US");
+    const double us = (e && *e) ? std::max(0.0, std::atof(e)) : 5e6;
+    return (unsigned long long)(us * (double)std::max(khz, 1) / 1000.0);
+}
 
 
 template <typename T>
@@ -23,8 +43,6 @@ void ensure_work(Problem& P, PersistentWork<T>& W) {
     TSFDE_HIP(hipMalloc(&W.part, sizeof(double) * 1024 * kNPart));
     TSFDE_HIP(hipMalloc(&W.bar, 64));
     TSFDE_HIP(hipMalloc(&W.iters, sizeof(long long)));
-    TSFDE_HIP(hipMalloc(&W.sigma, sizeof(double) * P.M));
-    TSFDE_HIP(hipMemcpy(W.sigma, P.sigma.data(), sizeof(double) * P.M, hipMemcpyHostToDevice));
     TSFDE_HIP(hipMemset(W.buf, 0, sizeof(T) * (size_t)(8 + kHB) * P.Nd));
 }
 
@@ -33,12 +51,15 @@ bool persistent_supported(const Problem& P) {
     return (!P.tau_ok || P.Ld == P.L) && P.L <= 8192;
 }
 
+// The forward substitution on the work buffers W (allocated by the caller); allocates nothing.
 template <typename T>
-long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T* z, T* y, double inner_tol,
+static long long run_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T* z, T* y, double inner_tol,
                               int inner_maxit, bool last_block, int extrap, int tblocks, hipStream_t st) {
-    if (!wptr) wptr = new PersistentWork<T>();
-    PersistentWork<T>& W = *static_cast<PersistentWork<T>*>(wptr);
-    ensure_work(P, W);
+    struct Release {  // the grid's CU slots go back however this call ends
+        ResidencyTicket& t;
+        ~Release() { t.release(); }
+    } release{W.ticket};
+    launch_fill(reinterpret_cast<float*>(W.bar) + 1, 1, 0.0f, st);  // clear the abort word
     const int L = P.L;
     const int vpt = (L <= 2048) ? 8 : (L == 4096 ? 16 : 32);
     const int mode = (P.d == 1) ? SEG_1D : ((P.tau_ok || P.tau_pad) ? SEG_2D_TAU : SEG_2D_DIAG);
@@ -70,17 +91,32 @@ long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T*
 #undef TSFDE_SEG_MODES
 #undef TSFDE_SEG
     }
-    long long it = 0;
-    TSFDE_HIP(hipMemcpyAsync(&it, W.iters, sizeof(long long), hipMemcpyDeviceToHost, st));
+    // iteration count and abort word into the problem's pinned scratch
+    long long* it_h = reinterpret_cast<long long*>(P.host_scalars + 56);
+    unsigned* abort_h = reinterpret_cast<unsigned*>(P.host_scalars + 57);
+    TSFDE_HIP(hipMemcpyAsync(it_h, W.iters, sizeof(long long), hipMemcpyDeviceToHost, st));
+    TSFDE_HIP(hipMemcpyAsync(abort_h, W.bar + 1, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     TSFDE_HIP(hipStreamSynchronize(st));
-    return it;
+    if (*abort_h != 0u)
+        throw HipError{hipErrorLaunchTimeOut,
+                       "persistent P^-1: a device-wide barrier wait timed out (workgroups not co-resident)"};
+    return *it_h;
+}
+
+template <typename T>
+long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T* z, T* y, double inner_tol,
+                              int inner_maxit, bool last_block, int extrap, int tblocks, hipStream_t st) {
+    if (!wptr) wptr = new PersistentWork<T>();
+    PersistentWork<T>& W = *static_cast<PersistentWork<T>*>(wptr);
+    ensure_work(P, W);
+    return run_segments(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, tblocks, st);
 }
 
 template <typename T>
 void pinv_persistent_free(void* wptr) {
     if (!wptr) return;
     PersistentWork<T>* W = static_cast<PersistentWork<T>*>(wptr);
-    void* ptrs[] = {W->buf, W->tt, W->spec, W->part, W->bar, W->iters, W->sigma};
+    void* ptrs[] = {W->buf, W->tt, W->spec, W->part, W->bar, W->iters};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete W;

@@ -339,7 +339,8 @@ void free_problem(Problem* P) {
     pinv_persistent_free<double>(P->pw64);
     pinv_persistent_free<float>(P->pw32);
     void* ptrs[] = {P->d_bw, P->d_rho, P->d_mu, P->z_rhs, P->xbuf, P->V, P->Z, P->arn_part, P->arn_h, P->rwork, P->adj_u,
-                    P->dev_scalars, P->strang64, P->strang32, P->strang_hist};
+                    P->dev_scalars, P->strang64, P->strang32, P->strang_hist, P->refine_work, P->vjp_work,
+                    P->d_sigma};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (P->host_scalars) (void)hipHostFree(P->host_scalars);
@@ -490,6 +491,7 @@ tsfde_status create(int d, int N, int M, double T, double beta, double omega, do
         build_dev<float>(*P, P->f32, dg, epad, sym, tw, twd, tau);
         P->have_f32 = true;
         P->d_bw = upload<double>(*P, P->b.data(), M);
+        P->d_sigma = upload<double>(*P, P->sigma.data(), M);
         P->d_rho = upload<double>(*P, P->rho_h.data(), Nd);
         P->d_mu = upload<double>(*P, P->mu_h.data(), Nd);
         P->z_rhs = alloc<double>(*P, P->ntot);

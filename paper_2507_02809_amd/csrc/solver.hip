@@ -18,7 +18,6 @@
 #include <cstdlib>
 #include <functional>
 #include <mutex>
-#include <shared_mutex>
 #include <string>
 #include <system_error>
 #include <thread>
@@ -559,15 +558,17 @@ static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o,
             launch_f2d(F.vecB, out, n, st);
             return it;
         };
-        double *r = nullptr, *d = nullptr, *rw = nullptr;
-        TSFDE_HIP(hipMalloc(&r, sizeof(double) * n));
-        TSFDE_HIP(hipMalloc(&d, sizeof(double) * n));
-        TSFDE_HIP(hipMalloc(&rw, sizeof(double) * n));
+        if (!P.refine_work) TSFDE_HIP(hipMalloc(&P.refine_work, sizeof(double) * 3 * (size_t)n));
+        double* r = P.refine_work;
+        double* d = r + n;
+        double* rw = r + 2 * n;
         const double bnorm = std::sqrt(dev_dot(P, b, b, n, st));
         double rel = 1.0;
         S.converged = 0;
         int used = 0;
-        for (int ref = 0; ref < o.max_refine; ++ref) {
+        // every correction is followed by a residual check: at most max_refine corrections, and the
+        // stats always describe the returned x
+        for (int ref = 0;; ++ref) {
             double t0 = now();
             apply_A_impl<double>(P, x, r, st);
             TSFDE_HIP(hipStreamSynchronize(st));
@@ -576,7 +577,7 @@ static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o,
             const double rn = std::sqrt(dev_dot(P, r, r, n, st));
             rel = bnorm > 0.0 ? rn / bnorm : 0.0;
             if (rel <= o.tol) { S.converged = 1; break; }
-            if (used >= maxit) break;
+            if (ref >= o.max_refine || used >= maxit) break;
             launch_fill(d, n, 0.0, st);
             bool conv = false;
             double rr = 1.0;
@@ -585,9 +586,6 @@ static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o,
             launch_axpby(1.0, x, 1.0, d, x, n, st);
             ++S.refinements;
         }
-        (void)hipFree(r);
-        (void)hipFree(d);
-        (void)hipFree(rw);
         S.rel_res = rel;
     }
     TSFDE_HIP(hipStreamSynchronize(st));
@@ -644,12 +642,6 @@ struct tsfde_problem {
         return TSFDE_ENOMEM;                                                              \
     }
 
-// Calls that launch the persistent P^-1 kernels hold this lock shared; a batch holds it exclusively,
-// so that its ordinary (non-cooperative) persistent launches never share the device with the
-// cooperative launches of another call of this library.
-static std::shared_mutex g_launch_mx;
-using SharedLaunch = std::shared_lock<std::shared_mutex>;
-
 static bool overlap(const void* a, const void* b, size_t bytes) {
     const char* x = static_cast<const char*>(a);
     const char* y = static_cast<const char*>(b);
@@ -682,15 +674,16 @@ static tsfde_status vjp_impl(Problem& P, const double* y, const double* gf, doub
     const long long n = P.ntot, Nd = P.Nd, last = (long long)P.M * P.Nd;
     tsfde_status rc = TSFDE_OK;
     TSFDE_GUARD("recover_f_vjp", {
-        double* w = nullptr;  // g = [0; gf], lam, then v = [0; y^(M)] and A v
-        TSFDE_HIP(hipMalloc(&w, sizeof(double) * 3 * n));
+        // g = [0; gf], lam, then v = [0; y^(M)] and A v (problem-owned, allocated on first use)
+        if (!P.vjp_work) TSFDE_HIP(hipMalloc(&P.vjp_work, sizeof(double) * 3 * (size_t)n));
+        double* w = P.vjp_work;
         double* g = w;
         double* lam = w + n;
         double* v = w + 2 * n;
         launch_fill(g, n, 0.0, st);
         launch_copy<double>(gf, g + last, Nd, st);
         launch_fill(lam, n, 0.0, st);
-        try {
+        {
             rc = adjoint_impl(P, g, lam, o, S, st);
             if (grad_mu) launch_copy<double>(lam + last, grad_mu, Nd, st);
             if (grad_gamma2) {
@@ -711,11 +704,7 @@ static tsfde_status vjp_impl(Problem& P, const double* y, const double* gf, doub
                 *grad_alpha = -dev_dot(P, lam + last, g + last, Nd, st) / P.alpha;
             }
             TSFDE_HIP(hipStreamSynchronize(st));
-        } catch (...) {
-            (void)hipFree(w);
-            throw;
         }
-        (void)hipFree(w);
     })
     if (rc == TSFDE_ENOCONV) set_error("recover_f_vjp: adjoint tolerance not reached (rel. residual %.3e)", S.rel_res);
     return rc;
@@ -723,9 +712,9 @@ static tsfde_status vjp_impl(Problem& P, const double* y, const double* gf, doub
 
 // Runs fn(i, problem i, its stats, a stream) for every problem of a batch, up to max_inflight at once,
 // each worker thread on a non-blocking stream of its own, largest problems first; the persistent
-// kernels of the workers are ordinary launches sized to fit together (set_shared_launch).  Checks the
-// batch, holds the launch lock exclusively, and returns the first device error by index, else
-// TSFDE_ENOCONV if any problem missed its tolerance.
+// grids of the workers are limited so that that many fit together, and every persistent grid of the
+// process holds its share of the device's CU slots while it runs (residency.hpp).  Checks the batch
+// and returns the first device error by index, else TSFDE_ENOCONV if any problem missed its tolerance.
 template <typename F>
 static tsfde_status run_batch(const char* name, tsfde_problem* const* probs, int count, const Opts& o,
                               tsfde_stats* stats, int max_inflight, void* stream, F&& fn) {
@@ -746,7 +735,6 @@ static tsfde_status run_batch(const char* name, tsfde_problem* const* probs, int
         if (!block_solver_supported(*probs[i]->p, o)) return TSFDE_ENOTIMPL;
     }
     if (count == 0) return TSFDE_OK;
-    std::unique_lock<std::shared_mutex> lk(g_launch_mx);
     int dev = 0;
     TSFDE_GUARD(name, {
         TSFDE_HIP(hipGetDevice(&dev));
@@ -906,7 +894,6 @@ tsfde_status tsfde_apply_P_inv(tsfde_problem* prob, const double* z, double* y, 
     const Opts o = get_opts(opts);
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
     if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
-    SharedLaunch lk(g_launch_mx);
     TSFDE_GUARD("apply_P_inv", pinv_impl<double>(P, z, y, o, (hipStream_t)stream, true);)
     return TSFDE_OK;
 }
@@ -920,7 +907,6 @@ tsfde_status tsfde_apply_P_inv_f32(tsfde_problem* prob, const float* z, float* y
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
     if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
     o.inner_tol = std::max(o.inner_tol, kInnerTolF32);
-    SharedLaunch lk(g_launch_mx);
     TSFDE_GUARD("apply_P_inv_f32", pinv_impl<float>(P, z, y, o, (hipStream_t)stream, true);)
     return TSFDE_OK;
 }
@@ -936,7 +922,6 @@ tsfde_status tsfde_gmres_solve(tsfde_problem* prob, const double* b, double* x, 
     tsfde_stats S{};
     tsfde_status rc = TSFDE_OK;
     hipStream_t st = (hipStream_t)stream;
-    SharedLaunch lk(g_launch_mx);
     TSFDE_GUARD("gmres_solve", {
         if (!b) {
             launch_build_z(P, P.z_rhs, st);
@@ -957,7 +942,6 @@ tsfde_status tsfde_recover_f(tsfde_problem* prob, double* f_out, double* work, c
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
     if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
     tsfde_stats S{};
-    SharedLaunch lk(g_launch_mx);
     const tsfde_status rc = recover_impl(P, f_out, work, o, S, (hipStream_t)stream);
     if (stats) *stats = S;
     return rc;
@@ -1018,7 +1002,6 @@ tsfde_status tsfde_forward_solve(tsfde_problem* prob, const double* f, double* v
     if (opts && !check_opts(o)) return TSFDE_EINVAL;
     o.block_solver = TSFDE_BLOCK_CG;  // the direct problem is solved, not preconditioned
     hipStream_t st = (hipStream_t)stream;
-    SharedLaunch lk(g_launch_mx);
     TSFDE_GUARD("forward_solve", {
         double* zh = nullptr;
         double* y = nullptr;
@@ -1095,7 +1078,6 @@ tsfde_status tsfde_arnoldi(tsfde_problem* prob, const double* b, int k, double* 
     if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
     hipStream_t st = (hipStream_t)stream;
     const long long n = P.ntot;
-    SharedLaunch lk(g_launch_mx);
     int done = 0;
     TSFDE_GUARD("arnoldi", {
         SolveOps ops;

@@ -101,6 +101,46 @@ def test_gmres_fp64_and_mixed_match_dense_lu(dense_case):
         assert np.linalg.norm(x.cpu().numpy() - x_lu) <= 1e-10 * np.linalg.norm(x_lu)
 
 
+def test_mixed_refinement_checks_the_last_correction():
+    """MIXED with a single refinement sweep: the residual of the corrected x is computed, so a sweep
+    that reaches the tolerance reports convergence (and the statistics describe the returned x)."""
+    inp = inputs.small(1, 12, 7)
+    p = workloads.with_data(inp)
+    x_lu = np.linalg.solve(system.dense_A(p), system.rhs_z(p))
+    with gpu_problem(inp, p) as g:
+        f, st = g.recover_f(tsfde.default_opts(tol=1e-4, precision=tsfde.MIXED, max_refine=1, refine_tol=1e-5),
+                            raise_noconv=True)
+        assert st.converged == 1 and st.refinements == 1 and st.rel_res <= 1e-4
+        assert rel_err(f.cpu().numpy(), x_lu[p.S * p.Nd:]) <= 1e-2
+        # two refinement sweeps to a tight tolerance, repeated on the same problem (problem-owned buffers)
+        for _ in range(2):
+            f2, s2 = g.recover_f(tsfde.default_opts(tol=1e-12, precision=tsfde.MIXED), raise_noconv=True)
+            assert s2.converged == 1 and s2.rel_res <= 1e-12
+            assert rel_err(f2.cpu().numpy(), x_lu[p.S * p.Nd:]) <= 1e-8
+
+
+def test_barrier_timeout_returns_edevice_and_recovers(monkeypatch):
+    """A device-wide barrier wait of the persistent P^-1 that outlasts its bound ends the grid normally
+    and the call reports EDEVICE; the bound is forced from the host (0 us, so the first workgroup to
+    wait gives up at once).  With the default bound the next call on the same problem is exact."""
+    inp = inputs.small(2, 15, 9, beta=0.5, omega=1.5)
+    p = workloads.with_data(inp)
+    P = system.dense_P(p)
+    zz = np.random.default_rng(41).standard_normal(p.n_tot)
+    ref = np.linalg.solve(P, zz)
+    o = tsfde.default_opts(inner_tol=1e-14, inner_maxit=500)
+    with gpu_problem(inp, p) as g:
+        monkeypatch.setenv("TSFDE_PINV_BLOCKS", "4")
+        monkeypatch.setenv("TSFDE_BARRIER_TIMEOUT_US", "0")
+        with pytest.raises(tsfde.TsfdeError) as ei:
+            g.apply_P_inv(torch.tensor(zz, device=DEV), opts=tsfde.default_opts(inner_tol=1e-14, inner_maxit=5))
+        assert ei.value.status == tsfde.EDEVICE
+        assert "timed out" in str(ei.value)
+        monkeypatch.delenv("TSFDE_BARRIER_TIMEOUT_US")
+        y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=o).cpu().numpy()
+    assert rel_err(y, ref) <= 1e-10
+
+
 @pytest.mark.parametrize("restart", [3, 70])
 def test_gmres_unpreconditioned_restarts_match_dense_lu(restart):
     """Arnoldi without the preconditioner: restart 70 takes the Gram-Schmidt sweeps past 64 basis
@@ -130,6 +170,31 @@ def test_forward_solve_matches_oracle():
     with tsfde.Problem.from_inputs(inp, stencil=p.a()) as g:
         v = g.forward_solve(torch.tensor(inp.f_true, device=DEV), opts=tsfde.default_opts(inner_tol=1e-14))
     assert rel_err(v.cpu().numpy(), ref) <= 1e-11
+
+
+@pytest.mark.parametrize("d,N,M", [(1, 12, 7), (2, 6, 5), (2, 15, 9)])
+def test_initial_state_rho_matches_dense(d, N, M):
+    """A nonzero initial state rho = v^(0): the library builds z^(s) = b_{s-1} D_1^(s) rho (§5, eq.
+    lin-syst) and z-hat of the direct problem (§6.1) itself; the whole solution y of recover_f and
+    the direct solve are checked against the dense LU solutions with the oracle's z and z-hat."""
+    import dataclasses
+    inp = inputs.small(d, N, M, beta=0.4, omega=1.7, alpha=1e-3)
+    rng = np.random.default_rng(31)
+    inp = dataclasses.replace(inp, rho=1.0 + rng.standard_normal(inp.Nd))
+    p = workloads.with_data(inp)
+    assert np.abs(p.rho).max() > 0.5
+    x_lu = np.linalg.solve(system.dense_A(p), system.rhs_z(p))
+    v_lu = np.linalg.solve(system.dense_Ahat(p), system.rhs_zhat(p, inp.f_true))
+    with gpu_problem(inp, p) as g:
+        work = torch.zeros(p.n_tot, dtype=torch.float64, device=DEV)
+        f, st = g.recover_f(tsfde.default_opts(tol=3e-13, inner_tol=1e-14, inner_maxit=500), work=work,
+                            raise_noconv=True)
+        v = g.forward_solve(torch.tensor(inp.f_true, device=DEV), opts=tsfde.default_opts(inner_tol=1e-14))
+        y = work.cpu().numpy()
+    assert st.converged == 1
+    assert rel_err(y, x_lu) <= 1e-10
+    assert rel_err(f.cpu().numpy(), x_lu[p.S * p.Nd:]) <= 1e-10
+    assert rel_err(v.cpu().numpy(), v_lu) <= 1e-11
 
 
 @pytest.mark.parametrize("shape", [(1, 100, 70), (1, 255, 130), (2, 13, 70), (2, 31, 20)])
