@@ -212,6 +212,28 @@ tsfde_status tsfde_apply_P_inv_f32(tsfde_problem* prob, const float* z, float* y
                                    const tsfde_opts* opts, void* stream);
 
 /*
+ * tsfde_apply_P_inv without device allocations, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same operation, options and kernels as tsfde_apply_P_inv, but
+ * the work buffers of the forward substitution live in a static device array of
+ * 32 MiB that the library holds on every device it runs on until the process ends
+ * (about 216 bytes per grid point of a slice: N^d up to about 150 000; 2D N = 255
+ * needs 14.6 MB).  The call allocates nothing: no hipMalloc, hipFree or allocating
+ * library routine.  The problem's own arrays come from tsfde_create_problem.
+ *   z, y   device, (M+1) N^d, must not overlap; the call synchronises `stream`
+ *   opts   as tsfde_apply_P_inv; TSFDE_BLOCK_STRANG returns TSFDE_ENOTIMPL (its
+ *          tables are built on first use), as do shapes without the persistent
+ *          kernels (circulant embedding L > 8192)
+ * Returns TSFDE_ENOMEM, with the sizes in the message, when the problem needs more
+ * than the static array holds.  Calls on one device share that array (it keeps the
+ * last call's contents; the call clears what must start at zero): concurrent calls
+ * on one device are serialised by the library, so overlapping calls from several
+ * host threads wait for each other.
+ */
+tsfde_status tsfde_apply_P_inv_noalloc(tsfde_problem* prob, const double* z, double* y,
+                                       const tsfde_opts* opts, void* stream);
+
+/*
  * Solve A x = b by right-preconditioned flexible GMRES(m) (§5: GMRES with P of §5.1).
  *   b      device, (M+1) N^d; NULL uses the system's own right-hand side z of eq. lin-syst
  *   x      device, (M+1) N^d; in: initial guess, out: solution (last iterate on ENOCONV)

@@ -192,6 +192,13 @@ long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T*
                               int inner_maxit, bool last_block, int extrap, int tblocks, hipStream_t st);
 template <typename T>
 void pinv_persistent_free(void* wptr);
+// The same FP64 forward substitution with every work buffer in the library's static device scratch
+// (tsfde_apply_P_inv_noalloc): allocates nothing.  pinv_noalloc_bytes is the scratch the problem
+// needs, kNoAllocScratchBytes what the scratch holds.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+size_t pinv_noalloc_bytes(const Problem& P);
+long long pinv_persistent_run_noalloc(Problem& P, const double* z, double* y, double inner_tol, int inner_maxit,
+                                      int extrap, int tblocks, hipStream_t st);
 void set_persistent_blocks(int g);
 // Batch mode of the calling thread: its persistent kernels are ordinary launches sized so that
 // kMaxInflight of them fit the device together (tsfde_recover_f_batch)

@@ -112,6 +112,80 @@ long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T*
     return run_segments(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, tblocks, st);
 }
 
+// ---------------------------------------------------------------------------
+// allocation-free form (tsfde_apply_P_inv_noalloc): the work buffers of PersistentWork<double> laid
+// out in one static device array
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr size_t kAlign = 256;
+size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+struct NoAllocLayout {  // byte offsets into the scratch
+    size_t buf, tt, spec, part, bar, iters, end;
+};
+
+NoAllocLayout noalloc_layout(const Problem& P) {
+    NoAllocLayout l{};
+    const size_t ns = (size_t)spec_stride(P.N), nt = (size_t)spec_stride(P.Nt);
+    size_t o = 0;
+    l.buf = o;
+    o = align_up(o + sizeof(double) * (size_t)(8 + kHB) * P.Nd);
+    l.tt = o;
+    if (P.d == 2) o = align_up(o + sizeof(double) * ((size_t)P.Nt + P.N) * nt);
+    l.spec = o;
+    if (P.d == 2) o = align_up(o + sizeof(cplx<double>) * (size_t)P.H * ns);
+    l.part = o;
+    o = align_up(o + sizeof(double) * 1024 * kNPart);
+    l.bar = o;
+    o = align_up(o + 64);
+    l.iters = o;
+    o = align_up(o + sizeof(long long));
+    l.end = o;
+    return l;
+}
+
+// the scratch's device address on each device, looked up once per device with that device current
+unsigned char* scratch_address(int dev) {
+    constexpr int kMaxDev = 64;
+    static std::mutex mx;
+    static unsigned char* addr[kMaxDev] = {};
+    if (dev < 0 || dev >= kMaxDev) throw HipError{hipErrorInvalidDevice, "apply_P_inv_noalloc: device index"};
+    std::lock_guard<std::mutex> lk(mx);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) throw HipError{e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)"};
+        addr[dev] = static_cast<unsigned char*>(p);
+    }
+    return addr[dev];
+}
+}  // namespace
+
+size_t pinv_noalloc_bytes(const Problem& P) { return noalloc_layout(P).end; }
+
+long long pinv_persistent_run_noalloc(Problem& P, const double* z, double* y, double inner_tol, int inner_maxit,
+                                      int extrap, int tblocks, hipStream_t st) {
+    const NoAllocLayout l = noalloc_layout(P);
+    if (l.end > kNoAllocScratchBytes)
+        throw HipError{hipErrorOutOfMemory, "apply_P_inv_noalloc: the problem needs more than the static scratch"};
+    int dev = 0;
+    TSFDE_HIP(hipGetDevice(&dev));
+    unsigned char* base = scratch_address(dev);
+    PersistentWork<double> W;
+    W.buf = reinterpret_cast<double*>(base + l.buf);
+    W.tt = P.d == 2 ? reinterpret_cast<double*>(base + l.tt) : nullptr;
+    W.spec = P.d == 2 ? reinterpret_cast<cplx<double>*>(base + l.spec) : nullptr;
+    W.part = reinterpret_cast<double*>(base + l.part);
+    W.bar = reinterpret_cast<unsigned*>(base + l.bar);
+    W.iters = reinterpret_cast<long long*>(base + l.iters);
+    // the scratch keeps the previous call's contents: the work vectors start from zero, as the
+    // problem-owned buffers do (the counters are cleared by the launches themselves)
+    launch_fill(reinterpret_cast<float*>(base), (long long)(l.part / sizeof(float)), 0.0f, st);
+    return run_segments<double>(P, P.f64, W, z, y, inner_tol, inner_maxit, true, extrap, tblocks, st);
+}
+
 template <typename T>
 void pinv_persistent_free(void* wptr) {
     if (!wptr) return;

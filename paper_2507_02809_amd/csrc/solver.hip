@@ -898,6 +898,44 @@ tsfde_status tsfde_apply_P_inv(tsfde_problem* prob, const double* z, double* y, 
     return TSFDE_OK;
 }
 
+tsfde_status tsfde_apply_P_inv_noalloc(tsfde_problem* prob, const double* z, double* y, const tsfde_opts* opts,
+                                       void* stream) {
+    if (!prob || !y || !z) { set_error("apply_P_inv_noalloc: NULL argument"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    if (overlap(y, z, sizeof(double) * P.ntot)) { set_error("apply_P_inv_noalloc: y and z overlap"); return TSFDE_EINVAL; }
+    const Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    if (o.block_solver == TSFDE_BLOCK_STRANG) {
+        set_error("apply_P_inv_noalloc: TSFDE_BLOCK_STRANG builds device tables on first use; use tsfde_apply_P_inv");
+        return TSFDE_ENOTIMPL;
+    }
+    if (!persistent_supported(P)) {
+        set_error("apply_P_inv_noalloc: this shape has no persistent forward-substitution kernel (L = %d)", P.L);
+        return TSFDE_ENOTIMPL;
+    }
+    if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
+    const size_t need = pinv_noalloc_bytes(P);
+    if (need > kNoAllocScratchBytes) {
+        set_error("apply_P_inv_noalloc: the problem needs %zu bytes of scratch, the static scratch holds %zu", need,
+                  kNoAllocScratchBytes);
+        return TSFDE_ENOMEM;
+    }
+    // calls on one device share its scratch: they are serialised (each call ends synchronised)
+    static std::mutex mx[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        set_error("apply_P_inv_noalloc: no usable current device");
+        return TSFDE_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(mx[dev]);
+    set_persistent_blocks(env_int("TSFDE_PINV_BLOCKS", -1));
+    set_persistent_fixed_length(env_int("TSFDE_PINV_FIXED", 1) != 0);
+    TSFDE_GUARD("apply_P_inv_noalloc",
+                pinv_persistent_run_noalloc(P, z, y, o.inner_tol, o.inner_maxit, env_int("TSFDE_EXTRAP", o.warm_start),
+                                            o.block_solver == TSFDE_BLOCK_TAU ? 1 : 0, (hipStream_t)stream);)
+    return TSFDE_OK;
+}
+
 tsfde_status tsfde_apply_P_inv_f32(tsfde_problem* prob, const float* z, float* y, const tsfde_opts* opts,
                                    void* stream) {
     if (!prob || !y || !z) { set_error("apply_P_inv_f32: NULL argument"); return TSFDE_EINVAL; }

@@ -22,7 +22,7 @@ EXPORTED = [
     "tsfde_default_opts", "tsfde_create_problem", "tsfde_create_problem_ex", "tsfde_set_mu", "tsfde_set_alpha",
     "tsfde_destroy_problem", "tsfde_vector_length", "tsfde_problem_scalars", "tsfde_get_stencil",
     "tsfde_compute_stencil", "tsfde_apply_A", "tsfde_apply_A_f32", "tsfde_apply_P_inv",
-    "tsfde_apply_P_inv_f32", "tsfde_gmres_solve", "tsfde_recover_f", "tsfde_recover_f_batch",
+    "tsfde_apply_P_inv_f32", "tsfde_apply_P_inv_noalloc", "tsfde_gmres_solve", "tsfde_recover_f", "tsfde_recover_f_batch",
     "tsfde_forward_solve", "tsfde_apply_AT", "tsfde_apply_PT_inv", "tsfde_adjoint_solve",
     "tsfde_recover_f_vjp", "tsfde_recover_f_vjp_batch", "tsfde_arnoldi", "tsfde_last_error",
 ]
@@ -78,6 +78,7 @@ def lib():
     L.tsfde_apply_A_f32.argtypes = [vp, vp, vp, vp]
     L.tsfde_apply_P_inv.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
     L.tsfde_apply_P_inv_f32.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
+    L.tsfde_apply_P_inv_noalloc.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
     L.tsfde_gmres_solve.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_recover_f.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_forward_solve.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
@@ -229,6 +230,14 @@ class Problem:
         fn = lib().tsfde_apply_P_inv_f32 if f32 else lib().tsfde_apply_P_inv
         _check(fn(self._h, _dptr(z, z.dtype, self.n_tot, "z"), _dptr(y, z.dtype, self.n_tot, "y"),
                   C.byref(opts) if opts is not None else None, _stream(stream)))
+        return y
+
+    def apply_P_inv_noalloc(self, z, y, opts: Optional[Opts] = None, stream=None):
+        """y = P^{-1} z (FP64) with the library's static device scratch: no device allocation, y given."""
+        import torch
+        _check(lib().tsfde_apply_P_inv_noalloc(self._h, _dptr(z, torch.float64, self.n_tot, "z"),
+                                               _dptr(y, torch.float64, self.n_tot, "y"),
+                                               C.byref(opts) if opts is not None else None, _stream(stream)))
         return y
 
     def gmres_solve(self, b=None, x=None, opts: Optional[Opts] = None, stream=None, raise_noconv=False):
