@@ -95,6 +95,16 @@ typedef struct tsfde_opts {
                             TSFDE_WARM_HALF (1.5 y^(s-1) - 0.5 y^(s-2)).  The
                             persistent P^{-1} applies it; the multi-launch path
                             always starts from y^(s-1)              (LINEAR) */
+    long long max_device_bytes; /* cap on the device memory of the problem's arrays
+                            plus the FGMRES basis (0: none).  If keeping the m
+                            preconditioned directions z_j would exceed it, they
+                            are recomputed (z_j = P^{-1} v_j again at the end of
+                            each cycle; P^{-1} is deterministic, so the same
+                            directions return); if even the basis V does not fit,
+                            the solve returns TSFDE_ENOMEM            (0)     */
+    int recompute_z;     /* 1: recompute the z_j at the end of each cycle instead
+                            of keeping them (halves the basis memory, adds m
+                            P^{-1} applications per cycle)              (0)     */
 } tsfde_opts;
 
 typedef enum { TSFDE_BLOCK_CG = 0, TSFDE_BLOCK_TAU = 1, TSFDE_BLOCK_STRANG = 2 } tsfde_block_solver;
@@ -118,6 +128,13 @@ typedef struct tsfde_stats {
     double t_precond;          /* seconds applying P^{-1}                       */
     double t_matvec;           /* seconds applying A                            */
     double t_ortho;            /* seconds in Gram-Schmidt and the x update      */
+    int history_len;           /* entries of history                            */
+    const double* history;     /* relative residuals as the solve saw them: the
+                                  true one at every (re)start, the least-squares
+                                  estimate after every Arnoldi step (MIXED: each
+                                  sweep relative to its own right-hand side).
+                                  Host memory owned by the problem, valid until
+                                  its next solve or its destruction            */
 } tsfde_stats;
 
 void tsfde_default_opts(tsfde_opts* opts);
@@ -160,6 +177,12 @@ tsfde_status tsfde_create_problem_ex(int d, int N, int M, double T, double beta,
 /* Replace mu_eps (host [N^d]) without rebuilding the problem. */
 tsfde_status tsfde_set_mu(tsfde_problem* prob, const double* mu);
 
+/* Replace the gamma2 samples (host [M][N^d], gamma_2(x_j, t_s) > 0; §4 eq. numer-scheme)
+ * without rebuilding the problem: the device copies of gamma2, of the symmetrised
+ * diagonal e_0 gamma1/gamma2 of every block of P and of its slice means are refreshed.
+ * Returns EINVAL for a sample <= 0, ENONFINITE for NaN/Inf. */
+tsfde_status tsfde_set_gamma2(tsfde_problem* prob, const double* gamma2);
+
 /* Replace the regularisation parameter alpha (> 0; §3): only c_f = alpha/h^omega
  * of the last block row changes, so nothing is rebuilt (a sweep over alpha
  * for a parameter choice rule reuses one problem). */
@@ -169,6 +192,10 @@ void tsfde_destroy_problem(tsfde_problem* prob);
 
 /* (M+1) * N^d, the length of y and z. */
 size_t tsfde_vector_length(const tsfde_problem* prob);
+
+/* Device bytes the problem holds now: its arrays, the work buffers its calls have
+   allocated so far and the FGMRES basis (opts.max_device_bytes caps this total). */
+size_t tsfde_device_bytes(const tsfde_problem* prob);
 
 /* Scalars of the discretisation: out[0] = h, out[1] = dt, out[2] = eta = dt^beta Gamma(2-beta),
    out[3] = eta/h^omega, out[4] = alpha/h^omega, out[5] = circulant embedding size L. */

@@ -20,6 +20,35 @@ def apply_AT(p: Problem, lam: np.ndarray) -> np.ndarray:
     return dense_A(p).T @ lam
 
 
+def matvec_T_entry(p: Problem, w: np.ndarray, m: int, j: int) -> float:
+    """Entry (m, j) of A^T w (0-based slice m, flat spatial index j), summed down column (m, j) of the
+    blocks of A in eq. lin-syst (§5), with the stencil sum written out (no FFT, no dense matrix):
+        m < S:  sum_{s=m}^{S-1} e_{s-m} gamma1^(s)_j w^(s)_j + c_t sum_i a_{i-j} gamma2^(m)_i w^(m)_i
+                + [m = S-1] w^(S)_j
+        m = S:  -eta sum_s q^(s) w^(s)_j + c_f sum_i a_{i-j} gamma2^(S)_i w^(S)_i
+    (1-based slices of the paper shifted by one; the last block column multiplies f~)."""
+    S, N, d = p.S, p.N, p.d
+    W = w.reshape(S + 1, p.Nd)
+    a = p.a()
+    if d == 1:
+        lag = np.abs(np.arange(N) - j)
+        Bcol = lambda v: float(np.dot(a[lag], v))
+    else:
+        j1, j2 = divmod(j, N)
+        l1 = np.abs(np.arange(N) - j1)
+        l2 = np.abs(np.arange(N) - j2)
+        Bcol = lambda v: float(np.sum(a[l1[:, None], l2[None, :]] * v.reshape(N, N)))
+    if m == S:
+        return (-p.eta * float(np.dot(p.q, W[:S, j]))
+                + p.c_f * Bcol(p.gamma2[S - 1] * W[S]))
+    e = p.e()
+    hist = sum(e[s - m] * p.gamma1[s, j] * W[s, j] for s in range(m, S))
+    out = hist + p.c_t * Bcol(p.gamma2[m] * W[m])
+    if m == S - 1:
+        out += W[S, j]
+    return float(out)
+
+
 def PT_solve(p: Problem, g: np.ndarray) -> np.ndarray:
     """P^{-T} g by a dense solve."""
     return np.linalg.solve(dense_P(p).T, g)

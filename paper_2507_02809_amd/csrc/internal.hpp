@@ -84,6 +84,8 @@ struct Problem {
     double* V = nullptr;
     double* Z = nullptr;
     int basis_m = 0;
+    int basis_zm = 0;            // preconditioned directions Z held (basis_m, or 1 when recomputed)
+    std::vector<double> res_hist;  // relative residuals of the last solve (tsfde_stats.history)
     double* arn_part = nullptr;  // Arnoldi block partials [kArnMaxK][kArnBlocks]
     double* arn_h = nullptr;     // Arnoldi coefficients, 2 (kMaxRestart + 2) + 1
     double* rwork = nullptr;     // FGMRES residual (n_tot)
@@ -97,10 +99,21 @@ struct Problem {
     double* strang_hist = nullptr;  // kHB slices: far history of one block of steps (FP64, or FP32 in place)
     void* pw64 = nullptr;           // persistent P^{-1} work buffers (FP64 / FP32)
     void* pw32 = nullptr;
+    double* fwd_work = nullptr;     // direct problem: z-hat and the substitution's output (2 n_tot)
     double* dev_scalars = nullptr;  // small device scratch (dots, flags)
     double* host_scalars = nullptr; // pinned mirror
-    size_t bytes = 0;
+    size_t bytes = 0;               // device bytes the problem holds (tsfde_device_bytes)
+    size_t basis_bytes = 0;         // of which the FGMRES basis V, Z
 };
+
+// hipMalloc of `count` values counted against the problem's device bytes
+template <typename T>
+inline void dev_alloc(Problem& P, T*& ptr, size_t count) {
+    void* p = nullptr;
+    TSFDE_HIP(hipMalloc(&p, sizeof(T) * count));
+    ptr = static_cast<T*>(p);
+    P.bytes += sizeof(T) * count;
+}
 
 // ---- launchers (kernels.hip / spectral.hip) ----
 template <typename T>

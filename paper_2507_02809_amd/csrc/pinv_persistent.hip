@@ -44,6 +44,8 @@ void ensure_work(Problem& P, PersistentWork<T>& W) {
     TSFDE_HIP(hipMalloc(&W.bar, 64));
     TSFDE_HIP(hipMalloc(&W.iters, sizeof(long long)));
     TSFDE_HIP(hipMemset(W.buf, 0, sizeof(T) * (size_t)(8 + kHB) * P.Nd));
+    P.bytes += sizeof(T) * (size_t)(8 + kHB) * P.Nd + sizeof(double) * 1024 * kNPart + 64 + sizeof(long long) +
+               (P.d == 2 ? sizeof(T) * ((size_t)P.Nt + P.N) * nt + sizeof(cplx<T>) * (size_t)P.H * ns : 0);
 }
 
 bool persistent_supported(const Problem& P) {

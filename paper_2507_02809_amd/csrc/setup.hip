@@ -340,7 +340,7 @@ void free_problem(Problem* P) {
     pinv_persistent_free<float>(P->pw32);
     void* ptrs[] = {P->d_bw, P->d_rho, P->d_mu, P->z_rhs, P->xbuf, P->V, P->Z, P->arn_part, P->arn_h, P->rwork, P->adj_u,
                     P->dev_scalars, P->strang64, P->strang32, P->strang_hist, P->refine_work, P->vjp_work,
-                    P->d_sigma};
+                    P->d_sigma, P->fwd_work};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (P->host_scalars) (void)hipHostFree(P->host_scalars);
@@ -508,6 +508,44 @@ tsfde_status create(int d, int N, int M, double T, double beta, double omega, do
         return TSFDE_ENOMEM;
     }
     *out = P;
+    return TSFDE_OK;
+}
+
+// copy host values into an existing device array of T
+template <typename T>
+static void refresh(T* d, const double* src, size_t n) {
+    std::vector<T> tmp(src, src + n);
+    TSFDE_HIP(hipMemcpy(d, tmp.data(), sizeof(T) * n, hipMemcpyHostToDevice));
+}
+
+tsfde_status set_gamma2(Problem* P, const double* gamma2) {
+    if (!P || !gamma2) { set_error("set_gamma2: NULL argument"); return TSFDE_EINVAL; }
+    const size_t MN = (size_t)P->M * P->Nd;
+    if (!finite_all(gamma2, MN)) { set_error("set_gamma2: non-finite value in gamma2"); return TSFDE_ENONFINITE; }
+    for (size_t i = 0; i < MN; ++i)
+        if (gamma2[i] <= 0.0) { set_error("set_gamma2: need gamma2 > 0 (index %zu)", i); return TSFDE_EINVAL; }
+    try {
+        P->gamma2_h.assign(gamma2, gamma2 + MN);
+        // the symmetrised diagonal e_0 gamma1/gamma2 of every block and its slice means
+        std::vector<double> dg(MN);
+        for (int s = 0; s < P->M; ++s) {
+            double acc = 0.0;
+            for (long long j = 0; j < P->Nd; ++j) {
+                const size_t o = (size_t)s * P->Nd + j;
+                dg[o] = P->e[0] * P->gamma1_h[o] / gamma2[o];
+                acc += dg[o];
+            }
+            P->sigma[s] = acc / P->Nd;
+        }
+        refresh(P->f64.gamma2, gamma2, MN);
+        refresh(P->f64.dg, dg.data(), MN);
+        refresh(P->f32.gamma2, gamma2, MN);
+        refresh(P->f32.dg, dg.data(), MN);
+        TSFDE_HIP(hipMemcpy(P->d_sigma, P->sigma.data(), sizeof(double) * P->M, hipMemcpyHostToDevice));
+    } catch (const HipError& e) {
+        set_error("set_gamma2: %s failed: %s", e.where.c_str(), hipGetErrorString(e.code));
+        return TSFDE_EDEVICE;
+    }
     return TSFDE_OK;
 }
 

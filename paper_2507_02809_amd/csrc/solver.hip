@@ -31,6 +31,7 @@ tsfde_status create(int d, int N, int M, double T, double beta, double omega, do
                     const double* gamma2, const double* q, const double* rho, const double* mu, double length,
                     const double* stencil, Problem** out);
 tsfde_status set_mu(Problem* P, const double* mu);
+tsfde_status set_gamma2(Problem* P, const double* gamma2);
 tsfde_status compute_stencil(int d, int N, double omega, double* out);
 void free_problem(Problem* P);
 const char* last_error();
@@ -54,6 +55,8 @@ struct Opts {
     int restart = 50, maxit = 0, precision = TSFDE_FP64, use_precond = 1, inner_maxit = 200, max_refine = 30;
     int block_solver = TSFDE_BLOCK_CG, warm_start = TSFDE_WARM_LINEAR;
     double tol = 1e-10, inner_tol = 1e-12, refine_tol = 1e-5;
+    long long max_device_bytes = 0;
+    int recompute_z = 0;
 };
 
 static Opts get_opts(const tsfde_opts* o) {
@@ -70,6 +73,8 @@ static Opts get_opts(const tsfde_opts* o) {
     r.max_refine = o->max_refine;
     r.block_solver = o->block_solver;
     r.warm_start = o->warm_start;
+    r.max_device_bytes = o->max_device_bytes;
+    r.recompute_z = o->recompute_z;
     return r;
 }
 
@@ -90,6 +95,10 @@ static bool check_opts(const Opts& o) {
     }
     if (o.block_solver != TSFDE_BLOCK_CG && o.block_solver != TSFDE_BLOCK_TAU && o.block_solver != TSFDE_BLOCK_STRANG) {
         set_error("opts.block_solver invalid");
+        return false;
+    }
+    if (o.max_device_bytes < 0 || o.recompute_z < 0 || o.recompute_z > 1) {
+        set_error("opts.max_device_bytes must be >= 0 and opts.recompute_z 0 or 1");
         return false;
     }
     return true;
@@ -262,7 +271,7 @@ static long long pinv_launch(Problem& P, const T* z, T* y, const Opts& o, hipStr
 // ---------------------------------------------------------------------------
 static void apply_AT_impl(Problem& P, const double* lam, double* z, hipStream_t st) {
     Dev<double>& D = P.f64;
-    if (!P.adj_u) TSFDE_HIP(hipMalloc(&P.adj_u, sizeof(double) * P.ntot));
+    if (!P.adj_u) dev_alloc(P, P.adj_u, P.ntot);
     launch_scale_g2<double>(P, D, lam, P.adj_u, -1, false, st);
     launch_history_adj<double>(P, D, lam, z, st);
     // B products of the gamma2-scaled slices added with weight c_t (c_f for the last); the last
@@ -303,15 +312,45 @@ struct SolveOps {
     std::function<long long(const double*, double*)> M; // out = M v (returns inner iterations)
 };
 
-static void ensure_basis(Problem& P, int m) {
-    if (P.basis_m >= m) return;
+// The Krylov basis V (m + 1 vectors) and the preconditioned directions Z (m vectors, or one when they
+// are recomputed at the end of each cycle instead of kept).  With a cap on the problem's device memory
+// (opts.max_device_bytes, 0 = none) Z is recomputed when keeping it would exceed the cap, and a basis
+// that does not fit even then is refused.  Returns whether Z is recomputed.
+struct CapError {
+    std::string msg;
+};
+
+static bool ensure_basis(Problem& P, int m, const Opts& o) {
+    const size_t vec = sizeof(double) * (size_t)P.ntot;
+    const size_t base = P.bytes - P.basis_bytes;  // the problem's other arrays
+    bool recompute = o.recompute_z != 0;
+    if (o.max_device_bytes > 0) {
+        const size_t cap = (size_t)o.max_device_bytes;
+        if (!recompute && base + (size_t)(2 * m + 1) * vec > cap) recompute = true;
+        if (base + (size_t)(m + 2) * vec > cap) {
+            char buf[256];
+            std::snprintf(buf, sizeof(buf),
+                          "max_device_bytes = %lld: the problem holds %zu bytes and the Krylov basis of restart %d needs "
+                          "at least %zu more (Z recomputed)",
+                          o.max_device_bytes, base, m, (size_t)(m + 2) * vec);
+            throw CapError{buf};
+        }
+    }
+    const int zm = recompute ? 1 : m;
+    if (P.basis_m >= m && P.basis_zm >= zm) return recompute;
     if (P.V) (void)hipFree(P.V);
     if (P.Z) (void)hipFree(P.Z);
     P.V = P.Z = nullptr;
-    P.basis_m = 0;
-    TSFDE_HIP(hipMalloc(&P.V, sizeof(double) * (size_t)(m + 1) * P.ntot));
-    TSFDE_HIP(hipMalloc(&P.Z, sizeof(double) * (size_t)m * P.ntot));
+    P.basis_m = P.basis_zm = 0;
+    P.bytes -= P.basis_bytes;
+    P.basis_bytes = 0;
+    dev_alloc(P, P.V, (size_t)(m + 1) * P.ntot);
+    P.basis_bytes += (size_t)(m + 1) * vec;
+    dev_alloc(P, P.Z, (size_t)zm * P.ntot);
+    P.basis_bytes += (size_t)zm * vec;
     P.basis_m = m;
+    P.basis_zm = zm;
+    return recompute;
 }
 
 // h = V[0..k)^T w, in chunks of at most kArnMaxK basis vectors
@@ -362,12 +401,12 @@ static double dev_dot(Problem& P, const double* a, const double* b, long long n,
 // Returns the number of Arnoldi steps; *conv set when the tolerance was met.
 static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, double* r_work, double rtol,
                   int restart, int maxit, hipStream_t st, tsfde_stats& S, bool& conv, double& relres,
-                  bool exact_final) {
+                  bool exact_final, const Opts& o) {
     const long long n = P.ntot;
-    ensure_basis(P, restart);
+    const bool recompute = ensure_basis(P, restart, o);
     const int nblk = kArnBlocks;
-    if (!P.arn_part) TSFDE_HIP(hipMalloc(&P.arn_part, sizeof(double) * kArnBlocks * kArnMaxK));
-    if (!P.arn_h) TSFDE_HIP(hipMalloc(&P.arn_h, sizeof(double) * (2 * (kMaxRestart + 2) + 1)));
+    if (!P.arn_part) dev_alloc(P, P.arn_part, kArnBlocks * kArnMaxK);
+    if (!P.arn_h) dev_alloc(P, P.arn_h, (2 * (kMaxRestart + 2) + 1));
     double* partials = P.arn_part;
     // hbuf: first-pass coefficients [0, restart + 2), second-pass ones [hs, 2 hs), then ||w||^2
     const int hs = restart + 2;
@@ -392,6 +431,7 @@ static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, d
         launch_axpby(1.0, b, -1.0, r_work, r_work, n, st);
         const double beta = std::sqrt(dev_dot(P, r_work, r_work, n, st));
         relres = beta / bnorm;
+        P.res_hist.push_back(relres);
         if (verbose())
             std::fprintf(stderr, "[tsfde] fgmres its=%d restarts=%d true relres=%.3e (target %.1e)\n", its, S.restarts,
                          relres, rtol);
@@ -405,7 +445,7 @@ static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, d
         bool lucky = false;
         for (int j = 0; j < m; ++j) {
             double* vj = P.V + (size_t)j * n;
-            double* zj = P.Z + (size_t)j * n;
+            double* zj = P.Z + (size_t)(recompute ? 0 : j) * n;
             double* w = P.V + (size_t)(j + 1) * n;
             t0 = now();
             S.inner_iters += ops.M(vj, zj);
@@ -442,6 +482,7 @@ static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, d
             k = j + 1;
             ++its;
             ++S.iters;
+            P.res_hist.push_back(std::fabs(g[j + 1]) / bnorm);
             if (verbose())
                 std::fprintf(stderr, "[tsfde]   it=%d est relres=%.3e inner=%lld\n", its, std::fabs(g[j + 1]) / bnorm,
                              (long long)S.inner_iters);
@@ -455,11 +496,24 @@ static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, d
             for (int l = i + 1; l < k; ++l) acc -= Hc[(size_t)i * restart + l] * yk[l];
             yk[i] = acc / Hc[(size_t)i * restart + i];
         }
-        TSFDE_HIP(hipMemcpyAsync(hbuf, yk.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
-        double t0u = now();
-        launch_gemv_add(P.Z, n, k, hbuf, x, st);
-        TSFDE_HIP(hipStreamSynchronize(st));
-        S.t_ortho += now() - t0u;
+        if (recompute) {
+            // z_j = M v_j again (the preconditioner is a deterministic function of its input, so the
+            // same directions come back), x += y_j z_j one at a time
+            for (int j = 0; j < k; ++j) {
+                double t0r = now();
+                S.inner_iters += ops.M(P.V + (size_t)j * n, P.Z);
+                TSFDE_HIP(hipStreamSynchronize(st));
+                S.t_precond += now() - t0r;
+                launch_axpby(yk[j], P.Z, 1.0, x, x, n, st);
+            }
+            TSFDE_HIP(hipStreamSynchronize(st));
+        } else {
+            TSFDE_HIP(hipMemcpyAsync(hbuf, yk.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+            double t0u = now();
+            launch_gemv_add(P.Z, n, k, hbuf, x, st);
+            TSFDE_HIP(hipStreamSynchronize(st));
+            S.t_ortho += now() - t0u;
+        }
         const double est = std::fabs(g[k]) / bnorm;
         if (est <= rtol && !exact_final) {
             relres = est;
@@ -477,10 +531,11 @@ static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, d
 // of M A (the same spectrum).
 static int arnoldi_impl(Problem& P, const SolveOps& ops, const double* b, int k, double* H, hipStream_t st) {
     const long long n = P.ntot;
-    ensure_basis(P, k);
+    Opts keep;  // Arnoldi keeps every direction z_j
+    ensure_basis(P, k, keep);
     const int nblk = kArnBlocks;
-    if (!P.arn_part) TSFDE_HIP(hipMalloc(&P.arn_part, sizeof(double) * kArnBlocks * kArnMaxK));
-    if (!P.arn_h) TSFDE_HIP(hipMalloc(&P.arn_h, sizeof(double) * (2 * (kMaxRestart + 2) + 1)));
+    if (!P.arn_part) dev_alloc(P, P.arn_part, kArnBlocks * kArnMaxK);
+    if (!P.arn_h) dev_alloc(P, P.arn_h, (2 * (kMaxRestart + 2) + 1));
     const int hs = k + 2;
     double* hbuf = P.arn_h;
     std::vector<double> hhost(2 * hs + 1);
@@ -510,6 +565,15 @@ static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o,
     const long long n = P.ntot;
     const int maxit = o.maxit > 0 ? o.maxit : (int)std::min<long long>(n, 1000);
     const double t_start = now();
+    P.res_hist.clear();
+    struct History {  // the stats point at the problem's history however the solve ends
+        Problem& P;
+        tsfde_stats& S;
+        ~History() {
+            S.history_len = (int)P.res_hist.size();
+            S.history = P.res_hist.data();
+        }
+    } hist{P, S};
     if (o.precision == TSFDE_FP64 || o.precision == TSFDE_PREC_F32) {
         SolveOps ops;
         ops.A = [&](const double* v, double* out) { apply_A_impl<double>(P, v, out, st); };
@@ -517,8 +581,8 @@ static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o,
         o32.inner_tol = std::max(o.inner_tol, kInnerTolF32);
         Dev<float>& F = P.f32;
         if (o.precision == TSFDE_PREC_F32 && !F.vecA) {
-            TSFDE_HIP(hipMalloc(&F.vecA, sizeof(float) * n));
-            TSFDE_HIP(hipMalloc(&F.vecB, sizeof(float) * n));
+            dev_alloc(P, F.vecA, n);
+            dev_alloc(P, F.vecB, n);
         }
         ops.M = [&](const double* v, double* out) -> long long {
             if (!o.use_precond) { launch_copy<double>(v, out, n, st); return 0; }
@@ -529,10 +593,10 @@ static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o,
             launch_f2d(F.vecB, out, n, st);
             return it;
         };
-        if (!P.rwork) TSFDE_HIP(hipMalloc(&P.rwork, sizeof(double) * n));
+        if (!P.rwork) dev_alloc(P, P.rwork, n);
         bool conv = false;
         double rel = 1.0;
-        fgmres(P, ops, b, x, P.rwork, o.tol, o.restart, maxit, st, S, conv, rel, true);
+        fgmres(P, ops, b, x, P.rwork, o.tol, o.restart, maxit, st, S, conv, rel, true, o);
         S.refinements = 1;
         S.converged = conv ? 1 : 0;
         S.rel_res = rel;
@@ -540,8 +604,8 @@ static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o,
         // iterative refinement: r = b - A x in FP64; inner FGMRES with FP32 operators on A d = r
         Dev<float>& F = P.f32;
         if (!F.vecA) {
-            TSFDE_HIP(hipMalloc(&F.vecA, sizeof(float) * n));
-            TSFDE_HIP(hipMalloc(&F.vecB, sizeof(float) * n));
+            dev_alloc(P, F.vecA, n);
+            dev_alloc(P, F.vecB, n);
         }
         SolveOps ops;
         ops.A = [&](const double* v, double* out) {
@@ -558,7 +622,7 @@ static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o,
             launch_f2d(F.vecB, out, n, st);
             return it;
         };
-        if (!P.refine_work) TSFDE_HIP(hipMalloc(&P.refine_work, sizeof(double) * 3 * (size_t)n));
+        if (!P.refine_work) dev_alloc(P, P.refine_work, 3 * (size_t)n);
         double* r = P.refine_work;
         double* d = r + n;
         double* rw = r + 2 * n;
@@ -582,7 +646,7 @@ static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o,
             bool conv = false;
             double rr = 1.0;
             used += fgmres(P, ops, r, d, rw, std::max(o.refine_tol, 0.5 * o.tol / std::max(rel, 1e-300)), o.restart,
-                           maxit - used, st, S, conv, rr, false);
+                           maxit - used, st, S, conv, rr, false, o);
             launch_axpby(1.0, x, 1.0, d, x, n, st);
             ++S.refinements;
         }
@@ -600,6 +664,15 @@ static tsfde_status adjoint_impl(Problem& P, const double* g, double* lam, const
     const long long n = P.ntot;
     const int maxit = o.maxit > 0 ? o.maxit : (int)std::min<long long>(n, 1000);
     const double t_start = now();
+    P.res_hist.clear();
+    struct History {
+        Problem& P;
+        tsfde_stats& S;
+        ~History() {
+            S.history_len = (int)P.res_hist.size();
+            S.history = P.res_hist.data();
+        }
+    } hist{P, S};
     SolveOps ops;
     ops.A = [&](const double* v, double* out) { apply_AT_impl(P, v, out, st); };
     ops.M = [&](const double* v, double* out) -> long long {
@@ -609,10 +682,10 @@ static tsfde_status adjoint_impl(Problem& P, const double* g, double* lam, const
         }
         return ptinv_launch(P, v, out, o, st);
     };
-    if (!P.rwork) TSFDE_HIP(hipMalloc(&P.rwork, sizeof(double) * n));
+    if (!P.rwork) dev_alloc(P, P.rwork, n);
     bool conv = false;
     double rel = 1.0;
-    fgmres(P, ops, g, lam, P.rwork, o.tol, o.restart, maxit, st, S, conv, rel, true);
+    fgmres(P, ops, g, lam, P.rwork, o.tol, o.restart, maxit, st, S, conv, rel, true, o);
     S.refinements = 1;
     S.converged = conv ? 1 : 0;
     S.rel_res = rel;
@@ -637,6 +710,9 @@ struct tsfde_problem {
     } catch (const HipError& e) {                                                         \
         set_error("%s: %s failed: %s", name, e.where.c_str(), hipGetErrorString(e.code)); \
         return e.code == hipErrorOutOfMemory ? TSFDE_ENOMEM : TSFDE_EDEVICE;              \
+    } catch (const CapError& e) {                                                         \
+        set_error("%s: %s", name, e.msg.c_str());                                         \
+        return TSFDE_ENOMEM;                                                              \
     } catch (const std::bad_alloc&) {                                                     \
         set_error("%s: host allocation failed", name);                                    \
         return TSFDE_ENOMEM;                                                              \
@@ -655,7 +731,7 @@ static tsfde_status recover_impl(Problem& P, double* f_out, double* work, const 
     TSFDE_GUARD("recover_f", {
         double* x = work;
         if (!x) {
-            if (!P.xbuf) TSFDE_HIP(hipMalloc(&P.xbuf, sizeof(double) * P.ntot));
+            if (!P.xbuf) dev_alloc(P, P.xbuf, P.ntot);
             x = P.xbuf;
         }
         launch_fill(x, P.ntot, 0.0, st);
@@ -675,7 +751,7 @@ static tsfde_status vjp_impl(Problem& P, const double* y, const double* gf, doub
     tsfde_status rc = TSFDE_OK;
     TSFDE_GUARD("recover_f_vjp", {
         // g = [0; gf], lam, then v = [0; y^(M)] and A v (problem-owned, allocated on first use)
-        if (!P.vjp_work) TSFDE_HIP(hipMalloc(&P.vjp_work, sizeof(double) * 3 * (size_t)n));
+        if (!P.vjp_work) dev_alloc(P, P.vjp_work, 3 * (size_t)n);
         double* w = P.vjp_work;
         double* g = w;
         double* lam = w + n;
@@ -804,6 +880,8 @@ void tsfde_default_opts(tsfde_opts* o) {
     o->inner_maxit = 200;
     o->refine_tol = 1e-5;
     o->max_refine = 30;
+    o->max_device_bytes = 0;
+    o->recompute_z = 0;
 }
 
 tsfde_status tsfde_create_problem_ex(int d, int N, int M, double T, double beta, double omega, double alpha,
@@ -832,6 +910,11 @@ tsfde_status tsfde_set_mu(tsfde_problem* prob, const double* mu) {
     return set_mu(prob->p, mu);
 }
 
+tsfde_status tsfde_set_gamma2(tsfde_problem* prob, const double* gamma2) {
+    if (!prob) { set_error("set_gamma2: NULL problem"); return TSFDE_EINVAL; }
+    return set_gamma2(prob->p, gamma2);
+}
+
 tsfde_status tsfde_set_alpha(tsfde_problem* prob, double alpha) {
     if (!prob) { set_error("set_alpha: NULL problem"); return TSFDE_EINVAL; }
     if (!(alpha > 0.0) || !std::isfinite(alpha)) { set_error("set_alpha: need alpha > 0"); return TSFDE_EINVAL; }
@@ -848,6 +931,8 @@ void tsfde_destroy_problem(tsfde_problem* prob) {
 }
 
 size_t tsfde_vector_length(const tsfde_problem* prob) { return prob ? (size_t)prob->p->ntot : 0; }
+
+size_t tsfde_device_bytes(const tsfde_problem* prob) { return prob ? prob->p->bytes : 0; }
 
 tsfde_status tsfde_problem_scalars(const tsfde_problem* prob, double out[6]) {
     if (!prob || !out) { set_error("problem_scalars: NULL argument"); return TSFDE_EINVAL; }
@@ -1041,16 +1126,13 @@ tsfde_status tsfde_forward_solve(tsfde_problem* prob, const double* f, double* v
     o.block_solver = TSFDE_BLOCK_CG;  // the direct problem is solved, not preconditioned
     hipStream_t st = (hipStream_t)stream;
     TSFDE_GUARD("forward_solve", {
-        double* zh = nullptr;
-        double* y = nullptr;
-        TSFDE_HIP(hipMalloc(&zh, sizeof(double) * P.ntot));
-        TSFDE_HIP(hipMalloc(&y, sizeof(double) * P.ntot));
+        if (!P.fwd_work) dev_alloc(P, P.fwd_work, 2 * (size_t)P.ntot);
+        double* zh = P.fwd_work;
+        double* y = P.fwd_work + P.ntot;
         launch_build_zhat(P, f, zh, st);
         pinv_impl<double>(P, zh, y, o, st, false);
         launch_copy<double>(y, v, (long long)P.M * P.Nd, st);
         TSFDE_HIP(hipStreamSynchronize(st));
-        (void)hipFree(zh);
-        (void)hipFree(y);
     })
     return TSFDE_OK;
 }

@@ -189,11 +189,39 @@ def c4(instance: int) -> Inputs:
                      modes=min(8, N), name=f"c4_{instance}")
 
 
+FIELD_K = 16  # control values per direction of the gradient workload's gamma2 field
+
+
+def bilinear_weights(N: int, K: int = FIELD_K, length: float = 1.0) -> np.ndarray:
+    """(N^2, K^2) weights of bilinear interpolation from a K x K grid of control values at
+    xi_k = k length/(K-1), k = 0..K-1 per direction (row-major, last index fastest), to the interior
+    grid points x_j = j length/(N+1) (last index fastest).  Each row has at most four nonzeros and
+    sums to one."""
+    x = grid_points(N, length) / length * (K - 1)
+    i0 = np.clip(np.floor(x).astype(int), 0, K - 2)
+    t = x - i0
+    W1 = np.zeros((N, K))
+    W1[np.arange(N), i0] = 1.0 - t
+    W1[np.arange(N), i0 + 1] += t
+    return np.kron(W1, W1)
+
+
+def c5_field(instance: int = 0) -> np.ndarray:
+    """The K x K control values of the gradient workload's gamma2 field, U(0.8, 1.2), from a
+    generator of its own (the other draws of the instance are unchanged)."""
+    rng = np.random.default_rng([SEED_BASE, 5, 100000 + instance])
+    return rng.uniform(0.8, 1.2, size=(FIELD_K, FIELD_K))
+
+
 def c5(instance: int = 0) -> Inputs:
     """The gradient workload's instance: d = 2, N = 127 per direction, M = 128, beta = 0.5,
-    omega = 1.5, alpha = 1e-3, coefficient amplitudes ~ U(0.1, 0.5), 8 x 8 sine modes."""
-    return synthetic(2, 127, 128, 0.5, 1.5, 1e-3, config_id=5, instance=instance, amp1=None, amp2=None,
-                     modes=8, name=f"c5_{instance}")
+    omega = 1.5, alpha = 1e-3, gamma1 amplitude ~ U(0.1, 0.5), 8 x 8 sine modes; gamma2 is the
+    bilinear interpolation of a 16 x 16 field of control values ~ U(0.8, 1.2) (c5_field), the same at
+    every time level."""
+    inp = synthetic(2, 127, 128, 0.5, 1.5, 1e-3, config_id=5, instance=instance, amp1=None, amp2=None,
+                    modes=8, name=f"c5_{instance}")
+    g2 = bilinear_weights(inp.N) @ c5_field(instance).reshape(-1)
+    return dataclasses.replace(inp, gamma2=np.tile(g2, (inp.M, 1)))
 
 
 def small(d: int, N: int, M: int, beta: float = 0.5, omega: float = 1.5, alpha: float = 1e-3,

@@ -19,8 +19,8 @@ WARM_PREVIOUS, WARM_LINEAR, WARM_QUADRATIC, WARM_HALF = 0, 1, 2, 3
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOCONV", 5: "ENONFINITE", 6: "ENOTIMPL"}
 
 EXPORTED = [
-    "tsfde_default_opts", "tsfde_create_problem", "tsfde_create_problem_ex", "tsfde_set_mu", "tsfde_set_alpha",
-    "tsfde_destroy_problem", "tsfde_vector_length", "tsfde_problem_scalars", "tsfde_get_stencil",
+    "tsfde_default_opts", "tsfde_create_problem", "tsfde_create_problem_ex", "tsfde_set_mu", "tsfde_set_gamma2", "tsfde_set_alpha",
+    "tsfde_destroy_problem", "tsfde_vector_length", "tsfde_device_bytes", "tsfde_problem_scalars", "tsfde_get_stencil",
     "tsfde_compute_stencil", "tsfde_apply_A", "tsfde_apply_A_f32", "tsfde_apply_P_inv",
     "tsfde_apply_P_inv_f32", "tsfde_apply_P_inv_noalloc", "tsfde_gmres_solve", "tsfde_recover_f", "tsfde_recover_f_batch",
     "tsfde_forward_solve", "tsfde_apply_AT", "tsfde_apply_PT_inv", "tsfde_adjoint_solve",
@@ -32,16 +32,23 @@ class Opts(C.Structure):
     _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("tol", C.c_double), ("precision", C.c_int),
                 ("use_precond", C.c_int), ("inner_tol", C.c_double), ("inner_maxit", C.c_int),
                 ("refine_tol", C.c_double), ("max_refine", C.c_int), ("block_solver", C.c_int),
-                ("warm_start", C.c_int)]
+                ("warm_start", C.c_int), ("max_device_bytes", C.c_longlong), ("recompute_z", C.c_int)]
 
 
 class Stats(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("refinements", C.c_int), ("converged", C.c_int),
                 ("inner_iters", C.c_longlong), ("rel_res", C.c_double), ("t_total", C.c_double),
-                ("t_precond", C.c_double), ("t_matvec", C.c_double), ("t_ortho", C.c_double)]
+                ("t_precond", C.c_double), ("t_matvec", C.c_double), ("t_ortho", C.c_double),
+                ("history_len", C.c_int), ("history_ptr", C.POINTER(C.c_double))]
+
+    def history(self) -> list:
+        """The solve's relative residual history (copied out of the problem's host buffer)."""
+        return [self.history_ptr[i] for i in range(self.history_len)] if self.history_len > 0 else []
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "history_ptr"}
+        d["history"] = self.history()
+        return d
 
 
 class TsfdeError(RuntimeError):
@@ -66,11 +73,14 @@ def lib():
     L.tsfde_create_problem.argtypes = [i, i, i, d, d, d, d, dp, dp, dp, dp, dp, pp]
     L.tsfde_create_problem_ex.argtypes = [i, i, i, d, d, d, d, dp, dp, dp, dp, dp, d, dp, pp]
     L.tsfde_set_mu.argtypes = [vp, dp]
+    L.tsfde_set_gamma2.argtypes = [vp, dp]
     L.tsfde_set_alpha.argtypes = [vp, d]
     L.tsfde_destroy_problem.argtypes = [vp]
     L.tsfde_destroy_problem.restype = None
     L.tsfde_vector_length.argtypes = [vp]
     L.tsfde_vector_length.restype = C.c_size_t
+    L.tsfde_device_bytes.argtypes = [vp]
+    L.tsfde_device_bytes.restype = C.c_size_t
     L.tsfde_problem_scalars.argtypes = [vp, dp]
     L.tsfde_get_stencil.argtypes = [vp, dp]
     L.tsfde_compute_stencil.argtypes = [i, i, d, dp]
@@ -92,7 +102,8 @@ def lib():
     L.tsfde_last_error.argtypes = []
     L.tsfde_last_error.restype = C.c_char_p
     for name in EXPORTED:
-        if name not in ("tsfde_default_opts", "tsfde_destroy_problem", "tsfde_vector_length", "tsfde_last_error"):
+        if name not in ("tsfde_default_opts", "tsfde_destroy_problem", "tsfde_vector_length", "tsfde_device_bytes",
+                        "tsfde_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -200,8 +211,17 @@ class Problem:
         _check(lib().tsfde_set_mu(self._h, ptr))
         self.mu_host = arr
 
+    def set_gamma2(self, gamma2):
+        """Replace the gamma2 samples ([M, N^d] host values, > 0)."""
+        arr, ptr = _host(gamma2, self.M * self.Nd, "gamma2")
+        _check(lib().tsfde_set_gamma2(self._h, ptr))
+
     def set_alpha(self, alpha: float):
         _check(lib().tsfde_set_alpha(self._h, float(alpha)))
+
+    def device_bytes(self) -> int:
+        """Device bytes the problem holds (arrays, work buffers allocated so far, Krylov basis)."""
+        return int(lib().tsfde_device_bytes(self._h))
 
     def scalars(self) -> dict:
         out = (C.c_double * 6)()
@@ -343,31 +363,47 @@ def recover_f_batch(problems, opts: Optional[Opts] = None, max_inflight: int = 2
     return [(fs[i], st[i]) for i in range(n)]
 
 
-def recover_f_autograd(problem: "Problem", mu, opts: Optional[Opts] = None, adjoint_opts: Optional[Opts] = None):
+def recover_f_autograd(problem: "Problem", mu, opts: Optional[Opts] = None, adjoint_opts: Optional[Opts] = None,
+                       log_alpha=None, gamma2=None):
     """f~ as a differentiable function of the final-time data mu_eps (a device FP64 tensor of N^d
-    values): the forward pass sets mu and runs tsfde_recover_f, the backward pass runs
-    tsfde_recover_f_vjp (the adjoint solve).  The problem's alpha gradient of the last backward pass
-    is left in problem.last_grad_alpha."""
+    values) and, optionally, of log alpha (a 0-d FP64 tensor) and the gamma2 samples (a device FP64
+    tensor [M, N^d]; any differentiable parameterisation, e.g. an interpolated coarse field, can
+    produce them).  The forward pass sets the inputs and runs tsfde_recover_f; the backward pass runs
+    tsfde_recover_f_vjp (one adjoint solve) and returns dL/dmu, dL/dlog alpha = alpha dL/dalpha and
+    dL/dgamma2.  The alpha gradient of the last backward pass is also left in problem.last_grad_alpha."""
+    import math
+
     import torch
 
     class _RecoverF(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, m):
+        def forward(ctx, m, la, g2):
             problem.set_mu(m.detach().cpu().numpy())
+            if la is not None:
+                problem.set_alpha(math.exp(float(la)))
+            if g2 is not None:
+                problem.set_gamma2(g2.detach().cpu().numpy())
             y = torch.empty(problem.n_tot, dtype=torch.float64, device="cuda")
             f, _ = problem.recover_f(opts, work=y, raise_noconv=True)
             ctx.save_for_backward(y)
+            ctx.alpha = math.exp(float(la)) if la is not None else None
+            ctx.has = (la is not None, g2 is not None)
+            ctx.g2shape = g2.shape if g2 is not None else None
             return f
 
         @staticmethod
         def backward(ctx, gf):
             (y,) = ctx.saved_tensors
-            gmu, ga, _ = problem.recover_f_vjp(y, gf.contiguous().to(torch.float64), adjoint_opts,
-                                               raise_noconv=True)
+            want_g2 = ctx.has[1] and ctx.needs_input_grad[2]
+            out = problem.recover_f_vjp(y, gf.contiguous().to(torch.float64), adjoint_opts, raise_noconv=True,
+                                        gamma2=want_g2)
+            gmu, ga = out[0], out[1]
             problem.last_grad_alpha = ga
-            return gmu
+            gla = torch.tensor(ga * ctx.alpha, dtype=torch.float64, device=gmu.device) if ctx.has[0] else None
+            gg2 = out[2].reshape(ctx.g2shape) if want_g2 else None
+            return gmu, gla, gg2
 
-    return _RecoverF.apply(mu)
+    return _RecoverF.apply(mu, log_alpha, gamma2)
 
 
 def discrepancy_curve(problem: "Problem", alphas, opts: Optional[Opts] = None, fwd_opts: Optional[Opts] = None):

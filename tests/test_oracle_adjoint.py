@@ -96,3 +96,15 @@ def test_grad_gamma2_matches_central_differences(prob):
             vals.append(gf @ f_tilde(dataclasses.replace(prob, gamma2=g2)))
         fd = (vals[0] - vals[1]) / (2 * h)
         assert G[s, j] == pytest.approx(fd, rel=1e-5)
+
+
+@pytest.mark.parametrize("d,N,M", [(1, 9, 6), (2, 5, 4)])
+def test_matvec_T_entry_matches_dense_transpose(d, N, M):
+    """Entries of A^T w summed down the columns of the block definition agree with the dense A^T."""
+    inp = inputs.small(d, N, M, beta=0.4, omega=1.7)
+    p = workloads.problem(inp, mu=np.zeros(inp.Nd))
+    w = np.random.default_rng(7).standard_normal(p.n_tot)
+    ref = system.dense_A(p).T @ w
+    for m in range(p.S + 1):
+        for j in range(p.Nd):
+            assert abs(adjoint.matvec_T_entry(p, w, m, j) - ref[m * p.Nd + j]) <= 1e-12 * np.abs(ref).max()
