@@ -77,9 +77,13 @@ typedef struct tsfde_opts {
                             Remark -- B replaced by its tau matrix and the block's
                             coefficient ratio gamma1/gamma2 frozen at its slice
                             mean, so each block is solved exactly by sine
-                            transforms (no inner iterations, no warm start).
-                            TSFDE_BLOCK_TAU needs d = 2 and 2(N+1) a power of
-                            two; otherwise the calls return TSFDE_ENOTIMPL.
+                            transforms (no inner iterations, no warm start), for
+                            d = 1, 2 and any N: FFT-based inside the persistent
+                            kernels when d = 2 and 2(N+1) is a power of two,
+                            dense sine-transform passes otherwise (ENOTIMPL if
+                            those do not fit the LDS, N above ~6700 in 1D and
+                            ~3300 in 2D, or the tau matrix is not positive
+                            definite).
                             TSFDE_BLOCK_STRANG: the S_{n,S} variant of the same
                             Remark -- B replaced by Strang's circulant (the
                             central diagonals of B wrapped around, per level),

@@ -97,6 +97,11 @@ struct Problem {
     float* strang32 = nullptr;
     double strang_min = 0;       // smallest eigenvalue of s(B)
     double* strang_hist = nullptr;  // kHB slices: far history of one block of steps (FP64, or FP32 in place)
+    // T_{n,S} blocks by dense sine transforms (any N), built on first use: [2(N+1)] sin table then [Nd]
+    // tau eigenvalues of B
+    double* taud64 = nullptr;
+    float* taud32 = nullptr;
+    double taud_min = 0;         // smallest tau eigenvalue
     void* pw64 = nullptr;           // persistent P^{-1} work buffers (FP64 / FP32)
     void* pw32 = nullptr;
     double* fwd_work = nullptr;     // direct problem: z-hat and the substitution's output (2 n_tot)
@@ -228,6 +233,13 @@ void set_persistent_fixed_length(bool on);
 double strang_tables(const Problem& P, std::vector<double>& cas, std::vector<double>& lam);
 bool strang_supported(const Problem& P);
 void ensure_strang(Problem& P);
+// T_{n,S} by the same dense passes with the sine transform (any N, d = 1, 2): tables (setup.hip),
+// whether the passes fit the LDS, the tables on the device (first use), y = T^{-1} z
+double tau_dense_tables(const Problem& P, std::vector<double>& tab, std::vector<double>& lam);
+bool tau_dense_supported(const Problem& P);
+void ensure_tau_dense(Problem& P);
+template <typename T>
+void pinv_tau_dense(Problem& P, const Dev<T>& D, const T* z, T* y, bool last_block, hipStream_t st);
 template <typename T>
 void pinv_strang(Problem& P, const Dev<T>& D, const T* z, T* y, bool last_block, hipStream_t st);
 // w[i] = (z_s - gamma1_s sum_{m < sa} e_{s-m} y_m) / gamma2_s for s = sa + i, i < cnt <= kHB

@@ -228,6 +228,25 @@ static std::vector<double> tau_eigs(int d, int N, const std::vector<double>& a) 
     return t;
 }
 
+// T_{n,S} blocks solved by dense sine transforms (any N): tab[m] = sin(pi m/(N+1)), m < 2(N+1), and the
+// tau eigenvalues of B_N as lam[k1][k2] (k2 the frequency of the fast index; 1D: lam[k]); returns the
+// smallest eigenvalue.
+double tau_dense_tables(const Problem& P, std::vector<double>& tab, std::vector<double>& lam) {
+    const int N = P.N;
+    const long long P2 = 2LL * (N + 1);
+    tab.resize(P2);
+    for (long long m = 0; m < P2; ++m) tab[m] = std::sin(M_PI * (double)m / (double)(N + 1));
+    const std::vector<double> t = tau_eigs(P.d, N, P.stencil);
+    if (P.d == 1) {
+        lam = t;
+    } else {
+        lam.resize((size_t)N * N);
+        for (int k1 = 0; k1 < N; ++k1)
+            for (int k2 = 0; k2 < N; ++k2) lam[(size_t)k1 * N + k2] = t[(size_t)k2 * N + k1];
+    }
+    return *std::min_element(lam.begin(), lam.end());
+}
+
 // Strang's circulant s(B) (§5.1 Remark): first column c_l = a_{f(l)} per level with f(l) = l for
 // l <= N/2 and N - l above (the central diagonals wrapped around).  cas[m] = cos + sin of 2 pi m/N,
 // lam[k1][k2] = sum_l c[l1][l2] cos(2 pi l1 k1/N) cos(2 pi l2 k2/N), its eigenvalues in the Hartley
@@ -340,7 +359,7 @@ void free_problem(Problem* P) {
     pinv_persistent_free<float>(P->pw32);
     void* ptrs[] = {P->d_bw, P->d_rho, P->d_mu, P->z_rhs, P->xbuf, P->V, P->Z, P->arn_part, P->arn_h, P->rwork, P->adj_u,
                     P->dev_scalars, P->strang64, P->strang32, P->strang_hist, P->refine_work, P->vjp_work,
-                    P->d_sigma, P->fwd_work};
+                    P->d_sigma, P->fwd_work, P->taud64, P->taud32};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (P->host_scalars) (void)hipHostFree(P->host_scalars);

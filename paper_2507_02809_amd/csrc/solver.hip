@@ -129,9 +129,14 @@ static int env_int(const char* name, int dflt) {
     return (e && *e) ? std::atoi(e) : dflt;
 }
 
-// the tau-block form runs on the persistent 2D sine-transform path only; the Strang form needs its
+// the tau-block form runs in the persistent kernels where they use the sine transform of size N (d = 2,
+// 2(N+1) a power of two), else by dense sine-transform passes of any N; the Strang form needs its
 // Hartley passes to fit the LDS and Strang's circulant of the stencil to be positive definite (its
 // tables are built here on first use)
+static bool tau_persistent(const Problem& P) {
+    return P.d == 2 && P.tau_ok && persistent_supported(P) && env_int("TSFDE_PINV", 1) != 0;
+}
+
 static bool block_solver_supported(Problem& P, const Opts& o) {
     if (!o.use_precond || o.block_solver == TSFDE_BLOCK_CG) return true;
     if (o.block_solver == TSFDE_BLOCK_STRANG) {
@@ -152,9 +157,23 @@ static bool block_solver_supported(Problem& P, const Opts& o) {
         }
         return true;
     }
-    if (P.d == 2 && P.tau_ok && persistent_supported(P) && env_int("TSFDE_PINV", 1) != 0) return true;
-    set_error("opts.block_solver = TSFDE_BLOCK_TAU needs d = 2 with 2(N+1) a power of two");
-    return false;
+    if (tau_persistent(P)) return true;
+    if (!tau_dense_supported(P)) {
+        set_error("opts.block_solver = TSFDE_BLOCK_TAU: N = %d is too large for the dense sine-transform passes", P.N);
+        return false;
+    }
+    try {
+        ensure_tau_dense(P);
+    } catch (const HipError& e) {
+        set_error("opts.block_solver = TSFDE_BLOCK_TAU: %s failed: %s", e.where.c_str(), hipGetErrorString(e.code));
+        return false;
+    }
+    if (!(P.taud_min > 0.0)) {
+        set_error("opts.block_solver = TSFDE_BLOCK_TAU: the tau matrix of the stencil is not positive definite "
+                  "(smallest eigenvalue %g)", P.taud_min);
+        return false;
+    }
+    return true;
 }
 
 template <typename T>
@@ -176,6 +195,10 @@ static long long pinv_impl(Problem& P, const T* z, T* y, const Opts& o, hipStrea
     // TSFDE_EXTRAP overrides opts.warm_start (the block CG's initial guess)
     if (o.block_solver == TSFDE_BLOCK_STRANG) {
         pinv_strang<T>(P, dev<T>(P), z, y, last_block, st);
+        return 0;
+    }
+    if (o.block_solver == TSFDE_BLOCK_TAU && !tau_persistent(P)) {
+        pinv_tau_dense<T>(P, dev<T>(P), z, y, last_block, st);
         return 0;
     }
     if (env_int("TSFDE_PINV", 1) != 0 && persistent_supported(P)) {
@@ -996,6 +1019,11 @@ tsfde_status tsfde_apply_P_inv_noalloc(tsfde_problem* prob, const double* z, dou
     }
     if (!persistent_supported(P)) {
         set_error("apply_P_inv_noalloc: this shape has no persistent forward-substitution kernel (L = %d)", P.L);
+        return TSFDE_ENOTIMPL;
+    }
+    if (o.block_solver == TSFDE_BLOCK_TAU && !tau_persistent(P)) {
+        set_error("apply_P_inv_noalloc: TSFDE_BLOCK_TAU on this shape uses the dense sine passes, whose tables are "
+                  "built on first use; use tsfde_apply_P_inv");
         return TSFDE_ENOTIMPL;
     }
     if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;

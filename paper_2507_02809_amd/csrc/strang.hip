@@ -1,33 +1,34 @@
-// S_{n,S} of the §5.1 Remark: the forward substitution of P with every B replaced by Strang's
-// circulant s(B) (per level, the central diagonals of B wrapped around the circle) and the
-// coefficient ratio of each diagonal block frozen at its slice mean sigma_s, the reading under
-// which T_{n,S} is built as well:
-//   s < M:  (sigma_s I + c_t s(B)) y_s = (z_s - gamma1_s sum_{m<s} e_{s-m} y_m) / gamma2_s
-//   s = M:  s(B) y_M = (z_M - y_{M-1}) / (c_f gamma2_{M-1}).
+// Dense-transform block solvers of the §5.1 Remark, for any N: the forward substitution of P with
+// every B replaced by Strang's circulant s(B) (S_{n,S}) or by its tau matrix tau(B) (T_{n,S}), and the
+// coefficient ratio of each diagonal block frozen at its slice mean sigma_s:
+//   s < M:  (sigma_s I + c_t X(B)) y_s = (z_s - gamma1_s sum_{m<s} e_{s-m} y_m) / gamma2_s
+//   s = M:  X(B) y_M = (z_M - y_{M-1}) / (c_f gamma2_{M-1}),     X = s or tau.
 //
-// A d-level symmetric circulant whose first column c is even along every level is diagonalised by
-// the real Hartley transform of size N per level: with H[j][k] = cas(2 pi j k / N), cas = cos + sin,
-// H H = N I and
+// Strang: a d-level symmetric circulant whose first column c is even along every level is
+// diagonalised by the real Hartley transform of size N per level: with H[j][k] = cas(2 pi j k / N),
+// cas = cos + sin, H H = N I and
 //   s(B) = (H x H) diag(lambda) (H x H) / N^d,
 //   lambda[k1][k2] = sum_{l1,l2} c[l1][l2] cos(2 pi l1 k1 / N) cos(2 pi l2 k2 / N)
-// (the cos-sin cross terms cancel by the evenness of c), so every block is solved exactly by two
-// transforms around a diagonal scaling, with no inner iterations.  N is arbitrary (it need not give
-// a power-of-two FFT), so each level's transform is a dense pass: N multiply-adds per output, the
-// cas table (N values, index j k mod N) and the workgroup's input rows held in LDS.  Every pass
-// transforms the fast index of its input and writes its output transposed, so the 2D solve is four
-// passes of one kernel and returns to the slice layout [i1][i2].
+// (the cos-sin cross terms cancel by the evenness of c).
+// tau: tau(B) = (2/(N+1))^d (S x S) diag(lambda) (S x S) with S[j][k] = sin(pi (j+1)(k+1)/(N+1))
+// (S S = (N+1)/2 I) and lambda the tau eigenvalues of B.
+// Either way every block is solved exactly by two transforms around a diagonal scaling, with no
+// inner iterations.  N is arbitrary (it need not give a power-of-two FFT), so each level's transform
+// is a dense pass: N multiply-adds per output, the table (Np values, index (j+o)(k+o) mod Np with
+// Np = N, o = 0 for cas and Np = 2(N+1), o = 1 for sin) and the workgroup's input rows held in LDS.
+// Every pass transforms the fast index of its input and writes its output transposed, so the 2D
+// solve is four passes of one kernel and returns to the slice layout [i1][i2].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "internal.hpp"
+#include "transform_lds.hpp"
 
 namespace tsfde {
 
-constexpr int kCasK = 64;      // outputs per workgroup along the transformed index (one per lane)
-constexpr int kCasRows = 4;    // rows per workgroup, one per wave
 constexpr int kCasU = 8;       // unrolled steps of the inner sum
-constexpr int kLdsBytes = 160 * 1024;
 
 // Where the first pass of a block solve takes its right-hand side from:
 //   NEAR: x = w[j] - dg_s[j] sum_{sa <= m < s} e_{s-m} y_m[j], w the far-history slice of step s
@@ -63,23 +64,24 @@ __device__ __forceinline__ T rhs_value(const RhsArgs<T>& ra, const T* __restrict
     return in[g];
 }
 
-// sum_{j0 <= j < j1} x[j] ct[(j k) mod N].  The sum runs in chunks of kCasU: the chunk's table
-// indices come from a short VALU chain, so its LDS reads are independent and in flight together,
-// and kCasU partial sums break the multiply-add dependence.
+// sum_{j0 <= j < j1} x[j] ct[((j + o)(k + o)) mod Np].  The sum runs in chunks of kCasU: the chunk's
+// table indices come from a short VALU chain, so its LDS reads are independent and in flight
+// together, and kCasU partial sums break the multiply-add dependence.
 template <typename T>
-__device__ __forceinline__ T cas_sum(const T* x, const T* ct, int N, int k, int j0, int j1) {
+__device__ __forceinline__ T cas_sum(const T* x, const T* ct, int Np, int o, int k, int j0, int j1) {
     T acc[kCasU];
 #pragma unroll
     for (int u = 0; u < kCasU; ++u) acc[u] = T(0);
-    int idx = (int)(((long long)j0 * k) % N);  // j k mod N
+    const int kk = k + o;                                    // < Np
+    int idx = (int)(((long long)(j0 + o) * kk) % Np);        // (j + o)(k + o) mod Np
     int j = j0;
     for (; j + kCasU <= j1; j += kCasU) {
         int id[kCasU];
         id[0] = idx;
 #pragma unroll
         for (int u = 1; u < kCasU; ++u) {
-            const int t = id[u - 1] + k;
-            id[u] = t >= N ? t - N : t;
+            const int t = id[u - 1] + kk;
+            id[u] = t >= Np ? t - Np : t;
         }
         T cv[kCasU], xv[kCasU];
 #pragma unroll
@@ -89,13 +91,13 @@ __device__ __forceinline__ T cas_sum(const T* x, const T* ct, int N, int k, int 
         }
 #pragma unroll
         for (int u = 0; u < kCasU; ++u) acc[u] += xv[u] * cv[u];
-        const int t = id[kCasU - 1] + k;
-        idx = t >= N ? t - N : t;
+        const int t = id[kCasU - 1] + kk;
+        idx = t >= Np ? t - Np : t;
     }
     for (; j < j1; ++j) {
         acc[0] += x[j] * ct[idx];
-        idx += k;
-        if (idx >= N) idx -= N;
+        idx += kk;
+        if (idx >= Np) idx -= Np;
     }
     T sum = T(0);
 #pragma unroll
@@ -103,18 +105,19 @@ __device__ __forceinline__ T cas_sum(const T* x, const T* ct, int N, int k, int 
     return sum;
 }
 
-// out[k][r] = sum_j x[r][j] cas[(j k) mod N] for r < nrow, k < N, with x[r][j] the right-hand side
-// value of point r N + j (rhs_value) times (lam ? scale / (sigma + c lam[r][j]) : 1).
+// out[k][r] = sum_j x[r][j] tab[((j + o)(k + o)) mod Np] for r < nrow, k < N, with x[r][j] the
+// right-hand side value of point r N + j (rhs_value) times (lam ? scale / (sigma + c lam[r][j]) : 1).
 template <typename T>
 __global__ __launch_bounds__(256) void cas_pass(const T* __restrict__ in, T* __restrict__ out,
-                                                const T* __restrict__ cas, const T* __restrict__ lam, T sigma,
-                                                T c, T scale, int N, int nrow, RhsArgs<T> ra) {
+                                                const T* __restrict__ tab, const T* __restrict__ lam, T sigma,
+                                                T c, T scale, int N, int Np, int o, int nrow, RhsArgs<T> ra) {
     extern __shared__ double cas_lds_raw[];
-    T* ct = reinterpret_cast<T*>(cas_lds_raw);  // [N]
-    T* xs = ct + N;                              // [nr][N]
+    T* ct = reinterpret_cast<T*>(cas_lds_raw);  // [Np]
+    T* xs = ct + Np;                             // [nr][N]
+    __shared__ T part[4][kCasK];                 // partial sums of a single row (d = 1)
     const int r0 = blockIdx.y * kCasRows;
     const int nr = min(kCasRows, nrow - r0);
-    for (int i = threadIdx.x; i < N; i += blockDim.x) ct[i] = cas[i];
+    for (int i = threadIdx.x; i < Np; i += blockDim.x) ct[i] = tab[i];
     const long long base = (long long)r0 * N;
     for (int i = threadIdx.x; i < nr * N; i += blockDim.x) {
         T v = rhs_value(ra, in, base + i);
@@ -126,10 +129,9 @@ __global__ __launch_bounds__(256) void cas_pass(const T* __restrict__ in, T* __r
     const int w = threadIdx.x / kCasK;
     if (nrow == 1) {
         // a single row (d = 1): the four waves split the sum over j and add their partial sums
-        __shared__ T part[4][kCasK];
         const int span = (N + 3) / 4;
         const int j0 = min(N, w * span), j1 = min(N, j0 + span);
-        part[w][threadIdx.x & (kCasK - 1)] = k < N ? cas_sum(xs, ct, N, k, j0, j1) : T(0);
+        part[w][threadIdx.x & (kCasK - 1)] = k < N ? cas_sum(xs, ct, Np, o, k, j0, j1) : T(0);
         __syncthreads();
         if (w == 0 && k < N) {
             const int l = threadIdx.x;
@@ -139,34 +141,52 @@ __global__ __launch_bounds__(256) void cas_pass(const T* __restrict__ in, T* __r
     }
     const int r = w;  // one row per wave
     if (k >= N || r >= nr) return;
-    const T sum = cas_sum(xs + r * N, ct, N, k, 0, N);
+    const T sum = cas_sum(xs + r * N, ct, Np, o, k, 0, N);
     out[(long long)k * nrow + r0 + r] = sum;
 }
 
-static size_t cas_lds_bytes(int N, int nrow, size_t elem) {
-    return (size_t)(1 + std::min(kCasRows, nrow)) * N * elem;
-}
+// the transform of a block solver: its table, period and index offset, eigenvalues and the scale
+// of the inverse (1 / N^d for Hartley, (2/(N+1))^d for sine)
+template <typename T>
+struct DenseXf {
+    const T* tab;
+    const T* lam;
+    int Np, o;
+    T inv;
+};
 
-bool strang_supported(const Problem& P) {
-    const int nrow = P.d == 2 ? P.N : 1;
-    return cas_lds_bytes(P.N, nrow, sizeof(double)) <= (size_t)kLdsBytes;
-}
+bool strang_supported(const Problem& P) { return dense_blocks_fit(P.d, P.N, P.N); }
+bool tau_dense_supported(const Problem& P) { return dense_blocks_fit(P.d, P.N, 2 * (P.N + 1)); }
 
 template <typename T>
-static void cas_launch(const T* in, T* out, const T* cas, const T* lam, T sigma, T c, T scale, int N, int nrow,
-                       hipStream_t st, const RhsArgs<T>& ra = RhsArgs<T>()) {
+static void cas_launch(const T* in, T* out, const DenseXf<T>& X, const T* lam, T sigma, T c, T scale, int N,
+                       int nrow, hipStream_t st, const RhsArgs<T>& ra = RhsArgs<T>()) {
     const dim3 grid((unsigned)((N + kCasK - 1) / kCasK), (unsigned)((nrow + kCasRows - 1) / kCasRows));
-    const size_t lds = cas_lds_bytes(N, nrow, sizeof(T));
-    hipLaunchKernelGGL(cas_pass<T>, grid, dim3(256), lds, st, in, out, cas, lam, sigma, c, scale, N, nrow, ra);
+    const size_t lds = pass_dyn_lds(N, X.Np, nrow, sizeof(T));
+    hipLaunchKernelGGL(cas_pass<T>, grid, dim3(256), lds, st, in, out, X.tab, lam, sigma, c, scale, N, X.Np, X.o,
+                       nrow, ra);
     TSFDE_HIP(hipGetLastError());
 }
 
 template <typename T>
-static T* strang_table(Problem& P);
+static T* table(Problem& P, bool tau);
 template <>
-double* strang_table<double>(Problem& P) { return P.strang64; }
+double* table<double>(Problem& P, bool tau) { return tau ? P.taud64 : P.strang64; }
 template <>
-float* strang_table<float>(Problem& P) { return P.strang32; }
+float* table<float>(Problem& P, bool tau) { return tau ? P.taud32 : P.strang32; }
+
+// Uploads [table][eigenvalues] in FP64 and FP32, and (once) the far-history slices of a block of steps.
+static void upload_tables(Problem& P, const std::vector<double>& tab, const std::vector<double>& lam, double*& d64,
+                          float*& d32) {
+    std::vector<double> t(tab);
+    t.insert(t.end(), lam.begin(), lam.end());
+    std::vector<float> t32(t.begin(), t.end());
+    dev_alloc(P, d64, t.size());
+    dev_alloc(P, d32, t32.size());
+    TSFDE_HIP(hipMemcpy(d64, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice));
+    TSFDE_HIP(hipMemcpy(d32, t32.data(), sizeof(float) * t32.size(), hipMemcpyHostToDevice));
+    if (!P.strang_hist) dev_alloc(P, P.strang_hist, (size_t)kHB * P.Nd);
+}
 
 // The cas table and the eigenvalues of s(B), computed on first use: [N] cas(2 pi m / N), then
 // [Nd] lambda (2D: [k1][k2], k2 the frequency of the fast index).
@@ -174,46 +194,41 @@ void ensure_strang(Problem& P) {
     if (P.strang64) return;
     std::vector<double> cas, lam;
     const double lmin = strang_tables(P, cas, lam);
-    std::vector<double> t(cas);
-    t.insert(t.end(), lam.begin(), lam.end());
-    std::vector<float> t32(t.begin(), t.end());
-    double* d64 = nullptr;
-    float* d32 = nullptr;
-    TSFDE_HIP(hipMalloc(&d64, sizeof(double) * t.size()));
-    if (hipMalloc(&d32, sizeof(float) * t32.size()) != hipSuccess) {
-        (void)hipFree(d64);
-        throw HipError{hipErrorOutOfMemory, "hipMalloc(strang32)"};
-    }
-    TSFDE_HIP(hipMemcpy(d64, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice));
-    TSFDE_HIP(hipMemcpy(d32, t32.data(), sizeof(float) * t32.size(), hipMemcpyHostToDevice));
-    double* hist = nullptr;
-    if (hipMalloc(&hist, sizeof(double) * (size_t)kHB * P.Nd) != hipSuccess) {
-        (void)hipFree(d64);
-        (void)hipFree(d32);
-        throw HipError{hipErrorOutOfMemory, "hipMalloc(strang_hist)"};
-    }
-    P.strang64 = d64;
-    P.strang32 = d32;
-    P.strang_hist = hist;
+    upload_tables(P, cas, lam, P.strang64, P.strang32);
     P.strang_min = lmin;
-    P.bytes += (sizeof(double) + sizeof(float)) * t.size() + sizeof(double) * (size_t)kHB * P.Nd;
+}
+
+// The sine table and the tau eigenvalues of B for the dense T_{n,S} blocks: [2(N+1)] sin(pi m/(N+1)),
+// then [Nd] lambda ([k1][k2]).
+void ensure_tau_dense(Problem& P) {
+    if (P.taud64) return;
+    std::vector<double> tab, lam;
+    const double lmin = tau_dense_tables(P, tab, lam);
+    upload_tables(P, tab, lam, P.taud64, P.taud32);
+    P.taud_min = lmin;
 }
 
 // The steps run in blocks of kHB: one bandwidth-bound kernel folds the history of all earlier blocks
 // into the block's right-hand sides, and each step's first transform pass adds the (< kHB) near terms
 // while loading its rows.
 template <typename T>
-void pinv_strang(Problem& P, const Dev<T>& D, const T* z, T* y, bool last_block, hipStream_t st) {
-    ensure_strang(P);
-    const T* cas = strang_table<T>(P);
-    const T* lam = cas + P.N;
+void pinv_dense_blocks(Problem& P, const Dev<T>& D, const T* z, T* y, bool last_block, bool tau, hipStream_t st) {
+    if (tau) ensure_tau_dense(P);
+    else ensure_strang(P);
     const long long Nd = P.Nd;
     const int N = P.N;
+    DenseXf<T> X;
+    X.tab = table<T>(P, tau);
+    X.Np = tau ? 2 * (N + 1) : N;
+    X.o = tau ? 1 : 0;
+    X.lam = X.tab + X.Np;
+    X.inv = tau ? T(std::pow(2.0 / (N + 1), P.d)) : T(1.0 / (double)Nd);  // S S = (N+1)/2 I;  H H = N I
+    const T* lam = X.lam;
     const int nrow = P.d == 2 ? N : 1;
     T* t1 = D.pcg + 5 * Nd;
     T* t2 = D.pcg + 6 * Nd;
     T* hist = reinterpret_cast<T*>(P.strang_hist);
-    const T inv = T(1.0 / (double)Nd);  // (H x H)^2 = N^d I
+    const T inv = X.inv;
     const int last = last_block ? P.M : P.M - 1;
     for (int sa = 0; sa <= last; sa += kHB) {
         const int cnt = std::min(kHB, P.M - sa);
@@ -239,19 +254,31 @@ void pinv_strang(Problem& P, const Dev<T>& D, const T* z, T* y, bool last_block,
             const T sigma = (s < P.M) ? T(P.sigma[s]) : T(0);
             const T c = (s < P.M) ? T(P.ct) : T(1);
             T* ys = y + (long long)s * Nd;
-            cas_launch<T>(in, t1, cas, nullptr, T(0), T(0), T(1), N, nrow, st, ra);  // [i1][i2] -> [k2][i1]
+            cas_launch<T>(in, t1, X, nullptr, T(0), T(0), T(1), N, nrow, st, ra);  // [i1][i2] -> [k2][i1]
             if (P.d == 1) {
-                cas_launch<T>(t1, ys, cas, lam, sigma, c, inv, N, 1, st);
+                cas_launch<T>(t1, ys, X, lam, sigma, c, inv, N, 1, st);
             } else {
-                cas_launch<T>(t1, t2, cas, nullptr, T(0), T(0), T(1), N, N, st);  // -> [k1][k2]
-                cas_launch<T>(t2, t1, cas, lam, sigma, c, inv, N, N, st);         // scaled, -> [m2][k1]
-                cas_launch<T>(t1, ys, cas, nullptr, T(0), T(0), T(1), N, N, st);  // -> [m1][m2]
+                cas_launch<T>(t1, t2, X, nullptr, T(0), T(0), T(1), N, N, st);  // -> [k1][k2]
+                cas_launch<T>(t2, t1, X, lam, sigma, c, inv, N, N, st);         // scaled, -> [m2][k1]
+                cas_launch<T>(t1, ys, X, nullptr, T(0), T(0), T(1), N, N, st);  // -> [m1][m2]
             }
         }
     }
 }
 
+template <typename T>
+void pinv_strang(Problem& P, const Dev<T>& D, const T* z, T* y, bool last_block, hipStream_t st) {
+    pinv_dense_blocks<T>(P, D, z, y, last_block, false, st);
+}
+
+template <typename T>
+void pinv_tau_dense(Problem& P, const Dev<T>& D, const T* z, T* y, bool last_block, hipStream_t st) {
+    pinv_dense_blocks<T>(P, D, z, y, last_block, true, st);
+}
+
 template void pinv_strang<double>(Problem&, const Dev<double>&, const double*, double*, bool, hipStream_t);
 template void pinv_strang<float>(Problem&, const Dev<float>&, const float*, float*, bool, hipStream_t);
+template void pinv_tau_dense<double>(Problem&, const Dev<double>&, const double*, double*, bool, hipStream_t);
+template void pinv_tau_dense<float>(Problem&, const Dev<float>&, const float*, float*, bool, hipStream_t);
 
 }  // namespace tsfde

@@ -341,25 +341,14 @@ def test_gmres_full_size_true_residual(which):
 # ---------------------------------------------------------------------------
 # T_{n,S}: the tau-block form of the preconditioner (opts.block_solver = BLOCK_TAU)
 # ---------------------------------------------------------------------------
-def _tau_path(p) -> bool:
-    """The tau-block form runs where the sine-transform path does: d = 2, 2(N+1) a power of two."""
-    n = 2 * (p.N + 1)
-    return p.d == 2 and (n & (n - 1)) == 0
-
-
 def test_apply_P_inv_tau_blocks_matches_dense_T(dense_case):
-    """y = T^{-1} z (each block solved by sine transforms) against LU of the assembled T; other
-    shapes report ENOTIMPL."""
+    """y = T^{-1} z (each block solved by sine transforms: FFT-based in the persistent kernels for d = 2
+    with 2(N+1) a power of two, dense sine passes for d = 1 and other N) against LU of the assembled T."""
     inp, p, _, _ = dense_case
     rng = np.random.default_rng(21)
     zz = rng.standard_normal(p.n_tot)
     o = tsfde.default_opts(block_solver=tsfde.BLOCK_TAU)
     with gpu_problem(inp, p) as g:
-        if not _tau_path(p):
-            with pytest.raises(tsfde.TsfdeError) as ei:
-                g.apply_P_inv(torch.tensor(zz, device=DEV), opts=o)
-            assert ei.value.status == tsfde.ENOTIMPL
-            return
         y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=o).cpu().numpy()
         y32 = g.apply_P_inv(torch.tensor(zz, device=DEV, dtype=torch.float32), opts=o).cpu().double().numpy()
     ref = np.linalg.solve(system.dense_T(p), zz)
@@ -370,8 +359,6 @@ def test_apply_P_inv_tau_blocks_matches_dense_T(dense_case):
 def test_gmres_tau_blocks_reaches_dense_lu(dense_case):
     """FGMRES preconditioned by T reaches the same solution as dense LU of A."""
     inp, p, A, _ = dense_case
-    if not _tau_path(p):
-        pytest.skip("the tau-block form needs d = 2 and 2(N+1) a power of two")
     x_lu = np.linalg.solve(A, system.rhs_z(p))
     with gpu_problem(inp, p) as g:
         f, st = g.recover_f(tsfde.default_opts(tol=3e-13, block_solver=tsfde.BLOCK_TAU), raise_noconv=True)
@@ -381,6 +368,27 @@ def test_gmres_tau_blocks_reaches_dense_lu(dense_case):
         assert sp.converged == 1
     assert rel_err(f.cpu().numpy(), x_lu[p.S * p.Nd:]) <= 1e-10
     assert rel_err(fp.cpu().numpy(), x_lu[p.S * p.Nd:]) <= 1e-10
+
+
+@pytest.mark.parametrize("shape", [(1, 100, 20), (1, 255, 12), (2, 37, 6), (2, 63, 5)])
+def test_tau_blocks_any_shape_match_oracle(shape, monkeypatch):
+    """T^{-1} at shapes beyond the dense LU (1D, and 2D with 2(N+1) a power of two or not) against the
+    oracle's matrix-free T^{-1} (orthonormal DST-I of size N); for N = 63 in 2D also the dense sine
+    passes (persistent kernels switched off) against the FFT-based persistent path."""
+    from oracle import matfree
+    d, N, M = shape
+    inp = inputs.small(d, N, M, beta=0.45, omega=1.35)
+    p = workloads.problem(inp, mu=np.zeros(inp.Nd))
+    zz = np.random.default_rng(24).standard_normal(p.n_tot)
+    ref = matfree.T_solve(p, zz)
+    o = tsfde.default_opts(block_solver=tsfde.BLOCK_TAU)
+    with gpu_problem(inp, p) as g:
+        y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=o).cpu().numpy()
+        assert rel_err(y, ref) <= 1e-12
+        if d == 2 and N == 63:
+            monkeypatch.setenv("TSFDE_PINV", "0")
+            y2 = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=o).cpu().numpy()
+            assert rel_err(y2, ref) <= 1e-12
 
 
 @pytest.mark.parametrize("fixed", [True, False])
@@ -536,9 +544,9 @@ def test_recover_f_batch_rejects_bad_batches():
         with pytest.raises(tsfde.TsfdeError) as e:
             tsfde.recover_f_batch([g, g])
         assert e.value.status == tsfde.EINVAL and "twice" in str(e.value)
-        with pytest.raises(tsfde.TsfdeError) as e:  # tau blocks need d = 2
-            tsfde.recover_f_batch([g], tsfde.default_opts(block_solver=tsfde.BLOCK_TAU))
-        assert e.value.status == tsfde.ENOTIMPL
+        with pytest.raises(tsfde.TsfdeError) as e:
+            tsfde.recover_f_batch([g], max_inflight=9)
+        assert e.value.status == tsfde.EINVAL
         assert tsfde.recover_f_batch([]) == []
 
 
