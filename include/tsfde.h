@@ -396,6 +396,40 @@ tsfde_status tsfde_recover_f_vjp_batch(tsfde_problem* const* probs, int count,
 tsfde_status tsfde_arnoldi(tsfde_problem* prob, const double* b, int k, double* H, int* steps,
                            const tsfde_opts* opts, void* stream);
 
+/*
+ * Ritz values: the eigenvalues of the leading m x m block of a Hessenberg matrix H (host,
+ * row-major with leading dimension ldh >= m, e.g. the (k+1) x k output of tsfde_arnoldi with
+ * ldh = k), by Francis' double-shift QR iteration on the host.  re, im: host, m values each.
+ * Returns ENOCONV if the iteration does not converge.  Needs no device.
+ */
+tsfde_status tsfde_ritz_values(const double* H, int ldh, int m, double* re, double* im);
+
+/*
+ * Estimates of the extreme singular values of M = A (precond = 0) or M = P^{-1} A (precond = 1),
+ * whose ratio sigma_max / sigma_min is the 2-norm condition number that the tables of §6.1.1 and
+ * §6.2 print: sigma_max^2 is the largest eigenvalue of M^T M and 1/sigma_min^2 that of
+ * M^{-1} M^{-T}, each found by Lanczos with full reorthogonalisation (the largest Ritz value),
+ * with M^{-1} = A^{-1} P and M^{-T} = P^T A^{-T} applied by FGMRES solves with A and A^T to
+ * opts->tol.  P^{-1} and P^{-T} must act as fixed linear operators: they are applied with
+ * opts->inner_tol (1e-13 when opts is NULL); opts->block_solver is ignored (P of §5.1).  Each
+ * Lanczos run stops when its estimate changes by less than 1e-12 relative in two consecutive
+ * steps, or after iters steps (1..1000); iterations (host, 2 ints, may be NULL) receives the steps
+ * taken.  The estimates approach the extremes from inside: sigma_max from below, sigma_min from
+ * above.  FP64.  The call keeps iters + 3 work vectors of (M+1) N^d in the problem.
+ */
+tsfde_status tsfde_singular_value_estimates(tsfde_problem* prob, int precond, int iters, double* sigma_max,
+                                           double* sigma_min, int* iterations, const tsfde_opts* opts,
+                                           void* stream);
+
+/*
+ * Morozov's discrepancy of a source f (device, N^d): ||v^(M)(f) - mu_eps||_2, with v the solution
+ * of the direct problem of §6.1 for f (the first M steps of the forward substitution, block solves
+ * to opts->inner_tol).  The largest alpha whose recovered f~ has a discrepancy within tau times the
+ * noise norm is Morozov's choice.  residual: host.  Synchronises `stream`.
+ */
+tsfde_status tsfde_discrepancy(tsfde_problem* prob, const double* f, double* residual, const tsfde_opts* opts,
+                               void* stream);
+
 /* Last error message of the calling thread ("" if none). */
 const char* tsfde_last_error(void);
 

@@ -105,6 +105,11 @@ struct Problem {
     void* pw64 = nullptr;           // persistent P^{-1} work buffers (FP64 / FP32)
     void* pw32 = nullptr;
     double* fwd_work = nullptr;     // direct problem: z-hat and the substitution's output (2 n_tot)
+    double* spec_work = nullptr;    // singular-value estimates: two scratch vectors and the Lanczos basis
+    size_t spec_vecs = 0;           // vectors of n_tot in spec_work
+    // the matvec's history sum runs on a stream of its own beside the Toeplitz passes (d = 2)
+    hipStream_t mv_aux = nullptr;
+    hipEvent_t mv_fork = nullptr, mv_join = nullptr;
     double* dev_scalars = nullptr;  // small device scratch (dots, flags)
     double* host_scalars = nullptr; // pinned mirror
     size_t bytes = 0;               // device bytes the problem holds (tsfde_device_bytes)
@@ -127,9 +132,12 @@ void launch_history_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, 
 // Toeplitz part of the matvec: z_s += c_t gamma2_s .* (B y_s) (s < M) and
 // z_M = c_f gamma2_{M-1} .* (B y_M) + ylast (ylast null: y_{M-1}; D.gamma2 null: ones).
 // d = 2 with workgroup-coalesced transposes (false if the shape is not covered), or the general path
+// before_inv: an event the stream waits for before the epilogue adds to z (the history sum running on
+// another stream), or null
+bool toeplitz2d_supported(const Problem& P);
 template <typename T>
 bool launch_toeplitz2d_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s,
-                              const T* ylast = nullptr);
+                              const T* ylast = nullptr, hipEvent_t before_inv = nullptr);
 template <typename T>
 void launch_toeplitz_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s,
                             const T* ylast = nullptr);
@@ -196,6 +204,11 @@ void launch_axpby(double a, const double* x, double b, const double* y, double* 
 void launch_build_z(const Problem& P, double* z, hipStream_t s);
 void launch_build_zhat(const Problem& P, const double* f, double* zhat, hipStream_t s);
 void launch_fill(double* p, long long n, double v, hipStream_t s);
+// P v = A v + eta (q (x) I) v^(M) in the rows s < M (transpose: P^T u = A^T u + eta sum_s q_s u^(s) in
+// the last block), added to out
+void launch_coupling(const Problem& P, const double* v, double* out, bool transpose, hipStream_t s);
+// uniform values in [-1, 1) from a hash of (seed, index)
+void launch_hash_fill(double* x, long long n, unsigned long long seed, hipStream_t s);
 void launch_fill(float* p, long long n, float v, hipStream_t s);
 template <typename T>
 void launch_sub_partials(const T* a, const T* b, T* out, long long n, T* partials, int* nparts, hipStream_t s);

@@ -598,6 +598,45 @@ __global__ void axpby_k(double a, const double* __restrict__ x, double b, const 
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         out[i] = a * x[i] + b * y[i];
 }
+// The last block column of A that P drops (§5.1): P v = A v + eta (q (x) I) v^(M) in the block rows
+// s < M; transposed, P^T u = A^T u + eta sum_{s < M} q_s u^(s) in the last block row.
+__global__ void coupling_k(double* __restrict__ out, const double* __restrict__ v, const double* __restrict__ q,
+                           double eta, long long Nd, int M, int transpose) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= Nd) return;
+    if (transpose) {
+        double acc = 0.0;
+        for (int s = 0; s < M; ++s) acc += q[s] * v[(long long)s * Nd + j];
+        out[(long long)M * Nd + j] += eta * acc;
+    } else {
+        const double f = eta * v[(long long)M * Nd + j];
+        for (int s = 0; s < M; ++s) out[(long long)s * Nd + j] += q[s] * f;
+    }
+}
+
+void launch_coupling(const Problem& P, const double* v, double* out, bool transpose, hipStream_t s) {
+    hipLaunchKernelGGL(coupling_k, dim3((unsigned)((P.Nd + 255) / 256)), dim3(256), 0, s, out, v, P.f64.q, P.eta,
+                       P.Nd, P.M, transpose ? 1 : 0);
+    TSFDE_HIP(hipGetLastError());
+}
+
+// x_i = a uniform value in [-1, 1) from a 64-bit hash of (seed, i) (splitmix64): a start vector with
+// components along every singular direction
+__global__ void hash_fill_k(double* __restrict__ x, long long n, unsigned long long seed) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (unsigned long long)(i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+void launch_hash_fill(double* x, long long n, unsigned long long seed, hipStream_t s) {
+    hipLaunchKernelGGL(hash_fill_k, dim3(blocks_for(n, 256, 1 << 30)), dim3(256), 0, s, x, n, seed);
+    TSFDE_HIP(hipGetLastError());
+}
+
 void launch_axpby(double a, const double* x, double b, const double* y, double* out, long long n, hipStream_t s) {
     hipLaunchKernelGGL(axpby_k, dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, a, x, b, y, out, n);
     TSFDE_HIP(hipGetLastError());

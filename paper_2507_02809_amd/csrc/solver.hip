@@ -23,6 +23,7 @@
 #include <thread>
 #include <vector>
 
+#include "hessenberg.hpp"
 #include "internal.hpp"
 
 namespace tsfde {
@@ -114,9 +115,28 @@ Dev<float>& dev<float>(Problem& P) { return P.f32; }
 // ---------------------------------------------------------------------------
 // A y
 // ---------------------------------------------------------------------------
+static int env_int(const char* name, int dflt);
+
+// d = 2 with TSFDE_MV_OVERLAP=1: the history sum (ALU-bound) runs on the problem's second stream while
+// the row and column Toeplitz passes (memory- and latency-bound) run on the caller's, which waits for it
+// before the epilogue adds c_t gamma2 .* B y to z.  Off by default: at N = 255, M = 256 the two
+// contend for the CUs and the call takes longer (0.571 against 0.532 ms in FP64).
 template <typename T>
 static void apply_A_impl(Problem& P, const T* y, T* z, hipStream_t st) {
     Dev<T>& D = dev<T>(P);
+    if (toeplitz2d_supported(P) && env_int("TSFDE_MV_OVERLAP", 0) != 0) {
+        if (!P.mv_aux) {
+            TSFDE_HIP(hipStreamCreateWithFlags(&P.mv_aux, hipStreamNonBlocking));
+            TSFDE_HIP(hipEventCreateWithFlags(&P.mv_fork, hipEventDisableTiming));
+            TSFDE_HIP(hipEventCreateWithFlags(&P.mv_join, hipEventDisableTiming));
+        }
+        TSFDE_HIP(hipEventRecord(P.mv_fork, st));
+        TSFDE_HIP(hipStreamWaitEvent(P.mv_aux, P.mv_fork, 0));
+        launch_history_matvec<T>(P, D, y, z, P.mv_aux);
+        TSFDE_HIP(hipEventRecord(P.mv_join, P.mv_aux));
+        launch_toeplitz2d_matvec<T>(P, D, y, z, st, nullptr, P.mv_join);
+        return;
+    }
     launch_history_matvec<T>(P, D, y, z, st);
     if (!launch_toeplitz2d_matvec<T>(P, D, y, z, st)) launch_toeplitz_matvec<T>(P, D, y, z, st);
 }
@@ -716,6 +736,137 @@ static tsfde_status adjoint_impl(Problem& P, const double* g, double* lam, const
     return conv ? TSFDE_OK : TSFDE_ENOCONV;
 }
 
+// ---------------------------------------------------------------------------
+// Spectral tools (§6.1.1, §6.2: the 2-norm condition numbers of A and P^{-1} A)
+// ---------------------------------------------------------------------------
+static double norm2(Problem& P, const double* x, hipStream_t st) { return std::sqrt(dev_dot(P, x, x, P.ntot, st)); }
+
+// The largest eigenvalue of a symmetric positive operator op by Lanczos with full reorthogonalisation
+// (Arnoldi with classical Gram-Schmidt twice on a symmetric operator; Q holds kmax + 1 vectors): the
+// largest Ritz value of the k x k matrix after each step, stopping when it changes by less than 1e-12
+// relative in two consecutive steps, at kmax steps, or on an exact breakdown.  *steps: steps taken.
+static double lanczos_max(Problem& P, const std::function<tsfde_status(const double*, double*)>& op, double* Q,
+                          int kmax, unsigned long long seed, int* steps, tsfde_status& rc, hipStream_t st) {
+    const long long n = P.ntot;
+    if (!P.arn_part) dev_alloc(P, P.arn_part, kArnBlocks * kArnMaxK);
+    if (!P.arn_h) dev_alloc(P, P.arn_h, (2 * (kMaxRestart + 2) + 1));
+    const int hs = kmax + 2;
+    std::vector<double> H((size_t)(kmax + 1) * kmax, 0.0), hhost(2 * hs + 1), A, re, im;
+    launch_hash_fill(Q, n, seed, st);
+    launch_axpby(1.0 / std::sqrt(dev_dot(P, Q, Q, n, st)), Q, 0.0, Q, Q, n, st);
+    double lam = 0.0, prev = -1.0;
+    int calm = 0, k = 0;
+    rc = TSFDE_OK;
+    for (; k < kmax; ++k) {
+        double* w = Q + (size_t)(k + 1) * n;
+        rc = op(Q + (size_t)k * n, w);
+        if (rc != TSFDE_OK) break;
+        cgs2(Q, n, k + 1, w, P.arn_part, kArnBlocks, P.arn_h, P.arn_h + hs, P.arn_h + 2 * hs, st);
+        TSFDE_HIP(hipMemcpyAsync(hhost.data(), P.arn_h, sizeof(double) * (2 * hs + 1), hipMemcpyDeviceToHost, st));
+        TSFDE_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i <= k; ++i) H[(size_t)i * kmax + k] = hhost[i] + hhost[hs + i];
+        const double hn = std::sqrt(hhost[2 * hs]);
+        H[(size_t)(k + 1) * kmax + k] = hn;
+        // Ritz values of the leading (k+1) x (k+1) block
+        const int m = k + 1;
+        A.assign((size_t)m * m, 0.0);
+        for (int r = 0; r < m; ++r)
+            for (int c = 0; c < m; ++c) A[(size_t)r * m + c] = H[(size_t)r * kmax + c];
+        if (hessenberg_eigenvalues(A, m, re, im)) {
+            lam = 0.0;
+            for (int r = 0; r < m; ++r) lam = std::max(lam, re[r]);
+        }
+        calm = (prev > 0.0 && std::fabs(lam - prev) <= 1e-12 * lam) ? calm + 1 : 0;
+        prev = lam;
+        if (calm >= 2 || !(hn > 1e-14 * lam)) { ++k; break; }
+        launch_axpby(1.0 / hn, w, 0.0, w, w, n, st);
+    }
+    *steps = k;
+    return lam;
+}
+
+// sigma_max and sigma_min of M = A or P^{-1} A: sigma_max^2 the largest eigenvalue of M^T M and
+// 1 / sigma_min^2 that of (M^T M)^{-1} = M^{-1} M^{-T}, both by Lanczos.  P^{-1} and P^{-T} are applied
+// with o.inner_tol (fixed linear operators: a tight tolerance); M^{-1} = A^{-1} P and M^{-T} = P^T A^{-T}
+// by FGMRES with A and A^T to o.tol.  used[0], used[1]: the Lanczos steps.
+static tsfde_status singular_values_impl(Problem& P, int precond, int kmax, double& smax, double& smin, int* used,
+                                         const Opts& o, hipStream_t st) {
+    const long long n = P.ntot;
+    const size_t nvec = (size_t)kmax + 3;
+    if (P.spec_vecs < nvec) {
+        if (P.spec_work) {
+            (void)hipFree(P.spec_work);
+            P.bytes -= sizeof(double) * P.spec_vecs * (size_t)n;
+            P.spec_work = nullptr;
+            P.spec_vecs = 0;
+        }
+        dev_alloc(P, P.spec_work, nvec * (size_t)n);
+        P.spec_vecs = nvec;
+    }
+    double* w = P.spec_work;       // operator scratch
+    double* t = w + n;             // operator scratch
+    double* Q = w + 2 * n;         // Lanczos vectors (kmax + 1)
+    Opts so = o;
+    so.precision = TSFDE_FP64;
+    so.use_precond = 1;
+    so.maxit = o.maxit > 0 ? o.maxit : 1000;
+    tsfde_stats S{};
+    auto MtM = [&](const double* in, double* out) -> tsfde_status {  // out = M^T M in
+        if (precond) {
+            apply_A_impl<double>(P, in, w, st);
+            pinv_impl<double>(P, w, t, so, st, true);
+            ptinv_launch(P, t, w, so, st);
+            apply_AT_impl(P, w, out, st);
+        } else {
+            apply_A_impl<double>(P, in, w, st);
+            apply_AT_impl(P, w, out, st);
+        }
+        return TSFDE_OK;
+    };
+    auto MtMinv = [&](const double* in, double* out) -> tsfde_status {  // out = M^{-1} M^{-T} in
+        // t = M^{-T} in = P^T A^{-T} in
+        launch_fill(w, n, 0.0, st);
+        tsfde_status rc = adjoint_impl(P, in, w, so, S, st);
+        if (rc != TSFDE_OK) return rc;
+        if (precond) {
+            apply_AT_impl(P, w, t, st);
+            launch_coupling(P, w, t, true, st);
+        } else {
+            launch_copy<double>(w, t, n, st);
+        }
+        // out = M^{-1} t = A^{-1} (P t)
+        const double* b = t;
+        if (precond) {
+            apply_A_impl<double>(P, t, w, st);
+            launch_coupling(P, t, w, false, st);
+            b = w;
+        }
+        launch_fill(out, n, 0.0, st);
+        return solve(P, b, out, so, S, st);
+    };
+    tsfde_status rc = TSFDE_OK;
+    smax = std::sqrt(lanczos_max(P, MtM, Q, kmax, 0x7a3f11ull, &used[0], rc, st));
+    if (rc != TSFDE_OK) return rc;
+    smin = 1.0 / std::sqrt(lanczos_max(P, MtMinv, Q, kmax, 0x51c9e2ull, &used[1], rc, st));
+    if (rc != TSFDE_OK) return rc;
+    TSFDE_HIP(hipStreamSynchronize(st));
+    return TSFDE_OK;
+}
+
+// Morozov's discrepancy of a source f (device): || v^(M)(f) - mu_eps ||_2 with v the direct problem's
+// solution for f (§6.1), the first M steps of the forward substitution
+static double discrepancy_impl(Problem& P, const double* f, const Opts& o, hipStream_t st) {
+    if (!P.fwd_work) dev_alloc(P, P.fwd_work, 2 * (size_t)P.ntot);
+    double* zh = P.fwd_work;
+    double* y = P.fwd_work + P.ntot;
+    Opts fo = o;
+    fo.block_solver = TSFDE_BLOCK_CG;  // the direct problem is solved, not preconditioned
+    launch_build_zhat(P, f, zh, st);
+    pinv_impl<double>(P, zh, y, fo, st, false);
+    launch_axpby(1.0, y + (size_t)(P.M - 1) * P.Nd, -1.0, P.d_mu, zh, P.Nd, st);
+    return std::sqrt(dev_dot(P, zh, zh, P.Nd, st));
+}
+
 }  // namespace tsfde
 
 // ===========================================================================
@@ -1244,6 +1395,58 @@ tsfde_status tsfde_arnoldi(tsfde_problem* prob, const double* b, int k, double* 
         done = arnoldi_impl(P, ops, b, k, H, st);
     })
     if (steps) *steps = done;
+    return TSFDE_OK;
+}
+
+tsfde_status tsfde_singular_value_estimates(tsfde_problem* prob, int precond, int iters, double* sigma_max,
+                                           double* sigma_min, int* iterations, const tsfde_opts* opts, void* stream) {
+    if (!prob || !sigma_max || !sigma_min) { set_error("singular_value_estimates: NULL argument"); return TSFDE_EINVAL; }
+    if (precond != 0 && precond != 1) { set_error("singular_value_estimates: precond must be 0 or 1"); return TSFDE_EINVAL; }
+    if (iters < 1 || iters > 1000) { set_error("singular_value_estimates: iters must be in [1, 1000]"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    o.block_solver = TSFDE_BLOCK_CG;  // the preconditioner of §5.1 itself
+    if (!opts) o.inner_tol = 1e-13;
+    int used[2] = {0, 0};
+    tsfde_status rc = TSFDE_OK;
+    TSFDE_GUARD("singular_value_estimates",
+                rc = singular_values_impl(P, precond, iters, *sigma_max, *sigma_min, used, o, (hipStream_t)stream);)
+    if (iterations) {
+        iterations[0] = used[0];
+        iterations[1] = used[1];
+    }
+    if (rc == TSFDE_ENOCONV) set_error("singular_value_estimates: an inner solve missed its tolerance");
+    return rc;
+}
+
+tsfde_status tsfde_discrepancy(tsfde_problem* prob, const double* f, double* residual, const tsfde_opts* opts,
+                               void* stream) {
+    if (!prob || !f || !residual) { set_error("discrepancy: NULL argument"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    const Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    TSFDE_GUARD("discrepancy", *residual = discrepancy_impl(P, f, o, (hipStream_t)stream);)
+    return TSFDE_OK;
+}
+
+tsfde_status tsfde_ritz_values(const double* H, int ldh, int m, double* re, double* im) {
+    if (!H || !re || !im || m < 1 || ldh < m) { set_error("ritz_values: need H, re, im and 1 <= m <= ldh"); return TSFDE_EINVAL; }
+    try {
+        std::vector<double> A((size_t)m * m);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) A[(size_t)i * m + j] = H[(size_t)i * ldh + j];
+        std::vector<double> wr, wi;
+        if (!hessenberg_eigenvalues(A, m, wr, wi)) {
+            set_error("ritz_values: the QR iteration did not converge");
+            return TSFDE_ENOCONV;
+        }
+        std::copy(wr.begin(), wr.end(), re);
+        std::copy(wi.begin(), wi.end(), im);
+    } catch (const std::bad_alloc&) {
+        set_error("ritz_values: host allocation failed");
+        return TSFDE_ENOMEM;
+    }
     return TSFDE_OK;
 }
 

@@ -226,7 +226,8 @@ __global__ __launch_bounds__(kMvBlock) void mv_rows_inv(const cplx<T>* __restric
 }
 
 template <typename T, int VPT, int LC>
-static void launch_mv(const Problem& P, const Dev<T>& D, const T* y, T* z, const T* ylast, hipStream_t st) {
+static void launch_mv(const Problem& P, const Dev<T>& D, const T* y, T* z, const T* ylast, hipStream_t st,
+                      hipEvent_t before_inv) {
     const int L = P.L, N = P.N, H = L / 2 + 1;
     const int nthr = L / VPT, gpb = kMvBlock / nthr;
     const size_t lds = sizeof(cplx<T>) * ((size_t)L + (size_t)gpb * lds_len(L));  // twiddles + sequences
@@ -257,33 +258,35 @@ static void launch_mv(const Problem& P, const Dev<T>& D, const T* y, T* z, const
         const int nrows = nsl * H;
         hipLaunchKernelGGL((mv_cols<T, VPT, LC>), dim3(std::min((nrows + gpb - 1) / gpb, res[1])), dim3(kMvBlock), lds,
                            st, D.spec, N, L, nrows, D.tw, D.sym);
+        // the epilogue adds to z: whatever else writes z (the history sum on another stream) first
+        if (before_inv && s0 == 0) TSFDE_HIP(hipStreamWaitEvent(st, before_inv, 0));
         hipLaunchKernelGGL((mv_rows_inv<T, VPT, LC>), dim3(std::min(nrb * nsl, res[2])), dim3(kMvBlock), lds, st,
                            D.spec, N, L, s0, nsl, P.M, D.tw, z, ylast, D.gamma2, T(P.ct), T(P.cf));
         TSFDE_HIP(hipGetLastError());
     }
 }
 
+bool toeplitz2d_supported(const Problem& P) { return P.d == 2 && 2 * P.N <= P.L && P.L >= 16 && P.L <= 4096; }
+
 template <typename T>
 bool launch_toeplitz2d_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t st,
-                              const T* ylast) {
-    if (P.d != 2 || 2 * P.N > P.L) return false;
+                              const T* ylast, hipEvent_t before_inv) {
+    if (!toeplitz2d_supported(P)) return false;
     const int L = P.L;
     if (!ylast) ylast = y + (long long)(P.M - 1) * P.Nd;
     if (L == 512) {
-        launch_mv<T, 8, 512>(P, D, y, z, ylast, st);
-    } else if (L >= 16 && L <= 2048) {
-        launch_mv<T, 8, 0>(P, D, y, z, ylast, st);
-    } else if (L == 4096) {
-        launch_mv<T, 16, 0>(P, D, y, z, ylast, st);
+        launch_mv<T, 8, 512>(P, D, y, z, ylast, st, before_inv);
+    } else if (L <= 2048) {
+        launch_mv<T, 8, 0>(P, D, y, z, ylast, st, before_inv);
     } else {
-        return false;
+        launch_mv<T, 16, 0>(P, D, y, z, ylast, st, before_inv);
     }
     return true;
 }
 
 template bool launch_toeplitz2d_matvec<double>(const Problem&, const Dev<double>&, const double*, double*,
-                                               hipStream_t, const double*);
+                                               hipStream_t, const double*, hipEvent_t);
 template bool launch_toeplitz2d_matvec<float>(const Problem&, const Dev<float>&, const float*, float*, hipStream_t,
-                                              const float*);
+                                              const float*, hipEvent_t);
 
 }  // namespace tsfde

@@ -24,7 +24,8 @@ EXPORTED = [
     "tsfde_compute_stencil", "tsfde_apply_A", "tsfde_apply_A_f32", "tsfde_apply_P_inv",
     "tsfde_apply_P_inv_f32", "tsfde_apply_P_inv_noalloc", "tsfde_gmres_solve", "tsfde_recover_f", "tsfde_recover_f_batch",
     "tsfde_forward_solve", "tsfde_apply_AT", "tsfde_apply_PT_inv", "tsfde_adjoint_solve",
-    "tsfde_recover_f_vjp", "tsfde_recover_f_vjp_batch", "tsfde_arnoldi", "tsfde_last_error",
+    "tsfde_recover_f_vjp", "tsfde_recover_f_vjp_batch", "tsfde_arnoldi", "tsfde_ritz_values",
+    "tsfde_singular_value_estimates", "tsfde_discrepancy", "tsfde_last_error",
 ]
 
 
@@ -95,6 +96,9 @@ def lib():
     L.tsfde_recover_f_batch.argtypes = [pp, i, pp, C.POINTER(Opts), C.POINTER(Stats), i, vp]
     L.tsfde_apply_AT.argtypes = [vp, vp, vp, vp]
     L.tsfde_arnoldi.argtypes = [vp, vp, i, dp, C.POINTER(C.c_int), C.POINTER(Opts), vp]
+    L.tsfde_ritz_values.argtypes = [dp, i, i, dp, dp]
+    L.tsfde_singular_value_estimates.argtypes = [vp, i, i, dp, dp, C.POINTER(C.c_int), C.POINTER(Opts), vp]
+    L.tsfde_discrepancy.argtypes = [vp, vp, dp, C.POINTER(Opts), vp]
     L.tsfde_recover_f_vjp_batch.argtypes = [pp, i, pp, pp, pp, dp, pp, C.POINTER(Opts), C.POINTER(Stats), i, vp]
     L.tsfde_apply_PT_inv.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
     L.tsfde_adjoint_solve.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
@@ -338,6 +342,24 @@ class Problem:
         m = steps.value
         return H.reshape(k + 1, k)[:m + 1, :m], m
 
+    def singular_value_estimates(self, precond: bool, iters: int = 200, opts: Optional[Opts] = None, stream=None):
+        """(sigma_max, sigma_min, (power steps, inverse steps)) of A or P^{-1} A (tsfde_singular_value_estimates);
+        sigma_max / sigma_min estimates the 2-norm condition number."""
+        smax, smin = C.c_double(0.0), C.c_double(0.0)
+        used = (C.c_int * 2)()
+        _check(lib().tsfde_singular_value_estimates(self._h, 1 if precond else 0, int(iters), C.byref(smax),
+                                                    C.byref(smin), used, C.byref(opts) if opts is not None else None,
+                                                    _stream(stream)))
+        return smax.value, smin.value, (used[0], used[1])
+
+    def discrepancy(self, f, opts: Optional[Opts] = None, stream=None) -> float:
+        """||v^(M)(f) - mu_eps||_2 for the direct problem solved with source f (tsfde_discrepancy)."""
+        import torch
+        r = C.c_double(0.0)
+        _check(lib().tsfde_discrepancy(self._h, _dptr(f, torch.float64, self.Nd, "f"), C.byref(r),
+                                       C.byref(opts) if opts is not None else None, _stream(stream)))
+        return r.value
+
     def forward_solve(self, f, opts: Optional[Opts] = None, stream=None):
         import torch
         v = torch.empty(self.M * self.Nd, dtype=torch.float64, device="cuda")
@@ -407,20 +429,15 @@ def recover_f_autograd(problem: "Problem", mu, opts: Optional[Opts] = None, adjo
 
 
 def discrepancy_curve(problem: "Problem", alphas, opts: Optional[Opts] = None, fwd_opts: Optional[Opts] = None):
-    """Morozov's discrepancy of the quasi-boundary-value reconstruction for each alpha: with f_alpha
-    recovered from the problem's data mu_eps (tsfde_recover_f after tsfde_set_alpha), the direct
-    problem is solved for f_alpha (tsfde_forward_solve) and ||v^(M)(f_alpha) - mu_eps||_2 returned.
+    """Morozov's discrepancy of the quasi-boundary-value reconstruction for each alpha: f_alpha
+    recovered from the problem's data mu_eps (tsfde_recover_f after tsfde_set_alpha), then
+    tsfde_discrepancy (the direct problem solved for f_alpha, ||v^(M)(f_alpha) - mu_eps||_2).
     The problem keeps the last alpha of the sweep.  Returns (residuals, list of f_alpha)."""
-    import torch
-    mu = torch.tensor(problem.mu_host, device="cuda") if hasattr(problem, "mu_host") else None
-    if mu is None:
-        raise ValueError("the problem's data were not set through set_mu")
     res, fs = [], []
     for a in alphas:
         problem.set_alpha(a)
         f, _ = problem.recover_f(opts, raise_noconv=True)
-        v = problem.forward_solve(f, opts=fwd_opts)
-        res.append(float((v[(problem.M - 1) * problem.Nd:] - mu).norm()))
+        res.append(problem.discrepancy(f, opts=fwd_opts))
         fs.append(f)
     return res, fs
 
@@ -458,6 +475,10 @@ def recover_f_vjp_batch(problems, gfs, ys=None, opts: Optional[Opts] = None, max
 
 
 def ritz_values(H):
-    """Eigenvalues of the leading square block of an Arnoldi Hessenberg matrix."""
+    """Eigenvalues of the leading square block of an Arnoldi Hessenberg matrix (tsfde_ritz_values)."""
     m = H.shape[1]
-    return np.linalg.eigvals(H[:m, :m])
+    A = np.ascontiguousarray(np.asarray(H, dtype=np.float64)[:m, :m])
+    re, im = np.empty(m), np.empty(m)
+    _check(lib().tsfde_ritz_values(A.ctypes.data_as(C.POINTER(C.c_double)), m, m,
+                                   re.ctypes.data_as(C.POINTER(C.c_double)), im.ctypes.data_as(C.POINTER(C.c_double))))
+    return re + 1j * im

@@ -108,3 +108,15 @@ def test_batch_arguments_checked_before_device_work():
     assert lib.tsfde_recover_f_batch(None, 0, None, None, None, 1, None) == tsfde.OK
     bad = tsfde.default_opts(restart=0)
     assert lib.tsfde_recover_f_batch(None, 0, None, C.byref(bad), None, 1, None) == tsfde.EINVAL
+
+
+def test_ritz_values_through_the_abi():
+    """tsfde_ritz_values (host-only) against LAPACK's eigenvalues of the leading square block of a
+    (k+1) x k Hessenberg matrix, as tsfde_arnoldi returns it."""
+    import numpy as np
+    rng = np.random.default_rng(9)
+    for k in (1, 2, 7, 25):
+        H = np.triu(rng.standard_normal((k + 1, k)), -1)
+        got = np.sort_complex(tsfde.ritz_values(H))
+        ref = np.sort_complex(np.linalg.eigvals(H[:k, :k]))
+        assert np.abs(got - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
