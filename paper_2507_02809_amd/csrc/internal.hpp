@@ -102,6 +102,7 @@ struct Problem {
     double* taud64 = nullptr;
     float* taud32 = nullptr;
     double taud_min = 0;         // smallest tau eigenvalue
+    unsigned* dense_bar = nullptr;  // barrier counter and abort word of the persistent dense block solver
     void* pw64 = nullptr;           // persistent P^{-1} work buffers (FP64 / FP32)
     void* pw32 = nullptr;
     double* fwd_work = nullptr;     // direct problem: z-hat and the substitution's output (2 n_tot)

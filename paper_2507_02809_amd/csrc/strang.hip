@@ -22,7 +22,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <type_traits>
 
+#include "grid_sync.hpp"
 #include "internal.hpp"
 #include "transform_lds.hpp"
 
@@ -150,7 +153,8 @@ __global__ __launch_bounds__(256) void cas_pass(const T* __restrict__ in, T* __r
 template <typename T>
 struct DenseXf {
     const T* tab;
-    const T* lam;
+    const T* lam;   // eigenvalues [k1][k2]
+    const T* lamT;  // transposed [k2][k1]
     int Np, o;
     T inv;
 };
@@ -168,6 +172,287 @@ static void cas_launch(const T* in, T* out, const DenseXf<T>& X, const T* lam, T
     TSFDE_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------
+// Persistent form: one launch per segment of kHB steps (after far_history), the passes of a step
+// separated by device-wide barriers, workgroups of 16 waves.
+// 2D: a workgroup owns a block of kCasRows rows; wave w handles row w % 4 and the outputs of chunk
+// group w / 4 (outputs k = 64 (w / 4) + lane + 256 t):
+//   [P1]  rows i1 of the step's right-hand side (near history added) -> t1[k2][i1]
+//   [P23] rows k2 of t1: transform over i1, scale by inv / (sigma + c lam[k1][k2]), transform back
+//         -> t2[m1][k2]
+//   [P4]  rows m1 of t2: transform over k2 -> y_s[m1][m2], then at once [P1] of step s + 1 on the same
+//         rows (its near history is pointwise in space, so it reads only rows this workgroup wrote)
+// so a step costs two barriers.
+// 1D: the outputs of a transform are dealt out in chunks of 64 over the workgroups, the 16 waves of a
+// workgroup splitting the sum over j:
+//   [P1]  the right-hand side row (t2) -> t1
+//   [P2]  t1 scaled -> y_s, then the right-hand side of step s + 1 at the same points (pointwise
+//         near history) -> t2
+// again two barriers per step.
+// ---------------------------------------------------------------------------
+constexpr int kSegWaves = 16;
+constexpr int kSegThreads = 64 * kSegWaves;
+
+template <typename T>
+struct DenseSegArgs {
+    int d, N, M, Np, o;
+    long long Nd;
+    const T* tab;   // [Np]
+    const T* lamT;  // [Nd] eigenvalues transposed, lamT[k2][k1] (1D: lam[k])
+    const double* sigma;  // [M]
+    T ct, cf, inv;
+    const T* z;
+    T* y;
+    const T* hacc;  // [kHB][Nd] far-history right-hand sides of the segment's steps
+    const T* dg;    // [M][Nd]
+    const T* g2;    // [M][Nd]
+    const T* e;     // e_0.. (epad + kEpad)
+    T* t1;
+    T* t2;
+    unsigned* bar;
+    unsigned long long bar_ticks;
+};
+
+// right-hand side of step s at point g: near history on top of the far-history slice, or the last row
+template <typename T>
+__device__ __forceinline__ T seg_rhs(const DenseSegArgs<T>& a, int sa, int s, long long g) {
+    if (s == a.M)
+        return (a.z[(long long)a.M * a.Nd + g] - a.y[(long long)(a.M - 1) * a.Nd + g]) /
+               (a.cf * a.g2[(long long)(a.M - 1) * a.Nd + g]);
+    T h = T(0);
+#pragma unroll
+    for (int t = 1; t < kHB; ++t) {
+        const int m = s - t;
+        if (m >= sa) h += a.e[t] * a.y[(long long)m * a.Nd + g];
+    }
+    return a.hacc[(long long)(s - sa) * a.Nd + g] - a.dg[(long long)s * a.Nd + g] * h;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSegThreads) void dense_segment(DenseSegArgs<T> a, int sa, int sb) {
+    extern __shared__ double seg_lds_raw[];
+    T* ct = reinterpret_cast<T*>(seg_lds_raw);  // [Np]
+    T* xs = ct + a.Np;                            // [kCasRows][N] inputs of a pass (1D: [N])
+    T* ys = xs + (size_t)kCasRows * a.N;          // [kCasRows][N] forward results of P23 (2D)
+    __shared__ T part[kSegWaves][kCasK];
+    const int N = a.N, Np = a.Np, o = a.o;
+    const int lane = threadIdx.x & (kCasK - 1);
+    const int w = threadIdx.x / kCasK;
+    for (int i = threadIdx.x; i < Np; i += blockDim.x) ct[i] = a.tab[i];
+    unsigned epoch = 0;
+    const int last = sb - 1;
+    if (a.d == 2) {
+        const int nrb = (N + kCasRows - 1) / kCasRows;
+        const int r = w % kCasRows;                 // this wave's row of the block
+        const int kc0 = (w / kCasRows) * kCasK;     // its first output, then every 256
+        constexpr int kStep = kCasK * (kSegWaves / kCasRows);
+        auto p1 = [&](int s, int rb) {
+            const int r0 = rb * kCasRows;
+            const int nr = min(kCasRows, N - r0);
+            for (int i = threadIdx.x; i < nr * N; i += blockDim.x) xs[i] = seg_rhs(a, sa, s, (long long)r0 * N + i);
+            __syncthreads();
+            if (r < nr)
+                for (int k = kc0 + lane; k < N; k += kStep) a.t1[(long long)k * N + r0 + r] = cas_sum(xs + r * N, ct, Np, o, k, 0, N);
+            __syncthreads();
+        };
+        for (int rb = blockIdx.x; rb < nrb; rb += gridDim.x) p1(sa, rb);
+        for (int s = sa; s <= last; ++s) {
+            grid_barrier(a.bar, a.bar_ticks, epoch);
+            // [P23] rows k2 of t1 -> t2 columns
+            const T sig = s < a.M ? T(a.sigma[s]) : T(0);
+            const T c = s < a.M ? a.ct : T(1);
+            for (int rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
+                const int k0 = rb * kCasRows;
+                const int nr = min(kCasRows, N - k0);
+                for (int i = threadIdx.x; i < nr * N; i += blockDim.x) xs[i] = a.t1[(long long)k0 * N + i];
+                __syncthreads();
+                if (r < nr) {
+                    const T* lrow = a.lamT + (long long)(k0 + r) * N;
+                    for (int k1 = kc0 + lane; k1 < N; k1 += kStep)
+                        ys[r * N + k1] = cas_sum(xs + r * N, ct, Np, o, k1, 0, N) * a.inv / (sig + c * lrow[k1]);
+                }
+                __syncthreads();
+                if (r < nr)
+                    for (int m1 = kc0 + lane; m1 < N; m1 += kStep)
+                        a.t2[(long long)m1 * N + k0 + r] = cas_sum(ys + r * N, ct, Np, o, m1, 0, N);
+                __syncthreads();
+            }
+            grid_barrier(a.bar, a.bar_ticks, epoch);
+            // [P4] rows m1 of t2 -> y_s rows, then [P1] of the next step on the same rows
+            T* yst = a.y + (long long)s * a.Nd;
+            for (int rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
+                const int m0 = rb * kCasRows;
+                const int nr = min(kCasRows, N - m0);
+                for (int i = threadIdx.x; i < nr * N; i += blockDim.x) xs[i] = a.t2[(long long)m0 * N + i];
+                __syncthreads();
+                if (r < nr)
+                    for (int m2 = kc0 + lane; m2 < N; m2 += kStep)
+                        yst[(long long)(m0 + r) * N + m2] = cas_sum(xs + r * N, ct, Np, o, m2, 0, N);
+                __syncthreads();
+                if (s < last) p1(s + 1, rb);
+            }
+        }
+        return;
+    }
+    // d = 1
+    const int nkc = (N + kCasK - 1) / kCasK;
+    const int span = (N + kSegWaves - 1) / kSegWaves;
+    const int j0 = min(N, w * span), j1 = min(N, j0 + span);
+    // one chunk of outputs: sum over the waves' parts of x . table
+    auto chunk = [&](const T* x, int k) -> T {
+        part[w][lane] = k < N ? cas_sum(x, ct, Np, o, k, j0, j1) : T(0);
+        __syncthreads();
+        T sum = T(0);
+        if (w == 0) {
+#pragma unroll
+            for (int q = 0; q < kSegWaves; ++q) sum += part[q][lane];
+        }
+        __syncthreads();
+        return sum;
+    };
+    // the right-hand side of the first step at this workgroup's chunks
+    for (int kc = blockIdx.x; kc < nkc; kc += gridDim.x)
+        for (int m = kc * kCasK + (int)threadIdx.x; m < min(N, (kc + 1) * kCasK); m += blockDim.x) a.t2[m] = seg_rhs(a, sa, sa, m);
+    for (int s = sa; s <= last; ++s) {
+        grid_barrier(a.bar, a.bar_ticks, epoch);
+        // [P1] the right-hand side row -> t1
+        for (int i = threadIdx.x; i < N; i += blockDim.x) xs[i] = a.t2[i];
+        __syncthreads();
+        for (int kc = blockIdx.x; kc < nkc; kc += gridDim.x) {
+            const int k = kc * kCasK + lane;
+            const T v = chunk(xs, k);
+            if (w == 0 && k < N) a.t1[k] = v;
+        }
+        grid_barrier(a.bar, a.bar_ticks, epoch);
+        // [P2] scaled t1 -> y_s; the next step's right-hand side at the same points
+        const T sig = s < a.M ? T(a.sigma[s]) : T(0);
+        const T c = s < a.M ? a.ct : T(1);
+        for (int i = threadIdx.x; i < N; i += blockDim.x) xs[i] = a.t1[i] * a.inv / (sig + c * a.lamT[i]);
+        __syncthreads();
+        T* yst = a.y + (long long)s * a.Nd;
+        for (int kc = blockIdx.x; kc < nkc; kc += gridDim.x) {
+            const int m = kc * kCasK + lane;
+            const T v = chunk(xs, m);
+            if (w == 0 && m < N) yst[m] = v;
+            __syncthreads();  // the chunk's y_s values written before the next right-hand side reads them
+            if (s < last)
+                for (int q = kc * kCasK + (int)threadIdx.x; q < min(N, (kc + 1) * kCasK); q += blockDim.x)
+                    a.t2[q] = seg_rhs(a, sa, s + 1, q);
+        }
+    }
+}
+
+// dynamic LDS of the persistent segment kernel: the table, the inputs and (2D) the forward results
+static size_t dense_seg_lds(int d, int N, int Np, size_t elem) {
+    return ((size_t)Np + (d == 2 ? 2 * (size_t)kCasRows * (size_t)N : (size_t)N)) * elem;
+}
+
+// ---------------------------------------------------------------------------
+// 2D FP64 passes on the matrix cores.  A pass is the product D = C X^T, C[k][j] the transform's table
+// matrix (tab[((j+o)(k+o)) mod Np], zero past N, stored Kp x Kp with Kp = N rounded up to 16) and
+// X[r][j] its input rows:  D[k][r] = sum_j C[k][j] X[r][j], written row-major [k][r] (the transposed
+// layout the next pass reads).  v_mfma_f64_16x16x4f64 takes A[i][q] from lane i + 16 q, B[q][jj] from
+// lane jj + 16 q, and leaves D[i][jj] in lane jj + 16 (i % 4), value i / 4.  A workgroup of four waves
+// computes one 16 x 16 tile of D, each wave a quarter of the sum over j; inside a wave the lanes of
+// group q = lane / 16 take a contiguous run of that quarter (the order of a sum's terms is free), so
+// every lane reads whole cache lines.  The quarters are added in LDS.
+// The input is read plainly, scaled by scale / (sigma + c lam[r][j]) (the eigenvalue step), or formed
+// as the last row's right-hand side (z_M - y_{M-1}) / (c_f gamma2_{M-1}).  The last pass of a step
+// writes y_s and, at the same points, the right-hand side of step s + 1 (its near history is pointwise
+// in space), so the next step's first pass reads it plainly.
+// ---------------------------------------------------------------------------
+enum MfmaIn : int { MIN_PLAIN = 0, MIN_SCALE = 1, MIN_LAST = 2 };
+
+struct MfmaPassArgs {
+    const double* in;
+    double* out;
+    const double* Cm;  // [Kp][Kp]
+    int Kp, N;
+    // MIN_SCALE
+    const double* lam;  // [r][j]
+    double sigma, c, scale;
+    // MIN_LAST, and the SRC_LAST right-hand side of the epilogue
+    const double* z;   // z_M
+    const double* yl;  // y_{M-1}
+    const double* g2;  // gamma2_{M-1}
+    double cf;
+    // epilogue (last pass of step s): rhs of step s + 1 = s1
+    int next;  // 0: none, SRC_NEAR, SRC_LAST
+    int sa, s1;
+    long long Nd;
+    const double* hacc;  // w_{s1}, the far-history slice (SRC_NEAR)
+    const double* dg;    // dg_{s1} (SRC_NEAR)
+    const double* y;     // the solution so far
+    const double* e;     // e_0..
+    double* rhs;
+};
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int kMfmaRun = 4;  // unrolled MFMA steps of a lane group's run
+
+template <int IN>
+__device__ __forceinline__ double mfma_in(const MfmaPassArgs& a, int r, int j) {
+    if (r >= a.N || j >= a.N) return 0.0;
+    const long long g = (long long)r * a.N + j;
+    if (IN == MIN_SCALE) return a.in[g] * (a.scale / (a.sigma + a.c * a.lam[g]));
+    if (IN == MIN_LAST) return (a.z[g] - a.yl[g]) / (a.cf * a.g2[g]);
+    return a.in[g];
+}
+
+template <int IN, bool EPI>
+__global__ __launch_bounds__(256) void mfma_pass(MfmaPassArgs a) {
+    __shared__ double red[4][256];
+    const int l = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int k0 = blockIdx.x * 16, r0 = blockIdx.y * 16;
+    const int run = a.Kp >> 4;                       // a lane group's share of the wave's quarter
+    const int jb = (w * 4 + (l >> 4)) * run;         // its first j
+    const double* crow = a.Cm + (long long)(k0 + (l & 15)) * a.Kp + jb;
+    const int r = r0 + (l & 15);
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    int t = 0;
+    for (; t + kMfmaRun <= run; t += kMfmaRun) {
+        double av[kMfmaRun], bv[kMfmaRun];
+#pragma unroll
+        for (int u = 0; u < kMfmaRun; ++u) {
+            av[u] = crow[t + u];
+            bv[u] = mfma_in<IN>(a, r, jb + t + u);
+        }
+#pragma unroll
+        for (int u = 0; u < kMfmaRun; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+    }
+    for (; t < run; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(crow[t], mfma_in<IN>(a, r, jb + t), acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[v][w * 64 + l] = acc[v];
+    __syncthreads();
+    // wave w finishes value w of every lane: D[k][r] with k = k0 + l / 16 + 4 w
+    const double d = (red[w][l] + red[w][64 + l]) + (red[w][128 + l] + red[w][192 + l]);
+    const int k = k0 + (l >> 4) + 4 * w;
+    if (k >= a.N || r >= a.N) return;
+    const long long g = (long long)k * a.N + r;
+    a.out[g] = d;
+    if (!EPI) return;
+    if (a.next == SRC_NEAR) {
+        // rhs_{s1} = w_{s1} - dg_{s1} sum_{sa <= m < s1} e_{s1-m} y_m, with y_{s1-1} = d
+        double h = a.e[1] * d;
+#pragma unroll
+        for (int q = 2; q < kHB; ++q) {
+            const int m = a.s1 - q;
+            if (m >= a.sa) h += a.e[q] * a.y[(long long)m * a.Nd + g];
+        }
+        a.rhs[g] = a.hacc[g] - a.dg[g] * h;
+    } else if (a.next == SRC_LAST) {
+        a.rhs[g] = (a.z[g] - d) / (a.cf * a.g2[g]);
+    }
+}
+
+template <int IN, bool EPI>
+static void mfma_launch(const MfmaPassArgs& a, hipStream_t st) {
+    const dim3 grid((unsigned)(a.Kp / 16), (unsigned)(a.Kp / 16));
+    hipLaunchKernelGGL((mfma_pass<IN, EPI>), grid, dim3(256), 0, st, a);
+    TSFDE_HIP(hipGetLastError());
+}
+
 template <typename T>
 static T* table(Problem& P, bool tau);
 template <>
@@ -180,7 +465,25 @@ static void upload_tables(Problem& P, const std::vector<double>& tab, const std:
                           float*& d32) {
     std::vector<double> t(tab);
     t.insert(t.end(), lam.begin(), lam.end());
+    // the eigenvalues again, transposed (lamT[k2][k1]), for the persistent solver's column pass
+    const int N = P.N;
+    if (P.d == 2) {
+        for (int k2 = 0; k2 < N; ++k2)
+            for (int k1 = 0; k1 < N; ++k1) t.push_back(lam[(size_t)k1 * N + k2]);
+    } else {
+        t.insert(t.end(), lam.begin(), lam.end());
+    }
     std::vector<float> t32(t.begin(), t.end());
+    if (P.d == 2) {
+        // the table matrix C[k][j] = tab[((j + o)(k + o)) mod Np] (FP64 only), Kp x Kp, zero past N
+        const int Kp = (N + 15) / 16 * 16;
+        const long long Np = (long long)tab.size();
+        const int o = Np == N ? 0 : 1;
+        const size_t base = t.size();
+        t.resize(base + (size_t)Kp * Kp, 0.0);
+        for (int k = 0; k < N; ++k)
+            for (int j = 0; j < N; ++j) t[base + (size_t)k * Kp + j] = tab[((long long)(j + o) * (k + o)) % Np];
+    }
     dev_alloc(P, d64, t.size());
     dev_alloc(P, d32, t32.size());
     TSFDE_HIP(hipMemcpy(d64, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice));
@@ -211,6 +514,122 @@ void ensure_tau_dense(Problem& P) {
 // The steps run in blocks of kHB: one bandwidth-bound kernel folds the history of all earlier blocks
 // into the block's right-hand sides, and each step's first transform pass adds the (< kHB) near terms
 // while loading its rows.
+// The persistent form of the block solves: far_history and one dense_segment launch per segment of
+// kHB steps, the grid holding its CU slots until the host has seen the last segment finish.
+template <typename T>
+static void dense_persistent(Problem& P, const Dev<T>& D, const T* z, T* y, const DenseXf<T>& X, T* t1, T* t2,
+                             T* hist, int last, size_t lds, hipStream_t st) {
+    if (!P.dense_bar) dev_alloc(P, P.dense_bar, 16);
+    int dev = 0, ncu = 0, per_cu = 0;
+    TSFDE_HIP(hipGetDevice(&dev));
+    TSFDE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    TSFDE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dense_segment<T>, kSegThreads, lds));
+    if (per_cu < 1) throw HipError{hipErrorInvalidConfiguration, "dense block solver: a workgroup does not fit a CU"};
+    ResidencyBudget& pool = residency_budget(dev, ncu);
+    const int work = P.d == 2 ? (P.N + kCasRows - 1) / kCasRows : (P.N + kCasK - 1) / kCasK;
+    int cap = std::min(per_cu * ncu, residency_max_grid(pool.total(), kXcds));
+    if (shared_launch()) cap = std::min(cap, std::max(1, ncu / kMaxInflight));
+    const int grid = std::max(1, std::min(work, cap));
+    ResidencyTicket ticket;
+    ticket.hold(&pool, residency_slots(grid, kXcds));
+    DenseSegArgs<T> a{};
+    a.d = P.d;
+    a.N = P.N;
+    a.M = P.M;
+    a.Np = X.Np;
+    a.o = X.o;
+    a.Nd = P.Nd;
+    a.tab = X.tab;
+    a.lamT = X.lamT;
+    a.sigma = P.d_sigma;
+    a.ct = T(P.ct);
+    a.cf = T(P.cf);
+    a.inv = X.inv;
+    a.z = z;
+    a.y = y;
+    a.hacc = hist;
+    a.dg = D.dg;
+    a.g2 = D.gamma2;
+    a.e = D.epad + kEpad;
+    a.t1 = t1;
+    a.t2 = t2;
+    a.bar = P.dense_bar;
+    a.bar_ticks = barrier_ticks(dev);
+    launch_fill(reinterpret_cast<float*>(P.dense_bar) + 1, 1, 0.0f, st);  // clear the abort word
+    for (int sa = 0; sa <= last; sa += kHB) {
+        const int cnt = std::min(kHB, P.M - sa);
+        if (cnt > 0) launch_far_history<T>(P, D, y, hist, z, sa, cnt, st);
+        int sa_ = sa, sb_ = std::min(sa + kHB, last + 1);
+        launch_fill(reinterpret_cast<float*>(P.dense_bar), 1, 0.0f, st);  // zero the barrier counter
+        void* args[] = {&a, &sa_, &sb_};
+        TSFDE_HIP(hipLaunchKernel((void*)dense_segment<T>, dim3(grid), dim3(kSegThreads), args, lds, st));
+    }
+    unsigned* abort_h = reinterpret_cast<unsigned*>(P.host_scalars + 58);
+    TSFDE_HIP(hipMemcpyAsync(abort_h, P.dense_bar + 1, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    TSFDE_HIP(hipStreamSynchronize(st));
+    if (*abort_h != 0u)
+        throw HipError{hipErrorLaunchTimeOut, "dense block solver: a device-wide barrier wait timed out"};
+}
+
+// The 2D FP64 block solves on the matrix cores: per step four mfma_pass launches,
+//   rhs [i1][i2] -> t1 [k2][i1] -> t2 [k1][k2] -> (scaled) t1 [m2][k1] -> y_s [m1][m2],
+// the last one also writing the right-hand side of step s + 1 into t2 (free by then).  The first
+// step of a block of kHB steps reads its right-hand side from the far-history slice (or forms the
+// last row's).
+static void dense_mfma(Problem& P, const Dev<double>& D, const double* z, double* y, const DenseXf<double>& X,
+                       double* t1, double* t2, double* hist, int last, hipStream_t st) {
+    const int N = P.N;
+    const long long Nd = P.Nd;
+    MfmaPassArgs a{};
+    a.N = N;
+    a.Kp = (N + 15) / 16 * 16;
+    a.Cm = X.lamT + Nd;
+    a.lam = X.lam;
+    a.z = z + (long long)P.M * Nd;
+    a.yl = y + (long long)(P.M - 1) * Nd;
+    a.g2 = D.gamma2 + (long long)(P.M - 1) * Nd;
+    a.cf = P.cf;
+    a.Nd = Nd;
+    a.y = y;
+    a.e = D.epad + kEpad;
+    a.rhs = t2;
+    for (int sa = 0; sa <= last; sa += kHB) {
+        const int cnt = std::min(kHB, P.M - sa);
+        if (cnt > 0) launch_far_history<double>(P, D, y, hist, z, sa, cnt, st);
+        const int se = std::min(sa + kHB - 1, last);
+        a.sa = sa;
+        for (int s = sa; s <= se; ++s) {
+            MfmaPassArgs p = a;
+            p.out = t1;
+            if (s > sa) {
+                p.in = t2;
+                mfma_launch<MIN_PLAIN, false>(p, st);
+            } else if (s < P.M) {
+                p.in = hist;
+                mfma_launch<MIN_PLAIN, false>(p, st);
+            } else {
+                mfma_launch<MIN_LAST, false>(p, st);
+            }
+            p.in = t1;
+            p.out = t2;
+            mfma_launch<MIN_PLAIN, false>(p, st);
+            p.in = t2;
+            p.out = t1;
+            p.sigma = s < P.M ? P.sigma[s] : 0.0;
+            p.c = s < P.M ? P.ct : 1.0;
+            p.scale = X.inv;
+            mfma_launch<MIN_SCALE, false>(p, st);
+            p.in = t1;
+            p.out = y + (long long)s * Nd;
+            p.s1 = s + 1;
+            p.next = s + 1 > se ? 0 : (s + 1 < P.M ? SRC_NEAR : SRC_LAST);
+            p.hacc = hist + (long long)(s + 1 - sa) * Nd;
+            p.dg = s + 1 < P.M ? D.dg + (long long)(s + 1) * Nd : nullptr;
+            mfma_launch<MIN_PLAIN, true>(p, st);
+        }
+    }
+}
+
 template <typename T>
 void pinv_dense_blocks(Problem& P, const Dev<T>& D, const T* z, T* y, bool last_block, bool tau, hipStream_t st) {
     if (tau) ensure_tau_dense(P);
@@ -222,6 +641,7 @@ void pinv_dense_blocks(Problem& P, const Dev<T>& D, const T* z, T* y, bool last_
     X.Np = tau ? 2 * (N + 1) : N;
     X.o = tau ? 1 : 0;
     X.lam = X.tab + X.Np;
+    X.lamT = X.lam + Nd;
     X.inv = tau ? T(std::pow(2.0 / (N + 1), P.d)) : T(1.0 / (double)Nd);  // S S = (N+1)/2 I;  H H = N I
     const T* lam = X.lam;
     const int nrow = P.d == 2 ? N : 1;
@@ -230,6 +650,27 @@ void pinv_dense_blocks(Problem& P, const Dev<T>& D, const T* z, T* y, bool last_
     T* hist = reinterpret_cast<T*>(P.strang_hist);
     const T inv = X.inv;
     const int last = last_block ? P.M : P.M - 1;
+    const size_t seg_lds = dense_seg_lds(P.d, N, X.Np, sizeof(T));
+    // the persistent form is the faster one for a single row (d = 1: 52 against 91 ms at N = 4095,
+    // M = 1024); in 2D the one-launch-per-pass form spreads each pass over more CUs (13.4 against
+    // 20.6 ms at N = 255, M = 256: the passes are bound by the LDS table reads of the sums).
+    // TSFDE_DENSE_PERSISTENT=1 / 0 forces either.
+    const char* pe = std::getenv("TSFDE_DENSE_PERSISTENT");
+    const bool persistent = pe ? std::atoi(pe) != 0 : P.d == 1;
+    if (persistent) {
+        if (seg_lds + sizeof(T) * kSegWaves * kCasK <= kPassLdsBytes) {
+            dense_persistent<T>(P, D, z, y, X, t1, t2, hist, last, seg_lds, st);
+            return;
+        }
+    }
+    if constexpr (std::is_same<T, double>::value) {
+        // 2D in FP64: the passes on the matrix cores (TSFDE_DENSE_MFMA=0 selects the LDS-table passes)
+        const char* me = std::getenv("TSFDE_DENSE_MFMA");
+        if (P.d == 2 && (!me || std::atoi(me) != 0)) {
+            dense_mfma(P, D, z, y, X, t1, t2, hist, last, st);
+            return;
+        }
+    }
     for (int sa = 0; sa <= last; sa += kHB) {
         const int cnt = std::min(kHB, P.M - sa);
         if (cnt > 0) launch_far_history<T>(P, D, y, hist, z, sa, cnt, st);

@@ -2,30 +2,35 @@
 M = 256 workload (beta = 0.6, omega = 1.6, alpha = 1e-4; paper_2507_02809_amd.inputs.c3), made by
 the CPU oracle alone.
 
-    python tests/golden/make_c3_reference.py          # about an hour on 8 cores, ~12 GB of memory
+    python tests/golden/make_c3_reference.py [--workdir DIR]     # about an hour on 8 cores
 
-It calls only oracle/ and the seeded input generator, and never the GPU library.
+It calls only oracle/ and the seeded input generator, and never the GPU library.  Each stage saves
+its result in the work directory (default tests/golden/_c3_work, not committed) and is skipped when
+that file exists, so an interrupted run resumes.
 
 1. The final-time data (§6.1 direct problem): v = A-hat^{-1} z-hat with f = f_true, by the
    forward substitution of §5.1 with tau-preconditioned CG blocks to relative residual 1e-14;
    mu = v^(M), then the input set's noise (relative norm 1e-3) gives mu_eps.
-2. Route R3, the all-at-once system of §5 (eq. lin-syst) A y = z matrix-free: restarted
-   flexible GMRES on the oracle's FFT matvec, right-preconditioned by P^{-1} of §5.1 applied
-   inexactly (CG blocks to 1e-6; FGMRES tolerates a varying preconditioner), to a true relative
-   residual <= 1e-13.  f_R3 = y^(M+1).
+2. Route R3, the all-at-once system of §5 (eq. lin-syst) A y = z matrix-free: restarted flexible
+   GMRES on the oracle's FFT matvec, right-preconditioned by T_{n,S} of the §5.1 Remark (the
+   oracle's T_solve: exact, no inner iterations; the preconditioner changes only the iteration),
+   until the true relative residual stops improving by a factor of two between restarts or
+   reaches 1e-14.  f_R3 = y^(M+1).
 3. Route R4, the Schur complement in f~: the first M block rows of A give
    v = A-hat^{-1}(z_{1:M} + (eta q (x) I) f~), and the last row then reads
        G f~ = mu_eps - [A-hat^{-1} z_{1:M}]_M,   G f = c_f D_2^(M) B f + [A-hat^{-1} (eta q (x) f)]_M,
    solved by flexible GMRES on the N^d unknowns, right-preconditioned by (c_f D_2^(M) B)^{-1}
-   (CG, inexact), every G application an accurate forward solve (CG blocks to 1e-14).
+   (CG, inexact), every G application an accurate direct solve (CG blocks to 1e-14).
 4. The two routes share the matvec pieces of the oracle but not the system they solve; their
-   agreement ||f_R3 - f_R4|| / ||f_R3|| <= 1e-11 certifies f_ref = f_R3.
+   agreement ||f_R3 - f_R4|| / ||f_R3|| <= 1e-11, with R3's true residual <= 1e-11, certifies
+   f_ref = f_R3.  (R3's true residual stops near 2e-12: the rounding floor of the FP64 matvec for
+   this z, whose first M blocks are zero while y is not; restarts no longer lower it.)
 
 Stored: mu_eps, f_ref, f_r4 and the residuals, iteration counts and wall times of each route.
 """
 from __future__ import annotations
 
-import multiprocessing as mp
+import argparse
 import os
 import sys
 import time
@@ -38,7 +43,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 OUT = os.path.join(HERE, "c3_reference.npz")
-R3_TOL = 1e-13
+R3_RES = 1e-11
 R4_TOL = 1e-13
 AGREE = 1e-11
 
@@ -52,33 +57,37 @@ def _problem(mu=None):
     return inp, p
 
 
-def make_mu(log):
+def make_mu():
     from oracle import matfree, system
     inp, p = _problem()
-    t = time.time()
     v = matfree.forward_solve(p, system.rhs_zhat(p, inp.f_true), inner="pcg", inner_tol=1e-14)
-    mu = v.reshape(p.S, p.Nd)[-1]
-    log(f"forward solve for mu: {time.time() - t:.0f} s")
-    return inp.noisy(mu)
+    return inp.noisy(v.reshape(p.S, p.Nd)[-1])
 
 
-def route_r3(mu_eps, workers, q):
+def route_r3(mu_eps, log):
+    """FGMRES(60) with T_{n,S}, restarted until the true residual stagnates; returns (f, residual,
+    iterations)."""
     from oracle import krylov, matfree, system
-    matfree.WORKERS = workers
     _, p = _problem(mu_eps)
     sym = matfree.circulant_symbol(p)
     z = system.rhs_z(p)
     A = lambda v: matfree.matvec(p, v, sym)
-    M = lambda v: matfree.P_solve(p, v, inner="pcg", inner_tol=1e-6)
-    t = time.time()
-    x, its, hist = krylov.fgmres(A, M, z, R3_TOL, restart=40, maxit=300)
-    res = float(np.linalg.norm(z - A(x)) / np.linalg.norm(z))
-    q.put(("r3", x[p.S * p.Nd:].copy(), res, its, time.time() - t, hist))
+    M = lambda v: matfree.T_solve(p, v)
+    x = np.zeros(p.n_tot)
+    total, best = 0, np.inf
+    while True:
+        x, its, hist = krylov.fgmres(A, M, z, 1e-14, restart=60, maxit=60, x0=x)
+        total += its
+        res = float(np.linalg.norm(z - A(x)) / np.linalg.norm(z))
+        log(f"R3: {total} iterations, true residual {res:.3e}")
+        if res <= 1e-14 or res > 0.5 * best or total >= 600:
+            best = min(best, res)
+            return x[p.S * p.Nd:].copy(), best, total
+        best = res
 
 
-def route_r4(mu_eps, workers, q):
+def route_r4(mu_eps, log):
     from oracle import krylov, matfree, system
-    matfree.WORKERS = workers
     _, p = _problem(mu_eps)
     S, Nd = p.S, p.Nd
     sym = matfree.circulant_symbol(p)
@@ -99,43 +108,55 @@ def route_r4(mu_eps, workers, q):
         x, _ = matfree._cg(Bop, r / (p.c_f * p.gamma2[S - 1]), np.zeros(Nd), 1e-8, 500, Bprec)
         return x
 
-    t = time.time()
     rhs = z[S * Nd:] - fwd(z[:S * Nd])
-    f, its, hist = krylov.fgmres(G, Minv, rhs, R4_TOL, restart=100, maxit=300)
+    f, its, _ = krylov.fgmres(G, Minv, rhs, R4_TOL, restart=100, maxit=300)
     res = float(np.linalg.norm(rhs - G(f)) / np.linalg.norm(rhs))
-    q.put(("r4", f, res, its, time.time() - t, hist))
+    log(f"R4: {its} iterations, residual {res:.3e}")
+    return f, res, its
 
 
 def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workdir", default=os.path.join(HERE, "_c3_work"))
+    a = ap.parse_args()
+    os.makedirs(a.workdir, exist_ok=True)
     t0 = time.time()
 
     def log(msg):
         print(f"[{time.time() - t0:7.0f} s] {msg}", flush=True)
 
-    mu_eps = make_mu(log)
-    ctx = mp.get_context("fork")
-    q = ctx.Queue()
-    ncpu = os.cpu_count() or 2
-    procs = [ctx.Process(target=route_r3, args=(mu_eps, max(1, ncpu // 2), q)),
-             ctx.Process(target=route_r4, args=(mu_eps, max(1, ncpu - ncpu // 2), q))]
-    for pr in procs:
-        pr.start()
-    out = {}
-    for _ in procs:
-        name, f, res, its, secs, hist = q.get()
-        out[name] = (f, res, its, secs, hist)
-        log(f"{name}: residual {res:.3e}, {its} iterations, {secs:.0f} s")
-    for pr in procs:
-        pr.join()
-    f3, res3, its3, sec3, _ = out["r3"]
-    f4, res4, its4, sec4, _ = out["r4"]
+    def stage(name, fn):
+        path = os.path.join(a.workdir, name + ".npz")
+        if os.path.exists(path):
+            with np.load(path) as d:
+                return {k: np.array(d[k]) for k in d.files}
+        ts = time.time()
+        out = fn()
+        out["seconds"] = np.array(time.time() - ts)
+        np.savez(path, **out)
+        log(f"{name} done in {float(out['seconds']):.0f} s")
+        return out
+
+    mu = stage("mu", lambda: {"mu_eps": make_mu()})["mu_eps"]
+
+    def r3():
+        f, res, its = route_r3(mu, log)
+        return {"f": f, "residual": np.array(res), "iterations": np.array(its)}
+
+    def r4():
+        f, res, its = route_r4(mu, log)
+        return {"f": f, "residual": np.array(res), "iterations": np.array(its)}
+
+    o3 = stage("r3", r3)
+    o4 = stage("r4", r4)
+    f3, f4 = o3["f"], o4["f"]
     agree = float(np.linalg.norm(f3 - f4) / np.linalg.norm(f3))
-    log(f"R3 vs R4: {agree:.3e}")
-    if not (res3 <= R3_TOL and agree <= AGREE):
-        raise SystemExit(f"not certified: R3 residual {res3:.3e}, R3/R4 agreement {agree:.3e}")
-    np.savez(OUT, mu_eps=mu_eps, f_ref=f3, f_r4=f4, r3_residual=res3, r4_residual=res4,
-             r3_iterations=its3, r4_iterations=its4, r3_seconds=sec3, r4_seconds=sec4,
-             r3_r4_agreement=agree)
+    log(f"R3 residual {float(o3['residual']):.3e}, R4 residual {float(o4['residual']):.3e}, agreement {agree:.3e}")
+    if not (float(o3["residual"]) <= R3_RES and agree <= AGREE):
+        raise SystemExit(f"not certified: R3 residual {float(o3['residual']):.3e}, agreement {agree:.3e}")
+    np.savez(OUT, mu_eps=mu, f_ref=f3, f_r4=f4, r3_residual=o3["residual"], r4_residual=o4["residual"],
+             r3_iterations=o3["iterations"], r4_iterations=o4["iterations"], r3_seconds=o3["seconds"],
+             r4_seconds=o4["seconds"], r3_r4_agreement=np.array(agree))
     log(f"wrote {OUT}")
 
 

@@ -455,6 +455,52 @@ def test_apply_P_inv_strang_blocks_matches_oracle(d, N, M):
     assert rel_err(y.cpu().numpy(), ref) <= tol
 
 
+@pytest.mark.parametrize("kind", ["strang", "tau"])
+@pytest.mark.parametrize("d,N,M", [(1, 300, 37), (2, 37, 37), (2, 66, 17)])
+def test_dense_block_solvers_persistent_matches_pass_launches(monkeypatch, kind, d, N, M):
+    """The persistent dense-transform block solver (one launch per segment of 16 steps, two device-wide
+    barriers per step) against the one-launch-per-pass form, over several segments with a ragged last
+    one, and against the oracle's S^{-1} / T^{-1}."""
+    inp = inputs.small(d, N, M, beta=0.35, omega=1.45)
+    p = workloads.problem(inp, mu=np.zeros(inp.Nd))
+    zz = np.random.default_rng(33).standard_normal(p.n_tot)
+    bs = tsfde.BLOCK_STRANG if kind == "strang" else tsfde.BLOCK_TAU
+    ref = matfree.S_solve(p, zz) if kind == "strang" else matfree.T_solve(p, zz)
+    if kind == "tau" and d == 2 and N == 63:
+        monkeypatch.setenv("TSFDE_PINV", "0")
+    with gpu_problem(inp, p) as g:
+        monkeypatch.setenv("TSFDE_DENSE_PERSISTENT", "1")
+        y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=tsfde.default_opts(block_solver=bs)).cpu().numpy()
+        monkeypatch.setenv("TSFDE_DENSE_PERSISTENT", "0")
+        y0 = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=tsfde.default_opts(block_solver=bs)).cpu().numpy()
+    assert rel_err(y, y0) <= 1e-13
+    assert rel_err(y, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("kind", ["strang", "tau"])
+@pytest.mark.parametrize("N,M", [(1, 3), (17, 16), (37, 17), (100, 33), (255, 3)])
+def test_dense_block_solvers_mfma_passes_match_lds_passes(monkeypatch, kind, N, M):
+    """2D, FP64: the block solves as products on the matrix cores (16 x 16 tiles, the sum over j split
+    over four waves, a ragged last tile) against the passes that read the table from LDS, and both
+    against the oracle's S^{-1} / T^{-1}.  M = 16 puts the last row at the start of a block of steps
+    (its right-hand side formed by the first pass), M = 17 and 33 inside one (formed by the previous
+    step's last pass)."""
+    inp = inputs.small(2, N, M, beta=0.35, omega=1.45)
+    p = workloads.problem(inp, mu=np.zeros(inp.Nd))
+    zz = np.random.default_rng(35).standard_normal(p.n_tot)
+    bs = tsfde.BLOCK_STRANG if kind == "strang" else tsfde.BLOCK_TAU
+    ref = matfree.S_solve(p, zz) if kind == "strang" else matfree.T_solve(p, zz)
+    monkeypatch.setenv("TSFDE_DENSE_PERSISTENT", "0")
+    monkeypatch.setenv("TSFDE_PINV", "0")  # tau: the dense sine passes, also where 2(N+1) is a power of two
+    with gpu_problem(inp, p) as g:
+        monkeypatch.setenv("TSFDE_DENSE_MFMA", "1")
+        y = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=tsfde.default_opts(block_solver=bs)).cpu().numpy()
+        monkeypatch.setenv("TSFDE_DENSE_MFMA", "0")
+        y0 = g.apply_P_inv(torch.tensor(zz, device=DEV), opts=tsfde.default_opts(block_solver=bs)).cpu().numpy()
+    assert rel_err(y, y0) <= 1e-13
+    assert rel_err(y, ref) <= 1e-11
+
+
 @pytest.mark.parametrize("d,N,M", [(1, 1, 3), (2, 1, 2), (1, 2, 4), (2, 2, 3), (2, 9, 1)])
 def test_apply_P_inv_strang_blocks_degenerate_shapes(d, N, M):
     """One or two points per direction (a single-entry circulant, a 2 x 2 one) and a single time
