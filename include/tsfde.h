@@ -309,6 +309,38 @@ tsfde_status tsfde_recover_f_batch(tsfde_problem* const* probs, int count, doubl
                                    void* stream);
 
 /*
+ * Several right-hand sides of one problem (§5, eq. lin-syst: A X = B, e.g. the same instance with
+ * several data sets mu): block flexible GMRES.  One block Krylov space of nrhs vectors per step
+ * serves all columns; P^{-1} (§5.1) is applied to each column, the block Gram-Schmidt products
+ * V^T W and V H run on the FP64 matrix cores, the block Hessenberg matrix is reduced by Givens
+ * rotations on the host.  A restart cycle of opts.restart steps holds (restart + 1) nrhs basis and
+ * restart nrhs preconditioned vectors, each (M+1) N^d doubles rounded up to a multiple of 64
+ * (counted against opts.max_device_bytes).
+ *   nrhs     1..16, with restart * nrhs <= 1024
+ *   B        device, nrhs vectors of (M+1) N^d, contiguous (column c at B + c (M+1) N^d)
+ *   X        device, same layout; in: initial guesses, out: solutions (last iterates on ENOCONV)
+ *   rel_res  host, nrhs values receiving each column's true relative residual, or NULL
+ *   opts     tol applies to every column; precision FP64 or PREC_F32 (MIXED: ENOTIMPL);
+ *            maxit counts block steps
+ * stats->iters counts block steps and stats->rel_res is the largest column residual.
+ * Returns EINVAL for NULL or overlapping B, X; ENOTIMPL for nrhs or restart out of range.
+ */
+tsfde_status tsfde_gmres_solve_block(tsfde_problem* prob, int nrhs, const double* B, double* X,
+                                     double* rel_res, const tsfde_opts* opts, tsfde_stats* stats,
+                                     void* stream);
+
+/*
+ * tsfde_recover_f for nrhs data sets of the same problem in one block solve: z(mu_c) built for each
+ * column (eq. lin-syst), X from zero, f~_c = the last block of column c.
+ *   mus      device, nrhs x N^d (mu_c at mus + c N^d); the problem's own mu is not used
+ *   f_out    device, nrhs x N^d
+ * The right-hand sides and solutions (2 nrhs vectors of (M+1) N^d) are held by the problem.
+ */
+tsfde_status tsfde_recover_f_block(tsfde_problem* prob, int nrhs, const double* mus, double* f_out,
+                                   double* rel_res, const tsfde_opts* opts, tsfde_stats* stats,
+                                   void* stream);
+
+/*
  * Direct problem of §6.1: v = A-hat^{-1} z-hat with z-hat^(s) = b_{s-1} D_1^(s) rho + eta q^(s) f,
  * i.e. the first M steps of the forward substitution (used to synthesise mu).
  *   f    device, N^d        v  device, M N^d (slices v^(1..M)); mu = v^(M)

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtsfde.so")
-SOURCES = ["setup.hip", "solver.hip", "spectral.hip", "kernels.hip", "pinv_persistent.hip", "pinv_fixed.hip", "pinv_fixed_tau.hip", "toeplitz2d.hip", "strang.hip"]
+SOURCES = ["setup.hip", "solver.hip", "spectral.hip", "kernels.hip", "pinv_persistent.hip", "pinv_fixed.hip", "pinv_fixed_tau.hip", "toeplitz2d.hip", "strang.hip", "block_krylov.hip"]
 ARCH = "gfx950"
 
 

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -115,7 +116,46 @@ struct Problem {
     double* host_scalars = nullptr; // pinned mirror
     size_t bytes = 0;               // device bytes the problem holds (tsfde_device_bytes)
     size_t basis_bytes = 0;         // of which the FGMRES basis V, Z
+    // block FGMRES (block_krylov.hip): basis and directions (vectors of a leading dimension rounded up
+    // to 64), Gram partial sums, a small transfer buffer; right-hand sides and solutions of
+    // tsfde_recover_f_block
+    double* blk_V = nullptr;
+    double* blk_part = nullptr;
+    double* blk_small = nullptr;
+    double* blk_io = nullptr;
+    size_t blk_bytes = 0;
+    int blk_nvec = 0, blk_p = 0, blk_io_cols = 0;
 };
+
+// Solver options (tsfde_opts, validated)
+struct Opts {
+    int restart = 50, maxit = 0, precision = TSFDE_FP64, use_precond = 1, inner_maxit = 200, max_refine = 30;
+    int block_solver = TSFDE_BLOCK_CG, warm_start = TSFDE_WARM_LINEAR;
+    double tol = 1e-10, inner_tol = 1e-12, refine_tol = 1e-5;
+    long long max_device_bytes = 0;
+    int recompute_z = 0;
+};
+
+// The two operators of a right-preconditioned Krylov solve (FP64 vectors of n_tot)
+struct SolveOps {
+    std::function<void(const double*, double*)> A;      // out = A v
+    std::function<long long(const double*, double*)> M; // out = M v (returns inner iterations)
+};
+
+// A device-memory cap (opts.max_device_bytes) that a solve's buffers would exceed
+struct CapError {
+    std::string msg;
+};
+
+// Block FGMRES (block_krylov.hip): p <= kBlockMaxCols columns, basis of at most kBlockMaxBasis vectors
+// per restart cycle (restart * p).  B, X: p vectors of n_tot each, contiguous; X holds the initial
+// guesses.  rel receives each column's relative residual (true residual at the end of the last cycle).
+constexpr int kBlockMaxCols = 16;
+constexpr int kBlockMaxBasis = 1024;
+size_t block_basis_bytes(const Problem& P, int p, int m);
+int block_fgmres(Problem& P, const SolveOps& ops, int p, const double* B, double* X, double rtol, int restart,
+                 int maxit, hipStream_t st, tsfde_stats& S, std::vector<double>& rel, bool& conv, const Opts& o);
+double now_seconds();
 
 // hipMalloc of `count` values counted against the problem's device bytes
 template <typename T>
@@ -202,7 +242,7 @@ void launch_gemv_add(const double* Z, long long n, int k, const double* y, doubl
 void launch_scale(double* v, long long n, const double* num, const double* den, hipStream_t s);
 void launch_axpby(double a, const double* x, double b, const double* y, double* out, long long n,
                   hipStream_t s);
-void launch_build_z(const Problem& P, double* z, hipStream_t s);
+void launch_build_z(const Problem& P, double* z, hipStream_t s, const double* mu = nullptr);  // mu: P's when null
 void launch_build_zhat(const Problem& P, const double* f, double* zhat, hipStream_t s);
 void launch_fill(double* p, long long n, double v, hipStream_t s);
 // P v = A v + eta (q (x) I) v^(M) in the rows s < M (transpose: P^T u = A^T u + eta sum_s q_s u^(s) in

@@ -662,10 +662,10 @@ __global__ void build_zhat_k(const double* __restrict__ g1, const double* __rest
     }
 }
 
-void launch_build_z(const Problem& P, double* z, hipStream_t s) {
+void launch_build_z(const Problem& P, double* z, hipStream_t s, const double* mu) {
     const long long n = P.ntot;
     hipLaunchKernelGGL(build_z_k, dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, P.f64.gamma1, P.d_bw, P.d_rho,
-                       P.d_mu, P.Nd, P.M, z);
+                       mu ? mu : P.d_mu, P.Nd, P.M, z);
     TSFDE_HIP(hipGetLastError());
 }
 void launch_build_zhat(const Problem& P, const double* f, double* zhat, hipStream_t s) {

@@ -48,17 +48,10 @@ static bool verbose() {
 static double now() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+double now_seconds() { return now(); }
 
 // FP32 diagonal-block solves cannot reach residuals much below the FP32 rounding level
 constexpr double kInnerTolF32 = 1e-6;
-
-struct Opts {
-    int restart = 50, maxit = 0, precision = TSFDE_FP64, use_precond = 1, inner_maxit = 200, max_refine = 30;
-    int block_solver = TSFDE_BLOCK_CG, warm_start = TSFDE_WARM_LINEAR;
-    double tol = 1e-10, inner_tol = 1e-12, refine_tol = 1e-5;
-    long long max_device_bytes = 0;
-    int recompute_z = 0;
-};
 
 static Opts get_opts(const tsfde_opts* o) {
     Opts r;
@@ -350,19 +343,11 @@ static long long ptinv_launch(Problem& P, const double* g, double* lam, const Op
 // ---------------------------------------------------------------------------
 // FGMRES (FP64 Arnoldi), operators given as callbacks on FP64 vectors
 // ---------------------------------------------------------------------------
-struct SolveOps {
-    std::function<void(const double*, double*)> A;     // out = A v
-    std::function<long long(const double*, double*)> M; // out = M v (returns inner iterations)
-};
 
 // The Krylov basis V (m + 1 vectors) and the preconditioned directions Z (m vectors, or one when they
 // are recomputed at the end of each cycle instead of kept).  With a cap on the problem's device memory
 // (opts.max_device_bytes, 0 = none) Z is recomputed when keeping it would exceed the cap, and a basis
 // that does not fit even then is refused.  Returns whether Z is recomputed.
-struct CapError {
-    std::string msg;
-};
-
 static bool ensure_basis(Problem& P, int m, const Opts& o) {
     const size_t vec = sizeof(double) * (size_t)P.ntot;
     const size_t base = P.bytes - P.basis_bytes;  // the problem's other arrays
@@ -918,6 +903,70 @@ static tsfde_status recover_impl(Problem& P, double* f_out, double* work, const 
     return rc;
 }
 
+// Block FGMRES on p right-hand sides (FP64, or PREC_F32: the preconditioner in FP32); B and X hold p
+// vectors of n_tot, X the initial guesses.  rel_out (host, p) gets each column's relative residual.
+static tsfde_status solve_block(Problem& P, int p, const double* B, double* X, double* rel_out, const Opts& o,
+                                tsfde_stats& S, hipStream_t st) {
+    const long long n = P.ntot;
+    const int maxit = o.maxit > 0 ? o.maxit : (int)std::min<long long>(n, 1000);
+    const double t_start = now();
+    P.res_hist.clear();
+    struct History {
+        Problem& P;
+        tsfde_stats& S;
+        ~History() {
+            S.history_len = (int)P.res_hist.size();
+            S.history = P.res_hist.data();
+        }
+    } hist{P, S};
+    SolveOps ops;
+    ops.A = [&](const double* v, double* out) { apply_A_impl<double>(P, v, out, st); };
+    Opts o32 = o;
+    o32.inner_tol = std::max(o.inner_tol, kInnerTolF32);
+    Dev<float>& F = P.f32;
+    if (o.precision == TSFDE_PREC_F32 && !F.vecA) {
+        dev_alloc(P, F.vecA, n);
+        dev_alloc(P, F.vecB, n);
+    }
+    ops.M = [&](const double* v, double* out) -> long long {
+        if (!o.use_precond) { launch_copy<double>(v, out, n, st); return 0; }
+        if (o.precision == TSFDE_FP64) return pinv_impl<double>(P, v, out, o, st, true);
+        launch_d2f(v, F.vecA, n, st);
+        const long long it = pinv_impl<float>(P, F.vecA, F.vecB, o32, st, true);
+        launch_f2d(F.vecB, out, n, st);
+        return it;
+    };
+    std::vector<double> rel;
+    bool conv = false;
+    block_fgmres(P, ops, p, B, X, o.tol, o.restart, maxit, st, S, rel, conv, o);
+    double worst = 0.0;
+    for (int c = 0; c < p; ++c) worst = std::max(worst, rel[c]);
+    if (rel_out) std::copy(rel.begin(), rel.end(), rel_out);
+    S.refinements = 1;
+    S.converged = conv ? 1 : 0;
+    S.rel_res = worst;
+    TSFDE_HIP(hipStreamSynchronize(st));
+    S.t_total = now() - t_start;
+    return conv ? TSFDE_OK : TSFDE_ENOCONV;
+}
+
+static bool check_block(const Problem& P, int nrhs, const Opts& o, const char* name) {
+    if (nrhs < 1 || nrhs > kBlockMaxCols) {
+        set_error("%s: nrhs must be in [1, %d]", name, kBlockMaxCols);
+        return false;
+    }
+    if ((long long)o.restart * nrhs > kBlockMaxBasis) {
+        set_error("%s: restart * nrhs must be <= %d", name, kBlockMaxBasis);
+        return false;
+    }
+    if (o.precision == TSFDE_MIXED) {
+        set_error("%s: precision MIXED is not available for blocks (FP64 or PREC_F32)", name);
+        return false;
+    }
+    (void)P;
+    return true;
+}
+
 // The vector-Jacobian product of f~ (see tsfde_recover_f_vjp); synchronises st.
 static tsfde_status vjp_impl(Problem& P, const double* y, const double* gf, double* grad_mu, double* grad_alpha,
                              double* grad_gamma2, const Opts& o, tsfde_stats& S, hipStream_t st) {
@@ -1294,6 +1343,63 @@ tsfde_status tsfde_recover_f_vjp_batch(tsfde_problem* const* probs, int count, c
                                          grad_alpha ? grad_alpha + i : nullptr,
                                          grad_gamma2 ? grad_gamma2[i] : nullptr, o, S, st);
                      });
+}
+
+tsfde_status tsfde_gmres_solve_block(tsfde_problem* prob, int nrhs, const double* B, double* X, double* rel_res,
+                                     const tsfde_opts* opts, tsfde_stats* stats, void* stream) {
+    if (!prob || !B || !X) { set_error("gmres_solve_block: NULL argument"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    const Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    if (!check_block(P, nrhs, o, "gmres_solve_block")) return TSFDE_ENOTIMPL;
+    if (overlap(B, X, sizeof(double) * (size_t)P.ntot * nrhs)) { set_error("gmres_solve_block: B and X overlap"); return TSFDE_EINVAL; }
+    if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
+    tsfde_stats S{};
+    tsfde_status rc = TSFDE_OK;
+    TSFDE_GUARD("gmres_solve_block", rc = solve_block(P, nrhs, B, X, rel_res, o, S, (hipStream_t)stream);)
+    if (stats) *stats = S;
+    if (rc == TSFDE_ENOCONV) set_error("gmres_solve_block: tolerance not reached (largest rel. residual %.3e)", S.rel_res);
+    return rc;
+}
+
+tsfde_status tsfde_recover_f_block(tsfde_problem* prob, int nrhs, const double* mus, double* f_out, double* rel_res,
+                                   const tsfde_opts* opts, tsfde_stats* stats, void* stream) {
+    if (!prob || !mus || !f_out) { set_error("recover_f_block: NULL argument"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    const Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    if (!check_block(P, nrhs, o, "recover_f_block")) return TSFDE_ENOTIMPL;
+    if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
+    tsfde_stats S{};
+    tsfde_status rc = TSFDE_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const long long n = P.ntot, Nd = P.Nd;
+    TSFDE_GUARD("recover_f_block", {
+        // right-hand sides z(mu_c) and solutions, 2 nrhs vectors held by the problem
+        if (P.blk_io_cols < nrhs) {
+            if (P.blk_io) {
+                (void)hipFree(P.blk_io);
+                P.bytes -= sizeof(double) * 2 * (size_t)n * P.blk_io_cols;
+                P.blk_io = nullptr;
+                P.blk_io_cols = 0;
+            }
+            if (o.max_device_bytes > 0 && P.bytes + sizeof(double) * 2 * (size_t)n * nrhs > (size_t)o.max_device_bytes)
+                throw CapError{"max_device_bytes: no room for the right-hand sides and solutions of the block"};
+            dev_alloc(P, P.blk_io, 2 * (size_t)n * nrhs);
+            P.blk_io_cols = nrhs;
+        }
+        double* Bz = P.blk_io;
+        double* Xs = P.blk_io + (size_t)n * nrhs;
+        for (int c = 0; c < nrhs; ++c) launch_build_z(P, Bz + (size_t)c * n, st, mus + (size_t)c * Nd);
+        launch_fill(Xs, n * nrhs, 0.0, st);
+        rc = solve_block(P, nrhs, Bz, Xs, rel_res, o, S, st);
+        for (int c = 0; c < nrhs; ++c)
+            launch_copy<double>(Xs + (size_t)c * n + (size_t)P.M * Nd, f_out + (size_t)c * Nd, Nd, st);
+        TSFDE_HIP(hipStreamSynchronize(st));
+    })
+    if (stats) *stats = S;
+    if (rc == TSFDE_ENOCONV) set_error("recover_f_block: tolerance not reached (largest rel. residual %.3e)", S.rel_res);
+    return rc;
 }
 
 tsfde_status tsfde_forward_solve(tsfde_problem* prob, const double* f, double* v, const tsfde_opts* opts,

@@ -25,7 +25,8 @@ EXPORTED = [
     "tsfde_apply_P_inv_f32", "tsfde_apply_P_inv_noalloc", "tsfde_gmres_solve", "tsfde_recover_f", "tsfde_recover_f_batch",
     "tsfde_forward_solve", "tsfde_apply_AT", "tsfde_apply_PT_inv", "tsfde_adjoint_solve",
     "tsfde_recover_f_vjp", "tsfde_recover_f_vjp_batch", "tsfde_arnoldi", "tsfde_ritz_values",
-    "tsfde_singular_value_estimates", "tsfde_discrepancy", "tsfde_last_error",
+    "tsfde_singular_value_estimates", "tsfde_discrepancy", "tsfde_gmres_solve_block", "tsfde_recover_f_block",
+    "tsfde_last_error",
 ]
 
 
@@ -103,6 +104,8 @@ def lib():
     L.tsfde_apply_PT_inv.argtypes = [vp, vp, vp, C.POINTER(Opts), vp]
     L.tsfde_adjoint_solve.argtypes = [vp, vp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_recover_f_vjp.argtypes = [vp, vp, vp, vp, dp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
+    L.tsfde_gmres_solve_block.argtypes = [vp, i, vp, vp, dp, C.POINTER(Opts), C.POINTER(Stats), vp]
+    L.tsfde_recover_f_block.argtypes = [vp, i, vp, vp, dp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_last_error.argtypes = []
     L.tsfde_last_error.restype = C.c_char_p
     for name in EXPORTED:
@@ -284,6 +287,36 @@ class Problem:
                                    C.byref(opts) if opts is not None else None, C.byref(st), _stream(stream))
         _check(rc, allow=() if raise_noconv else (ENOCONV,))
         return f, st
+
+    def gmres_solve_block(self, B, X=None, opts: Optional[Opts] = None, stream=None, raise_noconv=False):
+        """Block FGMRES on the columns of B (nrhs x n_tot device tensor); returns (X, stats, rel_res)."""
+        import torch
+        k = B.shape[0] if B.dim() == 2 else 1
+        if X is None:
+            X = torch.zeros(k, self.n_tot, dtype=torch.float64, device="cuda")
+        rel = np.zeros(k)
+        st = Stats()
+        rc = lib().tsfde_gmres_solve_block(self._h, k, _dptr(B, torch.float64, k * self.n_tot, "B"),
+                                           _dptr(X, torch.float64, k * self.n_tot, "X"),
+                                           rel.ctypes.data_as(C.POINTER(C.c_double)),
+                                           C.byref(opts) if opts is not None else None, C.byref(st), _stream(stream))
+        _check(rc, allow=() if raise_noconv else (ENOCONV,))
+        return X, st, rel
+
+    def recover_f_block(self, mus, opts: Optional[Opts] = None, stream=None, raise_noconv=False):
+        """f~ for each data set mu_c (rows of mus, nrhs x N^d device tensor) in one block solve;
+        returns (F (nrhs x N^d), stats, rel_res)."""
+        import torch
+        k = mus.shape[0]
+        F = torch.empty(k, self.Nd, dtype=torch.float64, device="cuda")
+        rel = np.zeros(k)
+        st = Stats()
+        rc = lib().tsfde_recover_f_block(self._h, k, _dptr(mus, torch.float64, k * self.Nd, "mus"),
+                                         _dptr(F, torch.float64, k * self.Nd, "F"),
+                                         rel.ctypes.data_as(C.POINTER(C.c_double)),
+                                         C.byref(opts) if opts is not None else None, C.byref(st), _stream(stream))
+        _check(rc, allow=() if raise_noconv else (ENOCONV,))
+        return F, st, rel
 
     def apply_AT(self, lam, z=None, stream=None):
         import torch
