@@ -341,6 +341,40 @@ tsfde_status tsfde_recover_f_block(tsfde_problem* prob, int nrhs, const double* 
                                    void* stream);
 
 /*
+ * Autotuner: settings picked by timing them on this problem (on `stream`, with the problem's own
+ * data mu), kept for its later calls or written back to opts.
+ *   what = 1  kernels: the 2D matvec's FFT tiling (tsfde_tuning.mv_ids: 0 = 8 values per thread
+ *             with the length fixed at 512, 1 / 2 / 3 = 8 / 16 / 32 values per thread at any
+ *             length, 4 = 16 values per thread at 512), and the grid of the persistent P^{-1}
+ *             kernel (2D; 0 = the built-in choice); both kept by the problem
+ *   what = 2  solver: recover_f from x0 = 0 with opts' tol, precision and block_solver, once with a
+ *             restart of at least 100 to learn the iteration count k (restart then k + 2 + k/10,
+ *             else the faster of 50 and 200), then, for CG blocks, inner_tol in {0.3, 0.1, 0.03,
+ *             0.01} and each warm start; the fastest converged setting goes to opts->restart,
+ *             opts->inner_tol and opts->warm_start
+ *   what = 3  both, kernels first
+ * out (may be NULL) receives every timing.  About 2 + 9 solves for what = 3 with CG blocks.
+ */
+typedef struct tsfde_tuning {
+    int mv_variant;            /* chosen matvec tiling (-1: not a 2D FFT matvec)     */
+    int n_mv;                  /* tilings timed                                     */
+    int mv_ids[8];
+    double mv_ms[8];           /* milliseconds per apply_A                          */
+    int pinv_blocks;           /* chosen P^{-1} grid (0: built-in)                  */
+    int n_pinv;                /* grids timed                                       */
+    int pinv_cand[8];
+    double pinv_ms[8];         /* milliseconds per apply_P_inv                      */
+    int restart;               /* chosen solver settings                            */
+    double inner_tol;
+    int warm_start;
+    double solve_s;            /* seconds of the fastest timed solve (-1: none)     */
+    int solves;                /* solves timed                                      */
+} tsfde_tuning;
+
+tsfde_status tsfde_autotune(tsfde_problem* prob, tsfde_opts* opts, int what, tsfde_tuning* out,
+                            void* stream);
+
+/*
  * Direct problem of §6.1: v = A-hat^{-1} z-hat with z-hat^(s) = b_{s-1} D_1^(s) rho + eta q^(s) f,
  * i.e. the first M steps of the forward substitution (used to synthesise mu).
  *   f    device, N^d        v  device, M N^d (slices v^(1..M)); mu = v^(M)

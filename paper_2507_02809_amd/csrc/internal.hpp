@@ -125,6 +125,10 @@ struct Problem {
     double* blk_io = nullptr;
     size_t blk_bytes = 0;
     int blk_nvec = 0, blk_p = 0, blk_io_cols = 0;
+    // tuned settings (tsfde_autotune; built-in choices when 0 / -1): the persistent P^-1 grid (2D)
+    // and the 2D matvec's FFT tiling (mv_variant_* in toeplitz2d.hip)
+    int pinv_blocks = 0;
+    int mv_variant = -1;
 };
 
 // Solver options (tsfde_opts, validated)
@@ -179,6 +183,10 @@ bool toeplitz2d_supported(const Problem& P);
 template <typename T>
 bool launch_toeplitz2d_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s,
                               const T* ylast = nullptr, hipEvent_t before_inv = nullptr);
+// 2D matvec FFT tilings: 0 = 8 values per thread, length fixed at 512; 1 = 8, 2 = 16, 3 = 32 values per
+// thread, run-time length; 4 = 16 values per thread, length 512.  Lists the ones that apply to P
+// (at least 8 threads per transform, the workgroup's LDS within 160 KiB); returns their number.
+int mv_variants(const Problem& P, int* ids, int max_ids);
 template <typename T>
 void launch_toeplitz_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z, hipStream_t s,
                             const T* ylast = nullptr);

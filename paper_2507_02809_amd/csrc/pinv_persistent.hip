@@ -65,7 +65,8 @@ static long long run_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W,
     const int L = P.L;
     const int vpt = (L <= 2048) ? 8 : (L == 4096 ? 16 : 32);
     const int mode = (P.d == 1) ? SEG_1D : ((P.tau_ok || P.tau_pad) ? SEG_2D_TAU : SEG_2D_DIAG);
-    const int blocks = g_blocks_override;
+    int blocks = g_blocks_override;
+    if (blocks <= 0 && P.pinv_blocks > 0) blocks = P.pinv_blocks;  // tuned grid
     if (tblocks) {
         // tau-block form: no inner iterations, no warm start (the caller has checked the path)
         if (mode != SEG_2D_TAU) throw HipError{hipErrorNotSupported, "tau-block P^-1 outside the 2D tau path"};

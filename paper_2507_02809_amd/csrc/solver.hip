@@ -1402,6 +1402,150 @@ tsfde_status tsfde_recover_f_block(tsfde_problem* prob, int nrhs, const double* 
     return rc;
 }
 
+// Autotuner: picks, by timing them on this problem, the 2D matvec's FFT tiling and the persistent
+// P^-1 grid (kept by the problem), then the restart length and, for CG blocks, the inner tolerance
+// and the warm start of recover_f (written to opts).
+tsfde_status tsfde_autotune(tsfde_problem* prob, tsfde_opts* opts, int what, tsfde_tuning* out, void* stream) {
+    if (!prob || !opts) { set_error("autotune: NULL argument"); return TSFDE_EINVAL; }
+    if (what < 1 || what > 3) { set_error("autotune: what must be 1 (kernels), 2 (solver) or 3 (both)"); return TSFDE_EINVAL; }
+    Problem& P = *prob->p;
+    Opts o = get_opts(opts);
+    if (!check_opts(o)) return TSFDE_EINVAL;
+    if (!block_solver_supported(P, o)) return TSFDE_ENOTIMPL;
+    tsfde_tuning T{};
+    T.mv_variant = -1;
+    hipStream_t st = (hipStream_t)stream;
+    auto body = [&]() {
+        const long long n = P.ntot;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        TSFDE_HIP(hipEventCreate(&e0));
+        TSFDE_HIP(hipEventCreate(&e1));
+        struct Events {
+            hipEvent_t a, b;
+            ~Events() {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+            }
+        } ev{e0, e1};
+        // milliseconds per call of fn, after one untimed call
+        auto time_ms = [&](int reps, const std::function<void()>& fn) {
+            fn();
+            TSFDE_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < reps; ++r) fn();
+            TSFDE_HIP(hipEventRecord(e1, st));
+            TSFDE_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            TSFDE_HIP(hipEventElapsedTime(&ms, e0, e1));
+            return (double)ms / reps;
+        };
+        if (what & 1) {
+            // a seeded vector and the problem's own scratch (the recover_f buffers)
+            if (!P.xbuf) dev_alloc(P, P.xbuf, n);
+            if (!P.rwork) dev_alloc(P, P.rwork, n);
+            launch_hash_fill(P.xbuf, n, 0x5eedULL, st);
+            int ids[8];
+            const int nv = mv_variants(P, ids, 8);
+            double best = 1e300;
+            for (int i = 0; i < nv; ++i) {
+                P.mv_variant = ids[i];
+                const double ms = time_ms(5, [&] { apply_A_impl<double>(P, P.xbuf, P.rwork, st); });
+                T.mv_ids[T.n_mv] = ids[i];
+                T.mv_ms[T.n_mv++] = ms;
+                if (ms < best) { best = ms; T.mv_variant = ids[i]; }
+            }
+            P.mv_variant = T.mv_variant;
+            // the persistent P^-1 grid (2D; the block forms the persistent kernel runs)
+            const bool pers = persistent_supported(P) && P.d == 2 && env_int("TSFDE_PINV", 1) != 0 &&
+                              (o.block_solver == TSFDE_BLOCK_CG || (o.block_solver == TSFDE_BLOCK_TAU && tau_persistent(P)));
+            if (pers) {
+                int dev = 0, ncu = 0;
+                TSFDE_HIP(hipGetDevice(&dev));
+                TSFDE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+                const int cand[7] = {0, ncu / 16, ncu / 8 + 1, ncu / 8 * 3 / 2 + 1, ncu / 4 + 1, ncu / 8 * 3 + 1, ncu / 2};
+                double bestp = 1e300;
+                Opts op = o;
+                launch_build_z(P, P.z_rhs, st);
+                for (int c : cand) {
+                    if (c < 0 || T.n_pinv >= 8) continue;
+                    P.pinv_blocks = c;
+                    const double ms = time_ms(2, [&] { pinv_impl<double>(P, P.z_rhs, P.rwork, op, st, true); });
+                    T.pinv_cand[T.n_pinv] = c;
+                    T.pinv_ms[T.n_pinv++] = ms;
+                    if (ms < bestp) { bestp = ms; T.pinv_blocks = c; }
+                }
+                P.pinv_blocks = T.pinv_blocks;
+            }
+        }
+        T.restart = o.restart;
+        T.inner_tol = o.inner_tol;
+        T.warm_start = o.warm_start;
+        if (what & 2) {
+            if (!P.xbuf) dev_alloc(P, P.xbuf, n);
+            // seconds of a recover_f with these settings, infinite if it misses the tolerance
+            auto run = [&](const Opts& oo, int* iters) {
+                tsfde_stats S{};
+                launch_fill(P.xbuf, n, 0.0, st);
+                launch_build_z(P, P.z_rhs, st);
+                TSFDE_HIP(hipStreamSynchronize(st));
+                const double t0 = now();
+                const tsfde_status rc = solve(P, P.z_rhs, P.xbuf, oo, S, st);
+                const double dt = now() - t0;
+                ++T.solves;
+                if (iters) *iters = S.iters;
+                return rc == TSFDE_OK ? dt : 1e300;
+            };
+            // the iteration count with a long cycle, then the shortest restart that holds it
+            Opts c = o;
+            c.restart = std::max(o.restart, 100);
+            int k0 = 0;
+            double best = run(c, &k0);
+            int r_best = c.restart;
+            if (best < 1e300 && k0 < c.restart) {
+                r_best = std::min(kMaxRestart, std::max(8, k0 + 2 + k0 / 10));
+            } else {
+                for (int r : {50, 200}) {
+                    Opts cr = o;
+                    cr.restart = r;
+                    const double t = run(cr, nullptr);
+                    if (t < best) { best = t; r_best = r; }
+                }
+            }
+            c.restart = r_best;
+            if (o.block_solver == TSFDE_BLOCK_CG && o.use_precond) {
+                double it_best = o.inner_tol;
+                for (double it : {0.3, 0.1, 0.03, 0.01}) {
+                    Opts ci = c;
+                    ci.inner_tol = it;
+                    const double t = run(ci, nullptr);
+                    if (t < best) { best = t; it_best = it; }
+                }
+                c.inner_tol = it_best;
+                int ws_best = o.warm_start;
+                for (int ws : {TSFDE_WARM_PREVIOUS, TSFDE_WARM_LINEAR, TSFDE_WARM_QUADRATIC, TSFDE_WARM_HALF}) {
+                    if (ws == c.warm_start) continue;
+                    Opts cw = c;
+                    cw.warm_start = ws;
+                    const double t = run(cw, nullptr);
+                    if (t < best) { best = t; ws_best = ws; }
+                }
+                c.warm_start = ws_best;
+            }
+            T.restart = c.restart;
+            T.inner_tol = c.inner_tol;
+            T.warm_start = c.warm_start;
+            T.solve_s = best < 1e300 ? best : -1.0;
+            opts->restart = c.restart;
+            opts->inner_tol = c.inner_tol;
+            opts->warm_start = c.warm_start;
+        }
+        T.pinv_blocks = P.pinv_blocks;
+        T.mv_variant = P.mv_variant;
+    };
+    TSFDE_GUARD("autotune", body();)
+    if (out) *out = T;
+    return TSFDE_OK;
+}
+
 tsfde_status tsfde_forward_solve(tsfde_problem* prob, const double* f, double* v, const tsfde_opts* opts,
                                  void* stream) {
     if (!prob || !f || !v) { set_error("forward_solve: NULL argument"); return TSFDE_EINVAL; }

@@ -20,6 +20,8 @@
 //
 // The transform length is a template constant for L = 512 (the C3 size), a run-time value
 // otherwise.  Requires N <= L/2 (the embedding has L >= 2N).
+#include <cstdlib>
+
 #include "fft.hpp"
 #include "internal.hpp"
 
@@ -274,14 +276,37 @@ bool launch_toeplitz2d_matvec(const Problem& P, const Dev<T>& D, const T* y, T* 
     if (!toeplitz2d_supported(P)) return false;
     const int L = P.L;
     if (!ylast) ylast = y + (long long)(P.M - 1) * P.Nd;
-    if (L == 512) {
-        launch_mv<T, 8, 512>(P, D, y, z, ylast, st, before_inv);
-    } else if (L <= 2048) {
-        launch_mv<T, 8, 0>(P, D, y, z, ylast, st, before_inv);
-    } else {
-        launch_mv<T, 16, 0>(P, D, y, z, ylast, st, before_inv);
+    // TSFDE_MV_VARIANT (diagnostics) overrides the problem's tuned tiling
+    int v = P.mv_variant;
+    if (const char* e = std::getenv("TSFDE_MV_VARIANT")) v = std::atoi(e);
+    if (v < 0) v = L == 512 ? 0 : (L <= 2048 ? 1 : 2);  // built-in choice
+    switch (v) {
+        case 0: launch_mv<T, 8, 512>(P, D, y, z, ylast, st, before_inv); break;
+        case 1: launch_mv<T, 8, 0>(P, D, y, z, ylast, st, before_inv); break;
+        case 2: launch_mv<T, 16, 0>(P, D, y, z, ylast, st, before_inv); break;
+        case 3: launch_mv<T, 32, 0>(P, D, y, z, ylast, st, before_inv); break;
+        case 4: launch_mv<T, 16, 512>(P, D, y, z, ylast, st, before_inv); break;
+        default: throw HipError{hipErrorInvalidValue, "2D matvec: unknown FFT tiling"};
     }
     return true;
+}
+
+int mv_variants(const Problem& P, int* ids, int max_ids) {
+    if (!toeplitz2d_supported(P)) return 0;
+    const int L = P.L;
+    const int vpt[5] = {8, 8, 16, 32, 16};
+    const bool fixed[5] = {true, false, false, false, true};
+    int n = 0;
+    for (int v = 0; v < 5 && n < max_ids; ++v) {
+        if (fixed[v] && L != 512) continue;
+        const int nthr = L / vpt[v];
+        if (nthr < 8 || nthr > kMvBlock) continue;
+        const int gpb = kMvBlock / nthr;
+        const size_t lds = sizeof(cplx<double>) * ((size_t)L + (size_t)gpb * lds_len(L));
+        if (lds > 160 * 1024) continue;
+        ids[n++] = v;
+    }
+    return n;
 }
 
 template bool launch_toeplitz2d_matvec<double>(const Problem&, const Dev<double>&, const double*, double*,

@@ -26,8 +26,23 @@ EXPORTED = [
     "tsfde_forward_solve", "tsfde_apply_AT", "tsfde_apply_PT_inv", "tsfde_adjoint_solve",
     "tsfde_recover_f_vjp", "tsfde_recover_f_vjp_batch", "tsfde_arnoldi", "tsfde_ritz_values",
     "tsfde_singular_value_estimates", "tsfde_discrepancy", "tsfde_gmres_solve_block", "tsfde_recover_f_block",
-    "tsfde_last_error",
+    "tsfde_autotune", "tsfde_last_error",
 ]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("mv_variant", C.c_int), ("n_mv", C.c_int), ("mv_ids", C.c_int * 8), ("mv_ms", C.c_double * 8),
+                ("pinv_blocks", C.c_int), ("n_pinv", C.c_int), ("pinv_cand", C.c_int * 8),
+                ("pinv_ms", C.c_double * 8), ("restart", C.c_int), ("inner_tol", C.c_double),
+                ("warm_start", C.c_int), ("solve_s", C.c_double), ("solves", C.c_int)]
+
+    def as_dict(self) -> dict:
+        return {"mv_variant": self.mv_variant,
+                "mv_ms": {int(self.mv_ids[i]): float(self.mv_ms[i]) for i in range(self.n_mv)},
+                "pinv_blocks": self.pinv_blocks,
+                "pinv_ms": {int(self.pinv_cand[i]): float(self.pinv_ms[i]) for i in range(self.n_pinv)},
+                "restart": self.restart, "inner_tol": self.inner_tol, "warm_start": self.warm_start,
+                "solve_s": self.solve_s, "solves": self.solves}
 
 
 class Opts(C.Structure):
@@ -106,6 +121,7 @@ def lib():
     L.tsfde_recover_f_vjp.argtypes = [vp, vp, vp, vp, dp, vp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_gmres_solve_block.argtypes = [vp, i, vp, vp, dp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_recover_f_block.argtypes = [vp, i, vp, vp, dp, C.POINTER(Opts), C.POINTER(Stats), vp]
+    L.tsfde_autotune.argtypes = [vp, C.POINTER(Opts), i, C.POINTER(Tuning), vp]
     L.tsfde_last_error.argtypes = []
     L.tsfde_last_error.restype = C.c_char_p
     for name in EXPORTED:
@@ -287,6 +303,14 @@ class Problem:
                                    C.byref(opts) if opts is not None else None, C.byref(st), _stream(stream))
         _check(rc, allow=() if raise_noconv else (ENOCONV,))
         return f, st
+
+    def autotune(self, opts: Optional[Opts] = None, what: int = 3, stream=None):
+        """tsfde_autotune: returns (tuned opts, Tuning); the kernel choices stay with the problem."""
+        o = opts if opts is not None else default_opts()
+        o = Opts.from_buffer_copy(o)
+        t = Tuning()
+        _check(lib().tsfde_autotune(self._h, C.byref(o), what, C.byref(t), _stream(stream)))
+        return o, t
 
     def gmres_solve_block(self, B, X=None, opts: Optional[Opts] = None, stream=None, raise_noconv=False):
         """Block FGMRES on the columns of B (nrhs x n_tot device tensor); returns (X, stats, rel_res)."""
