@@ -109,6 +109,16 @@ typedef struct tsfde_opts {
     int recompute_z;     /* 1: recompute the z_j at the end of each cycle instead
                             of keeping them (halves the basis memory, adds m
                             P^{-1} applications per cycle)              (0)     */
+    int graph;           /* 1: run each FGMRES restart cycle (FP64 or PREC_F32,
+                            persistent P^{-1} or none) as one HIP graph: the m
+                            Arnoldi steps with no host round trip, captured on
+                            first use, kept by the problem and replayed for later
+                            cycles and solves with the same settings; the host
+                            then applies the Givens rotations and takes the
+                            first k <= m steps that meet tol.  Steps after
+                            convergence in the last cycle are wasted work, so
+                            restart should be near the iteration count
+                            (tsfde_autotune).  Other settings: ignored  (0) */
 } tsfde_opts;
 
 typedef enum { TSFDE_BLOCK_CG = 0, TSFDE_BLOCK_TAU = 1, TSFDE_BLOCK_STRANG = 2 } tsfde_block_solver;

@@ -129,6 +129,18 @@ struct Problem {
     // and the 2D matvec's FFT tiling (mv_variant_* in toeplitz2d.hip)
     int pinv_blocks = 0;
     int mv_variant = -1;
+    // FGMRES restart cycles as HIP graphs (opts.graph): while capturing, the persistent P^-1 records
+    // the CU slots its grid needs (graph_slots) instead of holding them, and leaves its counters to
+    // the solver; the instantiated cycle, what it was captured for, its capture stream, the
+    // per-step coefficients (device) and their pinned mirror
+    bool capturing = false;
+    int graph_slots = 0;
+    hipGraphExec_t cyc_exec = nullptr;
+    hipStream_t cyc_stream = nullptr;
+    unsigned long long cyc_key[10] = {};
+    double* cyc_h = nullptr;
+    double* cyc_h_host = nullptr;
+    int cyc_len = 0;
 };
 
 // Solver options (tsfde_opts, validated)
@@ -138,6 +150,7 @@ struct Opts {
     double tol = 1e-10, inner_tol = 1e-12, refine_tol = 1e-5;
     long long max_device_bytes = 0;
     int recompute_z = 0;
+    int graph = 0;
 };
 
 // The two operators of a right-preconditioned Krylov solve (FP64 vectors of n_tot)
@@ -280,6 +293,13 @@ size_t pinv_noalloc_bytes(const Problem& P);
 long long pinv_persistent_run_noalloc(Problem& P, const double* z, double* y, double inner_tol, int inner_maxit,
                                       int extrap, int tblocks, hipStream_t st);
 void set_persistent_blocks(int g);
+// counters of the persistent P^-1 when it runs inside a captured graph: zero the iteration count and
+// the abort word before a replay; after it, read both (synchronises st; throws if a barrier wait
+// timed out) and return the iterations
+void pinv_graph_prepare(Problem& P, bool f32, hipStream_t st);
+long long pinv_graph_finish(Problem& P, bool f32, hipStream_t st);
+// v *= 1 / sqrt(*sq), or v = 0 when *sq is not a positive finite number
+void launch_scale_rsqrt(double* v, long long n, const double* sq, hipStream_t s);
 // Batch mode of the calling thread: its persistent kernels are ordinary launches sized so that
 // kMaxInflight of them fit the device together (tsfde_recover_f_batch)
 constexpr int kMaxInflight = 8;

@@ -593,6 +593,17 @@ void launch_scale(double* v, long long n, const double* num, const double* den, 
     TSFDE_HIP(hipGetLastError());
 }
 
+__global__ void scale_rsqrt_k(double* __restrict__ v, long long n, const double* __restrict__ sq) {
+    const double q = *sq;
+    const double inv = (q > 0.0 && q <= 1.79e308) ? 1.0 / sqrt(q) : 0.0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        v[i] *= inv;
+}
+void launch_scale_rsqrt(double* v, long long n, const double* sq, hipStream_t s) {
+    hipLaunchKernelGGL(scale_rsqrt_k, dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, v, n, sq);
+    TSFDE_HIP(hipGetLastError());
+}
+
 __global__ void axpby_k(double a, const double* __restrict__ x, double b, const double* __restrict__ y,
                         double* __restrict__ out, long long n) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)

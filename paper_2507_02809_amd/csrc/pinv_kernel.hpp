@@ -1329,8 +1329,14 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
     if (shared_launch()) cap = std::min(cap, std::max(1, ncu / kMaxInflight));
     grid = std::max(1, std::min(grid, cap));
     a.bar_ticks = barrier_ticks(dev);
-    W.ticket.hold(&pool, residency_slots(grid, kXcds));
-    launch_fill(reinterpret_cast<float*>(W.iters), 2, 0.0f, st);  // zero the iteration counter
+    if (P.capturing) {
+        // inside a captured graph: the solver holds the slots around each replay and zeroes the
+        // counter before it (the count then adds up over the cycle)
+        P.graph_slots = std::max(P.graph_slots, residency_slots(grid, kXcds));
+    } else {
+        W.ticket.hold(&pool, residency_slots(grid, kXcds));
+        launch_fill(reinterpret_cast<float*>(W.iters), 2, 0.0f, st);  // zero the iteration counter
+    }
     const int s_last = last_block ? P.M : P.M - 1;
     for (int sa = 0; sa <= s_last; sa += kHB) {
         int sa_ = sa;

@@ -3,6 +3,7 @@
 #include <atomic>
 #include <cstdlib>
 #include <mutex>
+#include <type_traits>
 
 #include "pinv_kernel.hpp"
 
@@ -61,7 +62,7 @@ static long long run_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W,
         ResidencyTicket& t;
         ~Release() { t.release(); }
     } release{W.ticket};
-    launch_fill(reinterpret_cast<float*>(W.bar) + 1, 1, 0.0f, st);  // clear the abort word
+    if (!P.capturing) launch_fill(reinterpret_cast<float*>(W.bar) + 1, 1, 0.0f, st);  // clear the abort word
     const int L = P.L;
     const int vpt = (L <= 2048) ? 8 : (L == 4096 ? 16 : 32);
     const int mode = (P.d == 1) ? SEG_1D : ((P.tau_ok || P.tau_pad) ? SEG_2D_TAU : SEG_2D_DIAG);
@@ -94,6 +95,7 @@ static long long run_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W,
 #undef TSFDE_SEG_MODES
 #undef TSFDE_SEG
     }
+    if (P.capturing) return 0;  // counters read by the solver after the replay
     // iteration count and abort word into the problem's pinned scratch
     long long* it_h = reinterpret_cast<long long*>(P.host_scalars + 56);
     unsigned* abort_h = reinterpret_cast<unsigned*>(P.host_scalars + 57);
@@ -113,6 +115,42 @@ long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T*
     PersistentWork<T>& W = *static_cast<PersistentWork<T>*>(wptr);
     ensure_work(P, W);
     return run_segments(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, tblocks, st);
+}
+
+template <typename T>
+static PersistentWork<T>& graph_work(Problem& P) {
+    void*& wp = std::is_same<T, float>::value ? P.pw32 : P.pw64;
+    if (!wp) throw HipError{hipErrorNotReady, "graph replay: the persistent P^-1 has not run on this problem"};
+    return *static_cast<PersistentWork<T>*>(wp);
+}
+
+template <typename T>
+static void graph_prepare(Problem& P, hipStream_t st) {
+    PersistentWork<T>& W = graph_work<T>(P);
+    launch_fill(reinterpret_cast<float*>(W.iters), 2, 0.0f, st);
+    launch_fill(reinterpret_cast<float*>(W.bar) + 1, 1, 0.0f, st);
+}
+
+template <typename T>
+static long long graph_finish(Problem& P, hipStream_t st) {
+    PersistentWork<T>& W = graph_work<T>(P);
+    long long* it_h = reinterpret_cast<long long*>(P.host_scalars + 56);
+    unsigned* abort_h = reinterpret_cast<unsigned*>(P.host_scalars + 57);
+    TSFDE_HIP(hipMemcpyAsync(it_h, W.iters, sizeof(long long), hipMemcpyDeviceToHost, st));
+    TSFDE_HIP(hipMemcpyAsync(abort_h, W.bar + 1, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    TSFDE_HIP(hipStreamSynchronize(st));
+    if (*abort_h != 0u)
+        throw HipError{hipErrorLaunchTimeOut, "graph replay: a device-wide barrier wait of P^-1 timed out"};
+    return *it_h;
+}
+
+void pinv_graph_prepare(Problem& P, bool f32, hipStream_t st) {
+    if (f32) graph_prepare<float>(P, st);
+    else graph_prepare<double>(P, st);
+}
+
+long long pinv_graph_finish(Problem& P, bool f32, hipStream_t st) {
+    return f32 ? graph_finish<float>(P, st) : graph_finish<double>(P, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -364,6 +364,10 @@ void free_problem(Problem* P) {
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (P->host_scalars) (void)hipHostFree(P->host_scalars);
+    if (P->cyc_exec) (void)hipGraphExecDestroy(P->cyc_exec);
+    if (P->cyc_stream) (void)hipStreamDestroy(P->cyc_stream);
+    if (P->cyc_h) (void)hipFree(P->cyc_h);
+    if (P->cyc_h_host) (void)hipHostFree(P->cyc_h_host);
     if (P->mv_fork) (void)hipEventDestroy(P->mv_fork);
     if (P->mv_join) (void)hipEventDestroy(P->mv_join);
     if (P->mv_aux) (void)hipStreamDestroy(P->mv_aux);

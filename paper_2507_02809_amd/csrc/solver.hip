@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <functional>
 #include <mutex>
 #include <string>
@@ -23,8 +24,10 @@
 #include <thread>
 #include <vector>
 
+#include "grid_sync.hpp"
 #include "hessenberg.hpp"
 #include "internal.hpp"
+#include "residency.hpp"
 
 namespace tsfde {
 
@@ -69,6 +72,7 @@ static Opts get_opts(const tsfde_opts* o) {
     r.warm_start = o->warm_start;
     r.max_device_bytes = o->max_device_bytes;
     r.recompute_z = o->recompute_z;
+    r.graph = o->graph;
     return r;
 }
 
@@ -91,8 +95,8 @@ static bool check_opts(const Opts& o) {
         set_error("opts.block_solver invalid");
         return false;
     }
-    if (o.max_device_bytes < 0 || o.recompute_z < 0 || o.recompute_z > 1) {
-        set_error("opts.max_device_bytes must be >= 0 and opts.recompute_z 0 or 1");
+    if (o.max_device_bytes < 0 || o.recompute_z < 0 || o.recompute_z > 1 || o.graph < 0 || o.graph > 1) {
+        set_error("opts.max_device_bytes must be >= 0, opts.recompute_z and opts.graph 0 or 1");
         return false;
     }
     return true;
@@ -553,6 +557,210 @@ static int fgmres(Problem& P, const SolveOps& ops, const double* b, double* x, d
     return its;
 }
 
+// Restart cycles as HIP graphs: the path applies when P^{-1} is the persistent forward substitution
+// (or absent) and the directions z_j are kept.
+static bool graph_supported(Problem& P, const Opts& o) {
+    if (o.recompute_z) return false;
+    if (!o.use_precond) return true;
+    if (env_int("TSFDE_PINV", 1) == 0 || !persistent_supported(P)) return false;
+    return o.block_solver == TSFDE_BLOCK_CG || (o.block_solver == TSFDE_BLOCK_TAU && tau_persistent(P));
+}
+
+// FGMRES(m) whose restart cycles run as one HIP graph each.  Per cycle, on the host: r = b - A x and
+// its norm (the true residual, the convergence test); then the graph, captured once per problem and
+// settings and replayed for every later cycle and solve: v_0 = r / ||r||, and m Arnoldi steps
+// z_j = M v_j, w = A z_j, classical Gram-Schmidt twice (coefficients and ||w||^2 into the device
+// array cyc_h, column j), v_{j+1} = w / ||w|| by the device-side norm, the coefficients copied to
+// pinned host memory at the end.  The host applies the Givens rotations, takes the first k <= m
+// steps whose least-squares residual meets rtol and adds Z y to x.  A breakdown (||w|| = 0) zeroes
+// the later directions, which the host never uses.
+static int fgmres_graph(Problem& P, const std::function<SolveOps(hipStream_t)>& make_ops, const double* b, double* x,
+                        double* r_work, double rtol, int m, int maxit, hipStream_t st, tsfde_stats& S, bool& conv,
+                        double& relres, const Opts& o) {
+    const long long n = P.ntot;
+    ensure_basis(P, m, o);
+    const int nblk = kArnBlocks;
+    if (!P.arn_part) dev_alloc(P, P.arn_part, kArnBlocks * kArnMaxK);
+    if (!P.arn_h) dev_alloc(P, P.arn_h, (2 * (kMaxRestart + 2) + 1));
+    const int hs = m + 2, stride = 2 * hs + 1;
+    const int len = m * stride + 1;  // the last slot: ||r||^2 of the cycle's start
+    if (P.cyc_len < len) {
+        if (P.cyc_h) (void)hipFree(P.cyc_h);
+        if (P.cyc_h_host) (void)hipHostFree(P.cyc_h_host);
+        P.cyc_h = nullptr;
+        P.cyc_h_host = nullptr;
+        P.cyc_len = 0;
+        TSFDE_HIP(hipMalloc(&P.cyc_h, sizeof(double) * len));
+        TSFDE_HIP(hipHostMalloc(&P.cyc_h_host, sizeof(double) * len, hipHostMallocDefault));
+        P.cyc_len = len;
+        if (P.cyc_exec) (void)hipGraphExecDestroy(P.cyc_exec);
+        P.cyc_exec = nullptr;
+    }
+    if (!P.cyc_stream) TSFDE_HIP(hipStreamCreateWithFlags(&P.cyc_stream, hipStreamNonBlocking));
+    double* beta2 = P.cyc_h + (size_t)m * stride;
+    const bool f32 = o.precision == TSFDE_PREC_F32;
+    const SolveOps ops = make_ops(st);
+    // what the captured cycle depends on
+    unsigned long long key[10];
+    {
+        double it = o.inner_tol;
+        unsigned long long itb = 0;
+        std::memcpy(&itb, &it, sizeof(itb));
+        key[0] = (unsigned long long)m;
+        key[1] = (unsigned long long)(uintptr_t)P.V;
+        key[2] = (unsigned long long)(uintptr_t)P.Z;
+        key[3] = (unsigned long long)(uintptr_t)r_work;
+        key[4] = (unsigned long long)(uintptr_t)P.cyc_h;
+        key[5] = itb;
+        key[6] = ((unsigned long long)o.block_solver << 32) | (unsigned)o.inner_maxit;
+        key[7] = ((unsigned long long)o.warm_start << 32) | (unsigned)o.precision;
+        key[8] = ((unsigned long long)o.use_precond << 32) | (unsigned)(P.mv_variant + 1);
+        key[9] = ((unsigned long long)(unsigned)P.pinv_blocks << 32) | (unsigned)(shared_launch() ? 1 : 0);
+    }
+    const double bnorm = std::sqrt(dev_dot(P, b, b, n, st));
+    conv = false;
+    relres = 1.0;
+    if (!(bnorm > 0.0)) {
+        launch_fill(x, n, 0.0, st);
+        conv = true;
+        relres = 0.0;
+        return 0;
+    }
+    std::vector<double> Hc((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), yk(m);
+    int its = 0;
+    bool warmed = P.cyc_exec != nullptr;
+    while (true) {
+        double t0 = now();
+        ops.A(x, r_work);
+        launch_axpby(1.0, b, -1.0, r_work, r_work, n, st);
+        int np = 0;
+        launch_dot_partials<double>(r_work, r_work, n, P.f64.partial, &np, st);
+        launch_sum_partials(P.f64.partial, np, beta2, st);
+        TSFDE_HIP(hipMemcpyAsync(P.host_scalars + 16, beta2, sizeof(double), hipMemcpyDeviceToHost, st));
+        TSFDE_HIP(hipStreamSynchronize(st));
+        S.t_matvec += now() - t0;
+        const double beta = std::sqrt(std::max(0.0, P.host_scalars[16]));
+        relres = beta / bnorm;
+        P.res_hist.push_back(relres);
+        if (relres <= rtol) { conv = true; break; }
+        if (its >= maxit) break;
+        if (!P.cyc_exec || std::memcmp(key, P.cyc_key, sizeof(key)) != 0) {
+            if (!warmed) {
+                // one preconditioner application outside the capture: work buffers and tables are
+                // allocated on first use
+                ops.M(r_work, P.Z);
+                TSFDE_HIP(hipStreamSynchronize(st));
+                warmed = true;
+            }
+            if (P.cyc_exec) (void)hipGraphExecDestroy(P.cyc_exec);
+            P.cyc_exec = nullptr;
+            const SolveOps gops = make_ops(P.cyc_stream);
+            hipStream_t cs_ = P.cyc_stream;
+            P.graph_slots = 0;
+            P.capturing = true;
+            struct Uncapture {  // capture mode ends however the capture ends
+                Problem& P;
+                hipStream_t s;
+                bool open = true;
+                ~Uncapture() {
+                    P.capturing = false;
+                    if (open) {
+                        hipGraph_t gr = nullptr;
+                        (void)hipStreamEndCapture(s, &gr);
+                        if (gr) (void)hipGraphDestroy(gr);
+                    }
+                }
+            } unc{P, cs_};
+            TSFDE_HIP(hipStreamBeginCapture(cs_, hipStreamCaptureModeThreadLocal));
+            launch_copy<double>(r_work, P.V, n, cs_);
+            launch_scale_rsqrt(P.V, n, beta2, cs_);
+            for (int j = 0; j < m; ++j) {
+                double* vj = P.V + (size_t)j * n;
+                double* zj = P.Z + (size_t)j * n;
+                double* w = P.V + (size_t)(j + 1) * n;
+                double* hj = P.cyc_h + (size_t)j * stride;
+                gops.M(vj, zj);
+                gops.A(zj, w);
+                cgs2(P.V, n, j + 1, w, P.arn_part, nblk, hj, hj + hs, hj + 2 * hs, cs_);
+                launch_scale_rsqrt(w, n, hj + 2 * hs, cs_);
+            }
+            TSFDE_HIP(hipMemcpyAsync(P.cyc_h_host, P.cyc_h, sizeof(double) * len, hipMemcpyDeviceToHost, cs_));
+            hipGraph_t graph = nullptr;
+            unc.open = false;
+            TSFDE_HIP(hipStreamEndCapture(cs_, &graph));
+            hipGraphExec_t exec = nullptr;
+            const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            TSFDE_HIP(ie);
+            P.cyc_exec = exec;
+            std::memcpy(P.cyc_key, key, sizeof(key));
+        }
+        // replay, the persistent grids' CU slots held around it
+        t0 = now();
+        long long inner = 0;
+        {
+            int dev = 0, ncu = 0;
+            TSFDE_HIP(hipGetDevice(&dev));
+            TSFDE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+            ResidencyTicket ticket;
+            struct Release {
+                ResidencyTicket& t;
+                ~Release() { t.release(); }
+            } rel{ticket};
+            const bool pers = o.use_precond && P.graph_slots > 0;
+            if (pers) {
+                pinv_graph_prepare(P, f32, st);
+                ticket.hold(&residency_budget(dev, ncu), P.graph_slots);
+            }
+            TSFDE_HIP(hipGraphLaunch(P.cyc_exec, st));
+            TSFDE_HIP(hipStreamSynchronize(st));
+            if (pers) inner = pinv_graph_finish(P, f32, st);
+        }
+        S.t_precond += now() - t0;  // the whole cycle (P^{-1} dominates it)
+        S.inner_iters += inner;
+        // Givens on the host over the cycle's coefficients, up to the first step that meets rtol
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        const double* hh = P.cyc_h_host;
+        int k = 0;
+        for (int j = 0; j < m && its < maxit; ++j) {
+            const double* hj = hh + (size_t)j * stride;
+            const double nrm2 = hj[2 * hs];
+            const double hn = (nrm2 > 0.0 && std::isfinite(nrm2)) ? std::sqrt(nrm2) : 0.0;
+            for (int i = 0; i <= j; ++i) Hc[(size_t)i * m + j] = hj[i] + hj[hs + i];
+            Hc[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                const double a = Hc[(size_t)i * m + j], bq = Hc[(size_t)(i + 1) * m + j];
+                Hc[(size_t)i * m + j] = cs[i] * a + sn[i] * bq;
+                Hc[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bq;
+            }
+            const double a = Hc[(size_t)j * m + j], bq = Hc[(size_t)(j + 1) * m + j];
+            const double rr = std::hypot(a, bq);
+            cs[j] = rr > 0.0 ? a / rr : 1.0;
+            sn[j] = rr > 0.0 ? bq / rr : 0.0;
+            Hc[(size_t)j * m + j] = rr;
+            Hc[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            ++its;
+            ++S.iters;
+            P.res_hist.push_back(std::fabs(g[j + 1]) / bnorm);
+            if (std::fabs(g[j + 1]) <= rtol * bnorm || hn == 0.0) break;
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int l = i + 1; l < k; ++l) acc -= Hc[(size_t)i * m + l] * yk[l];
+            yk[i] = Hc[(size_t)i * m + i] != 0.0 ? acc / Hc[(size_t)i * m + i] : 0.0;
+        }
+        TSFDE_HIP(hipMemcpyAsync(P.arn_h, yk.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+        launch_gemv_add(P.Z, n, k, P.arn_h, x, st);
+        TSFDE_HIP(hipStreamSynchronize(st));
+        ++S.restarts;
+    }
+    return its;
+}
+
 // k steps of Arnoldi (classical Gram-Schmidt twice) on the right-preconditioned operator A M from b;
 // H receives the (k+1) x k Hessenberg matrix row-major (host).  Returns the steps taken (fewer than k
 // on an exact breakdown).  The eigenvalues of its leading square part are Ritz values of A M, i.e.
@@ -603,8 +811,6 @@ static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o,
         }
     } hist{P, S};
     if (o.precision == TSFDE_FP64 || o.precision == TSFDE_PREC_F32) {
-        SolveOps ops;
-        ops.A = [&](const double* v, double* out) { apply_A_impl<double>(P, v, out, st); };
         Opts o32 = o;
         o32.inner_tol = std::max(o.inner_tol, kInnerTolF32);
         Dev<float>& F = P.f32;
@@ -612,19 +818,28 @@ static tsfde_status solve(Problem& P, const double* b, double* x, const Opts& o,
             dev_alloc(P, F.vecA, n);
             dev_alloc(P, F.vecB, n);
         }
-        ops.M = [&](const double* v, double* out) -> long long {
-            if (!o.use_precond) { launch_copy<double>(v, out, n, st); return 0; }
-            if (o.precision == TSFDE_FP64) return pinv_impl<double>(P, v, out, o, st, true);
-            // FP32 preconditioner inside the FP64 flexible Krylov solve
-            launch_d2f(v, F.vecA, n, st);
-            const long long it = pinv_impl<float>(P, F.vecA, F.vecB, o32, st, true);
-            launch_f2d(F.vecB, out, n, st);
-            return it;
+        // the two operators on stream s (the graph path captures them on a stream of its own)
+        auto make_ops = [&P, &o, &o32, &F, n](hipStream_t s) {
+            SolveOps ops;
+            ops.A = [&P, s](const double* v, double* out) { apply_A_impl<double>(P, v, out, s); };
+            ops.M = [&P, &o, &o32, &F, n, s](const double* v, double* out) -> long long {
+                if (!o.use_precond) { launch_copy<double>(v, out, n, s); return 0; }
+                if (o.precision == TSFDE_FP64) return pinv_impl<double>(P, v, out, o, s, true);
+                // FP32 preconditioner inside the FP64 flexible Krylov solve
+                launch_d2f(v, F.vecA, n, s);
+                const long long it = pinv_impl<float>(P, F.vecA, F.vecB, o32, s, true);
+                launch_f2d(F.vecB, out, n, s);
+                return it;
+            };
+            return ops;
         };
         if (!P.rwork) dev_alloc(P, P.rwork, n);
         bool conv = false;
         double rel = 1.0;
-        fgmres(P, ops, b, x, P.rwork, o.tol, o.restart, maxit, st, S, conv, rel, true, o);
+        if (o.graph && graph_supported(P, o))
+            fgmres_graph(P, make_ops, b, x, P.rwork, o.tol, o.restart, maxit, st, S, conv, rel, o);
+        else
+            fgmres(P, make_ops(st), b, x, P.rwork, o.tol, o.restart, maxit, st, S, conv, rel, true, o);
         S.refinements = 1;
         S.converged = conv ? 1 : 0;
         S.rel_res = rel;
@@ -1105,6 +1320,7 @@ void tsfde_default_opts(tsfde_opts* o) {
     o->max_refine = 30;
     o->max_device_bytes = 0;
     o->recompute_z = 0;
+    o->graph = 0;
 }
 
 tsfde_status tsfde_create_problem_ex(int d, int N, int M, double T, double beta, double omega, double alpha,

@@ -49,7 +49,8 @@ class Opts(C.Structure):
     _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("tol", C.c_double), ("precision", C.c_int),
                 ("use_precond", C.c_int), ("inner_tol", C.c_double), ("inner_maxit", C.c_int),
                 ("refine_tol", C.c_double), ("max_refine", C.c_int), ("block_solver", C.c_int),
-                ("warm_start", C.c_int), ("max_device_bytes", C.c_longlong), ("recompute_z", C.c_int)]
+                ("warm_start", C.c_int), ("max_device_bytes", C.c_longlong), ("recompute_z", C.c_int),
+                ("graph", C.c_int)]
 
 
 class Stats(C.Structure):
