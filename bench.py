@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--no-c4", action="store_true", help="skip the mixed batch of 64 independent problems")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient (adjoint) measurement")
     ap.add_argument("--no-c2", action="store_true", help="skip the d = 1, N = 4095, M = 1024 lines")
+    ap.add_argument("--no-block", action="store_true", help="skip the block solve of 8 data sets")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner and graph-cycle lines")
     ap.add_argument("--matvec-only", action="store_true",
                     help="only the apply_A timing (FP64, FP32), preceded by one FP64->FP32 conversion of a vector "
                          "(known bytes: a reference for hardware traffic counters); for profiling")
@@ -350,6 +352,53 @@ def main():
         strang_form = {"solves_per_s": 1.0 / dts, "ms_per_solve": 1e3 * dts, "f_rel_err": errs_s[0], "tol": tols,
                        "outer_iters": sts[-1]["iters"]}
 
+    # several data sets of the same instance in one block solve (tsfde_recover_f_block): mu_eps and
+    # 7 more noise draws of the same relative level, 8 columns per block Krylov step, block
+    # Gram-Schmidt on the FP64 matrix cores; column 0's f against the oracle's
+    multi_rhs = None
+    if not a.no_block:
+        kb = 8
+        rng = np.random.default_rng(2507)
+        mus = [mu_eps] + [mu_eps + 1e-3 * np.linalg.norm(mu_eps) * rng.standard_normal(inp.Nd) / np.sqrt(inp.Nd)
+                          for _ in range(kb - 1)]
+        mus_t = torch.tensor(np.stack(mus), device=dev)
+        multi_rhs = {"columns": kb, "data": "mu_eps and 7 further noise draws of relative level 1e-3"}
+        for name, bs in (("cg_blocks", tsfde.BLOCK_CG), ("tau_blocks", tsfde.BLOCK_TAU)):
+            tolb = tol64 if bs == tsfde.BLOCK_CG else (tau_forms["fp64"]["tol"] if tau_forms else tol64)
+            ob = tsfde.default_opts(tol=tolb, inner_tol=a.inner_tol, maxit=300, restart=50, warm_start=WARM,
+                                    block_solver=bs)
+            prob.recover_f_block(mus_t, ob)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Fb, sb, relb = prob.recover_f_block(mus_t, ob)
+            torch.cuda.synchronize()
+            dtk = time.perf_counter() - t0
+            e0 = float(np.linalg.norm(Fb[0].cpu().numpy() - f_ref) / nref)
+            log(f"block of {kb} data sets ({name}): {dtk:.2f} s ({kb / dtk:.2f} solves/s), {sb.iters} block steps, "
+                f"column 0 f error {e0:.2e}")
+            multi_rhs[name] = {"solves_per_s": kb / dtk, "s_per_block": dtk, "block_steps": sb.iters, "tol": tolb,
+                               "max_rel_res": float(relb.max()), "f_rel_err_column0": e0,
+                               "t_precond": sb.t_precond, "t_matvec": sb.t_matvec, "t_ortho": sb.t_ortho}
+
+    # the autotuner on this problem (kernel tilings, P^-1 grid, restart, inner tolerance, warm start),
+    # then the tuned settings and the graph-captured restart cycles at the same tolerance
+    tuned = None
+    if not a.no_tune:
+        t0 = time.perf_counter()
+        ot, tt = prob.autotune(o64, what=3)
+        t_tune = time.perf_counter() - t0
+        run(ot, 1)
+        dtt, errt, stt = run(ot, a.steps)
+        og = tsfde.Opts.from_buffer_copy(ot)
+        og.graph = 1
+        run(og, 1)
+        dtg, errg, stg = run(og, a.steps)
+        log(f"autotune: {t_tune:.1f} s; tuned {a.steps / dtt:.2f} solves/s, graph cycles {a.steps / dtg:.2f} solves/s")
+        tuned = {"tuning_s": t_tune, "choices": tt.as_dict(),
+                 "tuned": {"solves_per_s": a.steps / dtt, "f_rel_err": max(errt), "outer_iters": stt[-1]["iters"]},
+                 "graph_cycles": {"solves_per_s": a.steps / dtg, "f_rel_err": max(errg),
+                                  "outer_iters": stg[-1]["iters"], "restart": og.restart}}
+
     # throughput with several instances in flight: the same workload with other source modes and
     # noise, all solved by one tsfde_recover_f_batch call at the tolerance calibrated above
     batched = None
@@ -534,6 +583,10 @@ def main():
         "tau_blocks_preconditioner": tau_forms,
         # the paper's S_{n,S} (B replaced by Strang's circulant; same frozen-coefficient reading)
         "strang_blocks_preconditioner": strang_form,
+        # several data sets of the instance in one block Krylov solve (tsfde_recover_f_block)
+        "multi_rhs": multi_rhs,
+        # tsfde_autotune's choices, the tuned solve and the graph-captured restart cycles
+        "autotune": tuned,
         # independent instances of the workload solved side by side (tsfde_recover_f_batch)
         "batched": batched,
         # 64 independent problems of uneven shapes: even k d = 1, N ~ U[127, 2047]; odd k d = 2,

@@ -108,14 +108,24 @@ __global__ __launch_bounds__(256) void bgram_k(const double* __restrict__ V, lon
     }
 }
 
-// G[a][c] = sum over the y partial sums, in a fixed order (a < nv, c < p; G row-major nv x p)
-__global__ void bgram_finish_k(const double* __restrict__ partials, int ny, int nv, int p, double* __restrict__ G) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nv * p) return;
+// G[a][c] = sum over the y partial sums (a < nv, c < p; G row-major nv x p).  One wave per entry:
+// lane l adds the partial sums y = l, l + 64, ... (their loads independent), then the 64 lane sums
+// are added by a fixed shuffle tree, so the order is the same on every run.
+__global__ __launch_bounds__(256) void bgram_finish_k(const double* __restrict__ partials, int ny, int nv, int p,
+                                                      double* __restrict__ G) {
+    const int l = threadIdx.x & 63;
+    const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (idx >= nv * p) return;  // whole waves leave together
     const int a = idx / p, c = idx % p;
-    double s = 0.0;
-    for (int y = 0; y < ny; ++y) s += partials[((long long)y * nv + a) * 16 + c];
-    G[idx] = s;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int y = l;
+    for (; y + 192 < ny; y += 256)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += partials[((long long)(y + 64 * u) * nv + a) * 16 + c];
+    for (; y < ny; y += 64) acc[0] += partials[((long long)y * nv + a) * 16 + c];
+    double s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (l == 0) G[idx] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -186,7 +196,7 @@ void gram(Problem& P, const double* V, long long ldv, int nv, const double* W, l
         default: hipLaunchKernelGGL(bgram_k<8>, grid, dim3(256), 0, st, V, ldv, nv, W, ldw, p, n, cpb, P.blk_part); break;
     }
     TSFDE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(bgram_finish_k, dim3((nv * p + 255) / 256), dim3(256), 0, st, P.blk_part, ny, nv, p,
+    hipLaunchKernelGGL(bgram_finish_k, dim3((nv * p + 3) / 4), dim3(256), 0, st, P.blk_part, ny, nv, p,
                        P.blk_small);
     TSFDE_HIP(hipGetLastError());
     G.resize((size_t)nv * p);

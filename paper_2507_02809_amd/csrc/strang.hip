@@ -356,20 +356,25 @@ static size_t dense_seg_lds(int d, int N, int Np, size_t elem) {
 // computes one 16 x 16 tile of D, each wave a quarter of the sum over j; inside a wave the lanes of
 // group q = lane / 16 take a contiguous run of that quarter (the order of a sum's terms is free), so
 // every lane reads whole cache lines.  The quarters are added in LDS.
-// The input is read plainly, scaled by scale / (sigma + c lam[r][j]) (the eigenvalue step), or formed
-// as the last row's right-hand side (z_M - y_{M-1}) / (c_f gamma2_{M-1}).  The last pass of a step
-// writes y_s and, at the same points, the right-hand side of step s + 1 (its near history is pointwise
-// in space), so the next step's first pass reads it plainly.
+// The input is read plainly or formed as the last row's right-hand side (z_M - y_{M-1}) /
+// (c_f gamma2_{M-1}).  The second pass of a step stores its output
+// scaled by the eigenvalue factor (once per value, where scaling the third pass's input would repeat
+// the division in every tile that reads it); the last pass writes y_s and, at the same points, the
+// right-hand side of step s + 1 (its near history is pointwise in space), so the next step's first
+// pass reads it plainly.
 // ---------------------------------------------------------------------------
-enum MfmaIn : int { MIN_PLAIN = 0, MIN_SCALE = 1, MIN_LAST = 2 };
+enum MfmaIn : int { MIN_PLAIN = 0, MIN_LAST = 2 };
+// what a pass does with its output besides storing it: nothing, the eigenvalue scaling (then stored
+// scaled), or forming the next step's right-hand side
+enum MfmaEpi : int { EPI_NONE = 0, EPI_SCALE = 1, EPI_NEXT = 2 };
 
 struct MfmaPassArgs {
     const double* in;
     double* out;
     const double* Cm;  // [Kp][Kp]
     int Kp, N;
-    // MIN_SCALE
-    const double* lam;  // [r][j]
+    // EPI_SCALE
+    const double* lam;  // [k1][k2], the output index of the scaled pass
     double sigma, c, scale;
     // MIN_LAST, and the SRC_LAST right-hand side of the epilogue
     const double* z;   // z_M
@@ -394,12 +399,11 @@ template <int IN>
 __device__ __forceinline__ double mfma_in(const MfmaPassArgs& a, int r, int j) {
     if (r >= a.N || j >= a.N) return 0.0;
     const long long g = (long long)r * a.N + j;
-    if (IN == MIN_SCALE) return a.in[g] * (a.scale / (a.sigma + a.c * a.lam[g]));
     if (IN == MIN_LAST) return (a.z[g] - a.yl[g]) / (a.cf * a.g2[g]);
     return a.in[g];
 }
 
-template <int IN, bool EPI>
+template <int IN, int EPI>
 __global__ __launch_bounds__(256) void mfma_pass(MfmaPassArgs a) {
     __shared__ double red[4][256];
     const int l = threadIdx.x & 63;
@@ -430,8 +434,12 @@ __global__ __launch_bounds__(256) void mfma_pass(MfmaPassArgs a) {
     const int k = k0 + (l >> 4) + 4 * w;
     if (k >= a.N || r >= a.N) return;
     const long long g = (long long)k * a.N + r;
+    if (EPI == EPI_SCALE) {  // the eigenvalue step on this pass's output [k1][k2]
+        a.out[g] = d * (a.scale / (a.sigma + a.c * a.lam[g]));
+        return;
+    }
     a.out[g] = d;
-    if (!EPI) return;
+    if (EPI != EPI_NEXT) return;
     if (a.next == SRC_NEAR) {
         // rhs_{s1} = w_{s1} - dg_{s1} sum_{sa <= m < s1} e_{s1-m} y_m, with y_{s1-1} = d
         double h = a.e[1] * d;
@@ -446,7 +454,7 @@ __global__ __launch_bounds__(256) void mfma_pass(MfmaPassArgs a) {
     }
 }
 
-template <int IN, bool EPI>
+template <int IN, int EPI>
 static void mfma_launch(const MfmaPassArgs& a, hipStream_t st) {
     const dim3 grid((unsigned)(a.Kp / 16), (unsigned)(a.Kp / 16));
     hipLaunchKernelGGL((mfma_pass<IN, EPI>), grid, dim3(256), 0, st, a);
@@ -603,29 +611,30 @@ static void dense_mfma(Problem& P, const Dev<double>& D, const double* z, double
             p.out = t1;
             if (s > sa) {
                 p.in = t2;
-                mfma_launch<MIN_PLAIN, false>(p, st);
+                mfma_launch<MIN_PLAIN, EPI_NONE>(p, st);
             } else if (s < P.M) {
                 p.in = hist;
-                mfma_launch<MIN_PLAIN, false>(p, st);
+                mfma_launch<MIN_PLAIN, EPI_NONE>(p, st);
             } else {
-                mfma_launch<MIN_LAST, false>(p, st);
+                mfma_launch<MIN_LAST, EPI_NONE>(p, st);
             }
+            // [k2][i1] -> [k1][k2], each value scaled once by scale / (sigma + c lam[k1][k2])
             p.in = t1;
             p.out = t2;
-            mfma_launch<MIN_PLAIN, false>(p, st);
-            p.in = t2;
-            p.out = t1;
             p.sigma = s < P.M ? P.sigma[s] : 0.0;
             p.c = s < P.M ? P.ct : 1.0;
             p.scale = X.inv;
-            mfma_launch<MIN_SCALE, false>(p, st);
+            mfma_launch<MIN_PLAIN, EPI_SCALE>(p, st);
+            p.in = t2;
+            p.out = t1;
+            mfma_launch<MIN_PLAIN, EPI_NONE>(p, st);
             p.in = t1;
             p.out = y + (long long)s * Nd;
             p.s1 = s + 1;
             p.next = s + 1 > se ? 0 : (s + 1 < P.M ? SRC_NEAR : SRC_LAST);
             p.hacc = hist + (long long)(s + 1 - sa) * Nd;
             p.dg = s + 1 < P.M ? D.dg + (long long)(s + 1) * Nd : nullptr;
-            mfma_launch<MIN_PLAIN, true>(p, st);
+            mfma_launch<MIN_PLAIN, EPI_NEXT>(p, st);
         }
     }
 }
