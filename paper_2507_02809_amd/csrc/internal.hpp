@@ -133,6 +133,11 @@ struct Problem {
     // the CU slots its grid needs (graph_slots) instead of holding them, and leaves its counters to
     // the solver; the instantiated cycle, what it was captured for, its capture stream, the
     // per-step coefficients (device) and their pinned mirror
+    // the transposed sweep on the persistent kernels (pinv_adjoint_run): history weights per earlier
+    // step and reversed shifts while it runs; reversed right-hand sides and block weights, shifts
+    bool adjoint_sweep = false;
+    const double* sweep_sigma = nullptr;
+    double* adj_rev = nullptr;
     bool capturing = false;
     int graph_slots = 0;
     hipGraphExec_t cyc_exec = nullptr;
@@ -297,6 +302,13 @@ void set_persistent_blocks(int g);
 // the abort word before a replay; after it, read both (synchronises st; throws if a barrier wait
 // timed out) and return the iterations
 void pinv_graph_prepare(Problem& P, bool f32, hipStream_t st);
+long long pinv_adjoint_run(Problem& P, const double* zrev, const double* dgrev, const double* sigrev, double* urev,
+                           double inner_tol, int inner_maxit, int extrap, hipStream_t st);
+// P^{-T} sweep helpers (kernels.hip): zrev_k = g_{M-1-k} (k = 0 also minus lam_M), dgrev_k =
+// dg_{M-1-k}; then lam_m = urev_{M-1-m} / gamma2_m for m < M, in place (urev in lam's first M slices)
+void launch_adj_reverse(const Problem& P, const double* g, const double* lam, double* zrev, double* dgrev,
+                        hipStream_t s);
+void launch_adj_unreverse(const Problem& P, double* lam, hipStream_t s);
 long long pinv_graph_finish(Problem& P, bool f32, hipStream_t st);
 // v *= 1 / sqrt(*sq), or v = 0 when *sq is not a positive finite number
 void launch_scale_rsqrt(double* v, long long n, const double* sq, hipStream_t s);

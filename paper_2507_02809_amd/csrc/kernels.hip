@@ -593,6 +593,48 @@ void launch_scale(double* v, long long n, const double* num, const double* den, 
     TSFDE_HIP(hipGetLastError());
 }
 
+// The transposed sweep's inputs in reversed step order: zrev_k = g^(M-1-k) (k = 0: minus lam^(M), the
+// coupling of the last block row), dgrev_k = dg_{M-1-k}, k < M
+__global__ void adj_reverse_k(const double* __restrict__ g, const double* __restrict__ lam,
+                              const double* __restrict__ dg, double* __restrict__ zrev, double* __restrict__ dgrev,
+                              long long Nd, int M) {
+    const long long n = (long long)M * Nd;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const long long k = i / Nd, j = i - k * Nd;
+        const long long src = (long long)(M - 1 - k) * Nd + j;
+        double zv = g[src];
+        if (k == 0) zv -= lam[(long long)M * Nd + j];
+        zrev[i] = zv;
+        dgrev[i] = dg[src];
+    }
+}
+void launch_adj_reverse(const Problem& P, const double* g, const double* lam, double* zrev, double* dgrev,
+                        hipStream_t s) {
+    const long long n = (long long)P.M * P.Nd;
+    hipLaunchKernelGGL(adj_reverse_k, dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, g, lam, P.f64.dg, zrev, dgrev,
+                       P.Nd, P.M);
+    TSFDE_HIP(hipGetLastError());
+}
+
+// lam^(m) = urev_{M-1-m} ./ gamma2^(m) for m < M, in place over lam's first M slices (urev): the thread
+// of the pair (k, M-1-k) reads both before it writes either
+__global__ void adj_unreverse_k(double* __restrict__ lam, const double* __restrict__ g2, long long Nd, int M) {
+    const long long half = (long long)((M + 1) / 2) * Nd;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < half; i += (long long)gridDim.x * blockDim.x) {
+        const long long k = i / Nd, j = i - k * Nd;
+        const long long a = k * Nd + j, b = (long long)(M - 1 - k) * Nd + j;
+        const double ua = lam[a], ub = lam[b];
+        lam[a] = ub / g2[a];  // slice k from urev_{M-1-k}
+        lam[b] = ua / g2[b];  // slice M-1-k from urev_k (the same point when k = M-1-k)
+    }
+}
+void launch_adj_unreverse(const Problem& P, double* lam, hipStream_t s) {
+    const long long n = (long long)((P.M + 1) / 2) * P.Nd;
+    hipLaunchKernelGGL(adj_unreverse_k, dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, lam, P.f64.gamma2, P.Nd,
+                       P.M);
+    TSFDE_HIP(hipGetLastError());
+}
+
 __global__ void scale_rsqrt_k(double* __restrict__ v, long long n, const double* __restrict__ sq) {
     const double q = *sq;
     const double inv = (q > 0.0 && q <= 1.79e308) ? 1.0 / sqrt(q) : 0.0;

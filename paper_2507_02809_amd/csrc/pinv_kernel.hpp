@@ -59,6 +59,7 @@ struct PinvArgs {
     int Nt;       // size of the sine transform: N, or the padded size with L = 2 (Nt + 1)
     int nt;       // 2D: row stride of the sine-transform intermediates t1 [Nt][nt], t2 [N][nt]
     int extrap;   // block CG initial guess: 0 previous level, 1 linear, 2 quadratic, 3 half-linear extrapolation
+    int adj;      // 1: the transposed sweep (history weights per earlier step: rhs = w - sum e dg_m y_m)
     const T* z;
     T* y;
     const T* g1;
@@ -163,13 +164,15 @@ __device__ __forceinline__ void gather_totals(const double* part, double* tot) {
 
 // ---------------------------------------------------------------------------
 // far history folded into the right-hand side: for i < cnt (<= kHB), s = sa + i < M,
-//   w[i][j] = (z_s[j] - gamma1_s[j] sum_{m < sa} e_{s-m} y_m[j]) / gamma2_s[j].
+//   w[i][j] = (z_s[j] - gamma1_s[j] sum_{m < sa} e_{s-m} y_m[j]) / gamma2_s[j],
+// or, for the transposed sweep (g1 = g2 = null, dgcol = the per-step weights of the earlier steps),
+//   w[i][j] = z_s[j] - sum_{m < sa} e_{s-m} dgcol_m[j] y_m[j].
 // One workgroup = 64 points x 4 waves; wave w sums the steps m = w, w+4, ...
 template <typename T>
 __global__ __launch_bounds__(256) void far_history(const T* __restrict__ y, T* __restrict__ w_out,
                                                    const T* __restrict__ epad, const T* __restrict__ z,
                                                    const T* __restrict__ g1, const T* __restrict__ g2, int sa,
-                                                   int cnt, long long Nd) {
+                                                   int cnt, long long Nd, const T* __restrict__ dgcol) {
     __shared__ T part[4][kHB][64];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -181,7 +184,8 @@ __global__ __launch_bounds__(256) void far_history(const T* __restrict__ y, T* _
     if (j < Nd) {
 #pragma unroll 4
         for (int m = w; m < sa; m += 4) {
-            const T ym = y[(long long)m * Nd + j];
+            T ym = y[(long long)m * Nd + j];
+            if (dgcol) ym *= dgcol[(long long)m * Nd + j];
 #pragma unroll
             for (int i = 0; i < kHB; ++i) acc[i] += e[sa + i - m] * ym;
         }
@@ -194,7 +198,7 @@ __global__ __launch_bounds__(256) void far_history(const T* __restrict__ y, T* _
         for (int i = w; i < cnt; i += 4) {
             const long long o = (long long)(sa + i) * Nd + j;
             const T h = (part[0][i][lane] + part[1][i][lane]) + (part[2][i][lane] + part[3][i][lane]);
-            w_out[(long long)i * Nd + j] = (z[o] - g1[o] * h) / g2[o];
+            w_out[(long long)i * Nd + j] = g1 ? (z[o] - g1[o] * h) / g2[o] : z[o] - h;
         }
     }
 }
@@ -945,6 +949,12 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                 yv[i] = T(0);
                 if (!lastrow && i + 1 < nnear) yv[i] = a.y[(long long)(sa + i) * Nd + j];
             }
+            if (a.adj) {
+                // transposed sweep: each earlier step's term carries its own weight dg_m
+#pragma unroll
+                for (int i = 0; i < kHB; ++i)
+                    if (!lastrow && i + 1 < nnear) yv[i] *= a.dg[(long long)(sa + i) * Nd + j];
+            }
             T hn = T(0);
 #pragma unroll
             for (int i = 0; i < kHB; ++i) hn += ew[i] * yv[i];
@@ -960,6 +970,8 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
             T rhs, x0 = T(0), bx0 = T(0);
             if (lastrow) {
                 rhs = (v.zo - yprev) / (a.cf * v.g2o);
+            } else if (a.adj) {
+                rhs = v.zo - (v.hn + e1 * v.dgp * yprev);  // transposed sweep: weights of the earlier steps
             } else {
                 const T h = v.hn + e1 * yprev;
                 rhs = v.zo - v.dgo * h;
@@ -1277,7 +1289,8 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
     a.sym = D.sym;
     a.tau = D.tau;
     a.tw = D.tw;
-    a.sigma = P.d_sigma;
+    a.sigma = P.sweep_sigma ? P.sweep_sigma : P.d_sigma;
+    a.adj = P.adjoint_sweep ? 1 : 0;
     a.ct = T(P.ct);
     a.cf = T(P.cf);
     a.a0 = T(P.a0);
@@ -1343,8 +1356,12 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
         int sb_ = std::min(sa + kHB, s_last + 1);
         const int cnt = std::min(kHB, P.M - sa);
         if (cnt > 0) {
-            hipLaunchKernelGGL(far_history<T>, dim3((unsigned)((Nd + 63) / 64)), dim3(256), 0, st, y, a.hacc, D.epad,
-                               z, D.gamma1, D.gamma2, sa, cnt, Nd);
+            if (P.adjoint_sweep)  // transposed sweep: unscaled right-hand sides, weights per earlier step
+                hipLaunchKernelGGL(far_history<T>, dim3((unsigned)((Nd + 63) / 64)), dim3(256), 0, st, y, a.hacc,
+                                   D.epad, z, (const T*)nullptr, (const T*)nullptr, sa, cnt, Nd, D.dg);
+            else
+                hipLaunchKernelGGL(far_history<T>, dim3((unsigned)((Nd + 63) / 64)), dim3(256), 0, st, y, a.hacc,
+                                   D.epad, z, D.gamma1, D.gamma2, sa, cnt, Nd, (const T*)nullptr);
             TSFDE_HIP(hipGetLastError());
         }
         launch_fill(reinterpret_cast<float*>(W.bar), 1, 0.0f, st);  // zero the barrier counter

@@ -117,6 +117,31 @@ long long pinv_persistent_run(Problem& P, const Dev<T>& D, void*& wptr, const T*
     return run_segments(P, D, W, z, y, inner_tol, inner_maxit, last_block, extrap, tblocks, st);
 }
 
+// The transposed sweep of P^{-T} on the persistent kernels: the steps of the backward substitution
+// taken in reversed order (step k = block row M - 1 - k) as a forward sweep with per-step weights on
+// the history (PinvArgs.adj): zrev, dgrev, sigrev hold the reversed right-hand sides, block weights
+// and shifts; urev (M slices) receives the solutions in the same reversed order.
+long long pinv_adjoint_run(Problem& P, const double* zrev, const double* dgrev, const double* sigrev, double* urev,
+                           double inner_tol, int inner_maxit, int extrap, hipStream_t st) {
+    void*& wptr = P.pw64;
+    if (!wptr) wptr = new PersistentWork<double>();
+    PersistentWork<double>& W = *static_cast<PersistentWork<double>*>(wptr);
+    ensure_work(P, W);
+    Dev<double> D = P.f64;
+    D.dg = const_cast<double*>(dgrev);  // read only by the sweep
+    struct Sweep {  // the problem's forward settings come back however the sweep ends
+        Problem& P;
+        ~Sweep() {
+            P.adjoint_sweep = false;
+            P.sweep_sigma = nullptr;
+        }
+    } restore{P};
+    P.adjoint_sweep = true;
+    P.sweep_sigma = sigrev;
+    set_persistent_blocks(-1);
+    return run_segments<double>(P, D, W, zrev, urev, inner_tol, inner_maxit, false, extrap, 0, st);
+}
+
 template <typename T>
 static PersistentWork<T>& graph_work(Problem& P) {
     void*& wp = std::is_same<T, float>::value ? P.pw32 : P.pw64;
@@ -243,7 +268,7 @@ void launch_far_history(const Problem& P, const Dev<T>& D, const T* y, T* w, con
                         hipStream_t st) {
     if (cnt < 1 || cnt > kHB || sa + cnt > P.M) throw HipError{hipErrorInvalidValue, "far_history step range"};
     hipLaunchKernelGGL(far_history<T>, dim3((unsigned)((P.Nd + 63) / 64)), dim3(256), 0, st, y, w, D.epad, z,
-                       D.gamma1, D.gamma2, sa, cnt, P.Nd);
+                       D.gamma1, D.gamma2, sa, cnt, P.Nd, (const T*)nullptr);
     TSFDE_HIP(hipGetLastError());
 }
 

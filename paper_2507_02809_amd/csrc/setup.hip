@@ -360,7 +360,7 @@ void free_problem(Problem* P) {
     void* ptrs[] = {P->d_bw, P->d_rho, P->d_mu, P->z_rhs, P->xbuf, P->V, P->Z, P->arn_part, P->arn_h, P->rwork, P->adj_u,
                     P->dev_scalars, P->strang64, P->strang32, P->strang_hist, P->refine_work, P->vjp_work,
                     P->d_sigma, P->fwd_work, P->taud64, P->taud32, P->spec_work, P->dense_bar, P->blk_V, P->blk_part,
-                    P->blk_small, P->blk_io};
+                    P->blk_small, P->blk_io, P->adj_rev};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (P->host_scalars) (void)hipHostFree(P->host_scalars);

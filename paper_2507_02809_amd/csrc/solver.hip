@@ -332,6 +332,28 @@ static long long ptinv_launch(Problem& P, const double* g, double* lam, const Op
     double* x = D.pcg;
     double* rhs = x + 7 * Nd;
     long long total = 0;
+    // the block rows m < M on the persistent kernels (TSFDE_PTINV=0 keeps them on this loop): after the
+    // last block row, the transposed sweep in reversed step order
+    const bool pers = env_int("TSFDE_PTINV", 1) != 0 && env_int("TSFDE_PINV", 1) != 0 && persistent_supported(P);
+    if (pers) {
+        launch_adj_step_rhs<double>(P, D, g, lam, P.M, rhs, st);
+        launch_fill(x, Nd, 0.0, st);
+        total += block_cg<double>(P, D, rhs, x, nullptr, 1.0, 0.0, o, st);
+        launch_scale_g2<double>(P, D, x, lam, P.M, true, st);
+        const size_t MN = (size_t)P.M * Nd;
+        if (!P.adj_rev) dev_alloc(P, P.adj_rev, 2 * MN + (size_t)P.M);
+        double* zrev = P.adj_rev;
+        double* dgrev = P.adj_rev + MN;
+        double* sigrev = P.adj_rev + 2 * MN;
+        std::vector<double> sr(P.M);
+        for (int k = 0; k < P.M; ++k) sr[k] = P.sigma[P.M - 1 - k];
+        TSFDE_HIP(hipMemcpyAsync(sigrev, sr.data(), sizeof(double) * P.M, hipMemcpyHostToDevice, st));
+        launch_adj_reverse(P, g, lam, zrev, dgrev, st);
+        total += pinv_adjoint_run(P, zrev, dgrev, sigrev, lam, o.inner_tol, o.inner_maxit,
+                                  env_int("TSFDE_EXTRAP", o.warm_start), st);  // synchronises st
+        launch_adj_unreverse(P, lam, st);
+        return total;
+    }
     for (int m = P.M; m >= 0; --m) {
         launch_adj_step_rhs<double>(P, D, g, lam, m, rhs, st);
         const double* dg = (m < P.M) ? D.dg + (long long)m * Nd : nullptr;

@@ -682,6 +682,28 @@ def test_apply_AT_and_PT_inv_match_dense(dense_case):
         assert rel_err(w.cpu().numpy(), np.linalg.solve(P.T, lam)) <= 1e-10
 
 
+@pytest.mark.parametrize("shape", [(1, 60, 37), (2, 15, 40), (2, 12, 20), (2, 7, 17), (1, 5, 1), (2, 9, 16)])
+def test_apply_PT_inv_persistent_sweep_matches_host_loop_and_oracle(monkeypatch, shape):
+    """P^{-T} g on the persistent kernels (the backward substitution as a forward sweep in reversed
+    step order, history weights per earlier step) against the one-launch-per-CG-phase loop, over
+    several blocks of 16 steps with ragged ends (M = 1, 16, 17, 20, 37, 40; 1D, 2D with the sine
+    preconditioner and with its padded form), and against the oracle's dense P^T solve where that
+    fits."""
+    d, N, M = shape
+    inp = inputs.small(d, N, M, beta=0.55, omega=1.45)
+    p = workloads.problem(inp, mu=np.zeros(inp.Nd))
+    g_np = np.random.default_rng(37).standard_normal(p.n_tot)
+    o = tsfde.default_opts(inner_tol=1e-14, inner_maxit=500)
+    with gpu_problem(inp, p) as g:
+        gt = torch.tensor(g_np, device=DEV)
+        w = g.apply_PT_inv(gt, opts=o).cpu().numpy()
+        monkeypatch.setenv("TSFDE_PTINV", "0")
+        w0 = g.apply_PT_inv(gt, opts=o).cpu().numpy()
+    assert rel_err(w, w0) <= 1e-10
+    if p.n_tot <= 3000:
+        assert rel_err(w, np.linalg.solve(system.dense_P(p).T, g_np)) <= 1e-10
+
+
 @pytest.mark.parametrize("shape", [(1, 100, 70), (2, 13, 70), (2, 31, 20), (2, 64, 9)])
 def test_apply_AT_adjoint_identity_ragged(shape):
     """<A x, w> (oracle, FFT matvec) = <x, A^T w> (library) at sizes past the dense oracle: several
