@@ -459,6 +459,18 @@ def main():
                        "max_rel_res": max(st.rel_res for _, st in outs),
                        "outer_iters_min_mean_max": [min(its), float(np.mean(its)), max(its)],
                        "n_tot_total": int(sum(p.n_tot for p in cprobs)), "setup_s": t_c4}
+        # the same batch in lockstep, every P^-1 application of all unfinished problems in shared
+        # persistent launches (tsfde_recover_f_multi)
+        tsfde.recover_f_multi(cprobs, oc4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outm = tsfde.recover_f_multi(cprobs, oc4)
+        torch.cuda.synchronize()
+        dtm = time.perf_counter() - t0
+        log(f"mixed batch, shared P^-1 launches: {len(cprobs)} solves in {dtm:.2f} s ({len(cprobs) / dtm:.2f} problems/s)")
+        mixed_batch["shared_launches"] = {"problems_per_s": len(cprobs) / dtm, "s_per_batch": dtm,
+                                          "converged": int(sum(st.converged for _, st in outm)),
+                                          "max_rel_res": max(st.rel_res for _, st in outm)}
         for pk in cprobs:
             pk.close()
 

@@ -385,6 +385,19 @@ tsfde_status tsfde_autotune(tsfde_problem* prob, tsfde_opts* opts, int what, tsf
                             void* stream);
 
 /*
+ * tsfde_recover_f for several problems in lockstep, their P^{-1} applications sharing persistent
+ * launches: at each Arnoldi step one launch per block of 16 time steps runs the forward
+ * substitution of every unfinished problem side by side (each on its own share of the grid, with
+ * its own device-wide barrier); problems of one kernel form share a launch (2D: the same values
+ * per thread; 1D: also the same FFT length), launches take as many problems as fit the device's CU
+ * slots together.  Matvecs, Gram-Schmidt and the Givens rotations stay per problem (stream and
+ * host).  FP64 with CG blocks only (ENOTIMPL otherwise, and for a problem without the persistent
+ * P^{-1}); EINVAL for NULL entries or a repeated problem; ENOCONV if any problem missed tol.
+ */
+tsfde_status tsfde_recover_f_multi(tsfde_problem* const* probs, int count, double* const* f_out,
+                                   const tsfde_opts* opts, tsfde_stats* stats, void* stream);
+
+/*
  * Direct problem of §6.1: v = A-hat^{-1} z-hat with z-hat^(s) = b_{s-1} D_1^(s) rho + eta q^(s) f,
  * i.e. the first M steps of the forward substitution (used to synthesise mu).
  *   f    device, N^d        v  device, M N^d (slices v^(1..M)); mu = v^(M)

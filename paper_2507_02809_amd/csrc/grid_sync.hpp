@@ -25,10 +25,11 @@ unsigned long long barrier_ticks(int dev);
 // the word) returns at once.  The grid then runs its remaining, bounded loops on meaningless
 // values and exits normally; the host finds the word set and reports an error.  A wait can only
 // last that long when the grid's workgroups are not all resident at once.
-__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned long long ticks, unsigned& epoch) {
+// nb: the workgroups that meet at this barrier (the launch's grid, or one problem's share of it).
+__device__ __forceinline__ void grid_barrier_n(unsigned* bar, unsigned long long ticks, unsigned& epoch, int nb) {
     __syncthreads();
-    if (gridDim.x > 1) {
-        epoch += gridDim.x;
+    if (nb > 1) {
+        epoch += (unsigned)nb;
         if (threadIdx.x == 0) {
             __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
@@ -46,6 +47,10 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned long long t
         }
         __syncthreads();
     }
+}
+
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned long long ticks, unsigned& epoch) {
+    grid_barrier_n(bar, ticks, epoch, (int)gridDim.x);
 }
 
 }  // namespace tsfde

@@ -138,6 +138,10 @@ struct Problem {
     bool adjoint_sweep = false;
     const double* sweep_sigma = nullptr;
     double* adj_rev = nullptr;
+    // launch tables of shared P^-1 launches over several problems (device, pinned mirror)
+    void* multi_dev = nullptr;
+    void* multi_host = nullptr;
+    size_t multi_bytes = 0;
     bool capturing = false;
     int graph_slots = 0;
     hipGraphExec_t cyc_exec = nullptr;
@@ -302,6 +306,16 @@ void set_persistent_blocks(int g);
 // the abort word before a replay; after it, read both (synchronises st; throws if a barrier wait
 // timed out) and return the iterations
 void pinv_graph_prepare(Problem& P, bool f32, hipStream_t st);
+// y_i = P_i^{-1} z_i for several problems in shared persistent launches (FP64, CG blocks, every problem
+// with persistent_supported): problems of one kernel form share a launch (2D: the same values per
+// thread; 1D: also the same transform length); iters_i receives each problem's CG iterations
+struct PinvMultiJob {
+    Problem* P;
+    const double* z;
+    double* y;
+    long long iters;
+};
+void pinv_multi_run(std::vector<PinvMultiJob>& jobs, double inner_tol, int inner_maxit, int extrap, hipStream_t st);
 long long pinv_adjoint_run(Problem& P, const double* zrev, const double* dgrev, const double* sigrev, double* urev,
                            double inner_tol, int inner_maxit, int extrap, hipStream_t st);
 // P^{-T} sweep helpers (kernels.hip): zrev_k = g_{M-1-k} (k = 0 also minus lam_M), dgrev_k =

@@ -37,6 +37,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "fft.hpp"
 #include "grid_sync.hpp"
@@ -81,14 +82,17 @@ struct PinvArgs {
     unsigned* bar;     // [0] barrier counter, zero at launch; [1] abort word (see grid_barrier)
     unsigned long long bar_ticks;  // longest barrier wait, in wall-clock periods
     long long* iters;  // accumulated CG iterations
+    int vb, vg;        // this workgroup's index in the problem's grid and that grid's size
 };
 
+// (A problem's workgroups are numbered vb = 0 .. vg - 1 within its grid: the whole launch, or its share
+// of a launch that runs several problems side by side.)
 // Block-reduce K values at once into this block's slots: the shuffle trees of the K values are
 // interleaved so that their exchanges overlap.  red holds kSegBlock/64 * K doubles.  The order of
 // the additions is fixed (shuffle tree per wave, then the waves in order), so every block reduces
 // its values the same way on every run.
 template <int K, typename T>
-__device__ __forceinline__ void put_partials(double* part, const int (&slot)[K], const T (&val)[K], double* red) {
+__device__ __forceinline__ void put_partials(double* part, const int (&slot)[K], const T (&val)[K], double* red, int vb) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int nact = min(kWave, (int)blockDim.x - wid * kWave);  // active lanes of this wave
@@ -114,27 +118,26 @@ __device__ __forceinline__ void put_partials(double* part, const int (&slot)[K],
         for (int k = 0; k < K; ++k) {
             double r = 0.0;
             for (int w = 0; w < nw; ++w) r += red[w * K + k];
-            part[blockIdx.x * kNPart + slot[k]] = r;
+            part[vb * kNPart + slot[k]] = r;
         }
     }
     __syncthreads();
 }
 
 template <typename T>
-__device__ __forceinline__ void put_partial(double* part, int slot, T v, double* red) {
+__device__ __forceinline__ void put_partial(double* part, int slot, T v, double* red, int vb) {
     const int sl[1] = {slot};
     const T vv[1] = {v};
-    put_partials<1>(part, sl, vv, red);
+    put_partials<1>(part, sl, vv, red, vb);
 }
 
 // After a barrier: wave 0 loads every block's slots (lane b reads block b), reduces the slots in
 // MASK with the same shuffle tree in every block (the trees of the slots interleaved) and leaves
 // the totals in tot[] (LDS) for all threads.
 template <unsigned MASK = (1u << kNPart) - 1>
-__device__ __forceinline__ void gather_totals(const double* part, double* tot) {
+__device__ __forceinline__ void gather_totals(const double* part, double* tot, int G) {
     if (threadIdx.x < kWave) {
         const int lane = threadIdx.x;
-        const int G = gridDim.x;
         const int nact = min(kWave, (int)blockDim.x);
         double v[kNPart];
 #pragma unroll
@@ -778,10 +781,9 @@ __host__ __device__ constexpr int spec_stride(int N) { return (N + 15) & ~15; }
 // TB: the tau-block form (each block solved by one application of its frozen-coefficient tau
 // matrix, from zero; 2D tau path only)
 template <typename T, int VPT, int MODE, int LC, bool TB>
-__global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int sa, int sb) {
+__device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
     static_assert(LC == 0 || MODE == SEG_2D_TAU, "a fixed length is provided for the 2D tau path only");
     static_assert(!TB || MODE == SEG_2D_TAU, "the tau-block form runs on the 2D tau path only");
-    PinvArgs<T> a = ain;
     if constexpr (LC > 0) {
         a.d = 2;
         a.L = LC;
@@ -809,10 +811,10 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
     for (int k = threadIdx.x; k < twn; k += blockDim.x) lds[k] = a.tw[k];
     const cplx<T>* twl = TWL ? lds : a.tw;
     __syncthreads();
-    const int NG = gridDim.x * gpb;         // groups in the grid
-    const int gg = blockIdx.x * gpb + grp;  // this group's index
-    const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long gthreads = (long long)gridDim.x * blockDim.x;
+    const int NG = a.vg * gpb;         // groups in the grid
+    const int gg = a.vb * gpb + grp;  // this group's index
+    const long long gtid = (long long)a.vb * blockDim.x + threadIdx.x;
+    const long long gthreads = (long long)a.vg * blockDim.x;
     const int N = a.N;
     const long long Nd = a.Nd;
     const int M = a.M;
@@ -900,12 +902,12 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
             if (upd) {
                 const int sl[2] = {SL_RR, SL_RZ};
                 const T vv[2] = {rr, rzl};
-                put_partials<2>(a.part, sl, vv, red);
+                put_partials<2>(a.part, sl, vv, red, a.vb);
             } else {
-                put_partial(a.part, SL_RZ, rzl, red);
+                put_partial(a.part, SL_RZ, rzl, red, a.vb);
             }
-            grid_barrier(a.bar, a.bar_ticks, epoch);
-            gather_totals(a.part, tot);
+            grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
+            gather_totals(a.part, tot, a.vg);
         };
 
         // ---------------- E: finish step s-1, history, rhs, warm start, r0 ----------------
@@ -1006,7 +1008,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                 // row ownership (group: rows i0, i0 + 1), fused with pass A of z0 = M^{-1} r0: the new
                 // residual rows are sine-transformed into t1 right away
                 for (int rd = 0; rd < NR; ++rd) {
-                    const int ibase = 2 * (rd * NG + blockIdx.x * gpb);
+                    const int ibase = 2 * (rd * NG + a.vb * gpb);
                     const int i0 = ibase + 2 * grp;
                     const bool valid = i0 < N;
                     const bool two = i0 + 1 < N;
@@ -1052,10 +1054,10 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
             {
                 const int sl[2] = {SL_RR, SL_BB};
                 const T vv[2] = {rr, bb};
-                put_partials<2>(a.part, sl, vv, red);
+                put_partials<2>(a.part, sl, vv, red, a.vb);
             }
-            grid_barrier(a.bar, a.bar_ticks, epoch);
-            gather_totals<(1u << SL_RR) | (1u << SL_BB)>(a.part, tot);
+            grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
+            gather_totals<(1u << SL_RR) | (1u << SL_BB)>(a.part, tot, a.vg);
         }
         const double bbt = tot[SL_BB];
         double rrt = tot[SL_RR];
@@ -1065,7 +1067,7 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                 a.x[j] = T(0);
                 a.r[j] = T(0);
             }
-            grid_barrier(a.bar, a.bar_ticks, epoch);
+            grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
             continue;
         }
         if constexpr (TAU2) {
@@ -1075,12 +1077,12 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                 // device-wide barrier follows.
                 T rzl = T(0);
                 for (int rd = 0; rd < NRB; ++rd) {
-                    const int kbase = 2 * (rd * NG + blockIdx.x * gpb);
+                    const int kbase = 2 * (rd * NG + a.vb * gpb);
                     wg_pass_B<T, VPT>(a, cbase, c, twl, kbase, grp, gpb, sig, cc, scale, tid, nthr, rzl);
                 }
-                grid_barrier(a.bar, a.bar_ticks, epoch);
+                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
                 for (int rd = 0; rd < NR; ++rd) {
-                    const int ibase = 2 * (rd * NG + blockIdx.x * gpb);
+                    const int ibase = 2 * (rd * NG + a.vb * gpb);
                     const int i0 = ibase + 2 * grp;
                     const bool valid = i0 < N;
                     g_dst_rows<T, VPT>(a, c, twl, a.t2, a.nt, a.Nt, N, i0, valid, tid, nthr);
@@ -1107,12 +1109,12 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
             {
                 T rzl = T(0);
                 for (int rd = 0; rd < NRB; ++rd) {
-                    const int kbase = 2 * (rd * NG + blockIdx.x * gpb);
+                    const int kbase = 2 * (rd * NG + a.vb * gpb);
                     wg_pass_B<T, VPT>(a, cbase, c, twl, kbase, grp, gpb, sig, cc, scale, tid, nthr, rzl);
                 }
-                put_partial(a.part, SL_RZ, rzl, red);
-                grid_barrier(a.bar, a.bar_ticks, epoch);
-                gather_totals<1u << SL_RZ>(a.part, tot);
+                put_partial(a.part, SL_RZ, rzl, red, a.vb);
+                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
+                gather_totals<1u << SL_RZ>(a.part, tot, a.vg);
             }
             double rz = tot[SL_RZ];
             T beta = T(0);
@@ -1120,38 +1122,38 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
             while (true) {
                 T pdp = T(0), pbp = T(0), rr = T(0);
                 for (int rd = 0; rd < NR; ++rd) {
-                    const int ibase = 2 * (rd * NG + blockIdx.x * gpb);
+                    const int ibase = 2 * (rd * NG + a.vb * gpb);
                     wg_pass_DF<T, VPT>(a, cbase, c, twl, ibase, grp, gpb, beta, dg, tid, nthr, pdp);
                 }
-                put_partial(a.part, SL_PD, pdp, red);
-                grid_barrier(a.bar, a.bar_ticks, epoch);
+                put_partial(a.part, SL_PD, pdp, red, a.vb);
+                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
                 for (int rd = 0; rd < NC; ++rd) {
                     const int k2 = rd * NG + gg;
                     g_cols_pbp<T, VPT>(a, c, twl, k2, k2 < a.H, tid, nthr, pbp);
                 }
-                put_partial(a.part, SL_PB, pbp, red);
-                grid_barrier(a.bar, a.bar_ticks, epoch);
-                gather_totals<(1u << SL_PD) | (1u << SL_PB)>(a.part, tot);
+                put_partial(a.part, SL_PB, pbp, red, a.vb);
+                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
+                gather_totals<(1u << SL_PD) | (1u << SL_PB)>(a.part, tot, a.vg);
                 const double pqt = tot[SL_PD] + (double)cc * tot[SL_PB];
                 const T alpha = T(pqt != 0.0 ? rz / pqt : 0.0);
                 for (int rd = 0; rd < NR; ++rd) {
-                    const int ibase = 2 * (rd * NG + blockIdx.x * gpb);
+                    const int ibase = 2 * (rd * NG + a.vb * gpb);
                     wg_pass_IUA<T, VPT>(a, cbase, c, twl, ibase, grp, gpb, dg, cc, alpha, tid, nthr, rr);
                 }
-                put_partial(a.part, SL_RR, rr, red);
-                grid_barrier(a.bar, a.bar_ticks, epoch);
-                gather_totals<1u << SL_RR>(a.part, tot);
+                put_partial(a.part, SL_RR, rr, red, a.vb);
+                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
+                gather_totals<1u << SL_RR>(a.part, tot, a.vg);
                 ++it;
                 rrt = tot[SL_RR];
                 if (rrt <= a.tol2 * bbt || it >= a.maxit || !(rrt == rrt)) break;
                 T rzl = T(0);
                 for (int rd = 0; rd < NRB; ++rd) {
-                    const int kbase = 2 * (rd * NG + blockIdx.x * gpb);
+                    const int kbase = 2 * (rd * NG + a.vb * gpb);
                     wg_pass_B<T, VPT>(a, cbase, c, twl, kbase, grp, gpb, sig, cc, scale, tid, nthr, rzl);
                 }
-                put_partial(a.part, SL_RZ, rzl, red);
-                grid_barrier(a.bar, a.bar_ticks, epoch);
-                gather_totals<1u << SL_RZ>(a.part, tot);
+                put_partial(a.part, SL_RZ, rzl, red, a.vb);
+                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
+                gather_totals<1u << SL_RZ>(a.part, tot, a.vg);
                 const double rz_new = tot[SL_RZ];
                 beta = T(rz != 0.0 ? rz_new / rz : 0.0);
                 rz = rz_new;
@@ -1171,12 +1173,12 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                     const int pr = rd * NG + gg;
                     g_rows_fwd<T, VPT>(a, c, twl, pr, pr < NP, beta, tid, nthr);
                 }
-                grid_barrier(a.bar, a.bar_ticks, epoch);
+                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
                 for (int rd = 0; rd < NC; ++rd) {
                     const int k2 = rd * NG + gg;
                     g_cols<T, VPT>(a, c, twl, k2, k2 < a.H, tid, nthr);
                 }
-                grid_barrier(a.bar, a.bar_ticks, epoch);
+                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
                 for (int rd = 0; rd < NR; ++rd) {
                     const int pr = rd * NG + gg;
                     g_rows_inv<T, VPT>(a, c, twl, pr, pr < NP, dg, cc, tid, nthr, pq);
@@ -1225,9 +1227,9 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
                 }
                 __syncthreads();
             }
-            put_partial(a.part, SL_PQ, pq, red);
-            grid_barrier(a.bar, a.bar_ticks, epoch);
-            gather_totals(a.part, tot);
+            put_partial(a.part, SL_PQ, pq, red, a.vb);
+            grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
+            gather_totals(a.part, tot, a.vg);
             const double pqt = tot[SL_PQ];
             const T alpha = T(pqt != 0.0 ? rz / pqt : 0.0);
             // x += alpha p, r -= alpha q, (r, r), and pass A of z = M^{-1} r
@@ -1244,9 +1246,33 @@ __global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> ain, int s
     }
     // the segment's last step: y_{sb-1} = x (grid-stride ownership: in the tau-block mode x was
     // last written by row-owning groups, so the grid synchronises first)
-    if constexpr (TB) grid_barrier(a.bar, a.bar_ticks, epoch);
+    if constexpr (TB) grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
     for (long long j = gtid; j < Nd; j += gthreads) a.y[(long long)(sb - 1) * Nd + j] = a.x[j];
-    if (blockIdx.x == 0 && threadIdx.x == 0) *a.iters += total_it;
+    if (a.vb == 0 && threadIdx.x == 0) *a.iters += total_it;
+}
+
+
+// One problem per launch: the grid is the problem's.
+template <typename T, int VPT, int MODE, int LC, bool TB>
+__global__ __launch_bounds__(kSegBlock) void pinv_segment(PinvArgs<T> a, int sa, int sb) {
+    a.vb = blockIdx.x;
+    a.vg = gridDim.x;
+    segment_run<T, VPT, MODE, LC, TB>(a, sa, sb);
+}
+
+// Several problems in one launch (their P^-1 take the same kernel form): problem i owns the workgroups
+// [off[i], off[i+1]) and runs the steps [range[i].x, range[i].y) of its forward substitution with its
+// own arguments, work buffers and barrier; a problem with no steps in this launch has no workgroups.
+template <typename T, int VPT, int MODE>
+__global__ __launch_bounds__(kSegBlock) void pinv_segment_multi(const PinvArgs<T>* __restrict__ args,
+                                                                const int* __restrict__ off,
+                                                                const int2* __restrict__ range, int nprob) {
+    int i = 0;
+    while (i + 1 < nprob && (int)blockIdx.x >= off[i + 1]) ++i;
+    PinvArgs<T> a = args[i];
+    a.vb = (int)blockIdx.x - off[i];
+    a.vg = off[i + 1] - off[i];
+    segment_run<T, VPT, MODE, 0, false>(a, range[i].x, range[i].y);
 }
 
 // ---------------------------------------------------------------------------
@@ -1267,9 +1293,10 @@ struct PersistentWork {
 template <typename T>
 void ensure_work(Problem& P, PersistentWork<T>& W);
 
-template <typename T, int VPT, int MODE, int LC, bool TB>
-void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T* z, T* y, double inner_tol,
-                     int inner_maxit, bool last_block, int extrap, int blocks, hipStream_t st) {
+// The kernel arguments of one problem's forward substitution on the work buffers W.
+template <typename T>
+PinvArgs<T> make_pinv_args(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T* z, T* y, double inner_tol,
+                           int inner_maxit, int extrap) {
     PinvArgs<T> a{};
     a.d = P.d;
     a.N = P.N;
@@ -1315,6 +1342,14 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
     a.part = W.part;
     a.bar = W.bar;
     a.iters = W.iters;
+    return a;
+}
+
+template <typename T, int VPT, int MODE, int LC, bool TB>
+void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T* z, T* y, double inner_tol,
+                     int inner_maxit, bool last_block, int extrap, int blocks, hipStream_t st) {
+    PinvArgs<T> a = make_pinv_args<T>(P, D, W, z, y, inner_tol, inner_maxit, extrap);
+    const long long Nd = P.Nd;
     const int nthr = P.L / VPT;
     const int block = (P.d == 2) ? kSegBlock : nthr;
     const int gpb = block / nthr;
@@ -1368,6 +1403,170 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
         void* args[] = {&a, &sa_, &sb_};
         TSFDE_HIP(hipLaunchKernel((void*)pinv_segment<T, VPT, MODE, LC, TB>, dim3(grid), dim3(block), args, lds, st));
     }
+}
+
+// ---------------------------------------------------------------------------
+// Several problems' forward substitutions in shared launches (pinv_segment_multi): all of them take the
+// same kernel form (VPT, MODE, run-time length, CG blocks) and, in 1D, the same transform length.
+// Problem i keeps the grid it would have alone (2D: two rounds over the spectral rows; 1D: one
+// workgroup); a launch takes as many problems as fit the device's CU slots together (chunks), and
+// runs one block of kHB steps of each (a round); far_history runs per problem between rounds.  The
+// launch tables of every chunk and round are built on the host and copied to the device once.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct MultiItem {
+    Problem* P;
+    PersistentWork<T>* W;
+    PinvArgs<T> a;
+    int grid;
+    int s_last;
+};
+
+template <typename T, int VPT, int MODE>
+void launch_segments_multi(std::vector<MultiItem<T>>& items, hipStream_t st) {
+    const int n = (int)items.size();
+    if (n == 0) return;
+    const int L0 = items[0].P->L;
+    const int nthr0 = L0 / VPT;
+    const int block = (MODE != SEG_1D) ? kSegBlock : nthr0;
+    size_t lds = 0;
+    for (auto& it : items) {
+        if (MODE == SEG_1D && it.P->L != L0) throw HipError{hipErrorInvalidValue, "multi P^-1: 1D problems of one launch share L"};
+        const int nthr = it.P->L / VPT;
+        const int gpb = block / nthr;
+        const size_t l = sizeof(cplx<T>) * ((tw_in_lds<T>(VPT) ? it.P->L : 0) + (size_t)gpb * lds_len(it.P->L));
+        lds = std::max(lds, l);
+        it.grid = (MODE != SEG_1D) ? std::max(1, (it.P->H + 2 * gpb - 1) / (2 * gpb)) : 1;
+        it.s_last = it.P->M;  // the last block row included
+    }
+    if (lds > 160 * 1024) throw HipError{hipErrorInvalidConfiguration, "multi P^-1 LDS size"};
+    int per_cu = 0, dev = 0, ncu = 0;
+    TSFDE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pinv_segment_multi<T, VPT, MODE>, block, lds));
+    TSFDE_HIP(hipGetDevice(&dev));
+    TSFDE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (per_cu < 1) throw HipError{hipErrorInvalidConfiguration, "multi P^-1: a workgroup does not fit a CU"};
+    ResidencyBudget& pool = residency_budget(dev, ncu);
+    const int cap = std::min(per_cu * ncu, residency_max_grid(pool.total(), kXcds));
+    const unsigned long long ticks = barrier_ticks(dev);
+    for (auto& it : items) {
+        it.grid = std::min(it.grid, cap);
+        it.a.bar_ticks = ticks;
+    }
+    // chunks of problems whose grids fit together
+    std::vector<int> cstart{0};
+    for (int i = 0, g = 0; i < n; ++i) {
+        if (g > 0 && g + items[i].grid > cap) {
+            cstart.push_back(i);
+            g = 0;
+        }
+        g += items[i].grid;
+    }
+    cstart.push_back(n);
+    const int nchunk = (int)cstart.size() - 1;
+    int rounds = 0;
+    for (auto& it : items) rounds = std::max(rounds, (it.s_last + kHB) / kHB);
+    // launch tables: per chunk and round, [args x k][off x (k + 1)][range x k], 16-byte aligned
+    auto al = [](size_t v) { return (v + 15) & ~size_t(15); };
+    struct Launch {
+        size_t o_args, o_off, o_range;
+        int k, grid, chunk, round;
+    };
+    std::vector<Launch> launches;
+    size_t bytes = 0;
+    for (int c = 0; c < nchunk; ++c)
+        for (int r = 0; r < rounds; ++r) {
+            int k = 0, g = 0;
+            for (int i = cstart[c]; i < cstart[c + 1]; ++i)
+                if (r * kHB <= items[i].s_last) {
+                    ++k;
+                    g += items[i].grid;
+                }
+            if (k == 0) continue;
+            Launch l{};
+            l.k = k;
+            l.grid = g;
+            l.chunk = c;
+            l.round = r;
+            l.o_args = bytes;
+            bytes = al(bytes + sizeof(PinvArgs<T>) * k);
+            l.o_off = bytes;
+            bytes = al(bytes + sizeof(int) * (k + 1));
+            l.o_range = bytes;
+            bytes = al(bytes + sizeof(int2) * k);
+            launches.push_back(l);
+        }
+    Problem& P0 = *items[0].P;
+    if (P0.multi_bytes < bytes) {
+        if (P0.multi_dev) (void)hipFree(P0.multi_dev);
+        if (P0.multi_host) (void)hipHostFree(P0.multi_host);
+        P0.multi_dev = nullptr;
+        P0.multi_host = nullptr;
+        P0.multi_bytes = 0;
+        TSFDE_HIP(hipMalloc(&P0.multi_dev, bytes));
+        TSFDE_HIP(hipHostMalloc(&P0.multi_host, bytes, hipHostMallocDefault));
+        P0.multi_bytes = bytes;
+    }
+    unsigned char* hb = static_cast<unsigned char*>(P0.multi_host);
+    for (const Launch& l : launches) {
+        auto* args = reinterpret_cast<PinvArgs<T>*>(hb + l.o_args);
+        int* off = reinterpret_cast<int*>(hb + l.o_off);
+        int2* range = reinterpret_cast<int2*>(hb + l.o_range);
+        int k = 0, g = 0;
+        for (int i = cstart[l.chunk]; i < cstart[l.chunk + 1]; ++i) {
+            const int sa = l.round * kHB;
+            if (sa > items[i].s_last) continue;
+            args[k] = items[i].a;
+            off[k] = g;
+            range[k] = make_int2(sa, std::min(sa + kHB, items[i].s_last + 1));
+            g += items[i].grid;
+            ++k;
+        }
+        off[k] = g;
+    }
+    TSFDE_HIP(hipMemcpyAsync(P0.multi_dev, P0.multi_host, bytes, hipMemcpyHostToDevice, st));
+    int gmax = 0;
+    for (const Launch& l : launches) gmax = std::max(gmax, l.grid);
+    ResidencyTicket ticket;
+    struct Release {
+        ResidencyTicket& t;
+        ~Release() { t.release(); }
+    } release{ticket};
+    ticket.hold(&pool, residency_slots(gmax, kXcds));
+    for (auto& it : items) {
+        launch_fill(reinterpret_cast<float*>(it.W->iters), 2, 0.0f, st);
+        launch_fill(reinterpret_cast<float*>(it.W->bar) + 1, 1, 0.0f, st);  // abort word
+    }
+    unsigned char* db = static_cast<unsigned char*>(P0.multi_dev);
+    for (const Launch& l : launches) {
+        const int sa = l.round * kHB;
+        for (int i = cstart[l.chunk]; i < cstart[l.chunk + 1]; ++i) {
+            MultiItem<T>& it = items[i];
+            if (sa > it.s_last) continue;
+            Problem& P = *it.P;
+            const int cnt = std::min(kHB, P.M - sa);
+            if (cnt > 0) {
+                hipLaunchKernelGGL(far_history<T>, dim3((unsigned)((P.Nd + 63) / 64)), dim3(256), 0, st, it.a.y,
+                                   it.a.hacc, it.a.epad, it.a.z, it.a.g1, it.a.g2, sa, cnt, P.Nd, (const T*)nullptr);
+                TSFDE_HIP(hipGetLastError());
+            }
+            launch_fill(reinterpret_cast<float*>(it.W->bar), 1, 0.0f, st);  // barrier counter
+        }
+        hipLaunchKernelGGL((pinv_segment_multi<T, VPT, MODE>), dim3(l.grid), dim3(block), lds, st,
+                           reinterpret_cast<const PinvArgs<T>*>(db + l.o_args), reinterpret_cast<const int*>(db + l.o_off),
+                           reinterpret_cast<const int2*>(db + l.o_range), l.k);
+        TSFDE_HIP(hipGetLastError());
+    }
+    // iteration counts and abort words, then the host sees the last round finish
+    for (int i = 0; i < n; ++i) {
+        long long* ith = reinterpret_cast<long long*>(items[i].P->host_scalars + 56);
+        unsigned* abh = reinterpret_cast<unsigned*>(items[i].P->host_scalars + 57);
+        TSFDE_HIP(hipMemcpyAsync(ith, items[i].W->iters, sizeof(long long), hipMemcpyDeviceToHost, st));
+        TSFDE_HIP(hipMemcpyAsync(abh, items[i].W->bar + 1, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    }
+    TSFDE_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i)
+        if (*reinterpret_cast<unsigned*>(items[i].P->host_scalars + 57) != 0u)
+            throw HipError{hipErrorLaunchTimeOut, "multi P^-1: a device-wide barrier wait timed out"};
 }
 
 // launches of the fixed-length 2D sine-transform kernels (CG blocks: pinv_fixed.hip; tau blocks:

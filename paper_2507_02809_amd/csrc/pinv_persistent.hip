@@ -2,6 +2,7 @@
 // transform length is a run-time value (the device code is in pinv_kernel.hpp).
 #include <atomic>
 #include <cstdlib>
+#include <map>
 #include <mutex>
 #include <type_traits>
 
@@ -140,6 +141,57 @@ long long pinv_adjoint_run(Problem& P, const double* zrev, const double* dgrev, 
     P.sweep_sigma = sigrev;
     set_persistent_blocks(-1);
     return run_segments<double>(P, D, W, zrev, urev, inner_tol, inner_maxit, false, extrap, 0, st);
+}
+
+void pinv_multi_run(std::vector<PinvMultiJob>& jobs, double inner_tol, int inner_maxit, int extrap, hipStream_t st) {
+    // groups of one kernel form: (values per thread, mode, 1D transform length)
+    struct Key {
+        int vpt, mode, L;
+        bool operator<(const Key& o) const {
+            return vpt != o.vpt ? vpt < o.vpt : (mode != o.mode ? mode < o.mode : L < o.L);
+        }
+    };
+    std::map<Key, std::vector<int>> groups;
+    for (int i = 0; i < (int)jobs.size(); ++i) {
+        Problem& P = *jobs[i].P;
+        if (!persistent_supported(P)) throw HipError{hipErrorNotSupported, "multi P^-1: a problem without the persistent form"};
+        const int L = P.L;
+        const int vpt = (L <= 2048) ? 8 : (L == 4096 ? 16 : 32);
+        const int mode = (P.d == 1) ? SEG_1D : ((P.tau_ok || P.tau_pad) ? SEG_2D_TAU : SEG_2D_DIAG);
+        groups[Key{vpt, mode, P.d == 1 ? L : 0}].push_back(i);
+    }
+    for (auto& kv : groups) {
+        std::vector<MultiItem<double>> items;
+        for (int i : kv.second) {
+            Problem& P = *jobs[i].P;
+            if (!P.pw64) P.pw64 = new PersistentWork<double>();
+            PersistentWork<double>& W = *static_cast<PersistentWork<double>*>(P.pw64);
+            ensure_work(P, W);
+            MultiItem<double> it{};
+            it.P = &P;
+            it.W = &W;
+            it.a = make_pinv_args<double>(P, P.f64, W, jobs[i].z, jobs[i].y, inner_tol, inner_maxit, extrap);
+            items.push_back(it);
+        }
+        const Key& k = kv.first;
+#define TSFDE_MULTI(V, MD) launch_segments_multi<double, V, MD>(items, st)
+        if (k.vpt == 8) {
+            if (k.mode == SEG_1D) TSFDE_MULTI(8, SEG_1D);
+            else if (k.mode == SEG_2D_TAU) TSFDE_MULTI(8, SEG_2D_TAU);
+            else TSFDE_MULTI(8, SEG_2D_DIAG);
+        } else if (k.vpt == 16) {
+            if (k.mode == SEG_1D) TSFDE_MULTI(16, SEG_1D);
+            else if (k.mode == SEG_2D_TAU) TSFDE_MULTI(16, SEG_2D_TAU);
+            else TSFDE_MULTI(16, SEG_2D_DIAG);
+        } else {
+            if (k.mode == SEG_1D) TSFDE_MULTI(32, SEG_1D);
+            else if (k.mode == SEG_2D_TAU) TSFDE_MULTI(32, SEG_2D_TAU);
+            else TSFDE_MULTI(32, SEG_2D_DIAG);
+        }
+#undef TSFDE_MULTI
+        for (size_t j = 0; j < kv.second.size(); ++j)
+            jobs[kv.second[j]].iters = *reinterpret_cast<long long*>(items[j].P->host_scalars + 56);
+    }
 }
 
 template <typename T>

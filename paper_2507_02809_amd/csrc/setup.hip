@@ -364,6 +364,8 @@ void free_problem(Problem* P) {
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (P->host_scalars) (void)hipHostFree(P->host_scalars);
+    if (P->multi_dev) (void)hipFree(P->multi_dev);
+    if (P->multi_host) (void)hipHostFree(P->multi_host);
     if (P->cyc_exec) (void)hipGraphExecDestroy(P->cyc_exec);
     if (P->cyc_stream) (void)hipStreamDestroy(P->cyc_stream);
     if (P->cyc_h) (void)hipFree(P->cyc_h);

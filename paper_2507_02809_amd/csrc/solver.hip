@@ -1246,6 +1246,163 @@ static tsfde_status vjp_impl(Problem& P, const double* y, const double* gf, doub
     return rc;
 }
 
+// Several problems solved in lockstep with their P^{-1} applications in shared persistent launches
+// (pinv_multi_run): each Arnoldi step applies P^{-1} to the current basis vector of every unfinished
+// problem in one set of launches (one launch per round of kHB time steps and kernel form), then runs
+// each problem's matvec and Gram-Schmidt on the stream and its Givens rotations on the host.  FGMRES
+// is the single-problem one otherwise: restart cycles per problem, the true residual at every
+// (re)start, x0 = 0, f~ = the last block.  FP64, CG blocks, directions kept.
+static tsfde_status recover_multi_impl(const std::vector<Problem*>& probs, double* const* f_out, const Opts& o,
+                                       tsfde_stats* stats, hipStream_t st) {
+    struct Slot {
+        Problem* P = nullptr;
+        tsfde_stats S{};
+        bool done = false, conv = false;
+        int its = 0, j = 0, maxit = 0;
+        double bnorm = 0.0, t0 = 0.0;
+        std::vector<double> Hc, cs, sn, g, yk, hh;
+    };
+    const int m = o.restart, hs = m + 2;
+    const int nblk = kArnBlocks;
+    const int extrap = env_int("TSFDE_EXTRAP", o.warm_start);
+    std::vector<Slot> sl(probs.size());
+    auto vec = [](Problem& P, int k) { return P.V + (size_t)k * P.ntot; };
+    // r = b - A x and the true relative residual; a new cycle from it unless converged or out of steps
+    auto start_cycle = [&](Slot& q) {
+        Problem& P = *q.P;
+        const long long n = P.ntot;
+        const double t0 = now();
+        apply_A_impl<double>(P, P.xbuf, P.rwork, st);
+        launch_axpby(1.0, P.z_rhs, -1.0, P.rwork, P.rwork, n, st);
+        const double beta = std::sqrt(dev_dot(P, P.rwork, P.rwork, n, st));
+        q.S.t_matvec += now() - t0;
+        const double rel = q.bnorm > 0.0 ? beta / q.bnorm : 0.0;
+        P.res_hist.push_back(rel);
+        q.S.rel_res = rel;
+        if (rel <= o.tol) { q.done = true; q.conv = true; return; }
+        if (q.its >= q.maxit || !(beta > 0.0)) { q.done = true; return; }
+        launch_axpby(1.0 / beta, P.rwork, 0.0, P.rwork, P.V, n, st);
+        std::fill(q.g.begin(), q.g.end(), 0.0);
+        q.g[0] = beta;
+        q.j = 0;
+    };
+    for (size_t i = 0; i < probs.size(); ++i) {
+        Slot& q = sl[i];
+        q.P = probs[i];
+        Problem& P = *q.P;
+        const long long n = P.ntot;
+        q.t0 = now();
+        q.maxit = o.maxit > 0 ? o.maxit : (int)std::min<long long>(n, 1000);
+        P.res_hist.clear();
+        if (ensure_basis(P, m, o)) throw CapError{"multi solve: the directions z_j do not fit (recomputing them is not offered here)"};
+        if (!P.arn_part) dev_alloc(P, P.arn_part, kArnBlocks * kArnMaxK);
+        if (!P.arn_h) dev_alloc(P, P.arn_h, (2 * (kMaxRestart + 2) + 1));
+        if (!P.xbuf) dev_alloc(P, P.xbuf, n);
+        if (!P.rwork) dev_alloc(P, P.rwork, n);
+        q.Hc.assign((size_t)(m + 1) * m, 0.0);
+        q.cs.assign(m, 0.0);
+        q.sn.assign(m, 0.0);
+        q.g.assign(m + 1, 0.0);
+        q.yk.assign(m, 0.0);
+        q.hh.assign(2 * hs + 1, 0.0);
+        launch_fill(P.xbuf, n, 0.0, st);
+        launch_build_z(P, P.z_rhs, st);
+        q.bnorm = std::sqrt(dev_dot(P, P.z_rhs, P.z_rhs, n, st));
+        if (!(q.bnorm > 0.0)) { q.done = true; q.conv = true; q.S.rel_res = 0.0; continue; }
+        start_cycle(q);
+    }
+    std::vector<PinvMultiJob> jobs;
+    std::vector<int> who;
+    while (true) {
+        jobs.clear();
+        who.clear();
+        for (size_t i = 0; i < sl.size(); ++i)
+            if (!sl[i].done) {
+                Problem& P = *sl[i].P;
+                jobs.push_back(PinvMultiJob{&P, vec(P, sl[i].j), P.Z + (size_t)sl[i].j * P.ntot, 0});
+                who.push_back((int)i);
+            }
+        if (jobs.empty()) break;
+        double t0 = now();
+        if (o.use_precond) {
+            pinv_multi_run(jobs, o.inner_tol, o.inner_maxit, extrap, st);  // synchronises st
+        } else {
+            for (auto& jb : jobs) launch_copy<double>(jb.z, jb.y, jb.P->ntot, st);
+        }
+        const double tp = now() - t0;
+        t0 = now();
+        for (size_t k = 0; k < who.size(); ++k) {
+            Slot& q = sl[who[k]];
+            Problem& P = *q.P;
+            q.S.t_precond += tp;
+            q.S.inner_iters += jobs[k].iters;
+            double* w = vec(P, q.j + 1);
+            apply_A_impl<double>(P, P.Z + (size_t)q.j * P.ntot, w, st);
+            cgs2(P.V, P.ntot, q.j + 1, w, P.arn_part, nblk, P.arn_h, P.arn_h + hs, P.arn_h + 2 * hs, st);
+            TSFDE_HIP(hipMemcpyAsync(q.hh.data(), P.arn_h, sizeof(double) * (2 * hs + 1), hipMemcpyDeviceToHost, st));
+        }
+        TSFDE_HIP(hipStreamSynchronize(st));
+        const double tm = now() - t0;
+        for (int i : who) {
+            Slot& q = sl[i];
+            Problem& P = *q.P;
+            q.S.t_ortho += tm / (double)who.size();
+            const int j = q.j;
+            const double hn = std::sqrt(std::max(0.0, q.hh[2 * hs]));
+            for (int r = 0; r <= j; ++r) q.Hc[(size_t)r * m + j] = q.hh[r] + q.hh[hs + r];
+            q.Hc[(size_t)(j + 1) * m + j] = hn;
+            for (int r = 0; r < j; ++r) {
+                const double a = q.Hc[(size_t)r * m + j], bq = q.Hc[(size_t)(r + 1) * m + j];
+                q.Hc[(size_t)r * m + j] = q.cs[r] * a + q.sn[r] * bq;
+                q.Hc[(size_t)(r + 1) * m + j] = -q.sn[r] * a + q.cs[r] * bq;
+            }
+            const double a = q.Hc[(size_t)j * m + j], bq = q.Hc[(size_t)(j + 1) * m + j];
+            const double rr = std::hypot(a, bq);
+            q.cs[j] = rr > 0.0 ? a / rr : 1.0;
+            q.sn[j] = rr > 0.0 ? bq / rr : 0.0;
+            q.Hc[(size_t)j * m + j] = rr;
+            q.Hc[(size_t)(j + 1) * m + j] = 0.0;
+            q.g[j + 1] = -q.sn[j] * q.g[j];
+            q.g[j] = q.cs[j] * q.g[j];
+            ++q.its;
+            ++q.S.iters;
+            P.res_hist.push_back(std::fabs(q.g[j + 1]) / q.bnorm);
+            const bool end = std::fabs(q.g[j + 1]) <= o.tol * q.bnorm || j + 1 == m || q.its >= q.maxit || hn == 0.0;
+            if (!end) {
+                launch_axpby(1.0 / hn, vec(P, j + 1), 0.0, vec(P, j + 1), vec(P, j + 1), P.ntot, st);
+                q.j = j + 1;
+                continue;
+            }
+            const int k = j + 1;
+            for (int r = k - 1; r >= 0; --r) {
+                double acc = q.g[r];
+                for (int l = r + 1; l < k; ++l) acc -= q.Hc[(size_t)r * m + l] * q.yk[l];
+                q.yk[r] = q.Hc[(size_t)r * m + r] != 0.0 ? acc / q.Hc[(size_t)r * m + r] : 0.0;
+            }
+            TSFDE_HIP(hipMemcpyAsync(P.arn_h, q.yk.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+            launch_gemv_add(P.Z, P.ntot, k, P.arn_h, P.xbuf, st);
+            TSFDE_HIP(hipStreamSynchronize(st));
+            ++q.S.restarts;
+            start_cycle(q);
+        }
+    }
+    tsfde_status rc = TSFDE_OK;
+    for (size_t i = 0; i < sl.size(); ++i) {
+        Slot& q = sl[i];
+        Problem& P = *q.P;
+        launch_copy<double>(P.xbuf + (size_t)P.M * P.Nd, f_out[i], P.Nd, st);
+        q.S.converged = q.conv ? 1 : 0;
+        q.S.refinements = 1;
+        q.S.t_total = now() - q.t0;
+        q.S.history_len = (int)P.res_hist.size();
+        q.S.history = P.res_hist.data();
+        if (stats) stats[i] = q.S;
+        if (!q.conv && rc == TSFDE_OK) rc = TSFDE_ENOCONV;
+    }
+    TSFDE_HIP(hipStreamSynchronize(st));
+    return rc;
+}
+
 // Runs fn(i, problem i, its stats, a stream) for every problem of a batch, up to max_inflight at once,
 // each worker thread on a non-blocking stream of its own, largest problems first; the persistent
 // grids of the workers are limited so that that many fit together, and every persistent grid of the
@@ -1782,6 +1939,37 @@ tsfde_status tsfde_autotune(tsfde_problem* prob, tsfde_opts* opts, int what, tsf
     TSFDE_GUARD("autotune", body();)
     if (out) *out = T;
     return TSFDE_OK;
+}
+
+tsfde_status tsfde_recover_f_multi(tsfde_problem* const* probs, int count, double* const* f_out,
+                                   const tsfde_opts* opts, tsfde_stats* stats, void* stream) {
+    if (count < 0 || (count > 0 && (!probs || !f_out))) {
+        set_error("recover_f_multi: count < 0 or NULL arrays");
+        return TSFDE_EINVAL;
+    }
+    const Opts o = get_opts(opts);
+    if (opts && !check_opts(o)) return TSFDE_EINVAL;
+    if (o.precision != TSFDE_FP64 || o.block_solver != TSFDE_BLOCK_CG || o.recompute_z) {
+        set_error("recover_f_multi: FP64, CG blocks and kept directions only");
+        return TSFDE_ENOTIMPL;
+    }
+    std::vector<Problem*> ps;
+    for (int i = 0; i < count; ++i) {
+        if (!probs[i] || !f_out[i]) { set_error("recover_f_multi: NULL problem or output %d", i); return TSFDE_EINVAL; }
+        for (int k = 0; k < i; ++k)
+            if (probs[k] == probs[i]) { set_error("recover_f_multi: problem %d repeated", i); return TSFDE_EINVAL; }
+        Problem& P = *probs[i]->p;
+        if (o.use_precond && !(persistent_supported(P) && env_int("TSFDE_PINV", 1) != 0)) {
+            set_error("recover_f_multi: problem %d has no persistent P^-1", i);
+            return TSFDE_ENOTIMPL;
+        }
+        ps.push_back(&P);
+    }
+    if (count == 0) return TSFDE_OK;
+    tsfde_status rc = TSFDE_OK;
+    TSFDE_GUARD("recover_f_multi", rc = recover_multi_impl(ps, f_out, o, stats, (hipStream_t)stream);)
+    if (rc == TSFDE_ENOCONV) set_error("recover_f_multi: a problem missed the tolerance (see its stats)");
+    return rc;
 }
 
 tsfde_status tsfde_forward_solve(tsfde_problem* prob, const double* f, double* v, const tsfde_opts* opts,

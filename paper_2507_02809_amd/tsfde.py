@@ -26,7 +26,7 @@ EXPORTED = [
     "tsfde_forward_solve", "tsfde_apply_AT", "tsfde_apply_PT_inv", "tsfde_adjoint_solve",
     "tsfde_recover_f_vjp", "tsfde_recover_f_vjp_batch", "tsfde_arnoldi", "tsfde_ritz_values",
     "tsfde_singular_value_estimates", "tsfde_discrepancy", "tsfde_gmres_solve_block", "tsfde_recover_f_block",
-    "tsfde_autotune", "tsfde_last_error",
+    "tsfde_autotune", "tsfde_recover_f_multi", "tsfde_last_error",
 ]
 
 
@@ -123,6 +123,7 @@ def lib():
     L.tsfde_gmres_solve_block.argtypes = [vp, i, vp, vp, dp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_recover_f_block.argtypes = [vp, i, vp, vp, dp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_autotune.argtypes = [vp, C.POINTER(Opts), i, C.POINTER(Tuning), vp]
+    L.tsfde_recover_f_multi.argtypes = [pp, i, pp, C.POINTER(Opts), C.POINTER(Stats), vp]
     L.tsfde_last_error.argtypes = []
     L.tsfde_last_error.restype = C.c_char_p
     for name in EXPORTED:
@@ -439,6 +440,20 @@ def recover_f_batch(problems, opts: Optional[Opts] = None, max_inflight: int = 2
     st = (Stats * max(n, 1))()
     rc = lib().tsfde_recover_f_batch(hs, n, fp, C.byref(opts) if opts is not None else None, st, max_inflight,
                                      _stream(stream))
+    _check(rc, allow=() if raise_noconv else (ENOCONV,))
+    return [(fs[i], st[i]) for i in range(n)]
+
+
+def recover_f_multi(problems, opts: Optional[Opts] = None, stream=None, raise_noconv=False):
+    """tsfde_recover_f_multi: f~ of every problem, solved in lockstep with shared P^{-1} launches.
+    Returns a list of (f, stats)."""
+    import torch
+    n = len(problems)
+    fs = [torch.empty(p.Nd, dtype=torch.float64, device="cuda") for p in problems]
+    hs = (C.c_void_p * max(n, 1))(*[p._h.value for p in problems])
+    fp = (C.c_void_p * max(n, 1))(*[f.data_ptr() for f in fs])
+    st = (Stats * max(n, 1))()
+    rc = lib().tsfde_recover_f_multi(hs, n, fp, C.byref(opts) if opts is not None else None, st, _stream(stream))
     _check(rc, allow=() if raise_noconv else (ENOCONV,))
     return [(fs[i], st[i]) for i in range(n)]
 
