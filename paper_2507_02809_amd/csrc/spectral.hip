@@ -325,9 +325,13 @@ void launch_toeplitz_matvec(const Problem& P, const Dev<T>& D, const T* y, T* z,
     const size_t lds = sizeof(cplx<T>) * lds_len(L);
     const int nslices = P.M + 1;
     if (P.d == 1) {
+        // one transform per workgroup: as many threads as a workgroup takes (up to 1024), so that a long
+        // transform (L = 8192 at N = 4095) has 16 waves to hide its LDS and twiddle latencies rather than 4
+        const int vpt1 = std::max(8, L / 1024);
+        const int nthr1 = L / vpt1;
         const int npairs = (nslices + 1) / 2;
-        TSFDE_VPT_DISPATCH(vpt, hipLaunchKernelGGL((toep1d<T, VPT>), dim3(npairs), dim3(nthr), lds, s, y, nslices,
-                                                   P.N, L, D.tw, D.sym, 0, ea, (int)EPI_MATVEC));
+        TSFDE_VPT_DISPATCH(vpt1, hipLaunchKernelGGL((toep1d<T, VPT>), dim3(npairs), dim3(nthr1), lds, s, y, nslices,
+                                                    P.N, L, D.tw, D.sym, 0, ea, (int)EPI_MATVEC));
         TSFDE_HIP(hipGetLastError());
         return;
     }
