@@ -128,7 +128,20 @@ def cpu_baseline(inp, mu_eps, outer_iters: int, restarts: int, inner_tol: float)
                        f"{outer_iters} outer iterations x ({p.S + 1} steps + 1 matvec); SciPy FFTs on {threads} threads, "
                        f"{cpu_model()}"),
             "est_seconds_per_solve": t_solve, "matvec_s": t_mv, "matvec_GB_s": 8 * (2 * p.n_tot + 2 * p.S * p.Nd) / t_mv / 1e9,
-            "cpu_model": cpu_model()}
+            "cpu_model": cpu_model(), "full_oracle_solve": full_oracle_solve()}
+
+
+def full_oracle_solve():
+    """The oracle's complete solves of the same workload, as timed when the certified reference was
+    made (tests/golden/make_c3_reference.py, on the build host's 8 cores, not on this host): route R3,
+    FGMRES with the exact T_{n,S} solve, and route R4, the Schur complement in f."""
+    path = os.path.join(ROOT, "tests", "golden", "c3_reference.npz")
+    if not os.path.exists(path):
+        return None
+    with np.load(path) as d:
+        return {"r3_fgmres_seconds": float(d["r3_seconds"]), "r3_iterations": int(d["r3_iterations"]),
+                "r3_true_rel_residual": float(d["r3_residual"]), "r4_schur_seconds": float(d["r4_seconds"]),
+                "r4_iterations": int(d["r4_iterations"]), "host": "build host, 8 cores"}
 
 
 def c3_reference():
