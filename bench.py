@@ -133,7 +133,7 @@ def cpu_baseline(inp, mu_eps, outer_iters: int, restarts: int, inner_tol: float)
 
 def full_oracle_solve():
     """The oracle's complete solves of the same workload, as timed when the certified reference was
-    made (tests/golden/make_c3_reference.py, on the build host's 8 cores, not on this host): route R3,
+    made by tests/golden/make_c3_reference.py (on an 8-core host, not necessarily this one): route R3,
     FGMRES with the exact T_{n,S} solve, and route R4, the Schur complement in f."""
     path = os.path.join(ROOT, "tests", "golden", "c3_reference.npz")
     if not os.path.exists(path):
@@ -141,7 +141,7 @@ def full_oracle_solve():
     with np.load(path) as d:
         return {"r3_fgmres_seconds": float(d["r3_seconds"]), "r3_iterations": int(d["r3_iterations"]),
                 "r3_true_rel_residual": float(d["r3_residual"]), "r4_schur_seconds": float(d["r4_seconds"]),
-                "r4_iterations": int(d["r4_iterations"]), "host": "build host, 8 cores"}
+                "r4_iterations": int(d["r4_iterations"]), "host_cores": 8}
 
 
 def c3_reference():
