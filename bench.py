@@ -184,14 +184,24 @@ def matvec_timing(a, prob, inp, y, y32) -> dict:
             prob.apply_A(yy, zz, stream=stream)
         ev1.record(stream)
         torch.cuda.synchronize()
-        return ev0.elapsed_time(ev1) / a.matvec_reps  # ms
+        mean = ev0.elapsed_time(ev1) / a.matvec_reps  # ms, back-to-back calls
+        # per call (an event pair around each): median, p10, p90
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.matvec_reps)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            prob.apply_A(yy, zz, stream=stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        per = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+        return mean, float(np.median(per)), float(np.percentile(per, 10)), float(np.percentile(per, 90))
 
-    mv64 = time_mv(y, torch.empty_like(y))
-    mv32 = time_mv(y32, torch.empty_like(y32))
+    mv64, med64, p10_64, p90_64 = time_mv(y, torch.empty_like(y))
+    mv32, med32, _, _ = time_mv(y32, torch.empty_like(y32))
     n = prob.n_tot
     bytes64 = 8 * (2 * n + 2 * inp.M * inp.Nd)
     return {"fp64_ms": mv64, "fp64_GB_s": bytes64 / (mv64 * 1e-3) / 1e9, "fp32_ms": mv32,
-            "fp32_GB_s": (bytes64 / 2) / (mv32 * 1e-3) / 1e9, "algorithmic_bytes_fp64": bytes64}
+            "fp32_GB_s": (bytes64 / 2) / (mv32 * 1e-3) / 1e9, "algorithmic_bytes_fp64": bytes64,
+            "fp64_ms_median_p10_p90": [med64, p10_64, p90_64], "fp32_ms_median": med32}
 
 
 def c2_lines(a) -> dict:
@@ -620,7 +630,9 @@ def main():
         # one gradient pass: recover_f then the adjoint solve for d||f~ - f_true||^2 / d(mu, alpha)
         "gradients": gradients,
         "matvec": {"fp64_ms": mv64, "fp64_GB_s": gbs64, "fp32_ms": mv32, "fp32_GB_s": gbs32,
-                   "algorithmic_bytes_fp64": bytes64},
+                   "algorithmic_bytes_fp64": bytes64, "fp64_ms_median_p10_p90": mvr["fp64_ms_median_p10_p90"],
+                   # the counted HBM bytes (roofline.traffic) over the same time, against 8 TB/s
+                   "counted_traffic_frac": APPLY_A_TRAFFIC_FP64 / (mv64 * 1e-3) / 1e9 / HBM_PEAK_GBS},
         # traffic: HBM bytes of one FP64 apply_A from the FETCH_SIZE / WRITE_SIZE counter runs, scaled by
         # a copy of known size (profiles/c3_apply_A_hbm_counters.md); to be re-measured when the kernels change
         # P^-1 (pinv_segment) takes most of the solve time but is a dependent chain of small phases
