@@ -83,3 +83,31 @@ def test_multi_argument_errors():
     finally:
         a.close()
         b.close()
+
+
+def test_c4_instances_match_oracle_solutions():
+    """Two instances of the 64-problem mixed batch (its smallest: d = 1, N = 285, M = 80, alpha = 2.3e-5;
+    N = 131, M = 281), mu from the oracle's direct solve, solved together by the stream batch and by
+    the shared-launch form: f~ against the oracle's own FGMRES solution (T_{n,S}-preconditioned, to a
+    true relative residual of 1e-12)."""
+    from oracle import krylov, matfree
+    ks = (34, 36)
+    probs, refs = [], []
+    try:
+        for k in ks:
+            inp = inputs.c4(k)
+            p = workloads.with_data(inp)
+            sym = matfree.circulant_symbol(p)
+            x, _, _ = krylov.fgmres(lambda v: matfree.matvec(p, v, sym), lambda v: matfree.T_solve(p, v),
+                                    system.rhs_z(p), 1e-12, restart=100, maxit=400)
+            refs.append(x[p.S * p.Nd:])
+            probs.append(tsfde.Problem.from_inputs(inp, mu=p.mu, stencil=p.a()))
+        opts = tsfde.default_opts(tol=1e-11, inner_tol=1e-3, maxit=500, restart=100)
+        for outs in (tsfde.recover_f_batch(probs, opts, max_inflight=2, raise_noconv=True),
+                     tsfde.recover_f_multi(probs, opts, raise_noconv=True)):
+            for (f, st), ref in zip(outs, refs):
+                assert st.converged == 1
+                assert rel_err(f.cpu().numpy(), ref) <= 1e-8
+    finally:
+        for g in probs:
+            g.close()
