@@ -281,6 +281,7 @@ void launch_coupling(const Problem& P, const double* v, double* out, bool transp
 // uniform values in [-1, 1) from a hash of (seed, index)
 void launch_hash_fill(double* x, long long n, unsigned long long seed, hipStream_t s);
 void launch_fill(float* p, long long n, float v, hipStream_t s);
+void launch_fill(unsigned long long* p, long long n, unsigned long long v, hipStream_t s);
 template <typename T>
 void launch_sub_partials(const T* a, const T* b, T* out, long long n, T* partials, int* nparts, hipStream_t s);
 template <typename T>

@@ -372,6 +372,10 @@ void launch_fill(float* p, long long n, float v, hipStream_t s) {
     hipLaunchKernelGGL(fill_k<float>, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, p, n, v);
     TSFDE_HIP(hipGetLastError());
 }
+void launch_fill(unsigned long long* p, long long n, unsigned long long v, hipStream_t s) {
+    hipLaunchKernelGGL(fill_k<unsigned long long>, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, p, n, v);
+    TSFDE_HIP(hipGetLastError());
+}
 
 // ---------------------------------------------------------------------------
 // Arnoldi helpers (FP64): classical Gram-Schmidt with one reorthogonalisation over the basis

@@ -78,8 +78,8 @@ struct PinvArgs {
     T *x, *r, *zz, *p, *q, *t1, *t2, *rhs, *bxb, *bxb2;  // bxb, bxb2: B y_{s-2}, B y_{s-3} (warm start)
     T* hacc;           // [kHB][Nd]: w_s of the segment's steps (far history folded into the rhs)
     cplx<T>* spec;     // [H][ns]
-    double* part;      // [G][kNPart]
-    unsigned* bar;     // [0] barrier counter, zero at launch; [1] abort word (see grid_barrier)
+    double* part;      // [kRing][kMaxGrid][kNPart] reduction slots (phase_sync)
+    unsigned* bar;     // [1] abort word (see grid_barrier_n)
     unsigned long long bar_ticks;  // longest barrier wait, in wall-clock periods
     long long* iters;  // accumulated CG iterations
     int vb, vg;        // this workgroup's index in the problem's grid and that grid's size
@@ -87,82 +87,163 @@ struct PinvArgs {
 
 // (A problem's workgroups are numbered vb = 0 .. vg - 1 within its grid: the whole launch, or its share
 // of a launch that runs several problems side by side.)
-// Block-reduce K values at once into this block's slots: the shuffle trees of the K values are
-// interleaved so that their exchanges overlap.  red holds kSegBlock/64 * K doubles.  The order of
-// the additions is fixed (shuffle tree per wave, then the waves in order), so every block reduces
-// its values the same way on every run.
-template <int K, typename T>
-__device__ __forceinline__ void put_partials(double* part, const int (&slot)[K], const T (&val)[K], double* red, int vb) {
+
+// ---------------------------------------------------------------------------
+// Phase synchronisation of the segment kernel: the device-wide barrier and the reduction of the
+// phase's partial sums in one exchange.
+//
+// part holds kRing rings of [kMaxGrid][kNPart] slots; phase ph uses ring ph % kRing.  A slot is
+// empty (the bit pattern kEmpty) until its workgroup publishes the phase's value there, so a
+// workgroup has arrived at the barrier of phase ph once its slots of that phase are filled, and the
+// waiting workgroups read the values they reduce in the same loads that tell them so (no arrival
+// counter, no second round trip for the partial sums).  When it publishes phase ph, a workgroup
+// first empties its slots of ring ph + 1; a release fence orders that, and every store of the phase,
+// before the published values.  Ring ph + 1 was last read in phase ph - 3 (by a gather of that phase
+// or of the next one), and every workgroup has finished those reads before publishing phase ph - 1,
+// which the publishing workgroup has seen.  The launch starts at phase 0 with ring 0 emptied by the
+// host.  kEmpty is a NaN payload that arithmetic does not produce (an operation on finite values
+// that yields NaN gives the default NaN); a slot holding it by accident would end in the bounded
+// wait's time-out, not in a wrong sum.
+//
+// The wait is bounded as in grid_barrier_n (bar[1] is the abort word).  The additions are in a fixed
+// order (a shuffle tree per wave, the waves in order; then lane b of one wave adds workgroups b,
+// b + 64, ... and a shuffle tree adds the lanes), the same in every workgroup, so every workgroup
+// takes the same branches and results do not change with timing.
+// ---------------------------------------------------------------------------
+constexpr int kRing = 4;
+constexpr int kMaxGrid = 256;  // workgroups of one problem's grid at most (the ring stride)
+constexpr unsigned long long kEmpty = 0x7FF4DEAD7FF4DEADull;
+
+__device__ __forceinline__ unsigned long long* ring_slot(double* part, unsigned ph, int b, int k) {
+    return reinterpret_cast<unsigned long long*>(part + ((size_t)(ph % kRing) * kMaxGrid + b) * kNPart + k);
+}
+
+// Publish the K values (slots slot[k]) of this workgroup for phase ph, wait until all G workgroups
+// have published theirs, and (GATH) leave the totals in tot[] for all threads; PREV >= 0 also
+// gathers that slot from phase ph - 1 (published there without a gather).  VALS = false: a barrier
+// only (the value published marks the arrival; tot is left alone).  Advances ph.
+template <int K, bool GATH, int PREV, typename T, bool VALS = true>
+__device__ __forceinline__ void phase_sync(double* part, unsigned* bar, unsigned long long ticks, const int (&slot)[K],
+                                           const T (&val)[K], double* red, double* tot, unsigned& ph, int vb, int G) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
-    const int nact = min(kWave, (int)blockDim.x - wid * kWave);  // active lanes of this wave
-    double v[K];
+    {
+        const int nact = min(kWave, (int)blockDim.x - wid * kWave);
+        double v[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = (double)val[k];
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        double o[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) o[k] = __shfl_down(v[k], off, kWave);
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (lane + off < nact) v[k] += o[k];
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) red[wid * K + k] = v[k];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nw = (blockDim.x + kWave - 1) / kWave;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double r = 0.0;
-            for (int w = 0; w < nw; ++w) r += red[w * K + k];
-            part[vb * kNPart + slot[k]] = r;
-        }
-    }
-    __syncthreads();
-}
-
-template <typename T>
-__device__ __forceinline__ void put_partial(double* part, int slot, T v, double* red, int vb) {
-    const int sl[1] = {slot};
-    const T vv[1] = {v};
-    put_partials<1>(part, sl, vv, red, vb);
-}
-
-// After a barrier: wave 0 loads every block's slots (lane b reads block b), reduces the slots in
-// MASK with the same shuffle tree in every block (the trees of the slots interleaved) and leaves
-// the totals in tot[] (LDS) for all threads.
-template <unsigned MASK = (1u << kNPart) - 1>
-__device__ __forceinline__ void gather_totals(const double* part, double* tot, int G) {
-    if (threadIdx.x < kWave) {
-        const int lane = threadIdx.x;
-        const int nact = min(kWave, (int)blockDim.x);
-        double v[kNPart];
-#pragma unroll
-        for (int k = 0; k < kNPart; ++k) v[k] = 0.0;
-        for (int b = lane; b < G; b += kWave) {
-#pragma unroll
-            for (int k = 0; k < kNPart; ++k)
-                if (MASK & (1u << k)) v[k] += part[b * kNPart + k];
-        }
+        for (int k = 0; k < K; ++k) v[k] = (double)val[k];
         for (int off = kWave / 2; off > 0; off >>= 1) {
-            double o[kNPart];
+            double o[K];
 #pragma unroll
-            for (int k = 0; k < kNPart; ++k)
-                if (MASK & (1u << k)) o[k] = __shfl_down(v[k], off, kWave);
+            for (int k = 0; k < K; ++k) o[k] = __shfl_down(v[k], off, kWave);
 #pragma unroll
-            for (int k = 0; k < kNPart; ++k)
-                if ((MASK & (1u << k)) && lane + off < nact) v[k] += o[k];
+            for (int k = 0; k < K; ++k)
+                if (lane + off < nact) v[k] += o[k];
         }
         if (lane == 0) {
 #pragma unroll
+            for (int k = 0; k < K; ++k) red[wid * K + k] = v[k];
+        }
+    }
+    __syncthreads();  // red complete; every thread's stores of this phase issued before the release below
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + kWave - 1) / kWave;
+        double r[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            r[k] = 0.0;
+            for (int w = 0; w < nw; ++w) r[k] += red[w * K + k];
+        }
+        if (G <= 1) {
+            // the only workgroup: its sums are the totals (a slot published without a gather is
+            // kept in tot for the next phase's)
+            if constexpr (VALS) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) tot[slot[k]] = r[k];
+            }
+        } else {
+#pragma unroll
             for (int k = 0; k < kNPart; ++k)
-                if (MASK & (1u << k)) tot[k] = v[k];
+                __hip_atomic_store(ring_slot(part, ph + 1, vb, k), kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                __hip_atomic_store(ring_slot(part, ph, vb, slot[k]), (unsigned long long)__double_as_longlong(r[k]),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    if (G > 1 && wid == 0) {
+        // lane l waits for workgroups l, l + 64, ...; the loads of a poll are in flight together
+        constexpr int NB = kMaxGrid / kWave;
+        unsigned long long got[NB][K], prv[NB];
+        const unsigned long long t0 = (unsigned long long)wall_clock64();
+        while (true) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const int b = lane + i * kWave;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    got[i][k] = (b < G) ? __hip_atomic_load(ring_slot(part, ph, b, slot[k]), __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT)
+                                        : 0ull;
+                if constexpr (PREV >= 0)
+                    prv[i] = (b < G) ? __hip_atomic_load(ring_slot(part, ph - 1, b, PREV), __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)
+                                     : 0ull;
+            }
+            const unsigned ab = __hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            bool ready = true;
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int k = 0; k < K; ++k) ready = ready && got[i][k] != kEmpty;
+            if (__all(ready)) break;
+            if (ab != 0u) break;  // an earlier wait timed out: finish without waiting
+            if ((unsigned long long)wall_clock64() - t0 > ticks) {
+                if (lane == 0) __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if constexpr (GATH) {
+            constexpr int KG = K + (PREV >= 0 ? 1 : 0);
+            double v[KG];
+#pragma unroll
+            for (int k = 0; k < KG; ++k) v[k] = 0.0;
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                if (lane + i * kWave < G) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) v[k] += __longlong_as_double((long long)got[i][k]);
+                    if constexpr (PREV >= 0) v[K] += __longlong_as_double((long long)prv[i]);
+                }
+            }
+            for (int off = kWave / 2; off > 0; off >>= 1) {
+                double o[KG];
+#pragma unroll
+                for (int k = 0; k < KG; ++k) o[k] = __shfl_down(v[k], off, kWave);
+#pragma unroll
+                for (int k = 0; k < KG; ++k)
+                    if (lane + off < kWave) v[k] += o[k];
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) tot[slot[k]] = v[k];
+                if constexpr (PREV >= 0) tot[PREV] = v[K];
+            }
         }
     }
     __syncthreads();
+    ++ph;
+}
+
+// a device-wide barrier of the segment kernel (phase_sync with no sums)
+__device__ __forceinline__ void phase_barrier(double* part, unsigned* bar, unsigned long long ticks, double* red,
+                                              double* tot, unsigned& ph, int vb, int G) {
+    const int sl[1] = {0};
+    const double vv[1] = {0.0};
+    phase_sync<1, false, -1, double, false>(part, bar, ticks, sl, vv, red, tot, ph, vb, G);
 }
 
 // ---------------------------------------------------------------------------
@@ -824,7 +905,8 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
     const int NRB = ((a.Nt + 1) / 2 + NG - 1) / NG;  // rounds over frequency pairs of the sine transform
     const T* e = a.epad + kEpad;
     const T scale = two_d ? T(4.0 / ((double)(a.Nt + 1) * (a.Nt + 1))) : T(2.0 / (a.Nt + 1));
-    unsigned epoch = 0;
+    unsigned ph = 0;  // phase of the device-wide synchronisation (phase_sync)
+    auto sync_bar = [&]() { phase_barrier(a.part, a.bar, a.bar_ticks, red, tot, ph, a.vb, a.vg); };
     long long total_it = 0;
 
     for (int s = sa; s < sb; ++s) {
@@ -902,12 +984,12 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
             if (upd) {
                 const int sl[2] = {SL_RR, SL_RZ};
                 const T vv[2] = {rr, rzl};
-                put_partials<2>(a.part, sl, vv, red, a.vb);
+                phase_sync<2, true, -1>(a.part, a.bar, a.bar_ticks, sl, vv, red, tot, ph, a.vb, a.vg);
             } else {
-                put_partial(a.part, SL_RZ, rzl, red, a.vb);
+                const int sl[1] = {SL_RZ};
+                const T vv[1] = {rzl};
+                phase_sync<1, true, -1>(a.part, a.bar, a.bar_ticks, sl, vv, red, tot, ph, a.vb, a.vg);
             }
-            grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
-            gather_totals(a.part, tot, a.vg);
         };
 
         // ---------------- E: finish step s-1, history, rhs, warm start, r0 ----------------
@@ -1054,10 +1136,8 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
             {
                 const int sl[2] = {SL_RR, SL_BB};
                 const T vv[2] = {rr, bb};
-                put_partials<2>(a.part, sl, vv, red, a.vb);
+                phase_sync<2, true, -1>(a.part, a.bar, a.bar_ticks, sl, vv, red, tot, ph, a.vb, a.vg);
             }
-            grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
-            gather_totals<(1u << SL_RR) | (1u << SL_BB)>(a.part, tot, a.vg);
         }
         const double bbt = tot[SL_BB];
         double rrt = tot[SL_RR];
@@ -1067,7 +1147,7 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                 a.x[j] = T(0);
                 a.r[j] = T(0);
             }
-            grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
+            sync_bar();
             continue;
         }
         if constexpr (TAU2) {
@@ -1080,7 +1160,7 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                     const int kbase = 2 * (rd * NG + a.vb * gpb);
                     wg_pass_B<T, VPT>(a, cbase, c, twl, kbase, grp, gpb, sig, cc, scale, tid, nthr, rzl);
                 }
-                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
+                sync_bar();
                 for (int rd = 0; rd < NR; ++rd) {
                     const int ibase = 2 * (rd * NG + a.vb * gpb);
                     const int i0 = ibase + 2 * grp;
@@ -1112,9 +1192,9 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                     const int kbase = 2 * (rd * NG + a.vb * gpb);
                     wg_pass_B<T, VPT>(a, cbase, c, twl, kbase, grp, gpb, sig, cc, scale, tid, nthr, rzl);
                 }
-                put_partial(a.part, SL_RZ, rzl, red, a.vb);
-                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
-                gather_totals<1u << SL_RZ>(a.part, tot, a.vg);
+                const int sl[1] = {SL_RZ};
+                const T vv[1] = {rzl};
+                phase_sync<1, true, -1>(a.part, a.bar, a.bar_ticks, sl, vv, red, tot, ph, a.vb, a.vg);
             }
             double rz = tot[SL_RZ];
             T beta = T(0);
@@ -1125,24 +1205,31 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                     const int ibase = 2 * (rd * NG + a.vb * gpb);
                     wg_pass_DF<T, VPT>(a, cbase, c, twl, ibase, grp, gpb, beta, dg, tid, nthr, pdp);
                 }
-                put_partial(a.part, SL_PD, pdp, red, a.vb);
-                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
+                {
+                    const int sl[1] = {SL_PD};
+                    const T vv[1] = {pdp};
+                    phase_sync<1, false, -1>(a.part, a.bar, a.bar_ticks, sl, vv, red, tot, ph, a.vb, a.vg);
+                }
                 for (int rd = 0; rd < NC; ++rd) {
                     const int k2 = rd * NG + gg;
                     g_cols_pbp<T, VPT>(a, c, twl, k2, k2 < a.H, tid, nthr, pbp);
                 }
-                put_partial(a.part, SL_PB, pbp, red, a.vb);
-                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
-                gather_totals<(1u << SL_PD) | (1u << SL_PB)>(a.part, tot, a.vg);
+                {
+                    const int sl[1] = {SL_PB};
+                    const T vv[1] = {pbp};
+                    phase_sync<1, true, SL_PD>(a.part, a.bar, a.bar_ticks, sl, vv, red, tot, ph, a.vb, a.vg);
+                }
                 const double pqt = tot[SL_PD] + (double)cc * tot[SL_PB];
                 const T alpha = T(pqt != 0.0 ? rz / pqt : 0.0);
                 for (int rd = 0; rd < NR; ++rd) {
                     const int ibase = 2 * (rd * NG + a.vb * gpb);
                     wg_pass_IUA<T, VPT>(a, cbase, c, twl, ibase, grp, gpb, dg, cc, alpha, tid, nthr, rr);
                 }
-                put_partial(a.part, SL_RR, rr, red, a.vb);
-                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
-                gather_totals<1u << SL_RR>(a.part, tot, a.vg);
+                {
+                    const int sl[1] = {SL_RR};
+                    const T vv[1] = {rr};
+                    phase_sync<1, true, -1>(a.part, a.bar, a.bar_ticks, sl, vv, red, tot, ph, a.vb, a.vg);
+                }
                 ++it;
                 rrt = tot[SL_RR];
                 if (rrt <= a.tol2 * bbt || it >= a.maxit || !(rrt == rrt)) break;
@@ -1151,9 +1238,11 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                     const int kbase = 2 * (rd * NG + a.vb * gpb);
                     wg_pass_B<T, VPT>(a, cbase, c, twl, kbase, grp, gpb, sig, cc, scale, tid, nthr, rzl);
                 }
-                put_partial(a.part, SL_RZ, rzl, red, a.vb);
-                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
-                gather_totals<1u << SL_RZ>(a.part, tot, a.vg);
+                {
+                    const int sl[1] = {SL_RZ};
+                    const T vv[1] = {rzl};
+                    phase_sync<1, true, -1>(a.part, a.bar, a.bar_ticks, sl, vv, red, tot, ph, a.vb, a.vg);
+                }
                 const double rz_new = tot[SL_RZ];
                 beta = T(rz != 0.0 ? rz_new / rz : 0.0);
                 rz = rz_new;
@@ -1173,12 +1262,12 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                     const int pr = rd * NG + gg;
                     g_rows_fwd<T, VPT>(a, c, twl, pr, pr < NP, beta, tid, nthr);
                 }
-                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
+                sync_bar();
                 for (int rd = 0; rd < NC; ++rd) {
                     const int k2 = rd * NG + gg;
                     g_cols<T, VPT>(a, c, twl, k2, k2 < a.H, tid, nthr);
                 }
-                grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
+                sync_bar();
                 for (int rd = 0; rd < NR; ++rd) {
                     const int pr = rd * NG + gg;
                     g_rows_inv<T, VPT>(a, c, twl, pr, pr < NP, dg, cc, tid, nthr, pq);
@@ -1227,9 +1316,11 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                 }
                 __syncthreads();
             }
-            put_partial(a.part, SL_PQ, pq, red, a.vb);
-            grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
-            gather_totals(a.part, tot, a.vg);
+            {
+                const int sl[1] = {SL_PQ};
+                const T vv[1] = {pq};
+                phase_sync<1, true, -1>(a.part, a.bar, a.bar_ticks, sl, vv, red, tot, ph, a.vb, a.vg);
+            }
             const double pqt = tot[SL_PQ];
             const T alpha = T(pqt != 0.0 ? rz / pqt : 0.0);
             // x += alpha p, r -= alpha q, (r, r), and pass A of z = M^{-1} r
@@ -1246,7 +1337,7 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
     }
     // the segment's last step: y_{sb-1} = x (grid-stride ownership: in the tau-block mode x was
     // last written by row-owning groups, so the grid synchronises first)
-    if constexpr (TB) grid_barrier_n(a.bar, a.bar_ticks, epoch, a.vg);
+    if constexpr (TB) sync_bar();
     for (long long j = gtid; j < Nd; j += gthreads) a.y[(long long)(sb - 1) * Nd + j] = a.x[j];
     if (a.vb == 0 && threadIdx.x == 0) *a.iters += total_it;
 }
@@ -1283,8 +1374,8 @@ struct PersistentWork {
     T* buf = nullptr;       // x r zz p q rhs bxb bxb2: 8 Nd, then hacc: kHB Nd
     T* tt = nullptr;        // t1, t2: N ns each (2D)
     cplx<T>* spec = nullptr;  // [H][ns] (2D)
-    double* part = nullptr;
-    unsigned* bar = nullptr;  // [0] barrier counter, [1] abort word
+    double* part = nullptr;   // kRing * kMaxGrid * kNPart reduction slots
+    unsigned* bar = nullptr;  // [1] abort word
     long long* iters = nullptr;
     ResidencyTicket ticket;   // CU slots of the grid while its segments run
 };
@@ -1375,7 +1466,7 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
     ResidencyBudget& pool = residency_budget(dev, ncu);
     int cap = std::min(per_cu * ncu, residency_max_grid(pool.total(), kXcds));
     if (shared_launch()) cap = std::min(cap, std::max(1, ncu / kMaxInflight));
-    grid = std::max(1, std::min(grid, cap));
+    grid = std::max(1, std::min({grid, cap, kMaxGrid}));
     a.bar_ticks = barrier_ticks(dev);
     if (P.capturing) {
         // inside a captured graph: the solver holds the slots around each replay and zeroes the
@@ -1399,7 +1490,7 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
                                    D.epad, z, D.gamma1, D.gamma2, sa, cnt, Nd, (const T*)nullptr);
             TSFDE_HIP(hipGetLastError());
         }
-        launch_fill(reinterpret_cast<float*>(W.bar), 1, 0.0f, st);  // zero the barrier counter
+        launch_fill(reinterpret_cast<unsigned long long*>(W.part), (long long)kMaxGrid * kNPart, kEmpty, st);  // ring 0
         void* args[] = {&a, &sa_, &sb_};
         TSFDE_HIP(hipLaunchKernel((void*)pinv_segment<T, VPT, MODE, LC, TB>, dim3(grid), dim3(block), args, lds, st));
     }
@@ -1446,7 +1537,7 @@ void launch_segments_multi(std::vector<MultiItem<T>>& items, hipStream_t st) {
     TSFDE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     if (per_cu < 1) throw HipError{hipErrorInvalidConfiguration, "multi P^-1: a workgroup does not fit a CU"};
     ResidencyBudget& pool = residency_budget(dev, ncu);
-    const int cap = std::min(per_cu * ncu, residency_max_grid(pool.total(), kXcds));
+    const int cap = std::min({per_cu * ncu, residency_max_grid(pool.total(), kXcds), kMaxGrid});
     const unsigned long long ticks = barrier_ticks(dev);
     for (auto& it : items) {
         it.grid = std::min(it.grid, cap);
@@ -1549,7 +1640,8 @@ void launch_segments_multi(std::vector<MultiItem<T>>& items, hipStream_t st) {
                                    it.a.hacc, it.a.epad, it.a.z, it.a.g1, it.a.g2, sa, cnt, P.Nd, (const T*)nullptr);
                 TSFDE_HIP(hipGetLastError());
             }
-            launch_fill(reinterpret_cast<float*>(it.W->bar), 1, 0.0f, st);  // barrier counter
+            launch_fill(reinterpret_cast<unsigned long long*>(it.W->part), (long long)kMaxGrid * kNPart, kEmpty,
+                        st);  // ring 0 of the reduction slots
         }
         hipLaunchKernelGGL((pinv_segment_multi<T, VPT, MODE>), dim3(l.grid), dim3(block), lds, st,
                            reinterpret_cast<const PinvArgs<T>*>(db + l.o_args), reinterpret_cast<const int*>(db + l.o_off),

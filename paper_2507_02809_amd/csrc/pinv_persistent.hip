@@ -42,11 +42,11 @@ void ensure_work(Problem& P, PersistentWork<T>& W) {
         TSFDE_HIP(hipMalloc(&W.tt, sizeof(T) * ((size_t)P.Nt + P.N) * nt));
         TSFDE_HIP(hipMalloc(&W.spec, sizeof(cplx<T>) * (size_t)P.H * ns));
     }
-    TSFDE_HIP(hipMalloc(&W.part, sizeof(double) * 1024 * kNPart));
+    TSFDE_HIP(hipMalloc(&W.part, sizeof(double) * kRing * kMaxGrid * kNPart));
     TSFDE_HIP(hipMalloc(&W.bar, 64));
     TSFDE_HIP(hipMalloc(&W.iters, sizeof(long long)));
     TSFDE_HIP(hipMemset(W.buf, 0, sizeof(T) * (size_t)(8 + kHB) * P.Nd));
-    P.bytes += sizeof(T) * (size_t)(8 + kHB) * P.Nd + sizeof(double) * 1024 * kNPart + 64 + sizeof(long long) +
+    P.bytes += sizeof(T) * (size_t)(8 + kHB) * P.Nd + sizeof(double) * kRing * kMaxGrid * kNPart + 64 + sizeof(long long) +
                (P.d == 2 ? sizeof(T) * ((size_t)P.Nt + P.N) * nt + sizeof(cplx<T>) * (size_t)P.H * ns : 0);
 }
 
@@ -255,7 +255,7 @@ NoAllocLayout noalloc_layout(const Problem& P) {
     l.spec = o;
     if (P.d == 2) o = align_up(o + sizeof(cplx<double>) * (size_t)P.H * ns);
     l.part = o;
-    o = align_up(o + sizeof(double) * 1024 * kNPart);
+    o = align_up(o + sizeof(double) * kRing * kMaxGrid * kNPart);
     l.bar = o;
     o = align_up(o + 64);
     l.iters = o;

@@ -252,8 +252,11 @@ static void launch_mv(const Problem& P, const Dev<T>& D, const T* y, T* z, const
         res[2] = std::max(1, b2) * ncu;
         res[0] = std::max(1, b0) * ncu;
     }
-    for (int s0 = 0; s0 < nslices; s0 += P.nspec) {
-        const int nsl = std::min(P.nspec, nslices - s0);
+    // TSFDE_MV_CHUNK (diagnostics): slices per pass of the three kernels
+    int chunk = P.nspec;
+    if (const char* e = std::getenv("TSFDE_MV_CHUNK")) chunk = std::max(1, std::min(P.nspec, std::atoi(e)));
+    for (int s0 = 0; s0 < nslices; s0 += chunk) {
+        const int nsl = std::min(chunk, nslices - s0);
         const T* ys = y + (long long)s0 * P.Nd;
         hipLaunchKernelGGL((mv_rows_fwd<T, VPT, LC>), dim3(std::min(nrb * nsl, res[0])), dim3(kMvBlock), lds, st, ys,
                            N, L, nsl, D.tw, D.spec);
