@@ -37,6 +37,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "fft.hpp"
@@ -48,6 +49,8 @@ namespace tsfde {
 
 static_assert(kHB <= 64, "the weight table e carries 64 trailing zeros for the history tiles");
 constexpr int kNPart = 6;  // reduction slots per workgroup
+// near-history terms of a step of the segment kernel: y_m with sa <= m < s - 1 and s - sa <= kHB - 1
+constexpr int kNear = kHB - 2;
 // (r,r) (rhs,rhs) (r,z) (p,q) (p,dg p) (p,B p)
 enum : int { SL_RR = 0, SL_BB = 1, SL_RZ = 2, SL_PQ = 3, SL_PD = 4, SL_PB = 5 };
 
@@ -83,6 +86,8 @@ struct PinvArgs {
     unsigned long long bar_ticks;  // longest barrier wait, in wall-clock periods
     long long* iters;  // accumulated CG iterations
     int vb, vg;        // this workgroup's index in the problem's grid and that grid's size
+    int ring;          // 1: the segment's earlier solutions of the thread's own points kept in LDS (2D tau
+                       // path with one round over the row pairs; near-history terms read from there)
 };
 
 // (A problem's workgroups are numbered vb = 0 .. vg - 1 within its grid: the whole launch, or its share
@@ -225,7 +230,7 @@ __device__ __forceinline__ void phase_sync(double* part, unsigned* bar, unsigned
                 for (int k = 0; k < KG; ++k) o[k] = __shfl_down(v[k], off, kWave);
 #pragma unroll
                 for (int k = 0; k < KG; ++k)
-                    if (lane + off < kWave) v[k] += o[k];
+                    if (lane + off < min(kWave, (int)blockDim.x)) v[k] += o[k];
             }
             if (lane == 0) {
 #pragma unroll
@@ -889,6 +894,8 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
     const int twn = TWL ? a.L : 0;  // twiddles first (when in LDS), then the sequences
     cplx<T>* cbase = lds + twn;     // the groups' sequences
     cplx<T>* c = cbase + (size_t)grp * lds_len(a.L);
+    // near-history ring (a.ring): slot i holds y_{sa+i} of the thread's points, [i][u][q][thread]
+    T* ring = reinterpret_cast<T*>(cbase + (size_t)gpb * lds_len(a.L));
     for (int k = threadIdx.x; k < twn; k += blockDim.x) lds[k] = a.tw[k];
     const cplx<T>* twl = TWL ? lds : a.tw;
     __syncthreads();
@@ -1002,13 +1009,16 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
         };
         // weights of the near-history terms y_{sa+i}, i < kHB, of this step (zero for absent terms),
         // read once per step so that no load of a point waits on a weight
-        T ew[kHB];
+        T ew[kNear];
 #pragma unroll
-        for (int i = 0; i < kHB; ++i) ew[i] = (!lastrow && i + 1 < nnear) ? e[s - sa - i] : T(0);
+        for (int i = 0; i < kNear; ++i) ew[i] = (!lastrow && i + 1 < nnear) ? e[s - sa - i] : T(0);
         const T e1 = (nnear >= 1) ? e[1] : T(0);  // weight of y_{s-1} when it is a near term
         // loads of point j (no stores, so that the loads of several points can be in flight together);
-        // hn = sum over the near-history terms m in [sa, s-1) of e_{s-m} y_m
-        auto e_load = [&](long long j) -> EIn {
+        // hn = sum over the near-history terms m in [sa, s-1) of e_{s-m} y_m, read from the LDS ring when
+        // the thread keeps its points' earlier solutions there (a.ring), else from y
+        // (u, q): the point's column round and row within the thread's row pair (the ring's index), or
+        // q < 0 for the grid-stride form, which does not use the ring
+        auto e_load = [&](long long j, int u, int q) -> EIn {
             EIn v;
             const bool ext = (s >= 2 && !lastrow && a.extrap && !TB);
             const bool ext2 = (s >= 3 && !lastrow && a.extrap == 2 && !TB);
@@ -1027,37 +1037,41 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
             v.dgo = dg ? dg[j] : T(0);
             // y_m for m = sa + i < s - 1 (y_{s-1} is xv): the loads sit in uniform branches and are
             // used only after all of them have been issued
-            T yv[kHB];
+            const bool lring = a.ring && q >= 0;
+            T yv[kNear];
 #pragma unroll
-            for (int i = 0; i < kHB; ++i) {
+            for (int i = 0; i < kNear; ++i) {
                 yv[i] = T(0);
-                if (!lastrow && i + 1 < nnear) yv[i] = a.y[(long long)(sa + i) * Nd + j];
+                if (!lastrow && i + 1 < nnear)
+                    yv[i] = lring ? ring[((i * (VPT / 2) + u) * 2 + q) * (int)blockDim.x + threadIdx.x]
+                                  : a.y[(long long)(sa + i) * Nd + j];
             }
             if (a.adj) {
                 // transposed sweep: each earlier step's term carries its own weight dg_m
 #pragma unroll
-                for (int i = 0; i < kHB; ++i)
+                for (int i = 0; i < kNear; ++i)
                     if (!lastrow && i + 1 < nnear) yv[i] *= a.dg[(long long)(sa + i) * Nd + j];
             }
             T hn = T(0);
 #pragma unroll
-            for (int i = 0; i < kHB; ++i) hn += ew[i] * yv[i];
+            for (int i = 0; i < kNear; ++i) hn += ew[i] * yv[i];
             v.hn = hn;
             return v;
         };
         // the rest of point j: returns r0 and adds to (r, r), (b, b)
-        auto e_store = [&](long long j, const EIn& v, T& rr, T& bb) -> T {
+        auto e_store = [&](long long j, const EIn& v, T& rr, T& bb, int u, int q) -> T {
             const bool ext = (s >= 2 && !lastrow && a.extrap && !TB);
             const bool ext2 = (s >= 3 && !lastrow && a.extrap == 2 && !TB);
             const T yprev = v.xv;
             const T bxprev = (s > 0) ? (v.rhs_o - v.r_o - v.dgp * yprev) / a.ct : T(0);  // B y_{s-1}
+            const T hn = v.hn;
             T rhs, x0 = T(0), bx0 = T(0);
             if (lastrow) {
                 rhs = (v.zo - yprev) / (a.cf * v.g2o);
             } else if (a.adj) {
-                rhs = v.zo - (v.hn + e1 * v.dgp * yprev);  // transposed sweep: weights of the earlier steps
+                rhs = v.zo - (hn + e1 * v.dgp * yprev);  // transposed sweep: weights of the earlier steps
             } else {
-                const T h = v.hn + e1 * yprev;
+                const T h = hn + e1 * yprev;
                 rhs = v.zo - v.dgo * h;
                 if (s >= 1 && !TB) {
                     // linear (or, extrap = 2, quadratic) extrapolation in time of y and B y
@@ -1073,6 +1087,8 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
             }
             const T rv = rhs - (v.dgo * x0 + cc * bx0);
             if (s > 0) a.y[(long long)(s - 1) * Nd + j] = yprev;
+            if (a.ring && q >= 0 && s > sa && s - 1 - sa < kNear)
+                ring[(((s - 1 - sa) * (VPT / 2) + u) * 2 + q) * (int)blockDim.x + threadIdx.x] = yprev;
             if (s >= 1 && !lastrow && a.extrap && !TB) {
                 a.bxb[j] = bxprev;  // B y_{s-1} is "B y_{s-2}" next step
                 if (a.extrap == 2) a.bxb2[j] = v.bxb;  // and B y_{s-2} is "B y_{s-3}"
@@ -1097,7 +1113,11 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                     // points (i0 + q, m = tid + u nthr), m < N < L/2: the loads of EB columns u (both
                     // rows) are issued together, then the values are formed and stored
                     constexpr int VH = VPT / 2;
-                    constexpr int EB = (VH >= 2) ? 2 : 1;
+                    // EB columns per round: all of them when the near history comes from the ring (the
+                    // loads of a round then stay within the count of memory operations in flight that
+                    // the hardware tracks), else two
+                    auto e_rounds = [&](auto ebc) {
+                    constexpr int EB = decltype(ebc)::value;
 #pragma unroll 1
                     for (int u0 = 0; u0 < VH; u0 += EB) {
                         EIn v[EB][2];
@@ -1106,8 +1126,8 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                             const int m = tid + (u0 + du) * nthr;
                             if (valid && m < N) {
                                 const long long j0 = (long long)i0 * N + m;
-                                v[du][0] = e_load(j0);
-                                if (two) v[du][1] = e_load(j0 + N);
+                                v[du][0] = e_load(j0, u0 + du, 0);
+                                if (two) v[du][1] = e_load(j0 + N, u0 + du, 1);
                             }
                         }
 #pragma unroll
@@ -1117,13 +1137,16 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                             T r0 = T(0), r1 = T(0);
                             if (valid && m < N) {
                                 const long long j0 = (long long)i0 * N + m;
-                                r0 = e_store(j0, v[du][0], rr, bb);
-                                if (two) r1 = e_store(j0 + N, v[du][1], rr, bb);
+                                r0 = e_store(j0, v[du][0], rr, bb, u0 + du, 0);
+                                if (two) r1 = e_store(j0 + N, v[du][1], rr, bb, u0 + du, 1);
                             }
                             c[lx(m + 1)] = {r0, r1};
                             c[lx(a.L - m - 1)] = {-r0, -r1};
                         }
                     }
+                    };
+                    if (a.ring) e_rounds(std::integral_constant<int, VH>{});
+                    else e_rounds(std::integral_constant<int, (VH >= 2 ? 2 : 1)>{});
                     if (tid == 0) c[lx(0)] = {T(0), T(0)};
                     __syncthreads();
                     fft_lds<T, VPT, false>(c, a.L, twl, tid, nthr);
@@ -1131,7 +1154,7 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                     __syncthreads();
                 }
             } else {
-                for (long long j = gtid; j < Nd; j += gthreads) (void)e_store(j, e_load(j), rr, bb);
+                for (long long j = gtid; j < Nd; j += gthreads) (void)e_store(j, e_load(j, 0, -1), rr, bb, 0, -1);
             }
             {
                 const int sl[2] = {SL_RR, SL_BB};
@@ -1442,31 +1465,58 @@ void launch_segments(Problem& P, const Dev<T>& D, PersistentWork<T>& W, const T*
     PinvArgs<T> a = make_pinv_args<T>(P, D, W, z, y, inner_tol, inner_maxit, extrap);
     const long long Nd = P.Nd;
     const int nthr = P.L / VPT;
-    const int block = (P.d == 2) ? kSegBlock : nthr;
-    const int gpb = block / nthr;
-    const size_t lds = sizeof(cplx<T>) * ((tw_in_lds<T>(VPT) ? P.L : 0) + (size_t)gpb * lds_len(P.L));
-    if (lds > 160 * 1024) throw HipError{hipErrorInvalidConfiguration, "persistent P^-1 LDS size"};
-    // 2D: enough groups that the L/2+1 spectral rows take two rounds
-    int grid = 1;
-    if (P.d == 2) {
-        grid = (P.H + 2 * gpb - 1) / (2 * gpb);
-        if (blocks > 0) grid = blocks;
-    }
-    int per_cu = 0;
-    TSFDE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pinv_segment<T, VPT, MODE, LC, TB>, block, lds));
     int dev = 0, ncu = 0;
     TSFDE_HIP(hipGetDevice(&dev));
     TSFDE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    if (per_cu < 1) throw HipError{hipErrorInvalidConfiguration, "persistent P^-1: a workgroup does not fit a CU"};
     // The segment kernel's workgroups wait for each other, so all of them must be resident at once,
     // also beside the persistent grids of other streams: the grid is sized to its share of the
     // device's CU slots and holds them (W.ticket) until the host has seen the last segment finish
     // (residency.hpp).  Inside a batch, where up to kMaxInflight problems run side by side, a grid is
     // further limited to ncu / kMaxInflight workgroups, so that that many fit together.
     ResidencyBudget& pool = residency_budget(dev, ncu);
-    int cap = std::min(per_cu * ncu, residency_max_grid(pool.total(), kXcds));
-    if (shared_launch()) cap = std::min(cap, std::max(1, ncu / kMaxInflight));
-    grid = std::max(1, std::min({grid, cap, kMaxGrid}));
+    struct Cfg {
+        int block, gpb, grid;
+        size_t lds;
+    };
+    // a workgroup of `block` threads; ring: with the near-history ring in LDS
+    auto configure = [&](int block, bool ring) -> Cfg {
+        Cfg c{block, block / nthr, 1, 0};
+        c.lds = sizeof(cplx<T>) * ((tw_in_lds<T>(VPT) ? P.L : 0) + (size_t)c.gpb * lds_len(P.L)) +
+                (ring ? sizeof(T) * (size_t)kNear * (VPT / 2) * 2 * block : 0);
+        if (c.lds > 160 * 1024) return Cfg{0, 0, 0, 0};
+        // 2D: enough groups that the L/2+1 spectral rows take two rounds
+        if (P.d == 2) {
+            c.grid = (P.H + 2 * c.gpb - 1) / (2 * c.gpb);
+            if (blocks > 0) c.grid = blocks;
+        }
+        int per_cu = 0;
+        TSFDE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pinv_segment<T, VPT, MODE, LC, TB>, block, c.lds));
+        if (per_cu < 1) return Cfg{0, 0, 0, 0};
+        int cap = std::min(per_cu * ncu, residency_max_grid(pool.total(), kXcds));
+        if (shared_launch()) cap = std::min(cap, std::max(1, ncu / kMaxInflight));
+        c.grid = std::max(1, std::min({c.grid, cap, kMaxGrid}));
+        return c;
+    };
+    // 2D sine-transform path: workgroups of two (else one) transform groups with the segment's earlier
+    // solutions of their own points in LDS, when that fits and the grid takes the row pairs in one
+    // round (each thread then owns the same points in every step of the segment)
+    Cfg cfg{0, 0, 0, 0};
+    a.ring = 0;
+    const char* ring_env = std::getenv("TSFDE_PINV_RING");  // diagnostics: 0 keeps the ring off
+    if (MODE == SEG_2D_TAU && blocks <= 0 && !(ring_env && std::atoi(ring_env) == 0)) {
+        for (int g2 = 2; g2 >= 1 && a.ring == 0; --g2) {
+            if (g2 * nthr > kSegBlock || g2 * nthr < kWave) continue;  // phase_sync polls with one full wave
+            const Cfg c = configure(g2 * nthr, true);
+            if (c.block > 0 && (long long)c.grid * c.gpb >= (P.N + 1) / 2) {
+                cfg = c;
+                a.ring = 1;
+            }
+        }
+    }
+    if (!a.ring) cfg = configure(P.d == 2 ? kSegBlock : nthr, false);
+    if (cfg.block == 0) throw HipError{hipErrorInvalidConfiguration, "persistent P^-1: a workgroup does not fit a CU"};
+    const int block = cfg.block, grid = cfg.grid;
+    const size_t lds = cfg.lds;
     a.bar_ticks = barrier_ticks(dev);
     if (P.capturing) {
         // inside a captured graph: the solver holds the slots around each replay and zeroes the

@@ -103,14 +103,16 @@ def test_gmres_fp64_and_mixed_match_dense_lu(dense_case):
 
 def test_mixed_refinement_checks_the_last_correction():
     """MIXED with a single refinement sweep: the residual of the corrected x is computed, so a sweep
-    that reaches the tolerance reports convergence (and the statistics describe the returned x)."""
+    that reaches the tolerance reports convergence (and the statistics describe the returned x).  One
+    FP32 sweep ends near 1e-4 here (8e-5 to 1.4e-4 depending on the FP32 rounding order), so the
+    tolerance is 1e-3."""
     inp = inputs.small(1, 12, 7)
     p = workloads.with_data(inp)
     x_lu = np.linalg.solve(system.dense_A(p), system.rhs_z(p))
     with gpu_problem(inp, p) as g:
-        f, st = g.recover_f(tsfde.default_opts(tol=1e-4, precision=tsfde.MIXED, max_refine=1, refine_tol=1e-5),
+        f, st = g.recover_f(tsfde.default_opts(tol=1e-3, precision=tsfde.MIXED, max_refine=1, refine_tol=1e-5),
                             raise_noconv=True)
-        assert st.converged == 1 and st.refinements == 1 and st.rel_res <= 1e-4
+        assert st.converged == 1 and st.refinements == 1 and st.rel_res <= 1e-3
         assert rel_err(f.cpu().numpy(), x_lu[p.S * p.Nd:]) <= 1e-2
         # two refinement sweeps to a tight tolerance, repeated on the same problem (problem-owned buffers)
         for _ in range(2):
