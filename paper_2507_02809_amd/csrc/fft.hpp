@@ -69,20 +69,28 @@ __device__ __forceinline__ void dft8(cplx<T>* v) {
     v[7] = csub(e3, t3);
 }
 
-template <typename T, int R, int VPT, bool INV>
+template <typename T, int R, int VPT, bool INV, bool HT>
 __device__ __forceinline__ void stockham_pass(cplx<T>* a, int L, int Ns, const cplx<T>* __restrict__ tw,
                                               int tid, int nthr) {
     constexpr int NB = VPT / R;  // butterflies per thread
+    // HT with one butterfly per thread: its twiddles are read together with the data, before the
+    // barrier (they do not depend on it); callers whose registers are scarce leave HT off
+    constexpr bool HOIST = HT && NB == 1;
     const int nbut = L / R;
-    cplx<T> v[NB][R];
+    const int tstride = L / (Ns * R);
+    cplx<T> v[NB][R], w[HOIST ? R : 1];
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
         const int b = tid + c * nthr;
 #pragma unroll
         for (int r = 0; r < R; ++r) v[c][r] = a[lx(b + r * nbut)];
     }
+    if (HOIST && Ns > 1) {
+        const int k = tid & (Ns - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[HOIST ? r : 0] = tw[r * k * tstride];
+    }
     __syncthreads();
-    const int tstride = L / (Ns * R);
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
         const int b = tid + c * nthr;
@@ -90,8 +98,8 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* a, int L, int Ns, const c
         if (Ns > 1) {
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                cplx<T> w = tw[r * k * tstride];
-                v[c][r] = INV ? cmulc(v[c][r], w) : cmul(v[c][r], w);
+                const cplx<T> t = HOIST ? w[HOIST ? r : 0] : tw[r * k * tstride];
+                v[c][r] = INV ? cmulc(v[c][r], t) : cmul(v[c][r], t);
             }
         }
         if constexpr (R == 8) {
@@ -110,19 +118,19 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* a, int L, int Ns, const c
 
 // In-place FFT of a[0..L) (stored with the lx() padding) with L = VPT * nthr.  Must be called by all threads of the
 // workgroup (it contains __syncthreads()); `tid` is the thread's index within its group.
-template <typename T, int VPT, bool INV>
+template <typename T, int VPT, bool INV, bool HT = false>
 __device__ void fft_lds(cplx<T>* a, int L, const cplx<T>* __restrict__ tw, int tid, int nthr) {
     int Ns = 1;
     while (Ns < L) {
         const int rem = L / Ns;
         if (rem >= 8) {
-            stockham_pass<T, 8, VPT, INV>(a, L, Ns, tw, tid, nthr);
+            stockham_pass<T, 8, VPT, INV, HT>(a, L, Ns, tw, tid, nthr);
             Ns *= 8;
         } else if (rem == 4) {
-            stockham_pass<T, 4, VPT, INV>(a, L, Ns, tw, tid, nthr);
+            stockham_pass<T, 4, VPT, INV, HT>(a, L, Ns, tw, tid, nthr);
             Ns *= 4;
         } else {
-            stockham_pass<T, 2, VPT, INV>(a, L, Ns, tw, tid, nthr);
+            stockham_pass<T, 2, VPT, INV, HT>(a, L, Ns, tw, tid, nthr);
             Ns *= 2;
         }
     }
@@ -139,13 +147,20 @@ __device__ void fft_lds(cplx<T>* a, int L, const cplx<T>* __restrict__ tw, int t
 //   OUT_REG: on exit the LDS sequence holds scratch data and may be overwritten at once;
 //   !OUT_REG: on exit the output is in LDS and visible to the group.
 // ---------------------------------------------------------------------------
-template <typename T, int R, int VPT, bool INV>
+template <typename T, int R, int VPT, bool INV, bool HT>
 __device__ __forceinline__ void stockham_pass_x(cplx<T> (&v)[VPT], cplx<T>* a, int L, int Ns,
                                                 const cplx<T>* __restrict__ tw, int tid, int nthr, bool in_reg,
                                                 bool out_reg) {
     constexpr int NB = VPT / R;  // butterflies per thread
+    constexpr bool HOIST = HT && NB == 1;  // twiddles read before the data wait (as in stockham_pass)
     const int nbut = L / R;
-    cplx<T> w[NB][R];
+    const int tstride = L / (Ns * R);
+    cplx<T> w[NB][R], tt[HOIST ? R : 1];
+    if (HOIST && Ns > 1) {
+        const int k = tid & (Ns - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) tt[HOIST ? r : 0] = tw[r * k * tstride];
+    }
     if (in_reg) {
         // butterfly (b = tid + c nthr, r) reads position b + r L/R = tid + (c + NB r) nthr
 #pragma unroll
@@ -161,7 +176,6 @@ __device__ __forceinline__ void stockham_pass_x(cplx<T> (&v)[VPT], cplx<T>* a, i
         }
         __syncthreads();
     }
-    const int tstride = L / (Ns * R);
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
         const int b = tid + c * nthr;
@@ -169,7 +183,7 @@ __device__ __forceinline__ void stockham_pass_x(cplx<T> (&v)[VPT], cplx<T>* a, i
         if (Ns > 1) {
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                cplx<T> t = tw[r * k * tstride];
+                const cplx<T> t = HOIST ? tt[HOIST ? r : 0] : tw[r * k * tstride];
                 w[c][r] = INV ? cmulc(w[c][r], t) : cmul(w[c][r], t);
             }
         }
@@ -200,7 +214,7 @@ __device__ __forceinline__ void stockham_pass_x(cplx<T> (&v)[VPT], cplx<T>* a, i
     }
 }
 
-template <typename T, int VPT, bool INV, bool IN_REG, bool OUT_REG>
+template <typename T, int VPT, bool INV, bool IN_REG, bool OUT_REG, bool HT = false>
 __device__ __forceinline__ void fft_x(cplx<T> (&v)[VPT], cplx<T>* a, int L, const cplx<T>* __restrict__ tw, int tid,
                                       int nthr) {
     int Ns = 1;
@@ -212,11 +226,11 @@ __device__ __forceinline__ void fft_x(cplx<T> (&v)[VPT], cplx<T>* a, int L, cons
         const bool in_reg = IN_REG && first;
         const bool out_reg = OUT_REG && last;
         if (R == 8) {
-            stockham_pass_x<T, 8, VPT, INV>(v, a, L, Ns, tw, tid, nthr, in_reg, out_reg);
+            stockham_pass_x<T, 8, VPT, INV, HT>(v, a, L, Ns, tw, tid, nthr, in_reg, out_reg);
         } else if (R == 4) {
-            stockham_pass_x<T, 4, VPT, INV>(v, a, L, Ns, tw, tid, nthr, in_reg, out_reg);
+            stockham_pass_x<T, 4, VPT, INV, HT>(v, a, L, Ns, tw, tid, nthr, in_reg, out_reg);
         } else {
-            stockham_pass_x<T, 2, VPT, INV>(v, a, L, Ns, tw, tid, nthr, in_reg, out_reg);
+            stockham_pass_x<T, 2, VPT, INV, HT>(v, a, L, Ns, tw, tid, nthr, in_reg, out_reg);
         }
         Ns *= R;
     }

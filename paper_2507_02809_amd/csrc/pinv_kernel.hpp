@@ -330,7 +330,7 @@ __device__ __forceinline__ void g_rows_fwd(const PinvArgs<T>& a, cplx<T>* c, con
         c[lx(j)] = {v0, v1};
     }
     __syncthreads();
-    fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
+    fft_lds<T, VPT, false, true>(c, L, tw, tid, nthr);
     if (valid) {
         const int H = a.H;
         for (int k = tid; k < H; k += nthr) {
@@ -357,14 +357,14 @@ __device__ __forceinline__ void g_cols(const PinvArgs<T>& a, cplx<T>* c, const c
         sv[u] = valid ? sy[i] : T(0);
     }
     __syncthreads();
-    fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
+    fft_lds<T, VPT, false, true>(c, L, tw, tid, nthr);
 #pragma unroll
     for (int u = 0; u < VPT; ++u) {
         const int k1 = tid + u * nthr;
         c[lx(k1)] = {c[lx(k1)].x * sv[u], c[lx(k1)].y * sv[u]};
     }
     __syncthreads();
-    fft_lds<T, VPT, true>(c, L, tw, tid, nthr);
+    fft_lds<T, VPT, true, true>(c, L, tw, tid, nthr);
     if (valid) {
 #pragma unroll
         for (int u = 0; u < VPT; ++u) {
@@ -411,7 +411,7 @@ __device__ __forceinline__ void g_rows_inv(const PinvArgs<T>& a, cplx<T>* c, con
         }
     }
     __syncthreads();
-    fft_lds<T, VPT, true>(c, L, tw, tid, nthr);
+    fft_lds<T, VPT, true, true>(c, L, tw, tid, nthr);
     if (valid) {
 #pragma unroll
         for (int u = 0; u < VPT; ++u) {
@@ -503,7 +503,7 @@ __device__ __forceinline__ void g_dst_load(const PinvArgs<T>& a, cplx<T>* c, con
     }
     if (tid == 0) c[lx(0)] = {T(0), T(0)};
     __syncthreads();
-    fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
+    fft_lds<T, VPT, false, true>(c, L, tw, tid, nthr);
 }
 
 // Sine transform (size L/2 - 1) of rows (i0, i0 + 1) of `in` (n entries each, zero-padded up to
@@ -538,7 +538,7 @@ __device__ __forceinline__ void g_dst_rows(const PinvArgs<T>& a, cplx<T>* c, con
         }
         v[u] = {x0, x1};
     }
-    fft_x<T, VPT, false, true, false>(v, c, L, tw, tid, nthr);
+    fft_x<T, VPT, false, true, false, true>(v, c, L, tw, tid, nthr);
 }
 
 // ---------------------------------------------------------------------------
@@ -665,7 +665,7 @@ __device__ __forceinline__ void wg_pass_B(const PinvArgs<T>& a, cplx<T>* cbase, 
         c[lx(Nt + 1)] = {T(0), T(0)};
     }
     __syncthreads();
-    fft_lds<T, VPT, false>(c, a.L, tw, tid, nthr);
+    fft_lds<T, VPT, false, true>(c, a.L, tw, tid, nthr);
     // back in space along the columns: rows i < N of t2, columns k0, k0 + 1
     wg_write_T(a, cbase, a.t2, kbase, gpb, N, Nt);
     __syncthreads();
@@ -723,7 +723,7 @@ __device__ __forceinline__ void wg_pass_DF(const PinvArgs<T>& a, cplx<T>* cbase,
 #pragma unroll
     for (int u = 0; u < VPT; ++u) v[u] = (u < VH) ? cplx<T>{pn0[u], pn1[u]} : cplx<T>{T(0), T(0)};
     __syncthreads();  // every thread has read its sine-transform values: the sequence is free
-    fft_x<T, VPT, false, true, false>(v, c, L, tw, tid, nthr);
+    fft_x<T, VPT, false, true, false, true>(v, c, L, tw, tid, nthr);
     wg_write_spec(a, cbase, ibase, gpb);
     __syncthreads();
 }
@@ -746,7 +746,7 @@ __device__ __forceinline__ void g_cols_pbp(const PinvArgs<T>& a, cplx<T>* c, con
         v[u] = (u < VH && valid && i < N) ? row[i] : cplx<T>{T(0), T(0)};
         sv[u] = valid ? sy[i] : T(0);
     }
-    fft_x<T, VPT, false, true, true>(v, c, L, tw, tid, nthr);
+    fft_x<T, VPT, false, true, true, true>(v, c, L, tw, tid, nthr);
     const T wk = (k2 == 0 || 2 * k2 == L) ? T(1) : T(2);
     T acc = T(0);
 #pragma unroll
@@ -755,7 +755,7 @@ __device__ __forceinline__ void g_cols_pbp(const PinvArgs<T>& a, cplx<T>* c, con
         v[u] = {v[u].x * sv[u], v[u].y * sv[u]};
     }
     pbp += wk * acc;
-    fft_x<T, VPT, true, true, true>(v, c, L, tw, tid, nthr);
+    fft_x<T, VPT, true, true, true, true>(v, c, L, tw, tid, nthr);
     if (valid) {
 #pragma unroll
         for (int u = 0; u < VH; ++u) {
@@ -801,7 +801,7 @@ __device__ __forceinline__ void wg_pass_IUA(const PinvArgs<T>& a, cplx<T>* cbase
     wg_load_spec(a, cbase, ibase, gpb);
     __syncthreads();
     cplx<T> bp[VPT];
-    fft_x<T, VPT, true, false, true>(bp, c, L, tw, tid, nthr);  // B p rows left in registers
+    fft_x<T, VPT, true, false, true, true>(bp, c, L, tw, tid, nthr);  // B p rows left in registers
 #pragma unroll
     for (int u = 0; u < VH; ++u) {
         const int m = tid + u * nthr;
@@ -840,7 +840,7 @@ __device__ __forceinline__ void wg_pass_IUA(const PinvArgs<T>& a, cplx<T>* cbase
     }
     if (tid == 0) c[lx(0)] = {T(0), T(0)};
     __syncthreads();
-    fft_lds<T, VPT, false>(c, L, tw, tid, nthr);
+    fft_lds<T, VPT, false, true>(c, L, tw, tid, nthr);
     wg_write_T(a, cbase, a.t1, ibase, gpb, a.Nt, N);
     __syncthreads();
 }
@@ -883,6 +883,10 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
     extern __shared__ unsigned char smem_raw[];
     __shared__ double red[kSegBlock / 64 * 2];
     __shared__ double tot[kNPart];
+    // the history weights e_0 .. e_kHB and the shifts sigma_s of the segment's steps, read once per
+    // launch (a read from global memory after every device-wide synchronisation misses the caches)
+    __shared__ T s_e[kHB + 1];
+    __shared__ double s_sig[kHB];
     constexpr bool TWL = tw_in_lds<T>(VPT);
     constexpr bool TAU2 = (MODE == SEG_2D_TAU);
     constexpr bool two_d = (MODE != SEG_1D);
@@ -897,6 +901,8 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
     // near-history ring (a.ring): slot i holds y_{sa+i} of the thread's points, [i][u][q][thread]
     T* ring = reinterpret_cast<T*>(cbase + (size_t)gpb * lds_len(a.L));
     for (int k = threadIdx.x; k < twn; k += blockDim.x) lds[k] = a.tw[k];
+    for (int k = threadIdx.x; k <= kHB; k += blockDim.x) s_e[k] = (a.epad + kEpad)[k];
+    for (int k = threadIdx.x; k < kHB; k += blockDim.x) s_sig[k] = (sa + k < a.M) ? a.sigma[sa + k] : 0.0;
     const cplx<T>* twl = TWL ? lds : a.tw;
     __syncthreads();
     const int NG = a.vg * gpb;         // groups in the grid
@@ -910,7 +916,6 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
     const int NR = (NP + NG - 1) / NG;       // rounds over row pairs
     const int NC = (a.H + NG - 1) / NG;      // rounds over spectral rows
     const int NRB = ((a.Nt + 1) / 2 + NG - 1) / NG;  // rounds over frequency pairs of the sine transform
-    const T* e = a.epad + kEpad;
     const T scale = two_d ? T(4.0 / ((double)(a.Nt + 1) * (a.Nt + 1))) : T(2.0 / (a.Nt + 1));
     unsigned ph = 0;  // phase of the device-wide synchronisation (phase_sync)
     auto sync_bar = [&]() { phase_barrier(a.part, a.bar, a.bar_ticks, red, tot, ph, a.vb, a.vg); };
@@ -920,7 +925,7 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
         const bool lastrow = (s == M);
         const T* dg = lastrow ? nullptr : a.dg + (long long)s * Nd;
         const T cc = lastrow ? T(1) : a.ct;
-        const T sig = lastrow ? T(0) : T(a.sigma[s]);
+        const T sig = lastrow ? T(0) : T(s_sig[s - sa]);
 
         // z = M^{-1} r and (r, z) for the 1D tau and the diagonal preconditioners (the 2D tau
         // preconditioner has its own fused loop below), optionally after the CG update
@@ -957,7 +962,7 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                     c[lx(Nt + 1)] = {T(0), T(0)};
                 }
                 __syncthreads();
-                fft_lds<T, VPT, false>(c, a.L, twl, tid, nthr);
+                fft_lds<T, VPT, false, true>(c, a.L, twl, tid, nthr);
                 if (act) {
 #pragma unroll
                     for (int u = 0; u < VPT; ++u) {
@@ -1011,8 +1016,8 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
         // read once per step so that no load of a point waits on a weight
         T ew[kNear];
 #pragma unroll
-        for (int i = 0; i < kNear; ++i) ew[i] = (!lastrow && i + 1 < nnear) ? e[s - sa - i] : T(0);
-        const T e1 = (nnear >= 1) ? e[1] : T(0);  // weight of y_{s-1} when it is a near term
+        for (int i = 0; i < kNear; ++i) ew[i] = (!lastrow && i + 1 < nnear) ? s_e[s - sa - i] : T(0);
+        const T e1 = (nnear >= 1) ? s_e[1] : T(0);  // weight of y_{s-1} when it is a near term
         // loads of point j (no stores, so that the loads of several points can be in flight together);
         // hn = sum over the near-history terms m in [sa, s-1) of e_{s-m} y_m, read from the LDS ring when
         // the thread keeps its points' earlier solutions there (a.ring), else from y
@@ -1149,7 +1154,7 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                     else e_rounds(std::integral_constant<int, (VH >= 2 ? 2 : 1)>{});
                     if (tid == 0) c[lx(0)] = {T(0), T(0)};
                     __syncthreads();
-                    fft_lds<T, VPT, false>(c, a.L, twl, tid, nthr);
+                    fft_lds<T, VPT, false, true>(c, a.L, twl, tid, nthr);
                     wg_write_T(a, cbase, a.t1, ibase, gpb, a.Nt, N);
                     __syncthreads();
                 }
@@ -1318,14 +1323,14 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                     c[lx(j)] = {pv[u], T(0)};
                 }
                 __syncthreads();
-                fft_lds<T, VPT, false>(c, a.L, twl, tid, nthr);
+                fft_lds<T, VPT, false, true>(c, a.L, twl, tid, nthr);
 #pragma unroll
                 for (int u = 0; u < VPT; ++u) {
                     const int k = tid + u * nthr;
                     c[lx(k)] = {c[lx(k)].x * sy[u], c[lx(k)].y * sy[u]};
                 }
                 __syncthreads();
-                fft_lds<T, VPT, true>(c, a.L, twl, tid, nthr);
+                fft_lds<T, VPT, true, true>(c, a.L, twl, tid, nthr);
                 if (act) {
 #pragma unroll
                     for (int u = 0; u < VPT; ++u) {
