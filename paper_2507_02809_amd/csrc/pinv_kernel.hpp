@@ -1064,7 +1064,12 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
             return v;
         };
         // the rest of point j: returns r0 and adds to (r, r), (b, b)
-        auto e_store = [&](long long j, const EIn& v, T& rr, T& bb, int u, int q) -> T {
+        // the values of point j (no memory access), then its stores (e_write): a round forms all its
+        // points before it stores any, so that no store waits behind the loads of a later point
+        struct EOut {
+            T yprev, bxprev, bxb_old, rhs, x0, rv;
+        };
+        auto e_form = [&](const EIn& v) -> EOut {
             const bool ext = (s >= 2 && !lastrow && a.extrap && !TB);
             const bool ext2 = (s >= 3 && !lastrow && a.extrap == 2 && !TB);
             const T yprev = v.xv;
@@ -1091,19 +1096,21 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                 }
             }
             const T rv = rhs - (v.dgo * x0 + cc * bx0);
-            if (s > 0) a.y[(long long)(s - 1) * Nd + j] = yprev;
+            return EOut{yprev, bxprev, v.bxb, rhs, x0, rv};
+        };
+        auto e_write = [&](long long j, const EOut& o, T& rr, T& bb, int u, int q) {
+            if (s > 0) a.y[(long long)(s - 1) * Nd + j] = o.yprev;
             if (a.ring && q >= 0 && s > sa && s - 1 - sa < kNear)
-                ring[(((s - 1 - sa) * (VPT / 2) + u) * 2 + q) * (int)blockDim.x + threadIdx.x] = yprev;
+                ring[(((s - 1 - sa) * (VPT / 2) + u) * 2 + q) * (int)blockDim.x + threadIdx.x] = o.yprev;
             if (s >= 1 && !lastrow && a.extrap && !TB) {
-                a.bxb[j] = bxprev;  // B y_{s-1} is "B y_{s-2}" next step
-                if (a.extrap == 2) a.bxb2[j] = v.bxb;  // and B y_{s-2} is "B y_{s-3}"
+                a.bxb[j] = o.bxprev;  // B y_{s-1} is "B y_{s-2}" next step
+                if (a.extrap == 2) a.bxb2[j] = o.bxb_old;  // and B y_{s-2} is "B y_{s-3}"
             }
-            a.rhs[j] = rhs;
-            a.x[j] = x0;
-            a.r[j] = rv;
-            rr += rv * rv;
-            bb += rhs * rhs;
-            return rv;
+            a.rhs[j] = o.rhs;
+            a.x[j] = o.x0;
+            a.r[j] = o.rv;
+            rr += o.rv * o.rv;
+            bb += o.rhs * o.rhs;
         };
         {
             T rr = T(0), bb = T(0);
@@ -1135,6 +1142,15 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                                 if (two) v[du][1] = e_load(j0 + N, u0 + du, 1);
                             }
                         }
+                        EOut o[EB][2];
+#pragma unroll
+                        for (int du = 0; du < EB; ++du) {
+                            const int m = tid + (u0 + du) * nthr;
+                            if (valid && m < N) {
+                                o[du][0] = e_form(v[du][0]);
+                                if (two) o[du][1] = e_form(v[du][1]);
+                            }
+                        }
 #pragma unroll
                         for (int du = 0; du < EB; ++du) {
                             // m < L/2: zero past the data (padded entries, position L/2)
@@ -1142,8 +1158,12 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                             T r0 = T(0), r1 = T(0);
                             if (valid && m < N) {
                                 const long long j0 = (long long)i0 * N + m;
-                                r0 = e_store(j0, v[du][0], rr, bb, u0 + du, 0);
-                                if (two) r1 = e_store(j0 + N, v[du][1], rr, bb, u0 + du, 1);
+                                e_write(j0, o[du][0], rr, bb, u0 + du, 0);
+                                r0 = o[du][0].rv;
+                                if (two) {
+                                    e_write(j0 + N, o[du][1], rr, bb, u0 + du, 1);
+                                    r1 = o[du][1].rv;
+                                }
                             }
                             c[lx(m + 1)] = {r0, r1};
                             c[lx(a.L - m - 1)] = {-r0, -r1};
@@ -1159,7 +1179,7 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                     __syncthreads();
                 }
             } else {
-                for (long long j = gtid; j < Nd; j += gthreads) (void)e_store(j, e_load(j, 0, -1), rr, bb, 0, -1);
+                for (long long j = gtid; j < Nd; j += gthreads) e_write(j, e_form(e_load(j, 0, -1)), rr, bb, 0, -1);
             }
             {
                 const int sl[2] = {SL_RR, SL_BB};
