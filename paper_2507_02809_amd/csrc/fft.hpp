@@ -119,7 +119,7 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* a, int L, int Ns, const c
 // In-place FFT of a[0..L) (stored with the lx() padding) with L = VPT * nthr.  Must be called by all threads of the
 // workgroup (it contains __syncthreads()); `tid` is the thread's index within its group.
 template <typename T, int VPT, bool INV, bool HT = false>
-__device__ void fft_lds(cplx<T>* a, int L, const cplx<T>* __restrict__ tw, int tid, int nthr) {
+__device__ __forceinline__ void fft_lds(cplx<T>* a, int L, const cplx<T>* __restrict__ tw, int tid, int nthr) {
     int Ns = 1;
     while (Ns < L) {
         const int rem = L / Ns;
