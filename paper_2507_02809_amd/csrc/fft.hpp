@@ -74,7 +74,9 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* a, int L, int Ns, const c
                                               int tid, int nthr) {
     constexpr int NB = VPT / R;  // butterflies per thread
     // HT with one butterfly per thread: its twiddles are read together with the data, before the
-    // barrier (they do not depend on it); callers whose registers are scarce leave HT off
+    // barrier (they do not depend on it).  It pays where a pass waits on LDS latency (the persistent
+    // P^-1 kernels); the streaming matvec kernels, which hide that latency with other workgroups,
+    // ran slower with it (the registers it holds), so they leave HT off
     constexpr bool HOIST = HT && NB == 1;
     const int nbut = L / R;
     const int tstride = L / (Ns * R);

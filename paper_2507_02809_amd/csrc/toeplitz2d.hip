@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kMvBlock) void mv_rows_fwd(const T* __restrict__ y,
 #pragma unroll
         for (int u = 0; u < VPT; ++u) v[u] = (u < VH) ? cplx<T>{p0[u], p1[u]} : cplx<T>{T(0), T(0)};
         if (blk + (int)gridDim.x < nrb * nsl) load_rows(blk + gridDim.x);
-        fft_x<T, VPT, false, true, false, true>(v, c, L, tw, tid, nthr);
+        fft_x<T, VPT, false, true, false>(v, c, L, tw, tid, nthr);
         __syncthreads();  // the write-out reads every group's sequence
         cplx<T>* out = spec + (long long)slice * H * ns;
         for (int idx = threadIdx.x; idx < H * gpb; idx += kMvBlock) {
@@ -141,10 +141,10 @@ __global__ __launch_bounds__(kMvBlock) void mv_cols(cplx<T>* __restrict__ spec, 
             sv[u] = ps[u];
         }
         if (rd + 1 < rounds) load_row(rd + 1);
-        fft_x<T, VPT, false, true, true, true>(v, c, L, tw, tid, nthr);
+        fft_x<T, VPT, false, true, true>(v, c, L, tw, tid, nthr);
 #pragma unroll
         for (int u = 0; u < VPT; ++u) v[u] = {v[u].x * sv[u], v[u].y * sv[u]};
-        fft_x<T, VPT, true, true, true, true>(v, c, L, tw, tid, nthr);
+        fft_x<T, VPT, true, true, true>(v, c, L, tw, tid, nthr);
         if (valid) {
 #pragma unroll
             for (int u = 0; u < VH; ++u) {
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kMvBlock) void mv_rows_inv(const cplx<T>* __restric
         }
         __syncthreads();
         cplx<T> v[VPT];
-        fft_x<T, VPT, true, false, true, true>(v, c, L, tw, tid, nthr);  // ends with the sequences free
+        fft_x<T, VPT, true, false, true>(v, c, L, tw, tid, nthr);  // ends with the sequences free
         const T cc = last ? cf : ct;
 #pragma unroll
         for (int u = 0; u < VH; ++u) {
