@@ -1024,33 +1024,44 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
         // (u, q): the point's column round and row within the thread's row pair (the ring's index), or
         // q < 0 for the grid-stride form, which does not use the ring
         auto e_load = [&](long long j, int u, int q) -> EIn {
+            // Every load is issued unconditionally from an address inside its array (an unused value
+            // comes from x, or from a clamped slice) and the value is selected afterwards: a load
+            // under a condition with a zero default makes the compiler wait for every load in flight
+            // before it writes the default into the load's register, which serialises the points.
             EIn v;
             const bool ext = (s >= 2 && !lastrow && a.extrap && !TB);
             const bool ext2 = (s >= 3 && !lastrow && a.extrap == 2 && !TB);
-            v.xv = (s > 0) ? a.x[j] : T(0);
-            v.rhs_o = (s > 0) ? a.rhs[j] : T(0);
-            v.r_o = (s > 0) ? a.r[j] : T(0);
-            v.dgp = (s > 0) ? a.dg[(long long)(s - 1) * Nd + j] : T(0);
-            v.bxb = ext ? a.bxb[j] : T(0);
-            v.ym2 = ext ? a.y[(long long)(s - 2) * Nd + j] : T(0);
-            v.ym3 = ext2 ? a.y[(long long)(s - 3) * Nd + j] : T(0);
-            v.bxb2 = ext2 ? a.bxb2[j] : T(0);
+            const T xl = a.x[j], rhsl = a.rhs[j], rl = a.r[j];
+            const T dgpl = a.dg[(long long)max(s - 1, 0) * Nd + j];
+            const T bxbl = (ext ? a.bxb : a.x)[j];
+            const T ym2l = ext ? a.y[(long long)max(s - 2, 0) * Nd + j] : a.x[j];
+            const T ym3l = ext2 ? a.y[(long long)max(s - 3, 0) * Nd + j] : a.x[j];
+            const T bxb2l = (ext2 ? a.bxb2 : a.x)[j];
             // s < M: w_s (far history folded in) and dg_s = gamma1_s/gamma2_s (e_0 = 1);
             // s = M: z_M and gamma2_{M-1}
-            v.zo = lastrow ? a.z[(long long)M * Nd + j] : a.hacc[(long long)(s - sa) * Nd + j];
-            v.g2o = lastrow ? a.g2[(long long)(M - 1) * Nd + j] : T(1);
-            v.dgo = dg ? dg[j] : T(0);
-            // y_m for m = sa + i < s - 1 (y_{s-1} is xv): the loads sit in uniform branches and are
-            // used only after all of them have been issued
+            const T zol = (lastrow ? a.z + (long long)M * Nd : a.hacc + (long long)(s - sa) * Nd)[j];
+            const T g2l = (lastrow ? a.g2 + (long long)(M - 1) * Nd : a.x)[j];
+            const T dgol = (dg ? dg : a.dg)[j];
+            // y_m for m = sa + i < s - 1 (y_{s-1} is xv), from the ring or from y (slice clamped)
             const bool lring = a.ring && q >= 0;
             T yv[kNear];
 #pragma unroll
-            for (int i = 0; i < kNear; ++i) {
-                yv[i] = T(0);
-                if (!lastrow && i + 1 < nnear)
-                    yv[i] = lring ? ring[((i * (VPT / 2) + u) * 2 + q) * (int)blockDim.x + threadIdx.x]
-                                  : a.y[(long long)(sa + i) * Nd + j];
-            }
+            for (int i = 0; i < kNear; ++i)
+                yv[i] = lring ? ring[((i * (VPT / 2) + u) * 2 + q) * (int)blockDim.x + threadIdx.x]
+                              : a.y[(long long)min(sa + i, M - 1) * Nd + j];
+            v.xv = (s > 0) ? xl : T(0);
+            v.rhs_o = (s > 0) ? rhsl : T(0);
+            v.r_o = (s > 0) ? rl : T(0);
+            v.dgp = (s > 0) ? dgpl : T(0);
+            v.bxb = ext ? bxbl : T(0);
+            v.ym2 = ext ? ym2l : T(0);
+            v.ym3 = ext2 ? ym3l : T(0);
+            v.bxb2 = ext2 ? bxb2l : T(0);
+            v.zo = zol;
+            v.g2o = lastrow ? g2l : T(1);
+            v.dgo = dg ? dgol : T(0);
+#pragma unroll
+            for (int i = 0; i < kNear; ++i) yv[i] = (!lastrow && i + 1 < nnear) ? yv[i] : T(0);
             if (a.adj) {
                 // transposed sweep: each earlier step's term carries its own weight dg_m
 #pragma unroll
@@ -1063,7 +1074,6 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
             v.hn = hn;
             return v;
         };
-        // the rest of point j: returns r0 and adds to (r, r), (b, b)
         // the values of point j (no memory access), then its stores (e_write): a round forms all its
         // points before it stores any, so that no store waits behind the loads of a later point
         struct EOut {
