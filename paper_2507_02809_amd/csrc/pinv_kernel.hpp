@@ -1023,6 +1023,30 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
         // the thread keeps its points' earlier solutions there (a.ring), else from y
         // (u, q): the point's column round and row within the thread's row pair (the ring's index), or
         // q < 0 for the grid-stride form, which does not use the ring
+        // the common step (s > 0, not the last block row, no extrapolation, forward sweep): only the
+        // six values it uses are loaded, so that the loads of all of a thread's points stay within
+        // the count of memory operations in flight that the hardware tracks
+        auto e_load_lean = [&](long long j, int u, int q) -> EIn {
+            EIn v;
+            v.xv = a.x[j];
+            v.rhs_o = a.rhs[j];
+            v.r_o = a.r[j];
+            v.dgp = a.dg[(long long)(s - 1) * Nd + j];
+            v.zo = a.hacc[(long long)(s - sa) * Nd + j];
+            v.dgo = dg[j];
+            v.bxb = v.bxb2 = v.ym2 = v.ym3 = T(0);
+            v.g2o = T(1);
+            T yv[kNear];
+#pragma unroll
+            for (int i = 0; i < kNear; ++i) yv[i] = ring[((i * (VPT / 2) + u) * 2 + q) * (int)blockDim.x + threadIdx.x];
+#pragma unroll
+            for (int i = 0; i < kNear; ++i) yv[i] = (i + 1 < nnear) ? yv[i] : T(0);
+            T hn = T(0);
+#pragma unroll
+            for (int i = 0; i < kNear; ++i) hn += ew[i] * yv[i];
+            v.hn = hn;
+            return v;
+        };
         auto e_load = [&](long long j, int u, int q) -> EIn {
             // Every load is issued unconditionally from an address inside its array (an unused value
             // comes from x, or from a clamped slice) and the value is selected afterwards: a load
@@ -1138,8 +1162,9 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                     // EB columns per round: all of them when the near history comes from the ring (the
                     // loads of a round then stay within the count of memory operations in flight that
                     // the hardware tracks), else two
-                    auto e_rounds = [&](auto ebc) {
+                    auto e_rounds = [&](auto ebc, auto leanc) {
                     constexpr int EB = decltype(ebc)::value;
+                    constexpr bool LEAN = decltype(leanc)::value;
 #pragma unroll 1
                     for (int u0 = 0; u0 < VH; u0 += EB) {
                         EIn v[EB][2];
@@ -1148,8 +1173,13 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                             const int m = tid + (u0 + du) * nthr;
                             if (valid && m < N) {
                                 const long long j0 = (long long)i0 * N + m;
-                                v[du][0] = e_load(j0, u0 + du, 0);
-                                if (two) v[du][1] = e_load(j0 + N, u0 + du, 1);
+                                if constexpr (LEAN) {
+                                    v[du][0] = e_load_lean(j0, u0 + du, 0);
+                                    if (two) v[du][1] = e_load_lean(j0 + N, u0 + du, 1);
+                                } else {
+                                    v[du][0] = e_load(j0, u0 + du, 0);
+                                    if (two) v[du][1] = e_load(j0 + N, u0 + du, 1);
+                                }
                             }
                         }
                         EOut o[EB][2];
@@ -1180,8 +1210,10 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                         }
                     }
                     };
-                    if (a.ring) e_rounds(std::integral_constant<int, VH>{});
-                    else e_rounds(std::integral_constant<int, (VH >= 2 ? 2 : 1)>{});
+                    const bool lean = a.ring && s > 0 && !lastrow && !a.adj && !(a.extrap && s >= 2 && !TB);
+                    if (lean) e_rounds(std::integral_constant<int, VH>{}, std::true_type{});
+                    else if (a.ring) e_rounds(std::integral_constant<int, VH>{}, std::false_type{});
+                    else e_rounds(std::integral_constant<int, (VH >= 2 ? 2 : 1)>{}, std::false_type{});
                     if (tid == 0) c[lx(0)] = {T(0), T(0)};
                     __syncthreads();
                     fft_lds<T, VPT, false, true>(c, a.L, twl, tid, nthr);
