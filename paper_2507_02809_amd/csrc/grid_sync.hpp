@@ -1,4 +1,5 @@
-// The device-wide barrier of the persistent kernels (P^{-1} segments, dense-transform block solvers).
+// The device-wide barrier of the persistent dense-transform block solvers (the P^{-1} segment kernel
+// synchronises through its reduction slots instead: phase_sync in pinv_kernel.hpp).
 // Every workgroup of such a grid must be resident at once: the launchers take the grid's CU slots
 // from the per-device pool first (residency.hpp).
 #pragma once
