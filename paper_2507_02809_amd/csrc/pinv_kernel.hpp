@@ -1023,7 +1023,7 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
         // the thread keeps its points' earlier solutions there (a.ring), else from y
         // (u, q): the point's column round and row within the thread's row pair (the ring's index), or
         // q < 0 for the grid-stride form, which does not use the ring
-        // the common step (s > 0, not the last block row, no extrapolation, forward sweep): only the
+        // the common step (s > 0, not the last block row, no extrapolation; either sweep): only the
         // six values it uses are loaded, so that the loads of all of a thread's points stay within
         // the count of memory operations in flight that the hardware tracks
         auto e_load_lean = [&](long long j, int u, int q) -> EIn {
@@ -1086,8 +1086,9 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
             v.dgo = dg ? dgol : T(0);
 #pragma unroll
             for (int i = 0; i < kNear; ++i) yv[i] = (!lastrow && i + 1 < nnear) ? yv[i] : T(0);
-            if (a.adj) {
-                // transposed sweep: each earlier step's term carries its own weight dg_m
+            if (a.adj && !lring) {
+                // transposed sweep: each earlier step's term carries its own weight dg_m (the ring
+                // holds the products already)
 #pragma unroll
                 for (int i = 0; i < kNear; ++i)
                     if (!lastrow && i + 1 < nnear) yv[i] *= a.dg[(long long)(sa + i) * Nd + j];
@@ -1101,7 +1102,7 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
         // the values of point j (no memory access), then its stores (e_write): a round forms all its
         // points before it stores any, so that no store waits behind the loads of a later point
         struct EOut {
-            T yprev, bxprev, bxb_old, rhs, x0, rv;
+            T yprev, bxprev, bxb_old, rhs, x0, rv, dgp;
         };
         auto e_form = [&](const EIn& v) -> EOut {
             const bool ext = (s >= 2 && !lastrow && a.extrap && !TB);
@@ -1130,12 +1131,14 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                 }
             }
             const T rv = rhs - (v.dgo * x0 + cc * bx0);
-            return EOut{yprev, bxprev, v.bxb, rhs, x0, rv};
+            return EOut{yprev, bxprev, v.bxb, rhs, x0, rv, v.dgp};
         };
         auto e_write = [&](long long j, const EOut& o, T& rr, T& bb, int u, int q) {
             if (s > 0) a.y[(long long)(s - 1) * Nd + j] = o.yprev;
+            // the transposed sweep keeps dg_{s-1} y_{s-1}, the term its near-history sum weighs
             if (a.ring && q >= 0 && s > sa && s - 1 - sa < kNear)
-                ring[(((s - 1 - sa) * (VPT / 2) + u) * 2 + q) * (int)blockDim.x + threadIdx.x] = o.yprev;
+                ring[(((s - 1 - sa) * (VPT / 2) + u) * 2 + q) * (int)blockDim.x + threadIdx.x] =
+                    a.adj ? o.yprev * o.dgp : o.yprev;
             if (s >= 1 && !lastrow && a.extrap && !TB) {
                 a.bxb[j] = o.bxprev;  // B y_{s-1} is "B y_{s-2}" next step
                 if (a.extrap == 2) a.bxb2[j] = o.bxb_old;  // and B y_{s-2} is "B y_{s-3}"
@@ -1210,7 +1213,7 @@ __device__ __forceinline__ void segment_run(PinvArgs<T> a, int sa, int sb) {
                         }
                     }
                     };
-                    const bool lean = a.ring && s > 0 && !lastrow && !a.adj && !(a.extrap && s >= 2 && !TB);
+                    const bool lean = a.ring && s > 0 && !lastrow && !(a.extrap && s >= 2 && !TB);
                     if (lean) e_rounds(std::integral_constant<int, VH>{}, std::true_type{});
                     else if (a.ring) e_rounds(std::integral_constant<int, VH>{}, std::false_type{});
                     else e_rounds(std::integral_constant<int, (VH >= 2 ? 2 : 1)>{}, std::false_type{});
